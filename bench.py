@@ -1,0 +1,184 @@
+"""Benchmark: energy + adjoint-gradient evaluations per second of the 24-qubit
+workload (12 electrons, 200 sampled excitations, FP64 amplitudes) on one GPU,
+the HBM roofline fraction of its dominant kernel (the adjoint reverse step),
+the per-parameter finite-difference gradient on the same GPU, and the FP64
+CPU oracle timed on the host cores.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def qubit_of(so, m, ordering):
+    p, s = divmod(int(so), 2)
+    return int(so) if ordering == 0 else p + s * m
+
+
+def line_bytes(op, n, amp_bytes, ordering):
+    """Read + write of the 128-byte lines one pair kernel touches."""
+    m = n // 2
+    low = 3 if amp_bytes == 16 else 4
+    qs = [qubit_of(v, m, ordering) for v in op if v >= 0]
+    hi = sum(q >= low for q in qs)
+    frac = 1.0 if hi == 0 else min(1.0, 2.0 ** (1 - hi))
+    return 2.0 * (2 ** n) * amp_bytes * frac
+
+
+def model_bytes(p, amp_bytes):
+    per_op = [line_bytes(op, p.n_qubits, amp_bytes, p.ordering) for op in p.ops]
+    fwd = sum(per_op)
+    sigma = 2.0 * (2 ** p.n_qubits) * amp_bytes
+    return {"forward": fwd, "reverse": 2 * fwd, "sigma_floor": sigma, "eval": 3 * fwd + sigma,
+            "per_op": per_op}
+
+
+def cpu_baseline(p, max_seconds=30.0):
+    from oracle import sector
+    sector.build()
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        sector.energy_grad(p.n_orb, p.n_alpha, p.n_beta, p.ops, p.theta, p.h, p.g, p.e_core, p.ordering)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > max_seconds / 3 or n >= 3:
+            break
+    return {"value": n / el, "unit": "evals/s", "cores": sector.num_threads(), "kind": "oracle",
+            "sample": f"{n} full energy+adjoint-gradient evaluation(s) of the same 24-qubit workload "
+                      f"(sector-compressed FP64 C/OpenMP oracle), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C3")
+    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the state-vector path here is single-GPU "
+              "(sharding across GPUs is a design note, not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2405_11567_amd as fsv
+    from workloads import config
+
+    p = config(args.config)
+    amp_bytes = 16 if args.precision == 0 else 8
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    plan = fsv.Plan(p, precision=args.precision, device=dev)
+    psi, lam = plan.new_state(), plan.new_state()
+    print(f"[bench] plan ready: {args.config} n={p.n_qubits} K={p.n_ops} precision={args.precision}",
+          file=sys.stderr, flush=True)
+    if args.tune:
+        print(plan.autotune(psi, lam), file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        plan.energy_grad(p.theta, psi, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e, g = plan.energy_grad(p.theta, psi, lam)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    evals_s = args.steps / (t1 - t0)
+    print(f"[bench] timed {args.steps} evals: {ms:.3f} ms/eval", file=sys.stderr, flush=True)
+
+    # Stage timing with HIP events on the plan's stream: forward, sigma, reverse.
+    mb = model_bytes(p, amp_bytes)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_fwd, t_sig, t_rev = [], [], []
+    reps = max(3, min(args.steps, 10))
+    for _ in range(reps):
+        plan.set_theta(p.theta)
+        ev[0].record(stream)
+        plan.forward_async(psi)
+        ev[1].record(stream)
+        plan.sigma_async(psi, lam)
+        ev[2].record(stream)
+        plan.reverse_async(psi, lam)
+        ev[3].record(stream)
+        plan.finish()
+        torch.cuda.synchronize()
+        t_fwd.append(ev[0].elapsed_time(ev[1]))
+        t_sig.append(ev[1].elapsed_time(ev[2]))
+        t_rev.append(ev[2].elapsed_time(ev[3]))
+    t_rev_ms = float(np.median(t_rev))
+    k = p.n_ops
+    adj_launch_ms = t_rev_ms / k
+    adj_bytes_per_launch = mb["reverse"] / k
+    achieved = adj_bytes_per_launch / (adj_launch_ms * 1e-3) / 1e9
+    print(f"[bench] stages: forward {np.median(t_fwd):.3f} ms, sigma {np.median(t_sig):.3f} ms, "
+          f"reverse {t_rev_ms:.3f} ms ({adj_launch_ms*1e3:.2f} us/launch)", file=sys.stderr, flush=True)
+
+    fd = None
+    if not args.no_fd:
+        # central finite differences on the same GPU: 2K + 1 energy evaluations
+        t2 = time.perf_counter()
+        _, gfd = plan.energy_grad_fd(p.theta, 1e-5, psi)
+        t3 = time.perf_counter()
+        fd_s = t3 - t2
+        fd = {"gradient_s": fd_s, "evals_s": 1.0 / fd_s, "adjoint_speedup": fd_s / (ms * 1e-3),
+              "max_abs_diff_vs_adjoint": float(np.abs(gfd - g).max())}
+        print(f"[bench] FD gradient {fd_s:.3f} s ({2*k+1} energies), adjoint {ms:.3f} ms: "
+              f"{fd['adjoint_speedup']:.0f}x", file=sys.stderr, flush=True)
+
+    cpu = None if args.no_cpu else cpu_baseline(p)
+    out = {
+        "metric": "energy+gradient evals/s and achieved HBM GB/s at 24 qubits vs plain FD method",
+        "value": evals_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if args.precision == 0 else "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {p.n_qubits} qubits, {p.n_alpha + p.n_beta} electrons, "
+                               f"{k} sampled spin-conserving singles/doubles, energy + adjoint gradient",
+                   "n_qubits": p.n_qubits, "n_ops": k, "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "adjoint reverse step (k_adj)",
+                     "avg_launch_us": adj_launch_ms * 1e3,
+                     "algorithmic_bytes_per_launch": adj_bytes_per_launch},
+        "eval_model": {"bytes_per_eval": mb["eval"],
+                       "hbm_frac_per_eval": mb["eval"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "stage_ms": {"forward": float(np.median(t_fwd)), "sigma": float(np.median(t_sig)),
+                                    "reverse": t_rev_ms}},
+        "energy": e,
+        "fd_baseline": fd,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * fsv.h -- fermionic state-vector emulation on one AMD MI355X (gfx950).
+ *
+ * The GPU side of the hybrid scheme of arXiv 2405.11567 (Fig. 1: the QPU
+ * workload replaced by a GPU emulator): a variational fermionic ansatz on a
+ * 2^n complex amplitude vector, its energy <H> for a second-quantised
+ * Hamiltonian given by one- and two-electron integrals (exchanged as FCIDUMP
+ * integrals, Computational Details), the one-particle density matrix of
+ * Strategy 2, and the extra one-body potential that the self-consistent
+ * Strategy-2 loop adds to the Hamiltonian (effective Hamiltonian equation).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - n_qubits = 2 * n_orb.  Spin-orbital label so = 2 p + s (s = 0 alpha,
+ *    s = 1 beta).  The qubit holding so is so for ordering 0 (interleaved) and
+ *    p + s * n_orb for ordering 1 (blocked).  Bit j of a basis index x is the
+ *    occupation of qubit j, and |x> = prod_{j ascending} (a^+_j)^{x_j} |vac>
+ *    (Jordan-Wigner mapping, one spin-orbital per qubit).
+ *  - An operator is four int32 {a, b, j, i}: tau = a^+_a a^+_b a_j a_i; a
+ *    single excitation is {a, -1, -1, i}: tau = a^+_a a_i.  Indices are
+ *    spin-orbital labels; they must be distinct, in range and conserve the
+ *    number of alpha and of beta electrons.  U_k = exp(theta_k (tau - tau^+)),
+ *    theta in radians, and the ansatz is U_K ... U_1 |ref>: the first listed
+ *    operator acts first.  |ref> fills the lowest n_alpha alpha and n_beta beta
+ *    orbitals with amplitude +1 (the paper's HF initial state).
+ *  - H = e_core + sum_{pq,s} (h + v)_pq a^+_{ps} a_{qs}
+ *          + 1/2 sum_{pqrs,st} (pq|rs) a^+_{ps} a^+_{rt} a_{st} a_{qs},
+ *    h: n_orb x n_orb real symmetric, row-major; g: n_orb^4 real, row-major,
+ *    chemist notation (pq|rs) with 8-fold symmetry; v: the Strategy-2 one-body
+ *    potential (zero until set_onebody_potential is called).
+ *  - Amplitude buffers are device pointers to 2^n complex values: interleaved
+ *    (re, im) float64 for precision 0, float32 for precision 1.  The caller
+ *    owns and allocates them (fsv_state_bytes); the library never allocates
+ *    O(2^n) memory.  The plan owns only O(K + n_orb^4 + sector) tables and a
+ *    sector-sized workspace (the (n_alpha, n_beta) sector is the only part of
+ *    the state that the operators above ever make nonzero).
+ *  - Every function returns FSV_OK (0) or a negative status, never throws and
+ *    never exits.  fsv_last_error() returns a thread-local message for the last
+ *    failure on the calling thread.
+ *  - A plan is bound to the HIP stream given at creation (NULL: the legacy
+ *    default stream).  Work is ordered after all earlier work on that stream;
+ *    functions that write host outputs return after the results are on the
+ *    host.  A plan is not thread-safe: calls on one plan must not overlap.
+ */
+#ifndef FSV_H
+#define FSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSV_OK 0
+#define FSV_EINVAL -1     /* invalid argument: index, size, ordering, precision, symmetry */
+#define FSV_ENOMEM -2     /* plan tables could not be allocated (host or device) */
+#define FSV_EDEVICE -3    /* HIP runtime error; the message holds the HIP error string */
+#define FSV_ESTATE -4     /* wrong call order or a plan / batch mismatch */
+#define FSV_ENONFINITE -5 /* NaN or Inf in theta, h, g or v */
+
+typedef struct fsv_plan fsv_plan;
+typedef struct fsv_batch fsv_batch;
+
+typedef struct {
+    int32_t n_qubits;   /* 2 .. 34, even */
+    int32_t n_alpha;    /* 0 .. n_orb */
+    int32_t n_beta;     /* 0 .. n_orb */
+    int32_t ordering;   /* 0 interleaved (qubit 2p+s), 1 blocked (qubit p + s*n_orb) */
+    int32_t precision;  /* 0 complex128 amplitudes, 1 complex64 amplitudes (FP64 reductions) */
+    const double *h;    /* host, n_orb*n_orb, copied at plan creation */
+    const double *g;    /* host, n_orb^4, copied at plan creation */
+    double e_core;      /* constant added through H (0 for synthetic inputs) */
+    int32_t n_ops;      /* K >= 0 */
+    const int32_t *ops; /* host, K x 4 {a, b, j, i}, copied at plan creation */
+} fsv_problem;
+
+/* Message of the last failure on this thread ("" when none). */
+const char *fsv_last_error(void);
+
+/* Build a plan: validate the problem, compile each operator into bit masks,
+ * build the alpha/beta string tables of the sector and upload the integrals.
+ * hip_stream is a hipStream_t (NULL allowed).  On failure *out is NULL. */
+int fsv_plan_create(fsv_plan **out, const fsv_problem *problem, void *hip_stream);
+
+/* Release a plan and its device tables.  NULL is accepted. */
+int fsv_plan_destroy(fsv_plan *plan);
+
+/* Bytes of one amplitude buffer: 2^n_qubits * (16 or 8). 0 for NULL. */
+size_t fsv_state_bytes(const fsv_plan *plan);
+
+/* Sector dimensions: number of alpha strings, beta strings, and the dense
+ * index of the reference determinant.  Any pointer may be NULL. */
+int fsv_plan_info(const fsv_plan *plan, int64_t *n_alpha_strings, int64_t *n_beta_strings,
+                  uint64_t *reference_index);
+
+/* psi_dev <- U_K(theta_K) ... U_1(theta_1) |ref> (ansatz preparation on the
+ * GPU emulator, Fig. 1).  theta: host, K doubles.  Every amplitude of psi_dev
+ * is written (zero outside the sector). */
+int ansatz_apply(fsv_plan *plan, const double *theta, void *psi_dev);
+
+/* *E_out <- Re <psi| H |psi> for the (n_alpha, n_beta) sector component of
+ * psi, without normalisation (the expectation value <H> of Fig. 1; the
+ * Strategy-1 input).  psi_dev is read only. */
+int energy(fsv_plan *plan, const void *psi_dev, double *E_out);
+
+/* Energy of psi(theta) and its gradient dE/dtheta_k by the adjoint method:
+ * after the forward sweep lam = H psi, then for k = K..1
+ * grad_k = 2 Re <lam| (tau_k - tau_k^+) |psi>, psi <- U_k^+ psi,
+ * lam <- U_k^+ lam (the states are recomputed, never stored).  psi_dev and
+ * lam_dev are caller-owned work buffers of fsv_state_bytes each; their
+ * contents on return are unspecified.  grad_out: host, K doubles. */
+int energy_grad(fsv_plan *plan, const double *theta, void *psi_dev, void *lam_dev,
+                double *E_out, double *grad_out);
+
+/* Same energy and gradient by central finite differences of the energy,
+ * 2K + 1 energy evaluations with step `step` (the plain per-parameter method
+ * the adjoint is compared against).  psi_dev is a work buffer. */
+int energy_grad_fd(fsv_plan *plan, const double *theta, double step, void *psi_dev,
+                   double *E_out, double *grad_out);
+
+/* One-particle density matrix gamma[s][p][q] = <psi| a^+_{ps} a_{qs} |psi>
+ * (Strategy 2, density-matrix equation) for s = alpha, beta.  gamma_out: host,
+ * 2 * n_orb * n_orb complex128 as interleaved doubles (4 n_orb^2 doubles). */
+int rdm1(fsv_plan *plan, const void *psi_dev, double *gamma_out);
+
+/* Replace the one-body potential: the Hamiltonian becomes H with h -> h + v
+ * (the basis-set correction potential operator of Strategy 2, spin-independent).
+ * v: host, n_orb*n_orb real symmetric; NULL clears it.  Later energy,
+ * energy_grad and batch calls use the new Hamiltonian. */
+int set_onebody_potential(fsv_plan *plan, const double *v);
+
+/* ---- stage-level asynchronous entry points (device outputs, no host sync) ----
+ * They split energy_grad into its passes so that a caller can time or overlap
+ * them; energy_grad is exactly forward + sigma + reverse + finish. */
+
+/* Upload theta (host, K) into the plan's device angle table. */
+int fsv_set_theta(fsv_plan *plan, const double *theta);
+/* psi <- |ref>, then the K forward rotations with the uploaded angles. */
+int fsv_forward_async(fsv_plan *plan, void *psi_dev);
+/* lam <- H psi (zero outside the sector); E on the device. */
+int fsv_sigma_async(fsv_plan *plan, const void *psi_dev, void *lam_dev);
+/* Reverse adjoint sweep over all K operators; per-operator partial sums on the device. */
+int fsv_reverse_async(fsv_plan *plan, void *psi_dev, void *lam_dev);
+/* Reduce the partial sums, copy E and grad to the host and wait. */
+int fsv_finish(fsv_plan *plan, double *E_out, double *grad_out);
+
+/* Launch-shape tuning: time the rotation and adjoint kernels of this plan over
+ * the candidate shapes and keep the fastest (cached per shape class in the
+ * file named by FSV_TUNE_CACHE when set).  psi_dev and lam_dev are work
+ * buffers.  *report (may be NULL) receives a static summary string. */
+int fsv_autotune(fsv_plan *plan, void *psi_dev, void *lam_dev, const char **report);
+
+/* ---- batches: many independent instances in one persistent graph launch ----
+ * Each instance has its own problem (qubit count, electrons, integrals,
+ * operators); all must use the same precision (complex128 only).  The batch
+ * keeps each instance's sector state in a device arena that it owns. */
+int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count, void *hip_stream);
+int fsv_batch_destroy(fsv_batch *batch);
+/* theta_concat: host, sum_i K_i doubles in instance order.  E_out: host,
+ * count doubles.  grad_concat: host, sum_i K_i doubles. */
+int fsv_batch_energy_grad(fsv_batch *batch, const double *theta_concat, double *E_out,
+                          double *grad_concat);
+/* Device bytes the batch owns (arena + tables). */
+size_t fsv_batch_bytes(const fsv_batch *batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSV_H */

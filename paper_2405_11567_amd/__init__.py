@@ -1,0 +1,267 @@
+"""Fermionic state-vector emulation on AMD MI355X (gfx950).
+
+Python binding over the C-ABI library libfsv.so (include/fsv.h).  The binding
+only marshals arguments: every step of the path runs in the HIP kernels.
+PyTorch provides the device buffers and the stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import FsvError, Problem as _CProblem, check, load  # noqa: F401
+
+__all__ = ["Plan", "Batch", "EnergyFn", "FsvError", "load"]
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _cproblem(n_qubits, n_alpha, n_beta, h, g, ops, e_core, ordering, precision, keep):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    ops = np.ascontiguousarray(np.asarray(ops, dtype=np.int32).reshape(-1, 4))
+    keep.extend([h, g, ops])
+    return _CProblem(int(n_qubits), int(n_alpha), int(n_beta), int(ordering), int(precision),
+                     _dptr(h), _dptr(g), float(e_core), int(ops.shape[0]), _iptr(ops))
+
+
+class Plan:
+    """One problem (qubits, electrons, integrals, operator list) bound to one
+    HIP stream.  `problem` is any object with the attributes of
+    workloads.Problem (n_qubits, n_alpha, n_beta, h, g, ops, e_core, ordering)."""
+
+    def __init__(self, problem, precision: int = 0, ordering: int | None = None,
+                 stream=None, device=None):
+        torch = _torch()
+        lib = load()
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self.n_qubits = int(problem.n_qubits)
+        self.n_orb = self.n_qubits // 2
+        self.n_ops = int(np.asarray(problem.ops).reshape(-1, 4).shape[0])
+        self.precision = int(precision)
+        self.ordering = int(problem.ordering if ordering is None else ordering)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        keep = []
+        cp = _cproblem(problem.n_qubits, problem.n_alpha, problem.n_beta, problem.h, problem.g,
+                       problem.ops, getattr(problem, "e_core", 0.0), self.ordering, self.precision, keep)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.fsv_plan_create(ctypes.byref(handle), ctypes.byref(cp),
+                                      ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = handle
+        self._lib = lib
+        self.state_bytes = int(lib.fsv_state_bytes(handle))
+        nsa, nsb, ref = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
+        check(lib.fsv_plan_info(handle, ctypes.byref(nsa), ctypes.byref(nsb), ctypes.byref(ref)))
+        self.n_alpha_strings, self.n_beta_strings = nsa.value, nsb.value
+        self.reference_index = ref.value
+
+    # -- buffers ---------------------------------------------------------
+    @property
+    def dtype(self):
+        torch = _torch()
+        return torch.complex128 if self.precision == 0 else torch.complex64
+
+    def new_state(self):
+        torch = _torch()
+        return torch.empty(1 << self.n_qubits, dtype=self.dtype, device=self.device)
+
+    def _check_state(self, t):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != self.dtype \
+                or not t.is_contiguous() or t.numel() * t.element_size() < self.state_bytes:
+            raise ValueError("state must be a contiguous %s tensor of %d bytes on %s"
+                             % (self.dtype, self.state_bytes, self.device))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _theta(self, theta):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if th.size != self.n_ops:
+            raise ValueError(f"theta must have {self.n_ops} entries")
+        return th
+
+    # -- entry points ----------------------------------------------------
+    def ansatz_apply(self, theta, psi=None):
+        psi = self.new_state() if psi is None else psi
+        th = self._theta(theta)
+        check(self._lib.ansatz_apply(self._h, _dptr(th), self._check_state(psi)))
+        return psi
+
+    def energy(self, psi) -> float:
+        e = ctypes.c_double()
+        check(self._lib.energy(self._h, self._check_state(psi), ctypes.byref(e)))
+        return e.value
+
+    def energy_grad(self, theta, psi=None, lam=None):
+        psi = self.new_state() if psi is None else psi
+        lam = self.new_state() if lam is None else lam
+        th = self._theta(theta)
+        grad = np.zeros(self.n_ops)
+        e = ctypes.c_double()
+        check(self._lib.energy_grad(self._h, _dptr(th), self._check_state(psi), self._check_state(lam),
+                                    ctypes.byref(e), _dptr(grad)))
+        return e.value, grad
+
+    def energy_grad_fd(self, theta, step: float = 1e-5, psi=None):
+        psi = self.new_state() if psi is None else psi
+        th = self._theta(theta)
+        grad = np.zeros(self.n_ops)
+        e = ctypes.c_double()
+        check(self._lib.energy_grad_fd(self._h, _dptr(th), float(step), self._check_state(psi),
+                                       ctypes.byref(e), _dptr(grad)))
+        return e.value, grad
+
+    def rdm1(self, psi):
+        gam = np.zeros((2, self.n_orb, self.n_orb), dtype=np.complex128)
+        check(self._lib.rdm1(self._h, self._check_state(psi), _dptr(gam.view(np.float64))))
+        return gam
+
+    def set_onebody_potential(self, v=None):
+        if v is None:
+            check(self._lib.set_onebody_potential(self._h, None))
+        else:
+            vv = np.ascontiguousarray(v, dtype=np.float64)
+            if vv.shape != (self.n_orb, self.n_orb):
+                raise ValueError("v must be n_orb x n_orb")
+            check(self._lib.set_onebody_potential(self._h, _dptr(vv)))
+
+    # -- stages (async) -----------------------------------------------------
+    def set_theta(self, theta):
+        th = self._theta(theta)
+        check(self._lib.fsv_set_theta(self._h, _dptr(th)))
+
+    def forward_async(self, psi):
+        check(self._lib.fsv_forward_async(self._h, self._check_state(psi)))
+
+    def sigma_async(self, psi, lam):
+        check(self._lib.fsv_sigma_async(self._h, self._check_state(psi), self._check_state(lam)))
+
+    def reverse_async(self, psi, lam):
+        check(self._lib.fsv_reverse_async(self._h, self._check_state(psi), self._check_state(lam)))
+
+    def finish(self):
+        grad = np.zeros(self.n_ops)
+        e = ctypes.c_double()
+        check(self._lib.fsv_finish(self._h, ctypes.byref(e), _dptr(grad)))
+        return e.value, grad
+
+    def autotune(self, psi, lam) -> str:
+        rep = ctypes.c_char_p()
+        check(self._lib.fsv_autotune(self._h, self._check_state(psi), self._check_state(lam),
+                                     ctypes.byref(rep)))
+        return rep.value.decode() if rep.value else ""
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(self._lib.fsv_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent problems evaluated together (energy + adjoint gradient
+    of each) in one persistent graph launch."""
+
+    def __init__(self, problems, stream=None, device=None):
+        torch = _torch()
+        lib = load()
+        self.device = torch.device(device if device is not None else "cuda:0")
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        keep = []
+        arr = (_CProblem * len(problems))()
+        self.n_ops = []
+        for i, p in enumerate(problems):
+            arr[i] = _cproblem(p.n_qubits, p.n_alpha, p.n_beta, p.h, p.g, p.ops,
+                               getattr(p, "e_core", 0.0), p.ordering, 0, keep)
+            self.n_ops.append(int(np.asarray(p.ops).reshape(-1, 4).shape[0]))
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.fsv_batch_create(ctypes.byref(handle), arr, len(problems),
+                                       ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = handle
+        self._lib = lib
+        self.count = len(problems)
+        self.bytes = int(lib.fsv_batch_bytes(handle))
+
+    def energy_grad(self, thetas):
+        th = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64).reshape(-1)
+                                                  for t in thetas]))
+        if th.size != sum(self.n_ops):
+            raise ValueError("theta sizes do not match the batch")
+        e = np.zeros(self.count)
+        g = np.zeros(th.size)
+        check(self._lib.fsv_batch_energy_grad(self._h, _dptr(th), _dptr(e), _dptr(g)))
+        out, off = [], 0
+        for k in self.n_ops:
+            out.append(g[off:off + k])
+            off += k
+        return e, out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(self._lib.fsv_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _make_energy_fn():
+    torch = _torch()
+
+    class EnergyFn(torch.autograd.Function):
+        """E(theta) with the hand-written adjoint gradient as backward.
+        theta: 1-D float64 CPU tensor; returns a 0-d float64 tensor."""
+
+        @staticmethod
+        def forward(ctx, theta, plan, psi=None, lam=None):
+            th = theta.detach().cpu().numpy()
+            if ctx.needs_input_grad[0]:
+                e, g = plan.energy_grad(th, psi, lam)
+                ctx.save_for_backward(torch.from_numpy(g))
+            else:
+                buf = plan.ansatz_apply(th, psi)
+                e = plan.energy(buf)
+            return torch.tensor(e, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None, None, None
+
+    return EnergyFn
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _Lazy._cls is None:
+            _Lazy._cls = _make_energy_fn()
+        return getattr(_Lazy._cls, name)
+
+
+EnergyFn = _Lazy()

@@ -1,0 +1,997 @@
+// Host side of the C-ABI library: validation, operator compilation, sector
+// string tables, same-spin string Hamiltonians (Slater-Condon rules), graph
+// capture of the energy/gradient pass, finite differences and launch tuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fsv.h"
+#include "fsv_internal.h"
+
+using namespace fsv;
+
+// ------------------------------------------------------------------ errors --
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHECK(expr)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(FSV_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+int popcount64(uint64_t v) { return __builtin_popcountll(v); }
+
+// JW action of a^+_q (dag) or a_q on a bit string; 0 when annihilated.
+int jw_step(uint64_t &x, bool dag, int q) {
+    const uint64_t b = 1ull << q;
+    if (dag == ((x & b) != 0)) return 0;
+    const int s = (popcount64(x & (b - 1)) & 1) ? -1 : 1;
+    x ^= b;
+    return s;
+}
+
+bool finite_all(const double *a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+// -------------------------------------------------------------------- plan --
+struct fsv_plan {
+    int n = 0, M = 0, na = 0, nb = 0, ordering = 0, precision = 0, K = 0;
+    double ecore = 0.0;
+    std::vector<double> h, g, v;
+    std::vector<int32_t> ops;
+    std::vector<RotOp> rot;
+    std::vector<uint64_t> npairs;
+    Shape shape_rot{256, 4}, shape_adj{256, 2};
+    bool wide = false;   // 64-bit index math
+    int amp_bytes = 16;
+    uint64_t ref_index = 0;
+
+    // forward segmentation: fused LDS runs [k0, k1) (k1 - k0 >= 2) or single ops
+    struct Seg { int k0, k1; bool fused; };
+    std::vector<Seg> segs;
+    int tile_bits = 12;
+
+    // sector tables
+    int64_t nsa = 0, nsb = 0, dim = 0;
+    int nexcA = 0, nexcB = 0;
+    std::vector<uint32_t> sa, sb;
+    std::vector<int64_t> ha_ptr, hb_ptr;
+    std::vector<int32_t> ha_col, hb_col;
+    std::vector<double> ha_val, hb_val;
+
+    // device
+    hipStream_t user = nullptr, work = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<DevBuf> bufs;
+    RotOp *d_rot = nullptr;
+    double *d_cs = nullptr, *d_gpart = nullptr, *d_epart = nullptr, *d_out = nullptr;
+    int *d_gcount = nullptr, *d_ecount = nullptr;
+    uint64_t *d_Xa = nullptr, *d_Xb = nullptr;
+    uint32_t *d_sa = nullptr, *d_PPb = nullptr, *d_excA = nullptr, *d_excB = nullptr;
+    double *d_g = nullptr;
+    int64_t *d_ha_ptr = nullptr, *d_hb_ptr = nullptr;
+    int32_t *d_ha_col = nullptr, *d_hb_col = nullptr;
+    double *d_ha_val = nullptr, *d_hb_val = nullptr;
+    int32_t *d_binA_off = nullptr, *d_binA_idx = nullptr, *d_binB_off = nullptr, *d_binB_idx = nullptr;
+    double2 *d_C = nullptr, *d_S = nullptr, *d_CT = nullptr, *d_ST = nullptr, *d_O = nullptr;
+    double2 *d_gamma = nullptr;
+    double *h_pin = nullptr;  // pinned: cs (2K) then out (K + 1) then gamma (4 M^2)
+    size_t pin_doubles = 0;
+
+    // graphs
+    bool use_graph = true;
+    hipGraphExec_t g_eg = nullptr;
+    const void *g_eg_psi = nullptr, *g_eg_lam = nullptr;
+    hipGraphExec_t g_e = nullptr;
+    const void *g_e_psi = nullptr;
+
+    ~fsv_plan();
+};
+
+namespace {
+
+int qubit_of(const fsv_plan &P, int so) {
+    const int p = so / 2, s = so % 2;
+    return P.ordering == 0 ? so : p + s * P.M;
+}
+
+template <typename T>
+int dalloc(fsv_plan &P, T **out, size_t count) {
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FSV_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    P.bufs.push_back({p, bytes});
+    *out = (T *)p;
+    return FSV_OK;
+}
+
+template <typename T>
+int upload(fsv_plan &P, T *dst, const T *src, size_t count) {
+    if (count == 0) return FSV_OK;
+    HIPCHECK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, P.work));
+    HIPCHECK(hipStreamSynchronize(P.work));
+    return FSV_OK;
+}
+
+int validate_problem(const fsv_problem *p) {
+    if (!p) return fail(FSV_EINVAL, "problem is NULL");
+    if (p->n_qubits < 2 || p->n_qubits > 34 || (p->n_qubits & 1))
+        return fail(FSV_EINVAL, "n_qubits must be even and in 2..34 (got %d)", p->n_qubits);
+    const int M = p->n_qubits / 2;
+    if (p->n_alpha < 0 || p->n_alpha > M || p->n_beta < 0 || p->n_beta > M)
+        return fail(FSV_EINVAL, "n_alpha/n_beta out of range 0..%d", M);
+    if (p->ordering != 0 && p->ordering != 1) return fail(FSV_EINVAL, "ordering must be 0 or 1");
+    if (p->precision != 0 && p->precision != 1) return fail(FSV_EINVAL, "precision must be 0 or 1");
+    if (!p->h || !p->g) return fail(FSV_EINVAL, "h and g are required");
+    if (p->n_ops < 0 || (p->n_ops > 0 && !p->ops)) return fail(FSV_EINVAL, "bad n_ops/ops");
+    const size_t M2 = (size_t)M * M, M4 = M2 * M2;
+    if (!finite_all(p->h, M2) || !finite_all(p->g, M4) || !std::isfinite(p->e_core))
+        return fail(FSV_ENONFINITE, "non-finite value in h, g or e_core");
+    double scale = 0.0;
+    for (size_t i = 0; i < M4; ++i) scale = std::max(scale, std::fabs(p->g[i]));
+    for (size_t i = 0; i < M2; ++i) scale = std::max(scale, std::fabs(p->h[i]));
+    const double tol = 1e-12 * std::max(1.0, scale);
+    for (int a = 0; a < M; ++a)
+        for (int b = 0; b < M; ++b)
+            if (std::fabs(p->h[a * M + b] - p->h[b * M + a]) > tol)
+                return fail(FSV_EINVAL, "h is not symmetric at (%d,%d)", a, b);
+    for (int q = 0; q < M; ++q)
+        for (int r = 0; r < M; ++r)
+            for (int s = 0; s < M; ++s)
+                for (int t = 0; t < M; ++t) {
+                    const double x = p->g[((q * M + r) * M + s) * M + t];
+                    const double y1 = p->g[((r * M + q) * M + s) * M + t];
+                    const double y2 = p->g[((q * M + r) * M + t) * M + s];
+                    const double y3 = p->g[((s * M + t) * M + q) * M + r];
+                    if (std::fabs(x - y1) > tol || std::fabs(x - y2) > tol || std::fabs(x - y3) > tol)
+                        return fail(FSV_EINVAL, "g lacks 8-fold symmetry at (%d%d|%d%d)", q, r, s, t);
+                }
+    const int n = p->n_qubits;
+    for (int k = 0; k < p->n_ops; ++k) {
+        const int32_t *o = p->ops + 4 * k;
+        const int a = o[0], b = o[1], j = o[2], i = o[3];
+        const bool single = (b < 0);
+        if (single) {
+            if (j >= 0 || b != -1 || j != -1)
+                return fail(FSV_EINVAL, "op %d: a single excitation has b = j = -1", k);
+            if (a < 0 || a >= n || i < 0 || i >= n || a == i)
+                return fail(FSV_EINVAL, "op %d: indices out of range or repeated", k);
+            if ((a & 1) != (i & 1)) return fail(FSV_EINVAL, "op %d: spin-flip excitation", k);
+        } else {
+            if (a < 0 || a >= n || b < 0 || b >= n || j < 0 || j >= n || i < 0 || i >= n)
+                return fail(FSV_EINVAL, "op %d: index out of range", k);
+            if (a == b || a == j || a == i || b == j || b == i || j == i)
+                return fail(FSV_EINVAL, "op %d: repeated index", k);
+            const int up_c = ((a & 1) == 0) + ((b & 1) == 0);
+            const int up_a = ((i & 1) == 0) + ((j & 1) == 0);
+            if (up_c != up_a) return fail(FSV_EINVAL, "op %d: does not conserve alpha/beta counts", k);
+        }
+    }
+    return FSV_OK;
+}
+
+// Compile op k: sorted target qubits, source/destination patterns, the parity
+// mask of non-target bits and the constant sign of the JW string of tau.
+RotOp compile_op(const fsv_plan &P, const int32_t *o) {
+    RotOp r{};
+    const bool single = o[1] < 0;
+    const int qa = qubit_of(P, o[0]), qi = qubit_of(P, o[3]);
+    int qs[4], nt = 0;
+    uint64_t src = 1ull << qi, dst = 1ull << qa;
+    uint64_t par = ((1ull << qi) - 1) ^ ((1ull << qa) - 1);
+    qs[nt++] = qi;
+    qs[nt++] = qa;
+    int qb = -1, qj = -1;
+    if (!single) {
+        qb = qubit_of(P, o[1]);
+        qj = qubit_of(P, o[2]);
+        src |= 1ull << qj;
+        dst |= 1ull << qb;
+        par ^= ((1ull << qj) - 1) ^ ((1ull << qb) - 1);
+        qs[nt++] = qj;
+        qs[nt++] = qb;
+    }
+    std::sort(qs, qs + nt);
+    par &= ~(src | dst);
+    // constant part: the sign of tau acting on the bare source pattern
+    uint64_t x = src;
+    int sg = jw_step(x, false, qi);
+    if (!single) sg *= jw_step(x, false, qj);
+    if (!single) sg *= jw_step(x, true, qb);
+    sg *= jw_step(x, true, qa);
+    r.src = src;
+    r.dst = dst;
+    r.par = par;
+    for (int t = 0; t < 4; ++t) r.q[t] = t < nt ? (uint32_t)qs[t] : 0u;
+    r.nt = nt;
+    r.sign0 = sg;
+    return r;
+}
+
+std::vector<uint32_t> strings_of(int M, int N) {
+    std::vector<uint32_t> out;
+    if (N == 0) {
+        out.push_back(0);
+        return out;
+    }
+    if (N > M) return out;
+    uint32_t v = (1u << N) - 1;
+    const uint32_t lim = 1u << M;
+    while (v < lim) {
+        out.push_back(v);
+        const uint32_t t = v | (v - 1);  // next mask with the same popcount
+        v = (t + 1) | (((~t & -~t) - 1) >> (__builtin_ctz(v) + 1));
+    }
+    return out;
+}
+
+// sign of E_pq = a^+_p a_q acting on string J (q in J, p not in J \ {q})
+int sign_epq(uint32_t J, int p, int q) {
+    uint64_t x = J;
+    int s = jw_step(x, false, q);
+    s *= jw_step(x, true, p);
+    return s;
+}
+
+// Same-spin string Hamiltonian rows by the Slater-Condon rules.  Row I lists
+// the diagonal, then the singles (p in I replaced by q not in I), then the
+// doubles; the structure does not depend on the integral values.
+void build_string_h(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
+                    const double *ht, const double *g, std::vector<int64_t> &ptr,
+                    std::vector<int32_t> &col, std::vector<double> &val) {
+    const int M2 = M * M, M3 = M2 * M;
+    auto G = [&](int p, int q, int r, int s) { return g[p * M3 + q * M2 + r * M + s]; };
+    const size_t ns = str.size();
+    ptr.assign(ns + 1, 0);
+    col.clear();
+    val.clear();
+    std::vector<int> occ, vir;
+    for (size_t I = 0; I < ns; ++I) {
+        const uint32_t s = str[I];
+        occ.clear();
+        vir.clear();
+        for (int p = 0; p < M; ++p) (s >> p & 1u ? occ : vir).push_back(p);
+        // diagonal
+        double d = 0.0;
+        for (int i : occ) d += ht[i * M + i];
+        for (int i : occ)
+            for (int j : occ) d += 0.5 * (G(i, i, j, j) - G(i, j, j, i));
+        col.push_back((int32_t)I);
+        val.push_back(d);
+        // singles: I = E_pq J with J = I - p + q
+        for (int p : occ)
+            for (int q : vir) {
+                const uint32_t J = (s & ~(1u << p)) | (1u << q);
+                double v = ht[p * M + q];
+                for (int k : occ)
+                    if (k != p) v += G(p, q, k, k) - G(p, k, k, q);
+                col.push_back(rank[J]);
+                val.push_back(sign_epq(J, p, q) * v);
+            }
+        // doubles: I = a^+_p a^+_r a_s a_q J, J = I - {p, r} + {q, s}
+        for (size_t ip = 0; ip < occ.size(); ++ip)
+            for (size_t ir = ip + 1; ir < occ.size(); ++ir)
+                for (size_t iq = 0; iq < vir.size(); ++iq)
+                    for (size_t is = iq + 1; is < vir.size(); ++is) {
+                        const int p = occ[ip], r = occ[ir], q = vir[iq], t = vir[is];
+                        const uint32_t J = (s & ~(1u << p) & ~(1u << r)) | (1u << q) | (1u << t);
+                        uint64_t x = J;
+                        int sg = jw_step(x, false, q);
+                        sg *= jw_step(x, false, t);
+                        sg *= jw_step(x, true, r);
+                        sg *= jw_step(x, true, p);
+                        col.push_back(rank[J]);
+                        val.push_back(sg * (G(p, q, r, t) - G(p, t, r, q)));
+                    }
+        ptr[I + 1] = (int64_t)col.size();
+    }
+}
+
+// Gather-form single excitation lists: row I lists (J, p*M+q, sign) with
+// E_pq |J> = sign |I>, p in I and q either p or an empty orbital of I.
+void build_exc(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
+               std::vector<uint32_t> &exc, int &nexc) {
+    exc.clear();
+    nexc = 0;
+    for (size_t I = 0; I < str.size(); ++I) {
+        const uint32_t s = str[I];
+        int cnt = 0;
+        for (int p = 0; p < M; ++p) {
+            if (!(s >> p & 1u)) continue;
+            for (int q = 0; q < M; ++q) {
+                if (q != p && (s >> q & 1u)) continue;
+                const uint32_t J = (s & ~(1u << p)) | (1u << q);
+                const int sg = (q == p) ? 1 : sign_epq(J, p, q);
+                exc.push_back(pack_exc((uint32_t)rank[J], (uint32_t)(p * M + q), sg < 0));
+                ++cnt;
+            }
+        }
+        nexc = cnt;
+    }
+}
+
+void build_bins(int M, const std::vector<uint32_t> &exc, int nexc, std::vector<int32_t> &off,
+                std::vector<int32_t> &idx) {
+    const int nb = M * M;
+    std::vector<std::vector<int32_t>> bins(nb);
+    for (size_t k = 0; k < exc.size(); ++k) bins[(exc[k] >> 16) & 0x1FFu].push_back((int32_t)k);
+    off.assign(nb + 1, 0);
+    idx.clear();
+    for (int b = 0; b < nb; ++b) {
+        idx.insert(idx.end(), bins[b].begin(), bins[b].end());
+        off[b + 1] = (int32_t)idx.size();
+    }
+    (void)nexc;
+}
+
+int upload_hamiltonian_values(fsv_plan &P) {
+    std::vector<double> ht(P.h);
+    for (size_t i = 0; i < ht.size(); ++i) ht[i] += P.v[i];
+    std::vector<int32_t> ra(1u << P.M, -1), rb(1u << P.M, -1);
+    for (size_t i = 0; i < P.sa.size(); ++i) ra[P.sa[i]] = (int32_t)i;
+    for (size_t i = 0; i < P.sb.size(); ++i) rb[P.sb[i]] = (int32_t)i;
+    build_string_h(P.M, P.sa, ra, ht.data(), P.g.data(), P.ha_ptr, P.ha_col, P.ha_val);
+    build_string_h(P.M, P.sb, rb, ht.data(), P.g.data(), P.hb_ptr, P.hb_col, P.hb_val);
+    int rc;
+    if ((rc = upload(P, P.d_ha_val, P.ha_val.data(), P.ha_val.size()))) return rc;
+    if ((rc = upload(P, P.d_hb_val, P.hb_val.data(), P.hb_val.size()))) return rc;
+    return FSV_OK;
+}
+
+// Byte model of one pair kernel (read + write of the touched 128-byte lines).
+double op_line_bytes(const fsv_plan &P, const RotOp &r) {
+    const int low = P.amp_bytes == 16 ? 3 : 4;
+    int hi = 0;
+    for (int t = 0; t < r.nt; ++t) hi += (int)r.q[t] >= low;
+    const double full = 2.0 * std::ldexp(1.0, P.n) * P.amp_bytes;
+    const double frac = hi == 0 ? 1.0 : std::min(1.0, std::ldexp(1.0, 1 - hi));
+    return full * frac;
+}
+
+void plan_segments(fsv_plan &P) {
+    P.segs.clear();
+    P.tile_bits = P.precision == 0 ? 12 : 13;
+    const bool allow = P.n > P.tile_bits && std::getenv("FSV_NO_FUSE") == nullptr;
+    const bool force = std::getenv("FSV_FORCE_FUSE") != nullptr;
+    const double full = 2.0 * std::ldexp(1.0, P.n) * P.amp_bytes;
+    int k = 0;
+    while (k < P.K) {
+        int e = k;
+        double cost = 0.0;
+        if (allow) {
+            while (e < P.K) {
+                const RotOp &r = P.rot[e];
+                if ((int)r.q[r.nt - 1] >= P.tile_bits) break;
+                cost += op_line_bytes(P, r);
+                ++e;
+            }
+        }
+        if (e - k >= 2 && (force || full < 0.9 * cost)) {
+            P.segs.push_back({k, e, true});
+            k = e;
+        } else {
+            P.segs.push_back({k, k + 1, false});
+            ++k;
+        }
+    }
+}
+
+int upload_counts(fsv_plan &P) {
+    std::vector<int> gc(std::max(P.K, 1), 0);
+    for (int k = 0; k < P.K; ++k) gc[k] = (int)rot_grid(P.npairs[k], P.shape_adj);
+    return upload(P, P.d_gcount, gc.data(), (size_t)P.K);
+}
+
+void drop_graphs(fsv_plan &P) {
+    if (P.g_eg) (void)hipGraphExecDestroy(P.g_eg);
+    if (P.g_e) (void)hipGraphExecDestroy(P.g_e);
+    P.g_eg = nullptr;
+    P.g_e = nullptr;
+    P.g_eg_psi = P.g_eg_lam = P.g_e_psi = nullptr;
+}
+
+int fence_in(fsv_plan &P) {
+    HIPCHECK(hipEventRecord(P.ev_in, P.user));
+    HIPCHECK(hipStreamWaitEvent(P.work, P.ev_in, 0));
+    return FSV_OK;
+}
+
+int fence_out(fsv_plan &P) {
+    HIPCHECK(hipEventRecord(P.ev_out, P.work));
+    HIPCHECK(hipStreamWaitEvent(P.user, P.ev_out, 0));
+    return FSV_OK;
+}
+
+// ---- enqueue helpers (no synchronisation; usable under stream capture) ----
+int enq_forward(fsv_plan &P, void *psi) {
+    HIPCHECK(launch_fill_zero(psi, ((size_t)1 << P.n) * P.amp_bytes, P.work));
+    HIPCHECK(launch_set_amp(psi, P.precision, P.ref_index, 1.0, P.work));
+    for (const auto &sg : P.segs) {
+        if (sg.fused) {
+            HIPCHECK(launch_rot_fused(P.precision, psi, P.d_rot, P.d_cs, sg.k0, sg.k1, P.tile_bits,
+                                      1ull << P.n, P.work));
+        } else {
+            const int k = sg.k0;
+            HIPCHECK(launch_rot(P.precision, P.wide, psi, P.rot[k], P.d_cs, k, P.npairs[k],
+                                P.shape_rot, P.work));
+        }
+    }
+    return FSV_OK;
+}
+
+// lam == nullptr: energy only (no dense write of H psi).
+int enq_sigma(fsv_plan &P, const void *psi, void *lam) {
+    HIPCHECK(launch_gather(P.precision, psi, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.d_C, P.work));
+    HIPCHECK(launch_spmm_rows(P.d_ha_ptr, P.d_ha_col, P.d_ha_val, P.d_C, P.d_S, P.nsa, P.nsb, P.work));
+    if (P.nexcA > 0 && P.nexcB > 0)
+        HIPCHECK(launch_sigma_ab(P.d_excA, P.nexcA, P.d_excB, P.nexcB, P.d_g, P.M, P.d_C, P.d_S,
+                                 P.nsa, P.nsb, P.work));
+    HIPCHECK(launch_transpose(P.d_C, P.d_CT, P.nsa, P.nsb, P.work));
+    HIPCHECK(launch_spmm_rows(P.d_hb_ptr, P.d_hb_col, P.d_hb_val, P.d_CT, P.d_ST, P.nsb, P.nsa, P.work));
+    HIPCHECK(launch_combine(P.d_S, P.d_ST, P.d_C, P.ecore, P.nsa, P.nsb, P.d_epart, P.work));
+    HIPCHECK(launch_reduce_rows(P.d_epart, P.d_ecount, 0, 1, 1.0, P.d_out, P.work));
+    if (lam) {
+        HIPCHECK(launch_fill_zero(lam, ((size_t)1 << P.n) * P.amp_bytes, P.work));
+        HIPCHECK(launch_scatter(P.precision, lam, P.d_S, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.work));
+    }
+    return FSV_OK;
+}
+
+int enq_reverse(fsv_plan &P, void *psi, void *lam) {
+    const int G = max_grid();
+    for (int k = P.K - 1; k >= 0; --k)
+        HIPCHECK(launch_adj(P.precision, P.wide, psi, lam, P.rot[k], P.d_cs, k, P.npairs[k],
+                            P.shape_adj, P.d_gpart + (size_t)k * G, P.work));
+    HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_gcount, G, P.K, 2.0, P.d_out + 1, P.work));
+    return FSV_OK;
+}
+
+int upload_theta(fsv_plan &P, const double *theta) {
+    if (P.K > 0 && !theta) return fail(FSV_EINVAL, "theta is NULL");
+    if (!finite_all(theta, (size_t)P.K)) return fail(FSV_ENONFINITE, "non-finite theta");
+    double *h = P.h_pin;
+    for (int k = 0; k < P.K; ++k) {
+        h[2 * k] = std::cos(theta[k]);
+        h[2 * k + 1] = std::sin(theta[k]);
+    }
+    if (P.K > 0)
+        HIPCHECK(hipMemcpyAsync(P.d_cs, h, sizeof(double) * 2 * P.K, hipMemcpyHostToDevice, P.work));
+    return FSV_OK;
+}
+
+int download_out(fsv_plan &P, double *E_out, double *grad_out, bool with_grad) {
+    double *h = P.h_pin + 2 * (size_t)P.K;
+    const size_t cnt = with_grad ? (size_t)P.K + 1 : 1;
+    HIPCHECK(hipMemcpyAsync(h, P.d_out, sizeof(double) * cnt, hipMemcpyDeviceToHost, P.work));
+    HIPCHECK(hipStreamSynchronize(P.work));
+    if (E_out) *E_out = h[0];
+    if (with_grad && grad_out) std::memcpy(grad_out, h + 1, sizeof(double) * P.K);
+    return FSV_OK;
+}
+
+typedef int (*enq_fn)(fsv_plan &, void *, void *);
+
+int run_energy_grad_body(fsv_plan &P, void *psi, void *lam) {
+    int rc;
+    if ((rc = enq_forward(P, psi))) return rc;
+    if ((rc = enq_sigma(P, psi, lam))) return rc;
+    if ((rc = enq_reverse(P, psi, lam))) return rc;
+    return FSV_OK;
+}
+
+int run_energy_body(fsv_plan &P, void *psi) {
+    int rc;
+    if ((rc = enq_forward(P, psi))) return rc;
+    if ((rc = enq_sigma(P, psi, nullptr))) return rc;
+    return FSV_OK;
+}
+
+// Capture body into a graph exec; false when capture is unavailable.
+template <typename F>
+int capture(fsv_plan &P, F body, hipGraphExec_t *exec) {
+    hipGraph_t graph = nullptr;
+    HIPCHECK(hipStreamBeginCapture(P.work, hipStreamCaptureModeThreadLocal));
+    int rc = body();
+    hipGraph_t g2 = nullptr;
+    hipError_t e = hipStreamEndCapture(P.work, &g2);
+    graph = g2;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(FSV_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(FSV_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return FSV_OK;
+}
+
+int launch_energy_grad(fsv_plan &P, void *psi, void *lam) {
+    if (!P.use_graph) return run_energy_grad_body(P, psi, lam);
+    if (!P.g_eg || P.g_eg_psi != psi || P.g_eg_lam != lam) {
+        if (P.g_eg) (void)hipGraphExecDestroy(P.g_eg);
+        P.g_eg = nullptr;
+        int rc = capture(P, [&]() { return run_energy_grad_body(P, psi, lam); }, &P.g_eg);
+        if (rc) {
+            P.g_eg = nullptr;
+            return rc;
+        }
+        P.g_eg_psi = psi;
+        P.g_eg_lam = lam;
+    }
+    HIPCHECK(hipGraphLaunch(P.g_eg, P.work));
+    return FSV_OK;
+}
+
+int launch_energy_only(fsv_plan &P, void *psi) {
+    if (!P.use_graph) return run_energy_body(P, psi);
+    if (!P.g_e || P.g_e_psi != psi) {
+        if (P.g_e) (void)hipGraphExecDestroy(P.g_e);
+        P.g_e = nullptr;
+        int rc = capture(P, [&]() { return run_energy_body(P, psi); }, &P.g_e);
+        if (rc) {
+            P.g_e = nullptr;
+            return rc;
+        }
+        P.g_e_psi = psi;
+    }
+    HIPCHECK(hipGraphLaunch(P.g_e, P.work));
+    return FSV_OK;
+}
+
+int build_device(fsv_plan &P) {
+    int rc;
+    HIPCHECK(hipStreamCreateWithFlags(&P.work, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&P.ev_in, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&P.ev_out, hipEventDisableTiming));
+    const int M = P.M, G = max_grid();
+    const size_t M2 = (size_t)M * M;
+    P.pin_doubles = 2 * (size_t)P.K + (size_t)P.K + 1 + 4 * M2 + 8;
+    HIPCHECK(hipHostMalloc((void **)&P.h_pin, sizeof(double) * P.pin_doubles, hipHostMallocDefault));
+
+    // sector tables
+    P.sa = strings_of(M, P.na);
+    P.sb = strings_of(M, P.nb);
+    P.nsa = (int64_t)P.sa.size();
+    P.nsb = (int64_t)P.sb.size();
+    P.dim = P.nsa * P.nsb;
+    std::vector<int32_t> ra(1u << M, -1), rb(1u << M, -1);
+    for (size_t i = 0; i < P.sa.size(); ++i) ra[P.sa[i]] = (int32_t)i;
+    for (size_t i = 0; i < P.sb.size(); ++i) rb[P.sb[i]] = (int32_t)i;
+    std::vector<uint64_t> Xa(P.nsa), Xb(P.nsb);
+    std::vector<uint32_t> PPb(P.nsb);
+    for (int64_t i = 0; i < P.nsa; ++i) {
+        uint64_t x = 0;
+        for (int p = 0; p < M; ++p)
+            if (P.sa[i] >> p & 1u) x |= 1ull << qubit_of(P, 2 * p);
+        Xa[i] = x;
+    }
+    for (int64_t i = 0; i < P.nsb; ++i) {
+        uint64_t x = 0;
+        uint32_t pp = 0;
+        for (int p = 0; p < M; ++p)
+            if (P.sb[i] >> p & 1u) x |= 1ull << qubit_of(P, 2 * p + 1);
+        for (int q = 0; q < M; ++q) {
+            int c = 0;
+            for (int r = 0; r < M; ++r)
+                if ((P.sb[i] >> r & 1u) && qubit_of(P, 2 * r + 1) < qubit_of(P, 2 * q)) ++c;
+            if (c & 1) pp |= 1u << q;
+        }
+        Xb[i] = x;
+        PPb[i] = pp;
+    }
+    P.ref_index = Xa[0] | Xb[0];  // strings are ascending: index 0 fills the lowest orbitals
+    std::vector<uint32_t> excA, excB;
+    build_exc(M, P.sa, ra, excA, P.nexcA);
+    build_exc(M, P.sb, rb, excB, P.nexcB);
+    std::vector<int32_t> boA, biA, boB, biB;
+    build_bins(M, excA, P.nexcA, boA, biA);
+    build_bins(M, excB, P.nexcB, boB, biB);
+
+    if ((rc = dalloc(P, &P.d_rot, P.K))) return rc;
+    if ((rc = dalloc(P, &P.d_cs, 2 * (size_t)P.K))) return rc;
+    if ((rc = dalloc(P, &P.d_gpart, (size_t)std::max(P.K, 1) * G))) return rc;
+    if ((rc = dalloc(P, &P.d_gcount, (size_t)P.K))) return rc;
+    if ((rc = dalloc(P, &P.d_epart, 1024))) return rc;
+    if ((rc = dalloc(P, &P.d_ecount, 1))) return rc;
+    if ((rc = dalloc(P, &P.d_out, (size_t)P.K + 1))) return rc;
+    if ((rc = dalloc(P, &P.d_Xa, P.nsa))) return rc;
+    if ((rc = dalloc(P, &P.d_Xb, P.nsb))) return rc;
+    if ((rc = dalloc(P, &P.d_sa, P.nsa))) return rc;
+    if ((rc = dalloc(P, &P.d_PPb, P.nsb))) return rc;
+    if ((rc = dalloc(P, &P.d_excA, excA.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_excB, excB.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_g, M2 * M2))) return rc;
+    if ((rc = dalloc(P, &P.d_binA_off, boA.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_binA_idx, biA.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_binB_off, boB.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_binB_idx, biB.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_C, P.dim))) return rc;
+    if ((rc = dalloc(P, &P.d_S, P.dim))) return rc;
+    if ((rc = dalloc(P, &P.d_CT, P.dim))) return rc;
+    if ((rc = dalloc(P, &P.d_ST, P.dim))) return rc;
+    if ((rc = dalloc(P, &P.d_O, std::max(P.nsa * P.nexcA, P.nsb * P.nexcB)))) return rc;
+    if ((rc = dalloc(P, &P.d_gamma, 2 * M2))) return rc;
+
+    if ((rc = upload(P, P.d_rot, P.rot.data(), P.rot.size()))) return rc;
+    if ((rc = upload(P, P.d_Xa, Xa.data(), Xa.size()))) return rc;
+    if ((rc = upload(P, P.d_Xb, Xb.data(), Xb.size()))) return rc;
+    if ((rc = upload(P, P.d_sa, P.sa.data(), P.sa.size()))) return rc;
+    if ((rc = upload(P, P.d_PPb, PPb.data(), PPb.size()))) return rc;
+    if ((rc = upload(P, P.d_excA, excA.data(), excA.size()))) return rc;
+    if ((rc = upload(P, P.d_excB, excB.data(), excB.size()))) return rc;
+    if ((rc = upload(P, P.d_g, P.g.data(), P.g.size()))) return rc;
+    if ((rc = upload(P, P.d_binA_off, boA.data(), boA.size()))) return rc;
+    if ((rc = upload(P, P.d_binA_idx, biA.data(), biA.size()))) return rc;
+    if ((rc = upload(P, P.d_binB_off, boB.data(), boB.size()))) return rc;
+    if ((rc = upload(P, P.d_binB_idx, biB.data(), biB.size()))) return rc;
+    const int ec = (int)combine_grid(P.dim);
+    if ((rc = upload(P, P.d_ecount, &ec, 1))) return rc;
+    if ((rc = upload_counts(P))) return rc;
+
+    // string Hamiltonians: structure and values
+    std::vector<double> ht(P.h);
+    build_string_h(M, P.sa, ra, ht.data(), P.g.data(), P.ha_ptr, P.ha_col, P.ha_val);
+    build_string_h(M, P.sb, rb, ht.data(), P.g.data(), P.hb_ptr, P.hb_col, P.hb_val);
+    if ((rc = dalloc(P, &P.d_ha_ptr, P.ha_ptr.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_ha_col, P.ha_col.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_ha_val, P.ha_val.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_hb_ptr, P.hb_ptr.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_hb_col, P.hb_col.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_hb_val, P.hb_val.size()))) return rc;
+    if ((rc = upload(P, P.d_ha_ptr, P.ha_ptr.data(), P.ha_ptr.size()))) return rc;
+    if ((rc = upload(P, P.d_ha_col, P.ha_col.data(), P.ha_col.size()))) return rc;
+    if ((rc = upload(P, P.d_ha_val, P.ha_val.data(), P.ha_val.size()))) return rc;
+    if ((rc = upload(P, P.d_hb_ptr, P.hb_ptr.data(), P.hb_ptr.size()))) return rc;
+    if ((rc = upload(P, P.d_hb_col, P.hb_col.data(), P.hb_col.size()))) return rc;
+    if ((rc = upload(P, P.d_hb_val, P.hb_val.data(), P.hb_val.size()))) return rc;
+    return FSV_OK;
+}
+
+}  // namespace
+
+fsv_plan::~fsv_plan() {
+    drop_graphs(*this);
+    for (auto &b : bufs) (void)hipFree(b.p);
+    if (h_pin) (void)hipHostFree(h_pin);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (work) (void)hipStreamDestroy(work);
+}
+
+// ==================================================================== C ABI ==
+extern "C" {
+
+const char *fsv_last_error(void) { return g_err.c_str(); }
+
+int fsv_plan_create(fsv_plan **out, const fsv_problem *p, void *hip_stream) {
+    if (!out) return fail(FSV_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    fsv_plan *P = new (std::nothrow) fsv_plan();
+    if (!P) return fail(FSV_ENOMEM, "plan allocation failed");
+    P->n = p->n_qubits;
+    P->M = p->n_qubits / 2;
+    P->na = p->n_alpha;
+    P->nb = p->n_beta;
+    P->ordering = p->ordering;
+    P->precision = p->precision;
+    P->K = p->n_ops;
+    P->ecore = p->e_core;
+    P->amp_bytes = p->precision == 0 ? 16 : 8;
+    P->wide = P->n > 31;
+    const size_t M2 = (size_t)P->M * P->M;
+    P->h.assign(p->h, p->h + M2);
+    P->g.assign(p->g, p->g + M2 * M2);
+    P->v.assign(M2, 0.0);
+    P->ops.assign(p->ops, p->ops + 4 * (size_t)P->K);
+    P->user = (hipStream_t)hip_stream;
+    P->use_graph = std::getenv("FSV_NO_GRAPH") == nullptr;
+    for (int k = 0; k < P->K; ++k) {
+        P->rot.push_back(compile_op(*P, P->ops.data() + 4 * k));
+        P->npairs.push_back(1ull << (P->n - P->rot.back().nt));
+    }
+    plan_segments(*P);
+    rc = build_device(*P);
+    if (rc) {
+        delete P;
+        return rc;
+    }
+    *out = P;
+    g_err.clear();
+    return FSV_OK;
+}
+
+int fsv_plan_destroy(fsv_plan *P) {
+    if (!P) return FSV_OK;
+    if (P->work) (void)hipStreamSynchronize(P->work);
+    delete P;
+    return FSV_OK;
+}
+
+size_t fsv_state_bytes(const fsv_plan *P) {
+    if (!P) return 0;
+    return ((size_t)1 << P->n) * (size_t)P->amp_bytes;
+}
+
+int fsv_plan_info(const fsv_plan *P, int64_t *nsa, int64_t *nsb, uint64_t *ref) {
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    if (nsa) *nsa = P->nsa;
+    if (nsb) *nsb = P->nsb;
+    if (ref) *ref = P->ref_index;
+    return FSV_OK;
+}
+
+int fsv_set_theta(fsv_plan *P, const double *theta) {
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = upload_theta(*P, theta))) return rc;
+    return fence_out(*P);
+}
+
+int fsv_forward_async(fsv_plan *P, void *psi) {
+    if (!P || !psi) return fail(FSV_EINVAL, "plan or psi is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = enq_forward(*P, psi))) return rc;
+    return fence_out(*P);
+}
+
+int fsv_sigma_async(fsv_plan *P, const void *psi, void *lam) {
+    if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = enq_sigma(*P, psi, lam))) return rc;
+    return fence_out(*P);
+}
+
+int fsv_reverse_async(fsv_plan *P, void *psi, void *lam) {
+    if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = enq_reverse(*P, psi, lam))) return rc;
+    return fence_out(*P);
+}
+
+int fsv_finish(fsv_plan *P, double *E_out, double *grad_out) {
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
+    return fence_out(*P);
+}
+
+int ansatz_apply(fsv_plan *P, const double *theta, void *psi) {
+    if (!P || !psi) return fail(FSV_EINVAL, "plan or psi is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = upload_theta(*P, theta))) return rc;
+    if ((rc = enq_forward(*P, psi))) return rc;
+    HIPCHECK(hipStreamSynchronize(P->work));
+    return fence_out(*P);
+}
+
+int energy(fsv_plan *P, const void *psi, double *E_out) {
+    if (!P || !psi || !E_out) return fail(FSV_EINVAL, "plan, psi or E_out is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = enq_sigma(*P, psi, nullptr))) return rc;
+    if ((rc = download_out(*P, E_out, nullptr, false))) return rc;
+    return fence_out(*P);
+}
+
+int energy_grad(fsv_plan *P, const double *theta, void *psi, void *lam, double *E_out,
+                double *grad_out) {
+    if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
+    if (psi == lam) return fail(FSV_EINVAL, "psi and lam must be distinct buffers");
+    if (P->K > 0 && !grad_out) return fail(FSV_EINVAL, "grad_out is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = upload_theta(*P, theta))) return rc;
+    if ((rc = launch_energy_grad(*P, psi, lam))) return rc;
+    if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
+    return fence_out(*P);
+}
+
+int energy_grad_fd(fsv_plan *P, const double *theta, double step, void *psi, double *E_out,
+                   double *grad_out) {
+    if (!P || !psi || !theta) return fail(FSV_EINVAL, "plan, theta or psi is NULL");
+    if (!(step > 0.0) || !std::isfinite(step)) return fail(FSV_EINVAL, "step must be > 0");
+    if (P->K > 0 && !grad_out) return fail(FSV_EINVAL, "grad_out is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    std::vector<double> th(theta, theta + P->K);
+    double e0 = 0.0;
+    if ((rc = upload_theta(*P, th.data()))) return rc;
+    if ((rc = launch_energy_only(*P, psi))) return rc;
+    if ((rc = download_out(*P, &e0, nullptr, false))) return rc;
+    for (int k = 0; k < P->K; ++k) {
+        double ep = 0.0, em = 0.0;
+        th[k] = theta[k] + step;
+        if ((rc = upload_theta(*P, th.data()))) return rc;
+        if ((rc = launch_energy_only(*P, psi))) return rc;
+        if ((rc = download_out(*P, &ep, nullptr, false))) return rc;
+        th[k] = theta[k] - step;
+        if ((rc = upload_theta(*P, th.data()))) return rc;
+        if ((rc = launch_energy_only(*P, psi))) return rc;
+        if ((rc = download_out(*P, &em, nullptr, false))) return rc;
+        th[k] = theta[k];
+        grad_out[k] = (ep - em) / (2.0 * step);
+    }
+    if (E_out) *E_out = e0;
+    return fence_out(*P);
+}
+
+int rdm1(fsv_plan *P, const void *psi, double *gamma_out) {
+    if (!P || !psi || !gamma_out) return fail(FSV_EINVAL, "plan, psi or gamma_out is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    hipStream_t st = P->work;
+    const int M2 = P->M * P->M;
+    HIPCHECK(launch_gather(P->precision, psi, P->d_Xa, P->d_Xb, P->d_sa, P->d_PPb, P->nsa, P->nsb, P->d_C, st));
+    if (P->nexcA > 0) {
+        HIPCHECK(launch_rdm_overlap(P->d_C, P->nsa, P->nsb, P->d_excA, P->nexcA, P->d_O, st));
+        HIPCHECK(launch_rdm_bin(P->d_O, P->d_binA_off, P->d_binA_idx, M2, P->d_gamma, st));
+    } else {
+        HIPCHECK(launch_fill_zero(P->d_gamma, sizeof(double2) * M2, st));
+    }
+    HIPCHECK(launch_transpose(P->d_C, P->d_CT, P->nsa, P->nsb, st));
+    if (P->nexcB > 0) {
+        HIPCHECK(launch_rdm_overlap(P->d_CT, P->nsb, P->nsa, P->d_excB, P->nexcB, P->d_O, st));
+        HIPCHECK(launch_rdm_bin(P->d_O, P->d_binB_off, P->d_binB_idx, M2, P->d_gamma + M2, st));
+    } else {
+        HIPCHECK(launch_fill_zero(P->d_gamma + M2, sizeof(double2) * M2, st));
+    }
+    double *h = P->h_pin + 3 * (size_t)P->K + 1;
+    HIPCHECK(hipMemcpyAsync(h, P->d_gamma, sizeof(double2) * 2 * M2, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    std::memcpy(gamma_out, h, sizeof(double2) * 2 * M2);
+    return fence_out(*P);
+}
+
+int set_onebody_potential(fsv_plan *P, const double *v) {
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    const int M = P->M;
+    if (v) {
+        if (!finite_all(v, (size_t)M * M)) return fail(FSV_ENONFINITE, "non-finite v");
+        double scale = 1.0;
+        for (int i = 0; i < M * M; ++i) scale = std::max(scale, std::fabs(v[i]));
+        for (int a = 0; a < M; ++a)
+            for (int b = 0; b < M; ++b)
+                if (std::fabs(v[a * M + b] - v[b * M + a]) > 1e-12 * scale)
+                    return fail(FSV_EINVAL, "v is not symmetric at (%d,%d)", a, b);
+        P->v.assign(v, v + (size_t)M * M);
+    } else {
+        P->v.assign((size_t)M * M, 0.0);
+    }
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = upload_hamiltonian_values(*P))) return rc;
+    return fence_out(*P);
+}
+
+int fsv_autotune(fsv_plan *P, void *psi, void *lam, const char **report) {
+    static thread_local std::string rep;
+    if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    const char *cache = std::getenv("FSV_TUNE_CACHE");
+    char key[128];
+    snprintf(key, sizeof key, "n%d_p%d_o%d_K%d", P->n, P->precision, P->ordering, P->K);
+    if (cache) {
+        FILE *f = fopen(cache, "r");
+        if (f) {
+            char k2[128];
+            int b1, p1, b2, p2;
+            while (fscanf(f, "%127s %d %d %d %d", k2, &b1, &p1, &b2, &p2) == 5) {
+                if (std::strcmp(k2, key) == 0) {
+                    P->shape_rot = {b1, p1};
+                    P->shape_adj = {b2, p2};
+                    fclose(f);
+                    drop_graphs(*P);
+                    if ((rc = upload_counts(*P))) return rc;
+                    rep = std::string("cached ") + key;
+                    if (report) *report = rep.c_str();
+                    return fence_out(*P);
+                }
+            }
+            fclose(f);
+        }
+    }
+    std::vector<double> th(P->K, 0.1);
+    if ((rc = upload_theta(*P, th.data()))) return rc;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    const Shape cands[] = {{256, 1}, {256, 2}, {256, 4}, {256, 8}, {512, 2}, {512, 4}, {128, 4}, {1024, 2}};
+    float best_f = 1e30f, best_r = 1e30f;
+    Shape bf = P->shape_rot, br = P->shape_adj;
+    char line[160];
+    rep.clear();
+    const int nk = std::min(P->K, 64);
+    for (const Shape &sh : cands) {
+        // forward rotations
+        for (int rep_i = 0; rep_i < 2; ++rep_i) {
+            HIPCHECK(hipEventRecord(e0, P->work));
+            for (int k = 0; k < nk; ++k)
+                HIPCHECK(launch_rot(P->precision, P->wide, psi, P->rot[k], P->d_cs, k, P->npairs[k], sh, P->work));
+            HIPCHECK(hipEventRecord(e1, P->work));
+            HIPCHECK(hipEventSynchronize(e1));
+        }
+        float tf = 0.f;
+        HIPCHECK(hipEventElapsedTime(&tf, e0, e1));
+        float tr = 0.f;
+        for (int rep_i = 0; rep_i < 2; ++rep_i) {
+            HIPCHECK(hipEventRecord(e0, P->work));
+            for (int k = 0; k < nk; ++k)
+                HIPCHECK(launch_adj(P->precision, P->wide, psi, lam, P->rot[k], P->d_cs, k, P->npairs[k], sh,
+                                    P->d_gpart + (size_t)k * max_grid(), P->work));
+            HIPCHECK(hipEventRecord(e1, P->work));
+            HIPCHECK(hipEventSynchronize(e1));
+        }
+        HIPCHECK(hipEventElapsedTime(&tr, e0, e1));
+        snprintf(line, sizeof line, "block %d ppt %d: rot %.3f ms adj %.3f ms (%d ops)\n", sh.block,
+                 sh.ppt, tf, tr, nk);
+        rep += line;
+        if (tf < best_f) { best_f = tf; bf = sh; }
+        if (tr < best_r) { best_r = tr; br = sh; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->shape_rot = bf;
+    P->shape_adj = br;
+    drop_graphs(*P);
+    if ((rc = upload_counts(*P))) return rc;
+    snprintf(line, sizeof line, "chosen rot (%d,%d) adj (%d,%d)\n", bf.block, bf.ppt, br.block, br.ppt);
+    rep += line;
+    if (cache) {
+        FILE *f = fopen(cache, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %d %d\n", key, bf.block, bf.ppt, br.block, br.ppt);
+            fclose(f);
+        }
+    }
+    if (report) *report = rep.c_str();
+    return fence_out(*P);
+}
+
+// Batches are built in fsv_batch.hip.
+
+}  // extern "C"

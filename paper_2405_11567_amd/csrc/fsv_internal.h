@@ -1,0 +1,80 @@
+// Internal declarations shared by the kernel file and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsv {
+
+// One excitation rotation compiled for the dense kernels.  The active source
+// strings are base | src and their partners base | dst, where base has zeros
+// at the nt sorted target qubits q[]; the JW sign of tau on the source is
+// sign0 * (-1)^popcount(base & par).
+struct RotOp {
+    uint64_t src, dst, par;
+    uint32_t q[4];
+    int32_t nt;
+    int32_t sign0;
+};
+
+// Launch shape of the pair kernels.
+struct Shape {
+    int block;   // threads per workgroup
+    int ppt;     // pairs per thread per loop trip (1, 2, 4, 8)
+};
+
+// Packed string excitation: bits 0..15 source string J, 16..24 p*M+q,
+// bit 31 set for a negative sign.
+__host__ __device__ inline uint32_t pack_exc(uint32_t J, uint32_t pq, int neg) {
+    return J | (pq << 16) | (neg ? 0x80000000u : 0u);
+}
+
+// ---- launchers (fsv_kernels.hip) ----
+// precision: 0 complex128, 1 complex64.  Each returns the hipError_t of the launch.
+int max_grid();
+
+hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
+hipError_t launch_set_amp(void *psi, int precision, uint64_t x, double re, hipStream_t st);
+
+// Grid used for op with npairs pairs under shape sh (fixed per op: reductions
+// depend on it).
+unsigned rot_grid(uint64_t npairs, Shape sh);
+
+hipError_t launch_rot(int precision, bool wide, void *psi, const RotOp &op, const double *cs,
+                      int k, uint64_t npairs, Shape sh, hipStream_t st);
+hipError_t launch_adj(int precision, bool wide, void *psi, void *lam, const RotOp &op,
+                      const double *cs, int k, uint64_t npairs, Shape sh, double *partial,
+                      hipStream_t st);
+// LDS-staged fused run: ops [k0, k1) whose targets all lie below tile_bits are
+// applied block by block in one pass over psi (forward: +theta in order;
+// adjoint=true would need gradients and is not offered here).
+hipError_t launch_rot_fused(int precision, void *psi, const RotOp *ops_dev, const double *cs,
+                            int k0, int k1, int tile_bits, uint64_t n_amps, hipStream_t st);
+
+hipError_t launch_reduce_rows(const double *partial, const int *counts, int stride, int rows,
+                              double scale, double *out, hipStream_t st);
+
+hipError_t launch_gather(int precision, const void *psi, const uint64_t *Xa, const uint64_t *Xb,
+                         const uint32_t *sa, const uint32_t *PPb, int64_t nsa, int64_t nsb,
+                         double2 *C, hipStream_t st);
+hipError_t launch_scatter(int precision, void *lam, const double2 *S, const uint64_t *Xa,
+                          const uint64_t *Xb, const uint32_t *sa, const uint32_t *PPb,
+                          int64_t nsa, int64_t nsb, hipStream_t st);
+hipError_t launch_spmm_rows(const int64_t *rowptr, const int32_t *col, const double *val,
+                            const double2 *in, double2 *out, int64_t nrows, int64_t ncols,
+                            hipStream_t st);
+hipError_t launch_sigma_ab(const uint32_t *excA, int nexcA, const uint32_t *excB, int nexcB,
+                           const double *g, int M, const double2 *C, double2 *S, int64_t nsa,
+                           int64_t nsb, hipStream_t st);
+hipError_t launch_transpose(const double2 *in, double2 *out, int64_t rows, int64_t cols,
+                            hipStream_t st);
+// S[Ia][Ib] += ST[Ib][Ia] + ecore * C[Ia][Ib]; per-block partials of Re<C|S>.
+unsigned combine_grid(int64_t dim);
+hipError_t launch_combine(double2 *S, const double2 *ST, const double2 *C, double ecore,
+                          int64_t nsa, int64_t nsb, double *partial, hipStream_t st);
+hipError_t launch_rdm_overlap(const double2 *A, int64_t nrows, int64_t ncols,
+                              const uint32_t *exc, int nexc, double2 *O, hipStream_t st);
+hipError_t launch_rdm_bin(const double2 *O, const int32_t *off, const int32_t *idx, int nbins,
+                          double2 *out, hipStream_t st);
+
+}  // namespace fsv

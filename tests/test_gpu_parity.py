@@ -1,0 +1,216 @@
+"""HIP path vs the FP64 oracle, element by element on the same seeded inputs.
+
+Tolerances: FP64 energies 1e-10 Ha, adjoint gradients 1e-9 vs the oracle
+adjoint and 1e-6 vs central finite differences, density matrices 1e-9, state
+amplitudes 1e-12 (sums of K rotations of unit-norm pairs, rounding ~K eps).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dense, sector
+from workloads import config, potential_v0, random_problem
+from tests.gpu_helpers import dense_from_sector, oracle_energy_grad, oracle_state, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fsv(gpu):
+    import paper_2405_11567_amd as m
+    m.load()
+    return m
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ansatz_state_c1(fsv, ordering, precision):
+    p = config("C1", ordering=ordering)
+    say("ansatz C1", ordering, precision)
+    plan = fsv.Plan(p, precision=precision)
+    psi = _np(plan.ansatz_apply(p.theta))
+    ref = dense.ansatz_state(p.n_qubits, p.n_alpha, p.n_beta, p.ops, p.theta, ordering)
+    tol = 1e-13 if precision == 0 else 2e-6
+    assert np.abs(psi - ref).max() < tol
+
+
+@pytest.mark.parametrize("n,ne,k,seed,ordering", [
+    (10, 5, 40, 201, 0), (12, 6, 60, 202, 1), (14, 7, 80, 203, 0), (16, 8, 60, 204, 1),
+    (16, 5, 50, 205, 0), (18, 9, 40, 206, 1)])
+def test_ansatz_state_random(fsv, n, ne, k, seed, ordering):
+    # random draws from the whole pool: every low-qubit position combination occurs
+    p = random_problem(n, ne, k, seed=seed, theta_std=0.6, replace=True, ordering=ordering)
+    th = p.theta.copy()
+    th[::7] = 0.0
+    th[1::11] = np.pi / 2
+    th[2::13] = -np.pi / 2
+    say("ansatz random", n, ne, k, seed, ordering)
+    plan = fsv.Plan(p)
+    psi = _np(plan.ansatz_apply(th))
+    ref, idx = dense_from_sector(oracle_state(p, th), p)
+    assert np.abs(psi - ref).max() < 1e-12
+    outside = np.ones(psi.size, bool)
+    outside[idx] = False
+    assert np.all(psi[outside] == 0)
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2"])
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_energy_small_configs(fsv, cfg, ordering):
+    p = config(cfg, ordering=ordering)
+    say("energy", cfg, ordering)
+    plan = fsv.Plan(p)
+    psi = plan.ansatz_apply(p.theta)
+    e = plan.energy(psi)
+    e_ref = sector.energy(oracle_state(p), p.h, p.g, 0.0, p.n_alpha, p.n_beta, ordering)
+    assert abs(e - e_ref) < 1e-10
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_energy_grad_c2(fsv, ordering):
+    p = config("C2", ordering=ordering)
+    say("energy_grad C2", ordering)
+    plan = fsv.Plan(p)
+    e, g = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p)
+    assert abs(e - e_ref) < 1e-10
+    assert np.abs(g - g_ref).max() < 1e-9
+    e_fd, g_fd = plan.energy_grad_fd(p.theta, 1e-5)
+    assert abs(e_fd - e_ref) < 1e-10
+    assert np.abs(g - g_fd).max() < 1e-6
+
+
+def test_energy_complex_state_and_outside_sector(fsv):
+    # energy and 1-RDM of an arbitrary complex vector: only the sector counts
+    p = random_problem(12, 5, 10, seed=301, ordering=1)
+    rng = np.random.default_rng(9)
+    d = sector.dim(p.n_orb, p.n_alpha, p.n_beta)
+    vec = rng.normal(size=d) + 1j * rng.normal(size=d)
+    vec /= np.linalg.norm(vec)
+    full, idx = dense_from_sector(vec, p)
+    junk = rng.normal(size=full.size) + 1j * rng.normal(size=full.size)
+    junk[idx] = 0
+    import torch
+    plan = fsv.Plan(p)
+    say("complex state energy")
+    t = torch.from_numpy(full + 0.3 * junk).to(plan.device)
+    e = plan.energy(t)
+    assert abs(e - sector.energy(vec, p.h, p.g, 0.0, p.n_alpha, p.n_beta, 1)) < 1e-10
+    gam = plan.rdm1(t)
+    assert np.abs(gam - sector.rdm1(vec, p.n_orb, p.n_alpha, p.n_beta, 1)).max() < 1e-12
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_rdm1_and_potential(fsv, ordering):
+    p = config("C2", ordering=ordering)
+    say("rdm1 + potential", ordering)
+    plan = fsv.Plan(p)
+    psi = plan.ansatz_apply(p.theta)
+    gam = plan.rdm1(psi)
+    ref = sector.rdm1(oracle_state(p), p.n_orb, p.n_alpha, p.n_beta, ordering)
+    assert np.abs(gam - ref).max() < 1e-12
+    assert abs(np.trace(gam[0]).real - p.n_alpha) < 1e-12
+    v = potential_v0(p.n_orb, seed=12)
+    e0 = plan.energy(psi)
+    plan.set_onebody_potential(v)
+    e1 = plan.energy(psi)
+    assert abs((e1 - e0) - np.sum(v * (gam[0] + gam[1]).real)) < 1e-11
+    e, g = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p, h=p.h + v)
+    assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+    plan.set_onebody_potential(None)
+    assert abs(plan.energy(plan.ansatz_apply(p.theta)) - e0) < 1e-12
+
+
+def test_c3_full_size(fsv):
+    p = config("C3")
+    say("C3 full: energy, gradient, 1-RDM")
+    plan = fsv.Plan(p)
+    psi = plan.new_state()
+    lam = plan.new_state()
+    e, g = plan.energy_grad(p.theta, psi, lam)
+    e_ref, g_ref = oracle_energy_grad(p)
+    say("  E", e, e_ref, "max|dg|", np.abs(g - g_ref).max())
+    assert abs(e - e_ref) < 1e-10
+    assert np.abs(g - g_ref).max() < 1e-9
+    plan.ansatz_apply(p.theta, psi)
+    gam = plan.rdm1(psi)
+    ref = sector.rdm1(oracle_state(p), p.n_orb, p.n_alpha, p.n_beta, 0)
+    assert np.abs(gam - ref).max() < 1e-9
+    # bitwise determinism of the adjoint pass
+    e2, g2 = plan.energy_grad(p.theta, psi, lam)
+    assert e2 == e and np.array_equal(g2, g)
+
+
+def test_fused_lds_path(fsv, monkeypatch):
+    # operators restricted to low qubits so that the LDS-staged fused kernel runs
+    p = random_problem(16, 8, 400, seed=401, theta_std=0.5, replace=True, ordering=1)
+    keep = [op for op in p.ops if max(q % 2 * 8 + q // 2 for q in op if q >= 0) < 12]
+    p.ops = np.asarray(keep, dtype=np.int32)
+    p.theta = p.theta[:len(keep)]
+    monkeypatch.setenv("FSV_FORCE_FUSE", "1")
+    say("fused LDS path, K =", len(keep))
+    plan = fsv.Plan(p)
+    psi = _np(plan.ansatz_apply(p.theta))
+    ref, _ = dense_from_sector(oracle_state(p), p)
+    assert np.abs(psi - ref).max() < 1e-12
+    e, g = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p)
+    assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+
+
+def test_fp32_variant_c2(fsv):
+    p = config("C2")
+    plan = fsv.Plan(p, precision=1)
+    e, g = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p)
+    say("FP32 |dE| =", abs(e - e_ref), "max|dg| =", np.abs(g - g_ref).max())
+    assert abs(e - e_ref) < 1e-4
+
+
+def test_edge_cases(fsv):
+    # K = 0, a spin with no electrons, a full shell, the smallest system
+    for (n, ne, k) in [(8, 4, 0), (10, 1, 5), (8, 8, 0), (2, 1, 0), (4, 2, 3)]:
+        p = random_problem(n, ne, k if k else None, seed=500 + n + ne, theta_std=0.3,
+                           replace=True)
+        if k == 0:
+            p.ops = np.zeros((0, 4), dtype=np.int32)
+            p.theta = np.zeros(0)
+        say("edge", n, ne, len(p.ops))
+        plan = fsv.Plan(p)
+        e, g = plan.energy_grad(p.theta)
+        e_ref, g_ref = oracle_energy_grad(p)
+        assert abs(e - e_ref) < 1e-10
+        assert g.shape == (len(p.ops),) and (len(g) == 0 or np.abs(g - g_ref).max() < 1e-9)
+
+
+def test_autograd_energyfn(fsv):
+    import torch
+    p = config("C1")
+    plan = fsv.Plan(p)
+    th = torch.tensor(p.theta, dtype=torch.float64, requires_grad=True)
+    e = fsv.EnergyFn.apply(th, plan)
+    e.backward()
+    e_ref, g_ref = oracle_energy_grad(p)
+    assert abs(e.item() - e_ref) < 1e-10
+    assert np.abs(th.grad.numpy() - g_ref).max() < 1e-9
+
+
+def test_invalid_arguments(fsv):
+    p = config("C1")
+    bad = random_problem(8, 4, 3, seed=1)
+    bad.ops = np.array([[0, 2, 3, 1]], dtype=np.int32)  # alpha+alpha <- beta+alpha: spin flip
+    bad.theta = np.zeros(1)
+    with pytest.raises(fsv.FsvError) as ei:
+        fsv.Plan(bad)
+    assert ei.value.code == -1
+    plan = fsv.Plan(p)
+    with pytest.raises(fsv.FsvError) as ei:
+        plan.ansatz_apply(np.full(p.n_ops, np.nan))
+    assert ei.value.code == -5
