@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy three times (the known-size "
+                         "reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the state-vector path here is single-GPU "
@@ -89,6 +92,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     plan = fsv.Plan(p, precision=args.precision, device=dev)
     psi, lam = plan.new_state(), plan.new_state()
     print(f"[bench] plan ready: {args.config} n={p.n_qubits} K={p.n_ops} precision={args.precision}",

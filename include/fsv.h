@@ -163,6 +163,10 @@ int fsv_batch_energy_grad(fsv_batch *batch, const double *theta_concat, double *
                           double *grad_concat);
 /* Device bytes the batch owns (arena + tables). */
 size_t fsv_batch_bytes(const fsv_batch *batch);
+/* Launch-shape tuning of the persistent batch kernel (workgroup size and
+ * workgroups per CU), timed on this batch; *report (may be NULL) receives a
+ * static summary string. */
+int fsv_batch_autotune(fsv_batch *batch, const char **report);
 
 #ifdef __cplusplus
 }

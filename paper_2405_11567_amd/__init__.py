@@ -217,6 +217,11 @@ class Batch:
             off += k
         return e, out
 
+    def autotune(self) -> str:
+        rep = ctypes.c_char_p()
+        check(self._lib.fsv_batch_autotune(self._h, ctypes.byref(rep)))
+        return rep.value.decode() if rep.value else ""
+
     def close(self):
         if getattr(self, "_h", None):
             check(self._lib.fsv_batch_destroy(self._h))

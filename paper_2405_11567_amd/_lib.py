@@ -45,7 +45,7 @@ EXPORTS = [
     "ansatz_apply", "energy", "energy_grad", "energy_grad_fd", "rdm1", "set_onebody_potential",
     "fsv_set_theta", "fsv_forward_async", "fsv_sigma_async", "fsv_reverse_async", "fsv_finish",
     "fsv_autotune", "fsv_batch_create", "fsv_batch_destroy", "fsv_batch_energy_grad",
-    "fsv_batch_bytes",
+    "fsv_batch_bytes", "fsv_batch_autotune",
 ]
 
 _lib = None
@@ -85,6 +85,7 @@ def load():
     lib.fsv_batch_energy_grad.argtypes = [vp, d, d, d]
     lib.fsv_batch_bytes.restype = ctypes.c_size_t
     lib.fsv_batch_bytes.argtypes = [vp]
+    lib.fsv_batch_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p)]
     for name in EXPORTS:
         if name not in ("fsv_last_error", "fsv_state_bytes", "fsv_batch_bytes"):
             getattr(lib, name).restype = c_int

@@ -20,7 +20,7 @@
 using namespace fsv;
 
 // ------------------------------------------------------------------ errors --
-namespace {
+namespace fsv {
 thread_local std::string g_err;
 
 int fail(int code, const char *fmt, ...) {
@@ -32,6 +32,11 @@ int fail(int code, const char *fmt, ...) {
     g_err = buf;
     return code;
 }
+
+void clear_error() { g_err.clear(); }
+}  // namespace fsv
+
+namespace {
 
 #define HIPCHECK(expr)                                                                      \
     do {                                                                                    \
@@ -148,7 +153,9 @@ int upload(fsv_plan &P, T *dst, const T *src, size_t count) {
     return FSV_OK;
 }
 
-int validate_problem(const fsv_problem *p) {
+}  // namespace
+
+int fsv::validate_problem(const fsv_problem *p) {
     if (!p) return fail(FSV_EINVAL, "problem is NULL");
     if (p->n_qubits < 2 || p->n_qubits > 34 || (p->n_qubits & 1))
         return fail(FSV_EINVAL, "n_qubits must be even and in 2..34 (got %d)", p->n_qubits);
@@ -205,12 +212,14 @@ int validate_problem(const fsv_problem *p) {
     return FSV_OK;
 }
 
-// Compile op k: sorted target qubits, source/destination patterns, the parity
-// mask of non-target bits and the constant sign of the JW string of tau.
-RotOp compile_op(const fsv_plan &P, const int32_t *o) {
+// Compile one operator for a given qubit ordering: sorted target qubits,
+// source/destination patterns, the parity mask of non-target bits and the
+// constant sign of the JW string of tau.
+RotOp fsv::compile_op(int M, int ordering, const int32_t *o) {
+    auto qubit = [&](int so) { return ordering == 0 ? so : so / 2 + (so % 2) * M; };
     RotOp r{};
     const bool single = o[1] < 0;
-    const int qa = qubit_of(P, o[0]), qi = qubit_of(P, o[3]);
+    const int qa = qubit(o[0]), qi = qubit(o[3]);
     int qs[4], nt = 0;
     uint64_t src = 1ull << qi, dst = 1ull << qa;
     uint64_t par = ((1ull << qi) - 1) ^ ((1ull << qa) - 1);
@@ -218,8 +227,8 @@ RotOp compile_op(const fsv_plan &P, const int32_t *o) {
     qs[nt++] = qa;
     int qb = -1, qj = -1;
     if (!single) {
-        qb = qubit_of(P, o[1]);
-        qj = qubit_of(P, o[2]);
+        qb = qubit(o[1]);
+        qj = qubit(o[2]);
         src |= 1ull << qj;
         dst |= 1ull << qb;
         par ^= ((1ull << qj) - 1) ^ ((1ull << qb) - 1);
@@ -242,6 +251,8 @@ RotOp compile_op(const fsv_plan &P, const int32_t *o) {
     r.sign0 = sg;
     return r;
 }
+
+namespace fsv {
 
 std::vector<uint32_t> strings_of(int M, int N) {
     std::vector<uint32_t> out;
@@ -358,6 +369,10 @@ void build_bins(int M, const std::vector<uint32_t> &exc, int nexc, std::vector<i
     }
     (void)nexc;
 }
+
+}  // namespace fsv
+
+namespace {
 
 int upload_hamiltonian_values(fsv_plan &P) {
     std::vector<double> ht(P.h);
@@ -576,6 +591,7 @@ int launch_energy_only(fsv_plan &P, void *psi) {
 
 int build_device(fsv_plan &P) {
     int rc;
+    init_kernels();
     HIPCHECK(hipStreamCreateWithFlags(&P.work, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&P.ev_in, hipEventDisableTiming));
     HIPCHECK(hipEventCreateWithFlags(&P.ev_out, hipEventDisableTiming));
@@ -724,7 +740,7 @@ int fsv_plan_create(fsv_plan **out, const fsv_problem *p, void *hip_stream) {
     P->user = (hipStream_t)hip_stream;
     P->use_graph = std::getenv("FSV_NO_GRAPH") == nullptr;
     for (int k = 0; k < P->K; ++k) {
-        P->rot.push_back(compile_op(*P, P->ops.data() + 4 * k));
+        P->rot.push_back(compile_op(P->M, P->ordering, P->ops.data() + 4 * k));
         P->npairs.push_back(1ull << (P->n - P->rot.back().nt));
     }
     plan_segments(*P);
@@ -734,7 +750,7 @@ int fsv_plan_create(fsv_plan **out, const fsv_problem *p, void *hip_stream) {
         return rc;
     }
     *out = P;
-    g_err.clear();
+    clear_error();
     return FSV_OK;
 }
 

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
+#include "../../include/fsv.h"
+
 namespace fsv {
 
 // One excitation rotation compiled for the dense kernels.  The active source
@@ -29,9 +33,22 @@ __host__ __device__ inline uint32_t pack_exc(uint32_t J, uint32_t pq, int neg) {
     return J | (pq << 16) | (neg ? 0x80000000u : 0u);
 }
 
+// ---- host helpers shared by plans and batches (fsv_host.hip) ----
+int fail(int code, const char *fmt, ...);
+void clear_error();
+int validate_problem(const fsv_problem *p);
+RotOp compile_op(int M, int ordering, const int32_t *op);
+std::vector<uint32_t> strings_of(int M, int N);  // popcount-N masks, ascending
+void build_string_h(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
+                    const double *ht, const double *g, std::vector<int64_t> &ptr,
+                    std::vector<int32_t> &col, std::vector<double> &val);
+void build_exc(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
+               std::vector<uint32_t> &exc, int &nexc);
+
 // ---- launchers (fsv_kernels.hip) ----
 // precision: 0 complex128, 1 complex64.  Each returns the hipError_t of the launch.
 int max_grid();
+void init_kernels();  // once per process, before any capture
 
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
 hipError_t launch_set_amp(void *psi, int precision, uint64_t x, double re, hipStream_t st);

@@ -333,6 +333,61 @@ __global__ __launch_bounds__(256) void k_sigma_ab(const uint32_t *__restrict__ e
     }
 }
 
+// Same term with the source rows staged in LDS: for output row Ia the
+// alpha excitations are taken ec at a time; their rows C[J_e][:] and the
+// weights W[e][rs] = s_e (pq_e|rs) sit in LDS, and each thread gathers its
+// beta excitations from there.
+__global__ __launch_bounds__(512) void k_sigma_ab_lds(const uint32_t *__restrict__ excA, int nexcA,
+                                                      const uint32_t *__restrict__ excB, int nexcB,
+                                                      const double *__restrict__ g, int M,
+                                                      const double2 *__restrict__ C,
+                                                      double2 *__restrict__ S, int64_t nsb, int ec) {
+    extern __shared__ double2 smem[];
+    double2 *rows = smem;                                // ec * nsb
+    double *W = (double *)(smem + (int64_t)ec * nsb);    // ec * M2
+    const int64_t Ia = blockIdx.x;
+    const int M2 = M * M;
+    for (int e0 = 0; e0 < nexcA; e0 += ec) {
+        const int ne = min(ec, nexcA - e0);
+        for (int e = 0; e < ne; ++e) {
+            const uint32_t w = excA[Ia * nexcA + e0 + e];
+            const int64_t Ja = w & 0xFFFFu;
+            const int pq = (w >> 16) & 0x1FFu;
+            const double sa = (w >> 31) ? -1.0 : 1.0;
+            for (int64_t c = threadIdx.x; c < nsb; c += blockDim.x) rows[e * nsb + c] = C[Ja * nsb + c];
+            for (int rs = threadIdx.x; rs < M2; rs += blockDim.x) W[e * M2 + rs] = sa * g[pq * M2 + rs];
+        }
+        __syncthreads();
+        for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
+            double ar = 0.0, ai = 0.0;
+            for (int f = 0; f < nexcB; ++f) {
+                const uint32_t eb = excB[Ib * nexcB + f];
+                const int64_t Jb = eb & 0xFFFFu;
+                const int rs = (eb >> 16) & 0x1FFu;
+                double br = 0.0, bi = 0.0;
+                for (int e = 0; e < ne; ++e) {
+                    const double wv = W[e * M2 + rs];
+                    const double2 x = rows[e * nsb + Jb];
+                    br += wv * x.x;
+                    bi += wv * x.y;
+                }
+                if (eb >> 31) {
+                    ar -= br;
+                    ai -= bi;
+                } else {
+                    ar += br;
+                    ai += bi;
+                }
+            }
+            double2 o = S[Ia * nsb + Ib];
+            o.x += ar;
+            o.y += ai;
+            S[Ia * nsb + Ib] = o;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_transpose(const double2 *__restrict__ in, double2 *__restrict__ out,
                             int64_t rows, int64_t cols) {
     __shared__ double2 t[32][33];
@@ -448,6 +503,19 @@ unsigned blocks_for(int64_t n, int block) {
 
 int max_grid() { return kMaxGrid; }
 
+// LDS budget of the staged sigma kernel: up to the 160 KiB of a gfx950 CU when
+// the runtime grants it (set once, outside any stream capture).
+static int g_lds_max = -1;
+
+void init_kernels() {
+    if (g_lds_max > 0) return;
+    g_lds_max = 65536;
+    if (hipFuncSetAttribute((const void *)k_sigma_ab_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            163840) == hipSuccess)
+        g_lds_max = 163840;
+    (void)hipGetLastError();
+}
+
 unsigned rot_grid(uint64_t npairs, Shape sh) {
     const uint64_t per = (uint64_t)sh.block * (uint64_t)sh.ppt;
     uint64_t g = (npairs + per - 1) / per;
@@ -554,6 +622,17 @@ hipError_t launch_spmm_rows(const int64_t *rowptr, const int32_t *col, const dou
 hipError_t launch_sigma_ab(const uint32_t *excA, int nexcA, const uint32_t *excB, int nexcB,
                            const double *g, int M, const double2 *C, double2 *S, int64_t nsa,
                            int64_t nsb, hipStream_t st) {
+    const int lds_max = g_lds_max > 0 ? g_lds_max : 65536;
+    const int64_t per = nsb * (int64_t)sizeof(double2) + (int64_t)M * M * (int64_t)sizeof(double);
+    int64_t ec = per > 0 ? lds_max / per : 0;
+    if (ec > nexcA) ec = nexcA;
+    if (ec > 16) ec = 16;
+    if (ec >= 1) {
+        const size_t shm = (size_t)(ec * per);
+        hipLaunchKernelGGL(k_sigma_ab_lds, dim3((unsigned)nsa), dim3(512), shm, st, excA, nexcA, excB,
+                           nexcB, g, M, C, S, nsb, (int)ec);
+        return hipGetLastError();
+    }
     if (nexcA > kMaxExc) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sigma_ab, dim3((unsigned)nsa), dim3(256), 0, st, excA, nexcA, excB, nexcB, g, M, C, S, nsb);
     return hipGetLastError();

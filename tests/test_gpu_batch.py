@@ -1,0 +1,72 @@
+"""Batched persistent-kernel path vs the FP64 oracle, instance by instance."""
+
+import time
+
+import numpy as np
+import pytest
+
+from workloads import batch_config, random_problem
+from tests.gpu_helpers import oracle_energy_grad, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fsv(gpu):
+    import paper_2405_11567_amd as m
+    m.load()
+    return m
+
+
+def test_batch_mixed_small(fsv):
+    probs = []
+    shapes = [(4, 2, 3), (6, 3, 10), (8, 4, 26), (8, 1, 5), (10, 7, 20), (12, 6, 40), (12, 4, 30),
+              (10, 5, 0), (14, 7, 25), (6, 6, 0), (16, 9, 30)]
+    for i, (n, ne, k) in enumerate(shapes):
+        p = random_problem(n, ne, k if k else None, seed=700 + i, theta_std=0.3, replace=True,
+                           ordering=i % 2)
+        if k == 0:
+            p.ops = np.zeros((0, 4), dtype=np.int32)
+            p.theta = np.zeros(0)
+        p.e_core = 0.1 * i
+        probs.append(p)
+    say("batch mixed", len(probs))
+    b = fsv.Batch(probs)
+    e, g = b.energy_grad([p.theta for p in probs])
+    for i, p in enumerate(probs):
+        e_ref, g_ref = oracle_energy_grad(p)
+        assert abs(e[i] - e_ref) < 1e-10, (i, e[i], e_ref)
+        if p.n_ops:
+            assert np.abs(g[i] - g_ref).max() < 1e-9, i
+
+
+def test_batch_c4_full(fsv):
+    probs = batch_config()
+    say("batch C4: 256 instances")
+    b = fsv.Batch(probs)
+    thetas = [p.theta for p in probs]
+    e, g = b.energy_grad(thetas)
+    t0 = time.time()
+    worst_e = worst_g = 0.0
+    for i, p in enumerate(probs):
+        e_ref, g_ref = oracle_energy_grad(p)
+        worst_e = max(worst_e, abs(e[i] - e_ref))
+        worst_g = max(worst_g, float(np.abs(g[i] - g_ref).max()))
+    say(f"  oracle {time.time() - t0:.1f} s, max|dE| {worst_e:.2e}, max|dg| {worst_g:.2e}")
+    assert worst_e < 1e-10 and worst_g < 1e-9
+    e2, g2 = b.energy_grad(thetas)
+    assert np.array_equal(e, e2) and all(np.array_equal(a, c) for a, c in zip(g, g2))
+    rep = b.autotune()
+    say(rep)
+    e3, g3 = b.energy_grad(thetas)
+    assert np.abs(e3 - e).max() < 1e-12
+
+
+def test_batch_rejects_bad_input(fsv):
+    p = random_problem(8, 4, 5, seed=1)
+    with pytest.raises(fsv.FsvError):
+        fsv.Batch([])
+    b = fsv.Batch([p])
+    with pytest.raises(fsv.FsvError) as ei:
+        b.energy_grad([np.full(5, np.inf)])
+    assert ei.value.code == -5
