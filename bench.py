@@ -40,9 +40,43 @@ def line_bytes(op, n, amp_bytes, ordering):
 
 
 def model_bytes(p, amp_bytes):
+    """Dense line-granular model: each operator reads and writes the 128-byte
+    lines holding its active amplitude pairs."""
     per_op = [line_bytes(op, p.n_qubits, amp_bytes, p.ordering) for op in p.ops]
     fwd = sum(per_op)
     sigma = 2.0 * (2 ** p.n_qubits) * amp_bytes
+    return {"forward": fwd, "reverse": 2 * fwd, "sigma_floor": sigma, "eval": 3 * fwd + sigma,
+            "per_op": per_op}
+
+
+def sector_pairs(op, m, na, nb):
+    """Active pairs of one operator on the (na, nb) sector: strings of each spin
+    that hold its annihilated orbitals and lack its created ones."""
+    from math import comb
+    cnt = {0: [0, 0], 1: [0, 0]}  # spin -> [annihilated, created]
+    a, b, j, i = (int(v) for v in op)
+    for v in (i, j):
+        if v >= 0:
+            cnt[v % 2][0] += 1
+    for v in (a, b):
+        if v >= 0:
+            cnt[v % 2][1] += 1
+    out = 1
+    for s, ne in ((0, na), (1, nb)):
+        d, c = cnt[s]
+        out *= comb(m - d - c, ne - d) if (d or c) else comb(m, ne)
+    return out
+
+
+def sector_model_bytes(p, amp_bytes):
+    """Sector-compressed model: each operator reads and writes both amplitudes
+    of every active sector pair (forward: psi; reverse: psi and lambda)."""
+    m = p.n_orb
+    per_op = [4.0 * amp_bytes * sector_pairs(op, m, p.n_alpha, p.n_beta) for op in p.ops]
+    fwd = sum(per_op)
+    from math import comb
+    dim = comb(m, p.n_alpha) * comb(m, p.n_beta)
+    sigma = 2.0 * dim * amp_bytes
     return {"forward": fwd, "reverse": 2 * fwd, "sigma_floor": sigma, "eval": 3 * fwd + sigma,
             "per_op": per_op}
 
@@ -63,6 +97,54 @@ def cpu_baseline(p, max_seconds=30.0):
                       f"(sector-compressed FP64 C/OpenMP oracle), {el:.1f} s"}
 
 
+def time_engine(fsv, torch, p, precision, engine, steps, warmup, stream, psi, lam):
+    """Timed energy+gradient passes of one engine, then per-stage HIP-event
+    timing on the plan's stream."""
+    plan = fsv.Plan(p, precision=precision, device=psi.device, engine=engine)
+    for _ in range(warmup):
+        plan.energy_grad(p.theta, psi, lam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e, g = plan.energy_grad(p.theta, psi, lam)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_fwd, t_sig, t_rev = [], [], []
+    for _ in range(max(3, min(steps, 10))):
+        plan.set_theta(p.theta)
+        ev[0].record(stream)
+        plan.forward_async(psi)
+        ev[1].record(stream)
+        plan.sigma_async(psi, lam)
+        ev[2].record(stream)
+        plan.reverse_async(psi, lam)
+        ev[3].record(stream)
+        plan.finish()
+        torch.cuda.synchronize()
+        t_fwd.append(ev[0].elapsed_time(ev[1]))
+        t_sig.append(ev[1].elapsed_time(ev[2]))
+        t_rev.append(ev[2].elapsed_time(ev[3]))
+    stages = {"forward": float(np.median(t_fwd)), "sigma": float(np.median(t_sig)),
+              "reverse": float(np.median(t_rev))}
+    print(f"[bench] {engine}: {ms:.3f} ms/eval; stages forward {stages['forward']:.3f} ms, "
+          f"sigma {stages['sigma']:.3f} ms, reverse {stages['reverse']:.3f} ms",
+          file=sys.stderr, flush=True)
+    return plan, ms, steps / (t1 - t0), stages, e, g
+
+
+def roofline_of(mb, stages, k, kernel):
+    """Reverse-step kernel: algorithmic bytes per launch over its average launch
+    duration (the reverse stage's HIP-event time over its K launches)."""
+    launch_ms = stages["reverse"] / k
+    per_launch = mb["reverse"] / k
+    achieved = per_launch / (launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+            "avg_launch_us": launch_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +152,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--engine", default="sector", choices=["sector", "dense"])
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-engine comparison run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--tune", action="store_true")
@@ -100,60 +184,38 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    plan = fsv.Plan(p, precision=args.precision, device=dev)
-    psi, lam = plan.new_state(), plan.new_state()
-    print(f"[bench] plan ready: {args.config} n={p.n_qubits} K={p.n_ops} precision={args.precision}",
-          file=sys.stderr, flush=True)
+    dtype = torch.complex128 if args.precision == 0 else torch.complex64
+    psi = torch.empty(1 << p.n_qubits, dtype=dtype, device=dev)
+    lam = torch.empty_like(psi)
+    k = p.n_ops
+    print(f"[bench] {args.config} n={p.n_qubits} K={k} precision={args.precision}", file=sys.stderr, flush=True)
+
+    plan, ms, evals_s, stages, e, g = time_engine(fsv, torch, p, args.precision, args.engine,
+                                                  args.steps, args.warmup, stream, psi, lam)
     if args.tune:
         print(plan.autotune(psi, lam), file=sys.stderr, flush=True)
+    mb_dense = model_bytes(p, amp_bytes)
+    mb_sector = sector_model_bytes(p, amp_bytes)
+    mb = mb_sector if args.engine == "sector" else mb_dense
+    roof = roofline_of(mb, stages, k, "k_cadj (sector adjoint step)" if args.engine == "sector"
+                       else "k_adj (dense adjoint step)")
 
-    for _ in range(args.warmup):
-        plan.energy_grad(p.theta, psi, lam)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e, g = plan.energy_grad(p.theta, psi, lam)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    evals_s = args.steps / (t1 - t0)
-    print(f"[bench] timed {args.steps} evals: {ms:.3f} ms/eval", file=sys.stderr, flush=True)
-
-    # Stage timing with HIP events on the plan's stream: forward, sigma, reverse.
-    mb = model_bytes(p, amp_bytes)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    t_fwd, t_sig, t_rev = [], [], []
-    reps = max(3, min(args.steps, 10))
-    for _ in range(reps):
-        plan.set_theta(p.theta)
-        ev[0].record(stream)
-        plan.forward_async(psi)
-        ev[1].record(stream)
-        plan.sigma_async(psi, lam)
-        ev[2].record(stream)
-        plan.reverse_async(psi, lam)
-        ev[3].record(stream)
-        plan.finish()
-        torch.cuda.synchronize()
-        t_fwd.append(ev[0].elapsed_time(ev[1]))
-        t_sig.append(ev[1].elapsed_time(ev[2]))
-        t_rev.append(ev[2].elapsed_time(ev[3]))
-    t_rev_ms = float(np.median(t_rev))
-    k = p.n_ops
-    adj_launch_ms = t_rev_ms / k
-    adj_bytes_per_launch = mb["reverse"] / k
-    achieved = adj_bytes_per_launch / (adj_launch_ms * 1e-3) / 1e9
-    print(f"[bench] stages: forward {np.median(t_fwd):.3f} ms, sigma {np.median(t_sig):.3f} ms, "
-          f"reverse {t_rev_ms:.3f} ms ({adj_launch_ms*1e3:.2f} us/launch)", file=sys.stderr, flush=True)
+    dense = None
+    if args.engine == "sector" and not args.no_dense:
+        dplan, dms, devals, dstages, de, dg = time_engine(fsv, torch, p, args.precision, "dense",
+                                                          max(3, args.steps // 3), 1, stream, psi, lam)
+        dense = {"evals_s": devals, "ms_per_eval": dms, "stage_ms": dstages,
+                 "roofline": roofline_of(mb_dense, dstages, k, "k_adj (dense adjoint step)"),
+                 "dense_model_hbm_frac": mb_dense["eval"] / (dms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "max_abs_dE_vs_sector": abs(de - e), "max_abs_dg_vs_sector": float(np.abs(dg - g).max())}
+        del dplan
 
     fd = None
     if not args.no_fd:
-        # central finite differences on the same GPU: 2K + 1 energy evaluations
         t2 = time.perf_counter()
         _, gfd = plan.energy_grad_fd(p.theta, 1e-5, psi)
-        t3 = time.perf_counter()
-        fd_s = t3 - t2
-        fd = {"gradient_s": fd_s, "evals_s": 1.0 / fd_s, "adjoint_speedup": fd_s / (ms * 1e-3),
+        fd_s = time.perf_counter() - t2
+        fd = {"gradient_s": fd_s, "energies": 2 * k + 1, "adjoint_speedup": fd_s / (ms * 1e-3),
               "max_abs_diff_vs_adjoint": float(np.abs(gfd - g).max())}
         print(f"[bench] FD gradient {fd_s:.3f} s ({2*k+1} energies), adjoint {ms:.3f} ms: "
               f"{fd['adjoint_speedup']:.0f}x", file=sys.stderr, flush=True)
@@ -174,16 +236,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {p.n_qubits} qubits, {p.n_alpha + p.n_beta} electrons, "
                                f"{k} sampled spin-conserving singles/doubles, energy + adjoint gradient",
-                   "n_qubits": p.n_qubits, "n_ops": k, "precision": args.precision},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "adjoint reverse step (k_adj)",
-                     "avg_launch_us": adj_launch_ms * 1e3,
-                     "algorithmic_bytes_per_launch": adj_bytes_per_launch},
-        "eval_model": {"bytes_per_eval": mb["eval"],
-                       "hbm_frac_per_eval": mb["eval"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                       "stage_ms": {"forward": float(np.median(t_fwd)), "sigma": float(np.median(t_sig)),
-                                    "reverse": t_rev_ms}},
+                   "n_qubits": p.n_qubits, "n_ops": k, "precision": args.precision,
+                   "engine": args.engine},
+        "roofline": roof,
+        "eval_model": {"engine_bytes_per_eval": mb["eval"], "stage_ms": stages,
+                       "dense_line_model_bytes_per_eval": mb_dense["eval"],
+                       "dense_model_hbm_frac": mb_dense["eval"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "dense_engine": dense,
         "energy": e,
         "fd_baseline": fd,
         "cpu_baseline": cpu,

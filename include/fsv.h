@@ -94,6 +94,15 @@ size_t fsv_state_bytes(const fsv_plan *plan);
 int fsv_plan_info(const fsv_plan *plan, int64_t *n_alpha_strings, int64_t *n_beta_strings,
                   uint64_t *reference_index);
 
+/* Choose how energy_grad, energy_grad_fd and the stage calls hold the state:
+ * 0 (default) keeps only the (n_alpha, n_beta) sector, compactly, in the first
+ * C(n_orb, n_alpha) * C(n_orb, n_beta) amplitudes of the work buffers (every
+ * other amplitude of a state built from |ref> is exactly zero, since each
+ * operator conserves both electron counts); 1 uses the full 2^n layout and
+ * touches every active amplitude pair of each operator.  Results agree to
+ * rounding.  The environment variable FSV_ENGINE=dense selects 1 at creation. */
+int fsv_plan_set_engine(fsv_plan *plan, int engine);
+
 /* psi_dev <- U_K(theta_K) ... U_1(theta_1) |ref> (ansatz preparation on the
  * GPU emulator, Fig. 1).  theta: host, K doubles.  Every amplitude of psi_dev
  * is written (zero outside the sector). */

@@ -43,8 +43,10 @@ class Plan:
     HIP stream.  `problem` is any object with the attributes of
     workloads.Problem (n_qubits, n_alpha, n_beta, h, g, ops, e_core, ordering)."""
 
+    ENGINES = {"sector": 0, "dense": 1}
+
     def __init__(self, problem, precision: int = 0, ordering: int | None = None,
-                 stream=None, device=None):
+                 stream=None, device=None, engine: str | None = None):
         torch = _torch()
         lib = load()
         self.device = torch.device(device if device is not None else "cuda:0")
@@ -69,6 +71,14 @@ class Plan:
         check(lib.fsv_plan_info(handle, ctypes.byref(nsa), ctypes.byref(nsb), ctypes.byref(ref)))
         self.n_alpha_strings, self.n_beta_strings = nsa.value, nsb.value
         self.reference_index = ref.value
+        if engine is not None:
+            self.set_engine(engine)
+
+    def set_engine(self, engine: str):
+        """'sector' (default): energy_grad keeps only the (n_alpha, n_beta)
+        sector, compactly; 'dense': every active pair of the 2^n vector."""
+        check(self._lib.fsv_plan_set_engine(self._h, self.ENGINES[engine]))
+        self.engine = engine
 
     # -- buffers ---------------------------------------------------------
     @property

@@ -38,16 +38,7 @@ struct BInst {
     double ecore;
 };
 
-struct BOp {
-    int32_t nA, nB;      // pair-list lengths; -1 = every string maps to itself with sign +1
-    int64_t offA, offB;  // into the list arena
-    int32_t sign0, pad;
-};
-
-// list entry: source string (bits 0..14), partner (15..29), bit 31 = negative sign
-__host__ __device__ inline uint32_t pack_pair(uint32_t s, uint32_t d, int neg) {
-    return s | (d << 15) | (neg ? 0x80000000u : 0u);
-}
+using BOp = PairOp;
 
 constexpr int kWave = 64;
 
@@ -352,7 +343,6 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     for (int i = 0; i < count; ++i) {
         const fsv_problem &p = problems[i];
         const int M = p.n_qubits / 2;
-        const uint32_t mask = (1u << M) - 1u;
         BInst I{};
         I.M = M;
         I.K = p.n_ops;
@@ -394,31 +384,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         // operators in the alpha-first basis = the blocked JW ordering
         double pairs = 0.0;
         for (int k = 0; k < p.n_ops; ++k) {
-            const RotOp r = compile_op(M, 1, p.ops + 4 * k);
-            BOp o{};
-            o.sign0 = r.sign0;
-            const uint32_t srcA = (uint32_t)(r.src & mask), dstA = (uint32_t)(r.dst & mask),
-                           parA = (uint32_t)(r.par & mask);
-            const uint32_t srcB = (uint32_t)((r.src >> M) & mask), dstB = (uint32_t)((r.dst >> M) & mask),
-                           parB = (uint32_t)((r.par >> M) & mask);
-            auto make = [&](uint32_t src, uint32_t dst, uint32_t par, const std::vector<uint32_t> &str,
-                            const std::vector<int32_t> &rank, int32_t &n, int64_t &off) {
-                if (src == 0 && dst == 0) {
-                    n = -1;
-                    off = 0;
-                    return;
-                }
-                off = (int64_t)lists.size();
-                for (uint32_t s : str) {
-                    if ((s & src) != src || (s & dst) != 0) continue;
-                    const uint32_t d = s ^ src ^ dst;
-                    lists.push_back(pack_pair((uint32_t)rank[s], (uint32_t)rank[d],
-                                              __builtin_popcount(s & par) & 1));
-                }
-                n = (int32_t)((int64_t)lists.size() - off);
-            };
-            make(srcA, dstA, parA, sa, ra, o.nA, o.offA);
-            make(srcB, dstB, parB, sb, rb, o.nB, o.offB);
+            const BOp o = build_pair_op(M, p.ops + 4 * k, sa, ra, sb, rb, lists);
             pairs += (double)(o.nA >= 0 ? o.nA : I.nsa) * (double)(o.nB >= 0 ? o.nB : I.nsb);
             ops.push_back(o);
         }

@@ -81,6 +81,7 @@ struct fsv_plan {
     bool wide = false;   // 64-bit index math
     int amp_bytes = 16;
     uint64_t ref_index = 0;
+    double ref_phase = 1.0;  // ordering sign of the reference in the alpha-first basis
 
     // forward segmentation: fused LDS runs [k0, k1) (k1 - k0 >= 2) or single ops
     struct Seg { int k0, k1; bool fused; };
@@ -113,6 +114,12 @@ struct fsv_plan {
     double2 *d_gamma = nullptr;
     double *h_pin = nullptr;  // pinned: cs (2K) then out (K + 1) then gamma (4 M^2)
     size_t pin_doubles = 0;
+
+    // sector-compressed engine (default for energy_grad / ansatz_apply)
+    int engine = 0;  // 0 sector-compressed, 1 dense
+    std::vector<PairOp> pops;
+    uint32_t *d_plists = nullptr;
+    int *d_ccount = nullptr;
 
     // graphs
     bool use_graph = true;
@@ -370,6 +377,38 @@ void build_bins(int M, const std::vector<uint32_t> &exc, int nexc, std::vector<i
     (void)nexc;
 }
 
+// The operator compiled for the blocked ordering (qubit p + s*M), whose JW
+// basis restricted to the sector is the alpha-first product basis, splits
+// into an alpha and a beta part: source/destination/parity bits below M act on
+// the alpha string, those above on the beta string.
+PairOp build_pair_op(int M, const int32_t *op, const std::vector<uint32_t> &sa,
+                     const std::vector<int32_t> &ra, const std::vector<uint32_t> &sb,
+                     const std::vector<int32_t> &rb, std::vector<uint32_t> &lists) {
+    const RotOp r = compile_op(M, 1, op);
+    const uint64_t mask = (1ull << M) - 1ull;
+    PairOp o{};
+    o.sign0 = r.sign0;
+    auto make = [&](uint32_t src, uint32_t dst, uint32_t par, const std::vector<uint32_t> &str,
+                    const std::vector<int32_t> &rank, int32_t &n, int64_t &off) {
+        if (src == 0 && dst == 0) {  // no part on this spin: the parity mask is empty too
+            n = -1;
+            off = 0;
+            return;
+        }
+        off = (int64_t)lists.size();
+        for (uint32_t s : str) {
+            if ((s & src) != src || (s & dst) != 0) continue;
+            const uint32_t d = s ^ src ^ dst;
+            lists.push_back(pack_pair((uint32_t)rank[s], (uint32_t)rank[d], __builtin_popcount(s & par) & 1));
+        }
+        n = (int32_t)((int64_t)lists.size() - off);
+    };
+    make((uint32_t)(r.src & mask), (uint32_t)(r.dst & mask), (uint32_t)(r.par & mask), sa, ra, o.nA, o.offA);
+    make((uint32_t)((r.src >> M) & mask), (uint32_t)((r.dst >> M) & mask), (uint32_t)((r.par >> M) & mask),
+         sb, rb, o.nB, o.offB);
+    return o;
+}
+
 }  // namespace fsv
 
 namespace {
@@ -453,7 +492,7 @@ int fence_out(fsv_plan &P) {
 }
 
 // ---- enqueue helpers (no synchronisation; usable under stream capture) ----
-int enq_forward(fsv_plan &P, void *psi) {
+int enq_forward_dense(fsv_plan &P, void *psi) {
     HIPCHECK(launch_fill_zero(psi, ((size_t)1 << P.n) * P.amp_bytes, P.work));
     HIPCHECK(launch_set_amp(psi, P.precision, P.ref_index, 1.0, P.work));
     for (const auto &sg : P.segs) {
@@ -469,17 +508,23 @@ int enq_forward(fsv_plan &P, void *psi) {
     return FSV_OK;
 }
 
-// lam == nullptr: energy only (no dense write of H psi).
-int enq_sigma(fsv_plan &P, const void *psi, void *lam) {
-    HIPCHECK(launch_gather(P.precision, psi, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.d_C, P.work));
-    HIPCHECK(launch_spmm_rows(P.d_ha_ptr, P.d_ha_col, P.d_ha_val, P.d_C, P.d_S, P.nsa, P.nsb, P.work));
+// S = H C on the sector (alpha-first basis) and E = Re<C|S> into d_out[0].
+int enq_sector_sigma(fsv_plan &P, const double2 *C, double2 *S) {
+    HIPCHECK(launch_spmm_rows(P.d_ha_ptr, P.d_ha_col, P.d_ha_val, C, S, P.nsa, P.nsb, P.work));
     if (P.nexcA > 0 && P.nexcB > 0)
-        HIPCHECK(launch_sigma_ab(P.d_excA, P.nexcA, P.d_excB, P.nexcB, P.d_g, P.M, P.d_C, P.d_S,
-                                 P.nsa, P.nsb, P.work));
-    HIPCHECK(launch_transpose(P.d_C, P.d_CT, P.nsa, P.nsb, P.work));
+        HIPCHECK(launch_sigma_ab(P.d_excA, P.nexcA, P.d_excB, P.nexcB, P.d_g, P.M, C, S, P.nsa, P.nsb, P.work));
+    HIPCHECK(launch_transpose(C, P.d_CT, P.nsa, P.nsb, P.work));
     HIPCHECK(launch_spmm_rows(P.d_hb_ptr, P.d_hb_col, P.d_hb_val, P.d_CT, P.d_ST, P.nsb, P.nsa, P.work));
-    HIPCHECK(launch_combine(P.d_S, P.d_ST, P.d_C, P.ecore, P.nsa, P.nsb, P.d_epart, P.work));
+    HIPCHECK(launch_combine(S, P.d_ST, C, P.ecore, P.nsa, P.nsb, P.d_epart, P.work));
     HIPCHECK(launch_reduce_rows(P.d_epart, P.d_ecount, 0, 1, 1.0, P.d_out, P.work));
+    return FSV_OK;
+}
+
+// lam == nullptr: energy only (no dense write of H psi).
+int enq_sigma_dense(fsv_plan &P, const void *psi, void *lam) {
+    HIPCHECK(launch_gather(P.precision, psi, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.d_C, P.work));
+    int rc = enq_sector_sigma(P, P.d_C, P.d_S);
+    if (rc) return rc;
     if (lam) {
         HIPCHECK(launch_fill_zero(lam, ((size_t)1 << P.n) * P.amp_bytes, P.work));
         HIPCHECK(launch_scatter(P.precision, lam, P.d_S, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.work));
@@ -487,12 +532,74 @@ int enq_sigma(fsv_plan &P, const void *psi, void *lam) {
     return FSV_OK;
 }
 
-int enq_reverse(fsv_plan &P, void *psi, void *lam) {
+int enq_reverse_dense(fsv_plan &P, void *psi, void *lam) {
     const int G = max_grid();
     for (int k = P.K - 1; k >= 0; --k)
         HIPCHECK(launch_adj(P.precision, P.wide, psi, lam, P.rot[k], P.d_cs, k, P.npairs[k],
                             P.shape_adj, P.d_gpart + (size_t)k * G, P.work));
     HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_gcount, G, P.K, 2.0, P.d_out + 1, P.work));
+    return FSV_OK;
+}
+
+// ---- sector-compressed engine: the state is C[Ia][Ib] in the first
+// nsa*nsb amplitudes of the caller's buffer (complex128 or complex64) ----
+int enq_forward_sector(fsv_plan &P, void *c) {
+    HIPCHECK(launch_fill_zero(c, (size_t)P.dim * P.amp_bytes, P.work));
+    // The reference is string 0 x string 0.  Its alpha-first amplitude carries
+    // the ordering sign so that the dense image starts at exactly +1 |ref>.
+    HIPCHECK(launch_set_amp(c, P.precision, 0, P.ref_phase, P.work));
+    for (int k = 0; k < P.K; ++k)
+        HIPCHECK(launch_crot(P.precision, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
+    return FSV_OK;
+}
+
+// lam_c == nullptr: energy only.
+int enq_sigma_sector(fsv_plan &P, const void *c, void *lam_c) {
+    if (P.precision == 0) {
+        double2 *S = lam_c ? (double2 *)lam_c : P.d_S;
+        return enq_sector_sigma(P, (const double2 *)c, S);
+    }
+    HIPCHECK(launch_cvt(true, c, P.d_C, P.dim, P.work));
+    int rc = enq_sector_sigma(P, P.d_C, P.d_S);
+    if (rc) return rc;
+    if (lam_c) HIPCHECK(launch_cvt(false, P.d_S, lam_c, P.dim, P.work));
+    return FSV_OK;
+}
+
+int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
+    const int G = max_grid();
+    for (int k = P.K - 1; k >= 0; --k)
+        HIPCHECK(launch_cadj(P.precision, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
+                             P.d_gpart + (size_t)k * G, P.work));
+    HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_ccount, G, P.K, 2.0, P.d_out + 1, P.work));
+    return FSV_OK;
+}
+
+int enq_forward(fsv_plan &P, void *psi) {
+    return P.engine == 0 ? enq_forward_sector(P, psi) : enq_forward_dense(P, psi);
+}
+
+int enq_sigma(fsv_plan &P, const void *psi, void *lam) {
+    return P.engine == 0 ? enq_sigma_sector(P, psi, lam) : enq_sigma_dense(P, psi, lam);
+}
+
+int enq_reverse(fsv_plan &P, void *psi, void *lam) {
+    return P.engine == 0 ? enq_reverse_sector(P, psi, lam) : enq_reverse_dense(P, psi, lam);
+}
+
+// Dense output of the ansatz: prepared on the sector in the workspace, then
+// expanded (zero elsewhere) into the caller's 2^n buffer.
+int enq_ansatz_dense_out(fsv_plan &P, void *psi) {
+    if (P.engine != 0) return enq_forward_dense(P, psi);
+    int rc = enq_forward_sector(P, P.d_S);
+    if (rc) return rc;
+    const double2 *S = P.d_S;
+    if (P.precision != 0) {
+        HIPCHECK(launch_cvt(true, P.d_S, P.d_C, P.dim, P.work));
+        S = P.d_C;
+    }
+    HIPCHECK(launch_fill_zero(psi, ((size_t)1 << P.n) * P.amp_bytes, P.work));
+    HIPCHECK(launch_scatter(P.precision, psi, S, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.work));
     return FSV_OK;
 }
 
@@ -632,12 +739,24 @@ int build_device(fsv_plan &P) {
         PPb[i] = pp;
     }
     P.ref_index = Xa[0] | Xb[0];  // strings are ascending: index 0 fills the lowest orbitals
+    P.ref_phase = (__builtin_popcount(P.sa[0] & PPb[0]) & 1) ? -1.0 : 1.0;
     std::vector<uint32_t> excA, excB;
     build_exc(M, P.sa, ra, excA, P.nexcA);
     build_exc(M, P.sb, rb, excB, P.nexcB);
     std::vector<int32_t> boA, biA, boB, biB;
     build_bins(M, excA, P.nexcA, boA, biA);
     build_bins(M, excB, P.nexcB, boB, biB);
+    std::vector<uint32_t> plists;
+    std::vector<int> ccount(std::max(P.K, 1), 0);
+    P.pops.clear();
+    for (int k = 0; k < P.K; ++k) {
+        P.pops.push_back(build_pair_op(M, P.ops.data() + 4 * k, P.sa, ra, P.sb, rb, plists));
+        ccount[k] = cadj_blocks(P.pops.back(), P.nsa, P.nsb);
+    }
+    if ((rc = dalloc(P, &P.d_plists, plists.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_ccount, (size_t)std::max(P.K, 1)))) return rc;
+    if ((rc = upload(P, P.d_plists, plists.data(), plists.size()))) return rc;
+    if ((rc = upload(P, P.d_ccount, ccount.data(), (size_t)P.K))) return rc;
 
     if ((rc = dalloc(P, &P.d_rot, P.K))) return rc;
     if ((rc = dalloc(P, &P.d_cs, 2 * (size_t)P.K))) return rc;
@@ -739,6 +858,7 @@ int fsv_plan_create(fsv_plan **out, const fsv_problem *p, void *hip_stream) {
     P->ops.assign(p->ops, p->ops + 4 * (size_t)P->K);
     P->user = (hipStream_t)hip_stream;
     P->use_graph = std::getenv("FSV_NO_GRAPH") == nullptr;
+    if (const char *e = std::getenv("FSV_ENGINE")) P->engine = std::strcmp(e, "dense") == 0 ? 1 : 0;
     for (int k = 0; k < P->K; ++k) {
         P->rot.push_back(compile_op(P->M, P->ordering, P->ops.data() + 4 * k));
         P->npairs.push_back(1ull << (P->n - P->rot.back().nt));
@@ -771,6 +891,17 @@ int fsv_plan_info(const fsv_plan *P, int64_t *nsa, int64_t *nsb, uint64_t *ref) 
     if (nsa) *nsa = P->nsa;
     if (nsb) *nsb = P->nsb;
     if (ref) *ref = P->ref_index;
+    return FSV_OK;
+}
+
+int fsv_plan_set_engine(fsv_plan *P, int engine) {
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    if (engine != 0 && engine != 1) return fail(FSV_EINVAL, "engine must be 0 (sector) or 1 (dense)");
+    if (engine != P->engine) {
+        if (P->work) HIPCHECK(hipStreamSynchronize(P->work));
+        drop_graphs(*P);
+        P->engine = engine;
+    }
     return FSV_OK;
 }
 
@@ -819,7 +950,7 @@ int ansatz_apply(fsv_plan *P, const double *theta, void *psi) {
     int rc;
     if ((rc = fence_in(*P))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
-    if ((rc = enq_forward(*P, psi))) return rc;
+    if ((rc = enq_ansatz_dense_out(*P, psi))) return rc;
     HIPCHECK(hipStreamSynchronize(P->work));
     return fence_out(*P);
 }
@@ -828,7 +959,7 @@ int energy(fsv_plan *P, const void *psi, double *E_out) {
     if (!P || !psi || !E_out) return fail(FSV_EINVAL, "plan, psi or E_out is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
-    if ((rc = enq_sigma(*P, psi, nullptr))) return rc;
+    if ((rc = enq_sigma_dense(*P, psi, nullptr))) return rc;
     if ((rc = download_out(*P, E_out, nullptr, false))) return rc;
     return fence_out(*P);
 }

@@ -21,6 +21,22 @@ struct RotOp {
     int32_t sign0;
 };
 
+// One excitation on the sector-compressed state C[Ia][Ib] (alpha-string-first
+// product basis = blocked JW ordering restricted to the sector).  Its active
+// pairs are the product of an alpha pair list and a beta pair list; a list
+// length of -1 means "every string maps to itself with sign +1".  List entries
+// pack the source string (bits 0..14), the partner (15..29) and a negative-sign
+// flag (bit 31); the pair sign is sign0 times both flags.
+struct PairOp {
+    int32_t nA, nB;
+    int64_t offA, offB;
+    int32_t sign0, pad;
+};
+
+__host__ __device__ inline uint32_t pack_pair(uint32_t s, uint32_t d, int neg) {
+    return s | (d << 15) | (neg ? 0x80000000u : 0u);
+}
+
 // Launch shape of the pair kernels.
 struct Shape {
     int block;   // threads per workgroup
@@ -44,6 +60,10 @@ void build_string_h(int M, const std::vector<uint32_t> &str, const std::vector<i
                     std::vector<int32_t> &col, std::vector<double> &val);
 void build_exc(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
                std::vector<uint32_t> &exc, int &nexc);
+// Pair lists of one operator for the sector-compressed state; appends to lists.
+PairOp build_pair_op(int M, const int32_t *op, const std::vector<uint32_t> &sa,
+                     const std::vector<int32_t> &ra, const std::vector<uint32_t> &sb,
+                     const std::vector<int32_t> &rb, std::vector<uint32_t> &lists);
 
 // ---- launchers (fsv_kernels.hip) ----
 // precision: 0 complex128, 1 complex64.  Each returns the hipError_t of the launch.
@@ -93,5 +113,14 @@ hipError_t launch_rdm_overlap(const double2 *A, int64_t nrows, int64_t ncols,
                               const uint32_t *exc, int nexc, double2 *O, hipStream_t st);
 hipError_t launch_rdm_bin(const double2 *O, const int32_t *off, const int32_t *idx, int nbins,
                           double2 *out, hipStream_t st);
+
+// sector-compressed engine (state C[Ia][Ib], complex128 or complex64)
+int cadj_blocks(const PairOp &op, int64_t nsa, int64_t nsb);  // partials written by launch_cadj
+hipError_t launch_crot(int precision, void *psi, const PairOp &op, const uint32_t *lists,
+                       const double *cs, int k, int64_t nsa, int64_t nsb, hipStream_t st);
+hipError_t launch_cadj(int precision, void *psi, void *lam, const PairOp &op, const uint32_t *lists,
+                       const double *cs, int k, int64_t nsa, int64_t nsb, double *partial,
+                       hipStream_t st);
+hipError_t launch_cvt(bool to_double, const void *in, void *out, int64_t n, hipStream_t st);
 
 }  // namespace fsv

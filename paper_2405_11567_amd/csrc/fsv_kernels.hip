@@ -464,6 +464,139 @@ __global__ void k_rdm_bin(const double2 *__restrict__ O, const int32_t *__restri
     if (threadIdx.x == 0) out[b] = make_double2(re, im);
 }
 
+// ------------------------------------------ sector-compressed rotations ----
+// Active pair (u, v): alpha pair u of the operator's alpha list (row u when it
+// has no alpha part) and beta pair v (column v when it has no beta part).
+// Workgroups tile u with blockIdx.y (stride gridDim.y) and v with blockIdx.x
+// and the threads.
+struct CGrid {
+    unsigned gx, gy, block;
+};
+
+__host__ __device__ inline CGrid cgrid_of(const PairOp &op, int64_t nsa, int64_t nsb) {
+    const int64_t na = op.nA >= 0 ? op.nA : nsa, nb = op.nB >= 0 ? op.nB : nsb;
+    CGrid g;
+    g.block = nb <= 64 ? 64u : (nb <= 128 ? 128u : 256u);
+    const int64_t gy = na < 1024 ? (na > 0 ? na : 1) : 1024;
+    int64_t gx = (nb + g.block - 1) / g.block;
+    const int64_t cap = kMaxGrid / gy > 0 ? kMaxGrid / gy : 1;
+    if (gx > cap) gx = cap;
+    if (gx < 1) gx = 1;
+    g.gx = (unsigned)gx;
+    g.gy = (unsigned)gy;
+    return g;
+}
+
+__device__ __forceinline__ void cpair_row(const PairOp &op, const uint32_t *__restrict__ lists,
+                                          int64_t u, int64_t &ia, int64_t &ia2, bool &neg) {
+    if (op.nA >= 0) {
+        const uint32_t e = lists[op.offA + u];
+        ia = e & 0x7FFFu;
+        ia2 = (e >> 15) & 0x7FFFu;
+        neg = (op.sign0 < 0) ^ ((e >> 31) != 0);
+    } else {
+        ia = ia2 = u;
+        neg = op.sign0 < 0;
+    }
+}
+
+__device__ __forceinline__ void cpair_col(const PairOp &op, const uint32_t *__restrict__ lists,
+                                          int64_t v, int64_t &ib, int64_t &ib2, bool &neg) {
+    if (op.nB >= 0) {
+        const uint32_t e = lists[op.offB + v];
+        ib = e & 0x7FFFu;
+        ib2 = (e >> 15) & 0x7FFFu;
+        neg ^= (e >> 31) != 0;
+    } else {
+        ib = ib2 = v;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_crot(typename C2<R>::T *__restrict__ psi, PairOp op,
+                                              const uint32_t *__restrict__ lists,
+                                              const double *__restrict__ cs, int k, int64_t nsa,
+                                              int64_t nsb) {
+    using V = typename C2<R>::T;
+    const R c = (R)cs[2 * k], s = (R)cs[2 * k + 1];
+    const int64_t na = op.nA >= 0 ? op.nA : nsa, nb = op.nB >= 0 ? op.nB : nsb;
+    for (int64_t u = blockIdx.y; u < na; u += gridDim.y) {
+        int64_t ia, ia2;
+        bool nrow;
+        cpair_row(op, lists, u, ia, ia2, nrow);
+        for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nb;
+             v += (int64_t)gridDim.x * blockDim.x) {
+            int64_t ib, ib2;
+            bool neg = nrow;
+            cpair_col(op, lists, v, ib, ib2, neg);
+            const int64_t xs = ia * nsb + ib, xd = ia2 * nsb + ib2;
+            const R sg = neg ? -s : s;
+            const V a = psi[xs], b = psi[xd];
+            V na_, nb_;
+            na_.x = c * a.x - sg * b.x;
+            na_.y = c * a.y - sg * b.y;
+            nb_.x = c * b.x + sg * a.x;
+            nb_.y = c * b.y + sg * a.y;
+            psi[xs] = na_;
+            psi[xd] = nb_;
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cadj(typename C2<R>::T *__restrict__ psi,
+                                              typename C2<R>::T *__restrict__ lam, PairOp op,
+                                              const uint32_t *__restrict__ lists,
+                                              const double *__restrict__ cs, int k, int64_t nsa,
+                                              int64_t nsb, double *__restrict__ partial) {
+    using V = typename C2<R>::T;
+    const R c = (R)cs[2 * k], s = (R)cs[2 * k + 1];
+    const int64_t na = op.nA >= 0 ? op.nA : nsa, nb = op.nB >= 0 ? op.nB : nsb;
+    double acc = 0.0;
+    for (int64_t u = blockIdx.y; u < na; u += gridDim.y) {
+        int64_t ia, ia2;
+        bool nrow;
+        cpair_row(op, lists, u, ia, ia2, nrow);
+        for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nb;
+             v += (int64_t)gridDim.x * blockDim.x) {
+            int64_t ib, ib2;
+            bool neg = nrow;
+            cpair_col(op, lists, v, ib, ib2, neg);
+            const int64_t xs = ia * nsb + ib, xd = ia2 * nsb + ib2;
+            const V a = psi[xs], b = psi[xd], la = lam[xs], lb = lam[xd];
+            const double o = (double)lb.x * a.x + (double)lb.y * a.y - (double)la.x * b.x -
+                             (double)la.y * b.y;
+            acc += neg ? -o : o;
+            const R sg = neg ? -s : s;
+            V t0, t1;
+            t0.x = c * a.x + sg * b.x;
+            t0.y = c * a.y + sg * b.y;
+            t1.x = c * b.x - sg * a.x;
+            t1.y = c * b.y - sg * a.y;
+            psi[xs] = t0;
+            psi[xd] = t1;
+            t0.x = c * la.x + sg * lb.x;
+            t0.y = c * la.y + sg * lb.y;
+            t1.x = c * lb.x - sg * la.x;
+            t1.y = c * lb.y - sg * la.y;
+            lam[xs] = t0;
+            lam[xd] = t1;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ void k_cvt_f2d(const float2 *__restrict__ in, double2 *__restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = make_double2((double)in[i].x, (double)in[i].y);
+}
+
+__global__ void k_cvt_d2f(const double2 *__restrict__ in, float2 *__restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
 template <typename R, typename Idx>
 hipError_t rot_dispatch(void *psi, const RotOp &op, const double *cs, int k, uint64_t npairs,
                         Shape sh, hipStream_t st) {
@@ -660,6 +793,43 @@ hipError_t launch_combine(double2 *S, const double2 *ST, const double2 *C, doubl
 hipError_t launch_rdm_overlap(const double2 *A, int64_t nrows, int64_t ncols,
                               const uint32_t *exc, int nexc, double2 *O, hipStream_t st) {
     hipLaunchKernelGGL(k_rdm_overlap, dim3((unsigned)nrows), dim3(256), 0, st, A, ncols, exc, nexc, O);
+    return hipGetLastError();
+}
+
+int cadj_blocks(const PairOp &op, int64_t nsa, int64_t nsb) {
+    const CGrid g = cgrid_of(op, nsa, nsb);
+    return (int)(g.gx * g.gy);
+}
+
+hipError_t launch_crot(int precision, void *psi, const PairOp &op, const uint32_t *lists,
+                       const double *cs, int k, int64_t nsa, int64_t nsb, hipStream_t st) {
+    const CGrid g = cgrid_of(op, nsa, nsb);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_crot<double>, dim3(g.gx, g.gy), dim3(g.block), 0, st, (double2 *)psi, op, lists, cs, k, nsa, nsb);
+    else
+        hipLaunchKernelGGL(k_crot<float>, dim3(g.gx, g.gy), dim3(g.block), 0, st, (float2 *)psi, op, lists, cs, k, nsa, nsb);
+    return hipGetLastError();
+}
+
+hipError_t launch_cadj(int precision, void *psi, void *lam, const PairOp &op, const uint32_t *lists,
+                       const double *cs, int k, int64_t nsa, int64_t nsb, double *partial,
+                       hipStream_t st) {
+    const CGrid g = cgrid_of(op, nsa, nsb);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_cadj<double>, dim3(g.gx, g.gy), dim3(g.block), 0, st, (double2 *)psi,
+                           (double2 *)lam, op, lists, cs, k, nsa, nsb, partial);
+    else
+        hipLaunchKernelGGL(k_cadj<float>, dim3(g.gx, g.gy), dim3(g.block), 0, st, (float2 *)psi,
+                           (float2 *)lam, op, lists, cs, k, nsa, nsb, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_cvt(bool to_double, const void *in, void *out, int64_t n, hipStream_t st) {
+    const unsigned grid = blocks_for(n, 256);
+    if (to_double)
+        hipLaunchKernelGGL(k_cvt_f2d, dim3(grid), dim3(256), 0, st, (const float2 *)in, (double2 *)out, n);
+    else
+        hipLaunchKernelGGL(k_cvt_d2f, dim3(grid), dim3(256), 0, st, (const double2 *)in, (float2 *)out, n);
     return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@ from tests.gpu_helpers import dense_from_sector, oracle_energy_grad, oracle_stat
 
 pytestmark = pytest.mark.gpu
 
+ENGINES = ["sector", "dense"]
+
 
 @pytest.fixture(scope="module")
 def fsv(gpu):
@@ -28,12 +30,13 @@ def _np(t):
     return t.cpu().numpy()
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("ordering", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_ansatz_state_c1(fsv, ordering, precision):
+def test_ansatz_state_c1(fsv, ordering, precision, engine):
     p = config("C1", ordering=ordering)
     say("ansatz C1", ordering, precision)
-    plan = fsv.Plan(p, precision=precision)
+    plan = fsv.Plan(p, precision=precision, engine=engine)
     psi = _np(plan.ansatz_apply(p.theta))
     ref = dense.ansatz_state(p.n_qubits, p.n_alpha, p.n_beta, p.ops, p.theta, ordering)
     tol = 1e-13 if precision == 0 else 2e-6
@@ -43,15 +46,16 @@ def test_ansatz_state_c1(fsv, ordering, precision):
 @pytest.mark.parametrize("n,ne,k,seed,ordering", [
     (10, 5, 40, 201, 0), (12, 6, 60, 202, 1), (14, 7, 80, 203, 0), (16, 8, 60, 204, 1),
     (16, 5, 50, 205, 0), (18, 9, 40, 206, 1)])
-def test_ansatz_state_random(fsv, n, ne, k, seed, ordering):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_ansatz_state_random(fsv, n, ne, k, seed, ordering, engine):
     # random draws from the whole pool: every low-qubit position combination occurs
     p = random_problem(n, ne, k, seed=seed, theta_std=0.6, replace=True, ordering=ordering)
     th = p.theta.copy()
     th[::7] = 0.0
     th[1::11] = np.pi / 2
     th[2::13] = -np.pi / 2
-    say("ansatz random", n, ne, k, seed, ordering)
-    plan = fsv.Plan(p)
+    say("ansatz random", n, ne, k, seed, ordering, engine)
+    plan = fsv.Plan(p, engine=engine)
     psi = _np(plan.ansatz_apply(th))
     ref, idx = dense_from_sector(oracle_state(p, th), p)
     assert np.abs(psi - ref).max() < 1e-12
@@ -73,10 +77,11 @@ def test_energy_small_configs(fsv, cfg, ordering):
 
 
 @pytest.mark.parametrize("ordering", [0, 1])
-def test_energy_grad_c2(fsv, ordering):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_energy_grad_c2(fsv, ordering, engine):
     p = config("C2", ordering=ordering)
-    say("energy_grad C2", ordering)
-    plan = fsv.Plan(p)
+    say("energy_grad C2", ordering, engine)
+    plan = fsv.Plan(p, engine=engine)
     e, g = plan.energy_grad(p.theta)
     e_ref, g_ref = oracle_energy_grad(p)
     assert abs(e - e_ref) < 1e-10
@@ -107,10 +112,11 @@ def test_energy_complex_state_and_outside_sector(fsv):
 
 
 @pytest.mark.parametrize("ordering", [0, 1])
-def test_rdm1_and_potential(fsv, ordering):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_rdm1_and_potential(fsv, ordering, engine):
     p = config("C2", ordering=ordering)
-    say("rdm1 + potential", ordering)
-    plan = fsv.Plan(p)
+    say("rdm1 + potential", ordering, engine)
+    plan = fsv.Plan(p, engine=engine)
     psi = plan.ansatz_apply(p.theta)
     gam = plan.rdm1(psi)
     ref = sector.rdm1(oracle_state(p), p.n_orb, p.n_alpha, p.n_beta, ordering)
@@ -128,10 +134,11 @@ def test_rdm1_and_potential(fsv, ordering):
     assert abs(plan.energy(plan.ansatz_apply(p.theta)) - e0) < 1e-12
 
 
-def test_c3_full_size(fsv):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_c3_full_size(fsv, engine):
     p = config("C3")
-    say("C3 full: energy, gradient, 1-RDM")
-    plan = fsv.Plan(p)
+    say("C3 full: energy, gradient, 1-RDM", engine)
+    plan = fsv.Plan(p, engine=engine)
     psi = plan.new_state()
     lam = plan.new_state()
     e, g = plan.energy_grad(p.theta, psi, lam)
@@ -156,7 +163,7 @@ def test_fused_lds_path(fsv, monkeypatch):
     p.theta = p.theta[:len(keep)]
     monkeypatch.setenv("FSV_FORCE_FUSE", "1")
     say("fused LDS path, K =", len(keep))
-    plan = fsv.Plan(p)
+    plan = fsv.Plan(p, engine="dense")
     psi = _np(plan.ansatz_apply(p.theta))
     ref, _ = dense_from_sector(oracle_state(p), p)
     assert np.abs(psi - ref).max() < 1e-12
@@ -165,16 +172,18 @@ def test_fused_lds_path(fsv, monkeypatch):
     assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
 
 
-def test_fp32_variant_c2(fsv):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_fp32_variant_c2(fsv, engine):
     p = config("C2")
-    plan = fsv.Plan(p, precision=1)
+    plan = fsv.Plan(p, precision=1, engine=engine)
     e, g = plan.energy_grad(p.theta)
     e_ref, g_ref = oracle_energy_grad(p)
     say("FP32 |dE| =", abs(e - e_ref), "max|dg| =", np.abs(g - g_ref).max())
     assert abs(e - e_ref) < 1e-4
 
 
-def test_edge_cases(fsv):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_edge_cases(fsv, engine):
     # K = 0, a spin with no electrons, a full shell, the smallest system
     for (n, ne, k) in [(8, 4, 0), (10, 1, 5), (8, 8, 0), (2, 1, 0), (4, 2, 3)]:
         p = random_problem(n, ne, k if k else None, seed=500 + n + ne, theta_std=0.3,
@@ -183,7 +192,7 @@ def test_edge_cases(fsv):
             p.ops = np.zeros((0, 4), dtype=np.int32)
             p.theta = np.zeros(0)
         say("edge", n, ne, len(p.ops))
-        plan = fsv.Plan(p)
+        plan = fsv.Plan(p, engine=engine)
         e, g = plan.energy_grad(p.theta)
         e_ref, g_ref = oracle_energy_grad(p)
         assert abs(e - e_ref) < 1e-10
