@@ -502,8 +502,9 @@ static double overlap_T(const sec_t *S, const int32_t *op, const double *lam, co
  * Energy and gradient by the adjoint method with stored forward states:
  *   psi_k = U_k ... U_1 |ref>, lam_k = U_{k+1}^+ ... U_K^+ H psi_K,
  *   dE/dtheta_k = 2 Re <lam_k| T_k |psi_k>.
- * Forward states are stored every `stride` operators (stride = 1 stores all);
- * states in between are recomputed forward from the last stored one.
+ * The states before operators 0, stride, 2*stride, ... are kept; each
+ * segment's intermediate states are recomputed forward once from its kept
+ * state when the reverse pass reaches it (stride = 1 recomputes one operator).
  */
 int or_energy_grad(int M, int na, int nb, int ordering, const double *h, const double *g,
                    double e_core, int K, const int32_t *ops, const double *theta,
@@ -537,28 +538,25 @@ int or_energy_grad(int M, int na, int nb, int ordering, const double *h, const d
         for (long r = 0; r < dim; ++r) e += psi[2 * r] * lam[2 * r] + psi[2 * r + 1] * lam[2 * r + 1];
         *E = e;
     }
-    if (stride > 1) {
-        seg = (double *)malloc(vb * stride);
-        if (!seg) { rc = -2; goto done; }
-    }
-    for (int k = K - 1; k >= 0; --k) {
-        /* psi_{k+1} (state after op k, 0-based) */
-        const double *pk;
-        if (stride == 1) {
-            if (k + 1 <= K - 1) pk = store[k + 1];
-            else pk = psi;
-        } else {
-            /* recompute the segment that contains k + 1 */
-            int base = ((k + 1) / stride) * stride;
-            if (k + 1 == K) pk = psi;
-            else {
-                memcpy(seg, store[base / stride], vb);
-                for (int t = base; t < k + 1; ++t) rotate(&S, ops + 4 * t, theta[t], seg);
-                pk = seg;
-            }
+    /* Segments [b, e) of `stride` operators, last segment first: the states
+     * after operators b..e-1 are recomputed once from checkpoint b, then the
+     * segment's gradients are taken in reverse order. */
+    seg = (double *)malloc(vb * (size_t)stride);
+    if (!seg) { rc = -2; goto done; }
+    for (int i = (K - 1) / stride; K > 0 && i >= 0; --i) {
+        const int b = i * stride, e = (b + stride < K) ? b + stride : K;
+        memcpy(seg, store[i], vb);
+        rotate(&S, ops + 4 * b, theta[b], seg);
+        for (int t = b + 1; t < e; ++t) {
+            double *dst = seg + (size_t)(t - b) * 2 * dim;
+            memcpy(dst, dst - 2 * dim, vb);
+            rotate(&S, ops + 4 * t, theta[t], dst);
         }
-        grad[k] = 2.0 * overlap_T(&S, ops + 4 * k, lam, pk);
-        rotate(&S, ops + 4 * k, -theta[k], lam);
+        for (int k = e - 1; k >= b; --k) {
+            const double *pk = seg + (size_t)(k - b) * 2 * dim; /* state after operator k */
+            grad[k] = 2.0 * overlap_T(&S, ops + 4 * k, lam, pk);
+            rotate(&S, ops + 4 * k, -theta[k], lam);
+        }
     }
 done:
     if (store) for (int i = 0; i < nstore; ++i) free(store[i]);

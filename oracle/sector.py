@@ -130,8 +130,9 @@ def rdm1(psi, n_orb, n_alpha, n_beta, ordering=0) -> np.ndarray:
 
 
 def energy_grad(n_orb, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, stride=None):
-    """Stored-state adjoint (every `stride`-th forward state kept; default keeps
-    them all when they fit in 4 GiB)."""
+    """Stored-state adjoint: the state before every `stride`-th operator is
+    kept and each segment is recomputed once (default: all states when they fit
+    in 4 GiB, else stride ~ sqrt(K))."""
     ops = _ops(ops)
     theta = np.ascontiguousarray(theta, dtype=np.float64)
     h = np.ascontiguousarray(h, dtype=np.float64)
@@ -140,8 +141,8 @@ def energy_grad(n_orb, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, st
     if stride is None:
         vb = 16 * dim(n_orb, n_alpha, n_beta)
         stride = 1
-        while (k // stride + 1) * vb > (4 << 30):
-            stride *= 2
+        if (k + 2) * vb > (4 << 30):
+            stride = max(1, int(np.ceil(np.sqrt(k))))
     e = ctypes.c_double(0.0)
     grad = np.zeros(k, dtype=np.float64)
     _check(_load().or_energy_grad(n_orb, n_alpha, n_beta, ordering, _dp(h), _dp(g), float(e_core),
