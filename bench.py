@@ -252,7 +252,8 @@ def main():
     if args.tune:
         print(plan.autotune(psi, lam), file=sys.stderr, flush=True)
     mb_dense = model_bytes(p, amp_bytes)
-    mb_sector = sector_model_bytes(p, amp_bytes)
+    # the sector engine stores the (exactly real) state as real FP64 / FP32
+    mb_sector = sector_model_bytes(p, amp_bytes // 2)
     mb = mb_sector if args.engine == "sector" else mb_dense
     roof = roofline_of(mb, stages, k, "k_cadj (sector adjoint step)" if args.engine == "sector"
                        else "k_adj (dense adjoint step)")

@@ -160,10 +160,15 @@ int fsv_finish(fsv_plan *plan, double *E_out, double *grad_out);
  * buffers.  *report (may be NULL) receives a static summary string. */
 int fsv_autotune(fsv_plan *plan, void *psi_dev, void *lam_dev, const char **report);
 
-/* ---- batches: many independent instances in one persistent graph launch ----
+/* ---- batches: many independent instances in one graph launch ----
  * Each instance has its own problem (qubit count, electrons, integrals,
- * operators); all must use the same precision (complex128 only).  The batch
- * keeps each instance's sector state in a device arena that it owns. */
+ * operators; at most 30 qubits); all must use complex128 (precision 0).  The
+ * batch keeps each instance's sector state in a device arena that it owns.
+ * Two launch schemes, chosen by fsv_batch_autotune (or FSV_BATCH_MODE =
+ * persistent | phased at creation): a persistent kernel whose workgroups take
+ * whole instances from a device work queue, largest first; or phased launches
+ * (one per operator index and phase, every instance in each) captured into
+ * one graph.  Results are identical to rounding. */
 int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count, void *hip_stream);
 int fsv_batch_destroy(fsv_batch *batch);
 /* theta_concat: host, sum_i K_i doubles in instance order.  E_out: host,

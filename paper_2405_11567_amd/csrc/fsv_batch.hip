@@ -193,6 +193,159 @@ __global__ __launch_bounds__(1024) void k_batch(
     }
 }
 
+// ------------------------------------------------------- phased mode ----
+// One launch per phase and operator index across all instances: workgroup
+// (x, y) serves instance y, x of gridDim.x slices.  Kernel boundaries order
+// the phases; no workgroup ever waits on another.
+
+__device__ inline double2 sigma_elem(const BInst &I, const double2 *__restrict__ psi, int64_t t,
+                                     const double *__restrict__ gint, const int64_t *__restrict__ hptr,
+                                     const int32_t *__restrict__ hcol, const double *__restrict__ hval,
+                                     const uint32_t *__restrict__ exc) {
+    const int M2 = I.M * I.M;
+    const double *g = gint + I.off_g;
+    const int64_t *pa = hptr + I.off_ha, *pb = hptr + I.off_hb;
+    const uint32_t *ea = exc + I.off_excA, *eb = exc + I.off_excB;
+    const int64_t Ia = t / I.nsb, Ib = t - Ia * I.nsb;
+    const double2 x0 = psi[t];
+    double ar = I.ecore * x0.x, ai = I.ecore * x0.y;
+    for (int64_t q = pa[Ia]; q < pa[Ia + 1]; ++q) {
+        const double v = hval[q];
+        const double2 x = psi[(int64_t)hcol[q] * I.nsb + Ib];
+        ar += v * x.x;
+        ai += v * x.y;
+    }
+    for (int64_t q = pb[Ib]; q < pb[Ib + 1]; ++q) {
+        const double v = hval[q];
+        const double2 x = psi[Ia * I.nsb + hcol[q]];
+        ar += v * x.x;
+        ai += v * x.y;
+    }
+    for (int e = 0; e < I.nexcA; ++e) {
+        const uint32_t wa = ea[Ia * I.nexcA + e];
+        const int64_t Ja = wa & 0xFFFFu;
+        const double *gp = g + ((wa >> 16) & 0x1FFu) * M2;
+        double br = 0.0, bi = 0.0;
+        for (int f = 0; f < I.nexcB; ++f) {
+            const uint32_t wb = eb[Ib * I.nexcB + f];
+            const double gv = (wb >> 31) ? -gp[(wb >> 16) & 0x1FFu] : gp[(wb >> 16) & 0x1FFu];
+            const double2 x = psi[Ja * I.nsb + (wb & 0xFFFFu)];
+            br += gv * x.x;
+            bi += gv * x.y;
+        }
+        if (wa >> 31) {
+            ar -= br;
+            ai -= bi;
+        } else {
+            ar += br;
+            ai += bi;
+        }
+    }
+    return make_double2(ar, ai);
+}
+
+__global__ __launch_bounds__(256) void k_pinit(const BInst *__restrict__ inst, double2 *__restrict__ arena) {
+    const BInst I = inst[blockIdx.y];
+    double2 *psi = arena + I.off_state;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < I.dim;
+         t += (int64_t)gridDim.x * blockDim.x)
+        psi[t] = make_double2(t == I.ref ? 1.0 : 0.0, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_pfwd(const BInst *__restrict__ inst, const BOp *__restrict__ ops,
+                                              const uint32_t *__restrict__ lists,
+                                              const double *__restrict__ cs, double2 *__restrict__ arena,
+                                              int k) {
+    const BInst I = inst[blockIdx.y];
+    if (k >= I.K) return;
+    const BOp op = ops[I.off_ops + k];
+    const double c = cs[2 * (I.off_k + k)], s = cs[2 * (I.off_k + k) + 1];
+    double2 *psi = arena + I.off_state;
+    const int64_t na = op.nA >= 0 ? op.nA : I.nsa, nb = op.nB >= 0 ? op.nB : I.nsb;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na * nb;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t xs, xd;
+        bool neg;
+        pair_of(I, op, lists, t, nb, xs, xd, neg);
+        const double sg = neg ? -s : s;
+        const double2 a = psi[xs], b = psi[xd];
+        psi[xs] = make_double2(c * a.x - sg * b.x, c * a.y - sg * b.y);
+        psi[xd] = make_double2(c * b.x + sg * a.x, c * b.y + sg * a.y);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_psigma(const BInst *__restrict__ inst, const double *__restrict__ gint,
+                                                const int64_t *__restrict__ hptr,
+                                                const int32_t *__restrict__ hcol,
+                                                const double *__restrict__ hval,
+                                                const uint32_t *__restrict__ exc,
+                                                double2 *__restrict__ arena, double *__restrict__ epart) {
+    __shared__ double red[256 / kWave];
+    const BInst I = inst[blockIdx.y];
+    const double2 *psi = arena + I.off_state;
+    double2 *lam = arena + I.off_state + I.dim;
+    double acc = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < I.dim;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = sigma_elem(I, psi, t, gint, hptr, hcol, hval, exc);
+        lam[t] = v;
+        const double2 x0 = psi[t];
+        acc += x0.x * v.x + x0.y * v.y;
+    }
+    acc = bsum(acc, red);
+    if (threadIdx.x == 0) epart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_prev(const BInst *__restrict__ inst, const BOp *__restrict__ ops,
+                                              const uint32_t *__restrict__ lists,
+                                              const double *__restrict__ cs, double2 *__restrict__ arena,
+                                              int k, double *__restrict__ gpart) {
+    __shared__ double red[256 / kWave];
+    const BInst I = inst[blockIdx.y];
+    if (k >= I.K) return;  // uniform across the workgroup
+    const BOp op = ops[I.off_ops + k];
+    const double c = cs[2 * (I.off_k + k)], s = cs[2 * (I.off_k + k) + 1];
+    double2 *psi = arena + I.off_state;
+    double2 *lam = psi + I.dim;
+    const int64_t na = op.nA >= 0 ? op.nA : I.nsa, nb = op.nB >= 0 ? op.nB : I.nsb;
+    double acc = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na * nb;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t xs, xd;
+        bool neg;
+        pair_of(I, op, lists, t, nb, xs, xd, neg);
+        const double2 a = psi[xs], b = psi[xd], la = lam[xs], lb = lam[xd];
+        const double o = lb.x * a.x + lb.y * a.y - la.x * b.x - la.y * b.y;
+        acc += neg ? -o : o;
+        const double sg = neg ? -s : s;
+        psi[xs] = make_double2(c * a.x + sg * b.x, c * a.y + sg * b.y);
+        psi[xd] = make_double2(c * b.x - sg * a.x, c * b.y - sg * a.y);
+        lam[xs] = make_double2(c * la.x + sg * lb.x, c * la.y + sg * lb.y);
+        lam[xd] = make_double2(c * lb.x - sg * la.x, c * lb.y - sg * la.y);
+    }
+    acc = bsum(acc, red);
+    if (threadIdx.x == 0) gpart[(I.off_k + k) * gridDim.x + blockIdx.x] = acc;
+}
+
+// Ordered per-instance sums of the partials: E and 2 * per-operator sums.
+__global__ __launch_bounds__(64) void k_preduce(const BInst *__restrict__ inst, int gx,
+                                                const double *__restrict__ epart,
+                                                const double *__restrict__ gpart,
+                                                double *__restrict__ grad, double *__restrict__ eout) {
+    const int y = blockIdx.x;
+    const BInst I = inst[y];
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int x = 0; x < gx; ++x) e += epart[(int64_t)y * gx + x];
+        eout[y] = e;
+    }
+    for (int k = threadIdx.x; k < I.K; k += blockDim.x) {
+        double s = 0.0;
+        for (int x = 0; x < gx; ++x) s += gpart[(I.off_k + k) * gx + x];
+        grad[I.off_k + k] = 2.0 * s;
+    }
+}
+
 __global__ void k_zero_int(int *p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
@@ -232,6 +385,11 @@ struct fsv_batch {
     double2 *d_arena = nullptr;
     double *h_pin = nullptr;  // cs (2 total_k) | grad (total_k) | E (count)
     int block = 256, per_cu = 2, cus = 256;
+    int mode = 1;       // 0 persistent work-queue kernel, 1 phased launches
+    int gx = 32;        // phased mode: workgroups per instance per launch
+    int kmax = 0;
+    double *d_epart = nullptr, *d_gpart = nullptr;
+    size_t part_cap = 0;  // workgroups per instance the partial buffers hold
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;
     ~fsv_batch() {
@@ -255,6 +413,28 @@ namespace {
     } while (0)
 
 int enqueue(fsv_batch &B) {
+    if (B.mode == 1) {
+        const dim3 grid((unsigned)B.gx, (unsigned)B.count);
+        hipLaunchKernelGGL(k_pinit, grid, dim3(256), 0, B.work, B.d_inst, B.d_arena);
+        BHIP(hipGetLastError());
+        for (int k = 0; k < B.kmax; ++k) {
+            hipLaunchKernelGGL(k_pfwd, grid, dim3(256), 0, B.work, B.d_inst, B.d_ops, B.d_lists, B.d_cs,
+                               B.d_arena, k);
+            BHIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_psigma, grid, dim3(256), 0, B.work, B.d_inst, B.d_g, B.d_hptr, B.d_hcol,
+                           B.d_hval, B.d_exc, B.d_arena, B.d_epart);
+        BHIP(hipGetLastError());
+        for (int k = B.kmax - 1; k >= 0; --k) {
+            hipLaunchKernelGGL(k_prev, grid, dim3(256), 0, B.work, B.d_inst, B.d_ops, B.d_lists, B.d_cs,
+                               B.d_arena, k, B.d_gpart);
+            BHIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_preduce, dim3((unsigned)B.count), dim3(64), 0, B.work, B.d_inst, B.gx,
+                           B.d_epart, B.d_gpart, B.d_grad, B.d_e);
+        BHIP(hipGetLastError());
+        return FSV_OK;
+    }
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, B.work, B.d_counter);
     BHIP(hipGetLastError());
     const int grid = std::max(1, std::min(B.count, B.cus * B.per_cu));
@@ -332,6 +512,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     B->count = count;
     B->user = (hipStream_t)hip_stream;
     B->use_graph = std::getenv("FSV_NO_GRAPH") == nullptr;
+    if (const char *m = std::getenv("FSV_BATCH_MODE")) B->mode = std::strcmp(m, "persistent") == 0 ? 0 : 1;
 
     std::vector<BOp> ops;
     std::vector<uint32_t> lists, excs;
@@ -394,6 +575,8 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         B->inst.push_back(I);
     }
     B->total_k = kk;
+    for (int i = 0; i < count; ++i) B->kmax = std::max(B->kmax, problems[i].n_ops);
+    B->part_cap = 64;
     B->order.resize(count);
     std::iota(B->order.begin(), B->order.end(), 0);
     std::stable_sort(B->order.begin(), B->order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -427,7 +610,9 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         (rc = dmalloc(o, &B->d_cs, 2 * (size_t)kk)) || (rc = dmalloc(o, &B->d_g, gall.size())) ||
         (rc = dmalloc(o, &B->d_hval, hval.size())) || (rc = dmalloc(o, &B->d_hptr, hptr.size())) ||
         (rc = dmalloc(o, &B->d_hcol, hcol.size())) || (rc = dmalloc(o, &B->d_grad, (size_t)kk)) ||
-        (rc = dmalloc(o, &B->d_e, (size_t)count)) || (rc = dmalloc(o, &B->d_arena, (size_t)state)))
+        (rc = dmalloc(o, &B->d_e, (size_t)count)) || (rc = dmalloc(o, &B->d_arena, (size_t)state)) ||
+        (rc = dmalloc(o, &B->d_epart, (size_t)count * B->part_cap)) ||
+        (rc = dmalloc(o, &B->d_gpart, (size_t)kk * B->part_cap)))
         return fin(rc);
     B->bytes = sizeof(BInst) * B->inst.size() + sizeof(int) * (count + 4) + sizeof(BOp) * ops.size() +
                4 * (lists.size() + excs.size()) + 8 * (2 * kk + gall.size() + hval.size() + hptr.size() + kk + count) +
@@ -474,10 +659,16 @@ int fsv_batch_autotune(fsv_batch *B, const char **report) {
         int rc = run(*B, th.data(), e.data(), g.data());  // also leaves valid angles on the device
         if (rc) return rc;
     }
-    const int blocks[] = {256, 512, 1024};
-    const int pers[] = {1, 2, 4};
+    // candidates: persistent kernel (workgroup size x workgroups per CU) and
+    // phased launches (workgroups per instance)
+    struct Cand { int mode, block, per_cu, gx; };
+    std::vector<Cand> cands;
+    for (int blk : {256, 512, 1024})
+        for (int per : {1, 2, 4}) cands.push_back({0, blk, per, B->gx});
+    for (int gx : {8, 16, 32, 64})
+        if ((size_t)gx <= B->part_cap) cands.push_back({1, B->block, B->per_cu, gx});
     float best = 1e30f;
-    int bb = B->block, bp = B->per_cu;
+    Cand bestc{B->mode, B->block, B->per_cu, B->gx};
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
@@ -485,35 +676,41 @@ int fsv_batch_autotune(fsv_batch *B, const char **report) {
     char line[128];
     const bool graph = B->use_graph;
     B->use_graph = false;
-    for (int blk : blocks)
-        for (int per : pers) {
-            B->block = blk;
-            B->per_cu = per;
-            float ms = 0.f;
-            for (int r = 0; r < 2; ++r) {
-                BHIP(hipEventRecord(e0, B->work));
-                int rc = enqueue(*B);
-                if (rc) return rc;
-                BHIP(hipEventRecord(e1, B->work));
-                BHIP(hipEventSynchronize(e1));
-                BHIP(hipEventElapsedTime(&ms, e0, e1));
-            }
-            snprintf(line, sizeof line, "block %d x %d per CU: %.3f ms\n", blk, per, ms);
-            rep += line;
-            if (ms < best) {
-                best = ms;
-                bb = blk;
-                bp = per;
-            }
+    for (const Cand &c : cands) {
+        B->mode = c.mode;
+        B->block = c.block;
+        B->per_cu = c.per_cu;
+        B->gx = c.gx;
+        float ms = 0.f;
+        for (int r = 0; r < 2; ++r) {
+            BHIP(hipEventRecord(e0, B->work));
+            int rc = enqueue(*B);
+            if (rc) return rc;
+            BHIP(hipEventRecord(e1, B->work));
+            BHIP(hipEventSynchronize(e1));
+            BHIP(hipEventElapsedTime(&ms, e0, e1));
         }
+        if (c.mode == 0)
+            snprintf(line, sizeof line, "persistent: block %d x %d per CU: %.3f ms\n", c.block, c.per_cu, ms);
+        else
+            snprintf(line, sizeof line, "phased: %d workgroups per instance: %.3f ms\n", c.gx, ms);
+        rep += line;
+        if (ms < best) {
+            best = ms;
+            bestc = c;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     B->use_graph = graph;
-    B->block = bb;
-    B->per_cu = bp;
+    B->mode = bestc.mode;
+    B->block = bestc.block;
+    B->per_cu = bestc.per_cu;
+    B->gx = bestc.gx;
     if (B->graph) (void)hipGraphExecDestroy(B->graph);
     B->graph = nullptr;
-    snprintf(line, sizeof line, "chosen block %d x %d per CU\n", bb, bp);
+    snprintf(line, sizeof line, "chosen: %s block %d per_cu %d gx %d\n", bestc.mode ? "phased" : "persistent",
+             bestc.block, bestc.per_cu, bestc.gx);
     rep += line;
     if (report) *report = rep.c_str();
     return FSV_OK;

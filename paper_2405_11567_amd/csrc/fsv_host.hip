@@ -117,6 +117,8 @@ struct fsv_plan {
 
     // sector-compressed engine (default for energy_grad / ansatz_apply)
     int engine = 0;  // 0 sector-compressed, 1 dense
+    int svt = V_F64;  // storage of the sector state: real FP64, or real FP32 for precision 1
+    SectorTabs tabs{};
     std::vector<PairOp> pops;
     uint32_t *d_plists = nullptr;
     int *d_ccount = nullptr;
@@ -494,7 +496,7 @@ int fence_out(fsv_plan &P) {
 // ---- enqueue helpers (no synchronisation; usable under stream capture) ----
 int enq_forward_dense(fsv_plan &P, void *psi) {
     HIPCHECK(launch_fill_zero(psi, ((size_t)1 << P.n) * P.amp_bytes, P.work));
-    HIPCHECK(launch_set_amp(psi, P.precision, P.ref_index, 1.0, P.work));
+    HIPCHECK(launch_set_amp(psi, P.precision == 0 ? V_C128 : V_C64, P.ref_index, 1.0, P.work));
     for (const auto &sg : P.segs) {
         if (sg.fused) {
             HIPCHECK(launch_rot_fused(P.precision, psi, P.d_rot, P.d_cs, sg.k0, sg.k1, P.tile_bits,
@@ -508,22 +510,18 @@ int enq_forward_dense(fsv_plan &P, void *psi) {
     return FSV_OK;
 }
 
-// S = H C on the sector (alpha-first basis) and E = Re<C|S> into d_out[0].
-int enq_sector_sigma(fsv_plan &P, const double2 *C, double2 *S) {
-    HIPCHECK(launch_spmm_rows(P.d_ha_ptr, P.d_ha_col, P.d_ha_val, C, S, P.nsa, P.nsb, P.work));
-    if (P.nexcA > 0 && P.nexcB > 0)
-        HIPCHECK(launch_sigma_ab(P.d_excA, P.nexcA, P.d_excB, P.nexcB, P.d_g, P.M, C, S, P.nsa, P.nsb, P.work));
-    HIPCHECK(launch_transpose(C, P.d_CT, P.nsa, P.nsb, P.work));
-    HIPCHECK(launch_spmm_rows(P.d_hb_ptr, P.d_hb_col, P.d_hb_val, P.d_CT, P.d_ST, P.nsb, P.nsa, P.work));
-    HIPCHECK(launch_combine(S, P.d_ST, C, P.ecore, P.nsa, P.nsb, P.d_epart, P.work));
+// S = H C on the sector (alpha-first basis, complex or real FP64) and
+// E = Re<C|S> into d_out[0].
+int enq_sector_sigma(fsv_plan &P, bool cplex, const void *C, void *S) {
+    HIPCHECK(launch_sector_sigma(cplex, P.tabs, C, S, P.d_CT, P.d_ST, P.d_epart, P.work));
     HIPCHECK(launch_reduce_rows(P.d_epart, P.d_ecount, 0, 1, 1.0, P.d_out, P.work));
     return FSV_OK;
 }
 
-// lam == nullptr: energy only (no dense write of H psi).
+// Dense input: gather the complex sector, H on it; lam == nullptr: energy only.
 int enq_sigma_dense(fsv_plan &P, const void *psi, void *lam) {
     HIPCHECK(launch_gather(P.precision, psi, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.d_C, P.work));
-    int rc = enq_sector_sigma(P, P.d_C, P.d_S);
+    int rc = enq_sector_sigma(P, true, P.d_C, P.d_S);
     if (rc) return rc;
     if (lam) {
         HIPCHECK(launch_fill_zero(lam, ((size_t)1 << P.n) * P.amp_bytes, P.work));
@@ -542,34 +540,32 @@ int enq_reverse_dense(fsv_plan &P, void *psi, void *lam) {
 }
 
 // ---- sector-compressed engine: the state is C[Ia][Ib] in the first
-// nsa*nsb amplitudes of the caller's buffer (complex128 or complex64) ----
+// nsa*nsb amplitudes of the caller's buffer.  With real angles and real
+// integrals every amplitude stays real, so it is stored real (FP64 or FP32). ----
 int enq_forward_sector(fsv_plan &P, void *c) {
-    HIPCHECK(launch_fill_zero(c, (size_t)P.dim * P.amp_bytes, P.work));
+    HIPCHECK(launch_fill_zero(c, (size_t)P.dim * vtype_bytes(P.svt), P.work));
     // The reference is string 0 x string 0.  Its alpha-first amplitude carries
     // the ordering sign so that the dense image starts at exactly +1 |ref>.
-    HIPCHECK(launch_set_amp(c, P.precision, 0, P.ref_phase, P.work));
+    HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
     for (int k = 0; k < P.K; ++k)
-        HIPCHECK(launch_crot(P.precision, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
+        HIPCHECK(launch_crot(P.svt, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
     return FSV_OK;
 }
 
-// lam_c == nullptr: energy only.
+// lam_c == nullptr: energy only.  FP32 states are widened for the product.
 int enq_sigma_sector(fsv_plan &P, const void *c, void *lam_c) {
-    if (P.precision == 0) {
-        double2 *S = lam_c ? (double2 *)lam_c : P.d_S;
-        return enq_sector_sigma(P, (const double2 *)c, S);
-    }
-    HIPCHECK(launch_cvt(true, c, P.d_C, P.dim, P.work));
-    int rc = enq_sector_sigma(P, P.d_C, P.d_S);
+    if (P.svt == V_F64) return enq_sector_sigma(P, false, c, lam_c ? lam_c : (void *)P.d_S);
+    HIPCHECK(launch_convert(V_F32, c, V_F64, P.d_C, P.dim, P.work));
+    int rc = enq_sector_sigma(P, false, P.d_C, P.d_S);
     if (rc) return rc;
-    if (lam_c) HIPCHECK(launch_cvt(false, P.d_S, lam_c, P.dim, P.work));
+    if (lam_c) HIPCHECK(launch_convert(V_F64, P.d_S, V_F32, lam_c, P.dim, P.work));
     return FSV_OK;
 }
 
 int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
     const int G = max_grid();
     for (int k = P.K - 1; k >= 0; --k)
-        HIPCHECK(launch_cadj(P.precision, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
+        HIPCHECK(launch_cadj(P.svt, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
                              P.d_gpart + (size_t)k * G, P.work));
     HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_ccount, G, P.K, 2.0, P.d_out + 1, P.work));
     return FSV_OK;
@@ -593,13 +589,13 @@ int enq_ansatz_dense_out(fsv_plan &P, void *psi) {
     if (P.engine != 0) return enq_forward_dense(P, psi);
     int rc = enq_forward_sector(P, P.d_S);
     if (rc) return rc;
-    const double2 *S = P.d_S;
-    if (P.precision != 0) {
-        HIPCHECK(launch_cvt(true, P.d_S, P.d_C, P.dim, P.work));
-        S = P.d_C;
+    const double *S = (const double *)P.d_S;
+    if (P.svt == V_F32) {
+        HIPCHECK(launch_convert(V_F32, P.d_S, V_F64, P.d_C, P.dim, P.work));
+        S = (const double *)P.d_C;
     }
     HIPCHECK(launch_fill_zero(psi, ((size_t)1 << P.n) * P.amp_bytes, P.work));
-    HIPCHECK(launch_scatter(P.precision, psi, S, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.work));
+    HIPCHECK(launch_scatter_real(P.precision, psi, S, P.d_Xa, P.d_Xb, P.d_sa, P.d_PPb, P.nsa, P.nsb, P.work));
     return FSV_OK;
 }
 
@@ -815,6 +811,8 @@ int build_device(fsv_plan &P) {
     if ((rc = upload(P, P.d_hb_ptr, P.hb_ptr.data(), P.hb_ptr.size()))) return rc;
     if ((rc = upload(P, P.d_hb_col, P.hb_col.data(), P.hb_col.size()))) return rc;
     if ((rc = upload(P, P.d_hb_val, P.hb_val.data(), P.hb_val.size()))) return rc;
+    P.tabs = SectorTabs{P.nsa, P.nsb, M, P.nexcA, P.nexcB, P.d_ha_ptr, P.d_hb_ptr, P.d_ha_col,
+                        P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_g, P.ecore};
     return FSV_OK;
 }
 
@@ -850,6 +848,7 @@ int fsv_plan_create(fsv_plan **out, const fsv_problem *p, void *hip_stream) {
     P->K = p->n_ops;
     P->ecore = p->e_core;
     P->amp_bytes = p->precision == 0 ? 16 : 8;
+    P->svt = p->precision == 0 ? V_F64 : V_F32;
     P->wide = P->n > 31;
     const size_t M2 = (size_t)P->M * P->M;
     P->h.assign(p->h, p->h + M2);
@@ -1019,7 +1018,7 @@ int rdm1(fsv_plan *P, const void *psi, double *gamma_out) {
     } else {
         HIPCHECK(launch_fill_zero(P->d_gamma, sizeof(double2) * M2, st));
     }
-    HIPCHECK(launch_transpose(P->d_C, P->d_CT, P->nsa, P->nsb, st));
+    HIPCHECK(launch_ctranspose(true, P->d_C, P->d_CT, P->nsa, P->nsb, st));
     if (P->nexcB > 0) {
         HIPCHECK(launch_rdm_overlap(P->d_CT, P->nsb, P->nsa, P->d_excB, P->nexcB, P->d_O, st));
         HIPCHECK(launch_rdm_bin(P->d_O, P->d_binB_off, P->d_binB_idx, M2, P->d_gamma + M2, st));

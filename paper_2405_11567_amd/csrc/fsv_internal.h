@@ -68,7 +68,7 @@ PairOp build_pair_op(int M, const int32_t *op, const std::vector<uint32_t> &sa,
 // ---- launchers (fsv_kernels.hip) ----
 // precision: 0 complex128, 1 complex64.  Each returns the hipError_t of the launch.
 int max_grid();
-void init_kernels();  // once per process, before any capture
+void init_kernels();  // once per process, before any capture (sets kernel attributes)
 
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
 hipError_t launch_set_amp(void *psi, int precision, uint64_t x, double re, hipStream_t st);
@@ -97,30 +97,48 @@ hipError_t launch_gather(int precision, const void *psi, const uint64_t *Xa, con
 hipError_t launch_scatter(int precision, void *lam, const double2 *S, const uint64_t *Xa,
                           const uint64_t *Xb, const uint32_t *sa, const uint32_t *PPb,
                           int64_t nsa, int64_t nsb, hipStream_t st);
-hipError_t launch_spmm_rows(const int64_t *rowptr, const int32_t *col, const double *val,
-                            const double2 *in, double2 *out, int64_t nrows, int64_t ncols,
-                            hipStream_t st);
-hipError_t launch_sigma_ab(const uint32_t *excA, int nexcA, const uint32_t *excB, int nexcB,
-                           const double *g, int M, const double2 *C, double2 *S, int64_t nsa,
-                           int64_t nsb, hipStream_t st);
-hipError_t launch_transpose(const double2 *in, double2 *out, int64_t rows, int64_t cols,
-                            hipStream_t st);
-// S[Ia][Ib] += ST[Ib][Ia] + ecore * C[Ia][Ib]; per-block partials of Re<C|S>.
-unsigned combine_grid(int64_t dim);
-hipError_t launch_combine(double2 *S, const double2 *ST, const double2 *C, double ecore,
-                          int64_t nsa, int64_t nsb, double *partial, hipStream_t st);
 hipError_t launch_rdm_overlap(const double2 *A, int64_t nrows, int64_t ncols,
                               const uint32_t *exc, int nexc, double2 *O, hipStream_t st);
 hipError_t launch_rdm_bin(const double2 *O, const int32_t *off, const int32_t *idx, int nbins,
                           double2 *out, hipStream_t st);
 
-// sector-compressed engine (state C[Ia][Ib], complex128 or complex64)
+// ---- sector-compressed kernels (fsv_sigma.hip) ----
+// Amplitude storage of a compact sector vector.
+enum VType { V_C128 = 0, V_C64 = 1, V_F64 = 2, V_F32 = 3 };
+inline int vtype_bytes(int vt) { return vt == V_C128 ? 16 : (vt == V_F32 ? 4 : 8); }
+
+// Device tables of one sector Hamiltonian (alpha-first basis).
+struct SectorTabs {
+    int64_t nsa, nsb;
+    int M, nexcA, nexcB;
+    const int64_t *ha_ptr, *hb_ptr;
+    const int32_t *ha_col, *hb_col;
+    const double *ha_val, *hb_val;
+    const uint32_t *excA, *excB;
+    const double *g;
+    double ecore;
+};
+
 int cadj_blocks(const PairOp &op, int64_t nsa, int64_t nsb);  // partials written by launch_cadj
-hipError_t launch_crot(int precision, void *psi, const PairOp &op, const uint32_t *lists,
+hipError_t launch_crot(int vtype, void *psi, const PairOp &op, const uint32_t *lists,
                        const double *cs, int k, int64_t nsa, int64_t nsb, hipStream_t st);
-hipError_t launch_cadj(int precision, void *psi, void *lam, const PairOp &op, const uint32_t *lists,
+hipError_t launch_cadj(int vtype, void *psi, void *lam, const PairOp &op, const uint32_t *lists,
                        const double *cs, int k, int64_t nsa, int64_t nsb, double *partial,
                        hipStream_t st);
-hipError_t launch_cvt(bool to_double, const void *in, void *out, int64_t n, hipStream_t st);
+// out (vtype_out) <- in (vtype_in), element-wise; complex <-> real keeps the real part.
+hipError_t launch_convert(int vt_in, const void *in, int vt_out, void *out, int64_t n, hipStream_t st);
+// S = H C on the sector; C, S, CT, ST hold nsa*nsb values of type complex
+// (cplex) or real double.  Writes combine_grid(nsa*nsb) partials of Re<C|S>.
+unsigned combine_grid(int64_t dim);
+hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, void *S, void *CT,
+                               void *ST, double *epart, hipStream_t st);
+// Transpose of a compact vector (rows x cols -> cols x rows), complex or real.
+hipError_t launch_ctranspose(bool cplex, const void *in, void *out, int64_t rows, int64_t cols,
+                             hipStream_t st);
+// Real compact vector (double) -> dense complex buffer, like launch_scatter.
+hipError_t launch_scatter_real(int precision, void *lam, const double *S, const uint64_t *Xa,
+                               const uint64_t *Xb, const uint32_t *sa, const uint32_t *PPb,
+                               int64_t nsa, int64_t nsb, hipStream_t st);
+void init_sigma_kernels();
 
 }  // namespace fsv

@@ -1,0 +1,480 @@
+// Kernels of the sector-compressed state C[Ia][Ib] (alpha-string-first
+// product basis): excitation rotations and the adjoint step over alpha x beta
+// pair lists, the Hamiltonian product H C, and conversions.  Every kernel is
+// templated on the stored amplitude: complex or real, FP64 or FP32.  A state
+// built from the reference with real angles and real integrals is exactly
+// real, which halves every byte and flop of the energy/gradient pass.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fsv_device.h"
+#include "fsv_internal.h"
+
+namespace fsv {
+
+namespace {
+
+// ---- amplitude arithmetic (accumulations in FP64) ----
+template <typename V> struct Vt;
+template <> struct Vt<double2> { using R = double; using A = double2; };
+template <> struct Vt<float2> { using R = float; using A = double2; };
+template <> struct Vt<double> { using R = double; using A = double; };
+template <> struct Vt<float> { using R = float; using A = double; };
+
+// (a, b) <- (c a - s b, c b + s a)
+__device__ __forceinline__ void rot(double &a, double &b, double c, double s) {
+    const double t = a;
+    a = c * a - s * b;
+    b = c * b + s * t;
+}
+__device__ __forceinline__ void rot(float &a, float &b, float c, float s) {
+    const float t = a;
+    a = c * a - s * b;
+    b = c * b + s * t;
+}
+__device__ __forceinline__ void rot(double2 &a, double2 &b, double c, double s) {
+    rot(a.x, b.x, c, s);
+    rot(a.y, b.y, c, s);
+}
+__device__ __forceinline__ void rot(float2 &a, float2 &b, float c, float s) {
+    rot(a.x, b.x, c, s);
+    rot(a.y, b.y, c, s);
+}
+// Re(conj(l) p)
+__device__ __forceinline__ double dotre(double l, double p) { return l * p; }
+__device__ __forceinline__ double dotre(float l, float p) { return (double)l * p; }
+__device__ __forceinline__ double dotre(double2 l, double2 p) { return l.x * p.x + l.y * p.y; }
+__device__ __forceinline__ double dotre(float2 l, float2 p) { return (double)l.x * p.x + (double)l.y * p.y; }
+// acc += w x
+__device__ __forceinline__ void axpy(double &acc, double w, double x) { acc += w * x; }
+__device__ __forceinline__ void axpy(double2 &acc, double w, double2 x) {
+    acc.x += w * x.x;
+    acc.y += w * x.y;
+}
+template <typename A> __device__ __forceinline__ A zero();
+template <> __device__ __forceinline__ double zero<double>() { return 0.0; }
+template <> __device__ __forceinline__ double2 zero<double2>() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double neg_if(bool n, double v) { return n ? -v : v; }
+__device__ __forceinline__ double2 neg_if(bool n, double2 v) { return n ? make_double2(-v.x, -v.y) : v; }
+__device__ __forceinline__ double add(double a, double b) { return a + b; }
+__device__ __forceinline__ double2 add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// ---- conversions ----
+__device__ __forceinline__ void cvt(double a, double &b) { b = a; }
+__device__ __forceinline__ void cvt(double a, float &b) { b = (float)a; }
+__device__ __forceinline__ void cvt(float a, double &b) { b = a; }
+__device__ __forceinline__ void cvt(double a, double2 &b) { b = make_double2(a, 0.0); }
+__device__ __forceinline__ void cvt(double2 a, double2 &b) { b = a; }
+__device__ __forceinline__ void cvt(double2 a, float2 &b) { b = make_float2((float)a.x, (float)a.y); }
+__device__ __forceinline__ void cvt(float2 a, double2 &b) { b = make_double2(a.x, a.y); }
+__device__ __forceinline__ void cvt(double2 a, double &b) { b = a.x; }
+
+template <typename I, typename O>
+__global__ void k_convert(const I *__restrict__ in, O *__restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        cvt(in[i], out[i]);
+}
+
+// ------------------------------------------------------------ rotations ----
+struct CGrid {
+    unsigned gx, gy, block;
+};
+
+inline CGrid cgrid_of(const PairOp &op, int64_t nsa, int64_t nsb) {
+    const int64_t na = op.nA >= 0 ? op.nA : nsa, nb = op.nB >= 0 ? op.nB : nsb;
+    CGrid g;
+    g.block = nb <= 64 ? 64u : (nb <= 128 ? 128u : 256u);
+    const int64_t gy = na < 1024 ? (na > 0 ? na : 1) : 1024;
+    int64_t gx = (nb + g.block - 1) / g.block;
+    const int64_t cap = kMaxGrid / gy > 0 ? kMaxGrid / gy : 1;
+    if (gx > cap) gx = cap;
+    if (gx < 1) gx = 1;
+    g.gx = (unsigned)gx;
+    g.gy = (unsigned)gy;
+    return g;
+}
+
+// Alpha pair u of the operator (row u when it has no alpha part).
+__device__ __forceinline__ void pair_row(const PairOp &op, const uint32_t *__restrict__ lists,
+                                         int64_t u, int64_t &ia, int64_t &ia2, bool &neg) {
+    if (op.nA >= 0) {
+        const uint32_t e = lists[op.offA + u];
+        ia = e & 0x7FFFu;
+        ia2 = (e >> 15) & 0x7FFFu;
+        neg = (op.sign0 < 0) ^ ((e >> 31) != 0);
+    } else {
+        ia = ia2 = u;
+        neg = op.sign0 < 0;
+    }
+}
+
+// Beta pair v (column v when it has no beta part).
+__device__ __forceinline__ void pair_col(const PairOp &op, const uint32_t *__restrict__ lists,
+                                         int64_t v, int64_t &ib, int64_t &ib2, bool &neg) {
+    if (op.nB >= 0) {
+        const uint32_t e = lists[op.offB + v];
+        ib = e & 0x7FFFu;
+        ib2 = (e >> 15) & 0x7FFFu;
+        neg ^= (e >> 31) != 0;
+    } else {
+        ib = ib2 = v;
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_crot(V *__restrict__ psi, PairOp op,
+                                              const uint32_t *__restrict__ lists,
+                                              const double *__restrict__ cs, int k, int64_t nsa,
+                                              int64_t nsb) {
+    using R = typename Vt<V>::R;
+    const R c = (R)cs[2 * k], s = (R)cs[2 * k + 1];
+    const int64_t na = op.nA >= 0 ? op.nA : nsa, nb = op.nB >= 0 ? op.nB : nsb;
+    for (int64_t u = blockIdx.y; u < na; u += gridDim.y) {
+        int64_t ia, ia2;
+        bool nrow;
+        pair_row(op, lists, u, ia, ia2, nrow);
+        for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nb;
+             v += (int64_t)gridDim.x * blockDim.x) {
+            int64_t ib, ib2;
+            bool neg = nrow;
+            pair_col(op, lists, v, ib, ib2, neg);
+            const int64_t xs = ia * nsb + ib, xd = ia2 * nsb + ib2;
+            V a = psi[xs], b = psi[xd];
+            rot(a, b, c, neg ? -s : s);
+            psi[xs] = a;
+            psi[xd] = b;
+        }
+    }
+}
+
+// Partial of Re<lam|T|psi> over the operator's pairs, then psi, lam <- U^+ psi, U^+ lam.
+template <typename V>
+__global__ __launch_bounds__(256) void k_cadj(V *__restrict__ psi, V *__restrict__ lam, PairOp op,
+                                              const uint32_t *__restrict__ lists,
+                                              const double *__restrict__ cs, int k, int64_t nsa,
+                                              int64_t nsb, double *__restrict__ partial) {
+    using R = typename Vt<V>::R;
+    const R c = (R)cs[2 * k], s = (R)cs[2 * k + 1];
+    const int64_t na = op.nA >= 0 ? op.nA : nsa, nb = op.nB >= 0 ? op.nB : nsb;
+    double acc = 0.0;
+    for (int64_t u = blockIdx.y; u < na; u += gridDim.y) {
+        int64_t ia, ia2;
+        bool nrow;
+        pair_row(op, lists, u, ia, ia2, nrow);
+        for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nb;
+             v += (int64_t)gridDim.x * blockDim.x) {
+            int64_t ib, ib2;
+            bool neg = nrow;
+            pair_col(op, lists, v, ib, ib2, neg);
+            const int64_t xs = ia * nsb + ib, xd = ia2 * nsb + ib2;
+            V a = psi[xs], b = psi[xd], la = lam[xs], lb = lam[xd];
+            const double o = dotre(lb, a) - dotre(la, b);
+            acc += neg ? -o : o;
+            const R sg = neg ? s : -s;  // U^+ = U(-theta)
+            rot(a, b, c, sg);
+            rot(la, lb, c, sg);
+            psi[xs] = a;
+            psi[xd] = b;
+            lam[xs] = la;
+            lam[xd] = lb;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
+// ---------------------------------------------------------------- sigma ----
+// out[I][:] = sum_k val[k] in[col[k]][:].  Blocks are dispatched row-fastest
+// over one column tile at a time (blockIdx.x = row, blockIdx.y = tile), so the
+// workgroups in flight share the input rows of the same tile in L2.
+template <typename A>
+__global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col,
+                                              const double *__restrict__ val, const A *__restrict__ in,
+                                              A *__restrict__ out, int64_t ncols) {
+    const int64_t I = blockIdx.x;
+    const int64_t k0 = rowptr[I], k1 = rowptr[I + 1];
+    const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    A acc = zero<A>();
+    for (int64_t k = k0; k < k1; ++k) axpy(acc, val[k], in[(int64_t)col[k] * ncols + c]);
+    out[I * ncols + c] = acc;
+}
+
+// Alpha-beta two-body term, one workgroup per output row Ia:
+//   S[Ia][Ib] += sum_{e in exc(Ia)} sum_{f in exc(Ib)} s_e s_f (pq_e|rs_f) C[J_e][J_f].
+// The alpha excitations are taken ec at a time.  Their source rows are staged
+// in LDS interleaved as Rt[Jb][e] and their weights as Wt[rs][e] = s_e (pq_e|rs),
+// so each beta excitation of a thread's Ib costs one contiguous LDS read of
+// the ec row values and one of the ec weights.
+template <typename A>
+__global__ __launch_bounds__(512) void k_sigma_ab(const uint32_t *__restrict__ excA, int nexcA,
+                                                  const uint32_t *__restrict__ excB, int nexcB,
+                                                  const double *__restrict__ g, int M,
+                                                  const A *__restrict__ C, A *__restrict__ S,
+                                                  int64_t nsb, int ec) {
+    extern __shared__ double smem_d[];
+    A *Rt = (A *)smem_d;                           // nsb * ec
+    double *Wt = (double *)(Rt + (int64_t)nsb * ec);  // M2 * ec
+    const int64_t Ia = blockIdx.x;
+    const int M2 = M * M;
+    for (int e0 = 0; e0 < nexcA; e0 += ec) {
+        const int ne = min(ec, nexcA - e0);
+        for (int e = 0; e < ne; ++e) {
+            const uint32_t w = excA[Ia * nexcA + e0 + e];
+            const int64_t Ja = w & 0xFFFFu;
+            const int pq = (w >> 16) & 0x1FFu;
+            const double sa = (w >> 31) ? -1.0 : 1.0;
+            for (int64_t jb = threadIdx.x; jb < nsb; jb += blockDim.x) Rt[jb * ec + e] = C[Ja * nsb + jb];
+            for (int rs = threadIdx.x; rs < M2; rs += blockDim.x) Wt[rs * ec + e] = sa * g[pq * M2 + rs];
+        }
+        __syncthreads();
+        for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
+            A acc = zero<A>();
+            for (int f = 0; f < nexcB; ++f) {
+                const uint32_t eb = excB[Ib * nexcB + f];
+                const A *r = Rt + (int64_t)(eb & 0xFFFFu) * ec;
+                const double *wr = Wt + (int)((eb >> 16) & 0x1FFu) * ec;
+                A t = zero<A>();
+                for (int e = 0; e < ne; ++e) axpy(t, wr[e], r[e]);
+                acc = add(acc, neg_if((eb >> 31) != 0, t));
+            }
+            S[Ia * nsb + Ib] = add(S[Ia * nsb + Ib], acc);
+        }
+        __syncthreads();
+    }
+}
+
+// Same term without LDS staging (rows too long for LDS): gathers from global.
+template <typename A>
+__global__ __launch_bounds__(256) void k_sigma_ab_global(const uint32_t *__restrict__ excA, int nexcA,
+                                                         const uint32_t *__restrict__ excB, int nexcB,
+                                                         const double *__restrict__ g, int M,
+                                                         const A *__restrict__ C, A *__restrict__ S,
+                                                         int64_t nsb) {
+    const int64_t Ia = blockIdx.x;
+    const int M2 = M * M;
+    for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
+        A acc = zero<A>();
+        for (int e = 0; e < nexcA; ++e) {
+            const uint32_t w = excA[Ia * nexcA + e];
+            const int64_t Ja = w & 0xFFFFu;
+            const double *gp = g + ((w >> 16) & 0x1FFu) * M2;
+            A t = zero<A>();
+            for (int f = 0; f < nexcB; ++f) {
+                const uint32_t eb = excB[Ib * nexcB + f];
+                const double gv = gp[(eb >> 16) & 0x1FFu];
+                axpy(t, (eb >> 31) ? -gv : gv, C[Ja * nsb + (eb & 0xFFFFu)]);
+            }
+            acc = add(acc, neg_if((w >> 31) != 0, t));
+        }
+        S[Ia * nsb + Ib] = add(S[Ia * nsb + Ib], acc);
+    }
+}
+
+template <typename A>
+__global__ void k_transpose(const A *__restrict__ in, A *__restrict__ out, int64_t rows, int64_t cols) {
+    __shared__ A t[32][33];
+    const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+    for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+        const int64_t r = r0 + j, c = c0 + threadIdx.x;
+        if (r < rows && c < cols) t[j][threadIdx.x] = in[r * cols + c];
+    }
+    __syncthreads();
+    for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+        const int64_t c = c0 + j, r = r0 + threadIdx.x;
+        if (r < rows && c < cols) out[c * rows + r] = t[threadIdx.x][j];
+    }
+}
+
+// S[Ia][Ib] += ST[Ib][Ia] + ecore C[Ia][Ib]; per-block partials of Re<C|S>.
+// The transposed operand is read through an LDS tile.
+template <typename A>
+__global__ void k_combine(A *__restrict__ S, const A *__restrict__ ST, const A *__restrict__ C,
+                          double ecore, int64_t nsa, int64_t nsb, double *__restrict__ partial) {
+    __shared__ A t[32][33];
+    double acc = 0.0;
+    const int64_t tiles_b = (nsb + 31) / 32, tiles = ((nsa + 31) / 32) * tiles_b;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t a0 = (tile / tiles_b) * 32, b0 = (tile % tiles_b) * 32;
+        for (int j = threadIdx.y; j < 32; j += blockDim.y) {  // ST rows b0+j, columns a0+x
+            const int64_t ib = b0 + j, ia = a0 + threadIdx.x;
+            if (ib < nsb && ia < nsa) t[j][threadIdx.x] = ST[ib * nsa + ia];
+        }
+        __syncthreads();
+        for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+            const int64_t ia = a0 + j, ib = b0 + threadIdx.x;
+            if (ia < nsa && ib < nsb) {
+                const A c = C[ia * nsb + ib];
+                A s = S[ia * nsb + ib];
+                s = add(s, t[threadIdx.x][j]);
+                axpy(s, ecore, c);
+                S[ia * nsb + ib] = s;
+                acc += dotre(c, s);
+            }
+        }
+        __syncthreads();
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.x] = acc;
+}
+
+template <typename O>  // O = double2 or float2 (dense complex amplitude)
+__global__ void k_scatter_real(O *__restrict__ lam,
+                               const double *__restrict__ S, const uint64_t *__restrict__ Xa,
+                               const uint64_t *__restrict__ Xb, const uint32_t *__restrict__ sa,
+                               const uint32_t *__restrict__ PPb, int64_t nsb) {
+    const int64_t Ia = blockIdx.y;
+    for (int64_t Ib = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; Ib < nsb;
+         Ib += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = Xa[Ia] | Xb[Ib];
+        const bool neg = popc(sa[Ia] & PPb[Ib]) & 1;
+        const double v = S[Ia * nsb + Ib];
+        lam[x].x = (decltype(lam->x))(neg ? -v : v);
+        lam[x].y = (decltype(lam->x))0;
+    }
+}
+
+int g_lds_max = -1;
+
+template <typename A>
+hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, double *epart, hipStream_t st) {
+    const int64_t nsa = T.nsa, nsb = T.nsb;
+    // same-spin alpha part (with the alpha one-body terms)
+    {
+        const dim3 grid((unsigned)nsa, (unsigned)((nsb + 255) / 256));
+        hipLaunchKernelGGL(k_spmm<A>, grid, dim3(256), 0, st, T.ha_ptr, T.ha_col, T.ha_val, C, S, nsb);
+    }
+    // alpha-beta part
+    if (T.nexcA > 0 && T.nexcB > 0) {
+        const int lds = g_lds_max > 0 ? g_lds_max : 65536;
+        const int64_t per = nsb * (int64_t)sizeof(A) + (int64_t)T.M * T.M * (int64_t)sizeof(double);
+        int64_t ec = lds / per;
+        if (ec > T.nexcA) ec = T.nexcA;
+        if (ec >= 1)
+            hipLaunchKernelGGL(k_sigma_ab<A>, dim3((unsigned)nsa), dim3(512), (size_t)(ec * per), st, T.excA,
+                               T.nexcA, T.excB, T.nexcB, T.g, T.M, C, S, nsb, (int)ec);
+        else  // a source row does not fit in LDS
+            hipLaunchKernelGGL(k_sigma_ab_global<A>, dim3((unsigned)nsa), dim3(256), 0, st, T.excA, T.nexcA,
+                               T.excB, T.nexcB, T.g, T.M, C, S, nsb);
+    }
+    // same-spin beta part on the transpose, then combine
+    {
+        const dim3 grid((unsigned)((nsb + 31) / 32), (unsigned)((nsa + 31) / 32));
+        hipLaunchKernelGGL(k_transpose<A>, grid, dim3(32, 8), 0, st, C, CT, nsa, nsb);
+    }
+    {
+        const dim3 grid((unsigned)nsb, (unsigned)((nsa + 255) / 256));
+        hipLaunchKernelGGL(k_spmm<A>, grid, dim3(256), 0, st, T.hb_ptr, T.hb_col, T.hb_val, CT, ST, nsa);
+    }
+    hipLaunchKernelGGL(k_combine<A>, dim3(combine_grid(nsa * nsb)), dim3(32, 8), 0, st, S, ST, C, T.ecore,
+                       nsa, nsb, epart);
+    return hipGetLastError();
+}
+
+template <typename V>
+hipError_t crot_impl(void *psi, const PairOp &op, const uint32_t *lists, const double *cs, int k,
+                     int64_t nsa, int64_t nsb, hipStream_t st) {
+    const CGrid g = cgrid_of(op, nsa, nsb);
+    hipLaunchKernelGGL(k_crot<V>, dim3(g.gx, g.gy), dim3(g.block), 0, st, (V *)psi, op, lists, cs, k, nsa, nsb);
+    return hipGetLastError();
+}
+
+template <typename V>
+hipError_t cadj_impl(void *psi, void *lam, const PairOp &op, const uint32_t *lists, const double *cs,
+                     int k, int64_t nsa, int64_t nsb, double *partial, hipStream_t st) {
+    const CGrid g = cgrid_of(op, nsa, nsb);
+    hipLaunchKernelGGL(k_cadj<V>, dim3(g.gx, g.gy), dim3(g.block), 0, st, (V *)psi, (V *)lam, op, lists, cs,
+                       k, nsa, nsb, partial);
+    return hipGetLastError();
+}
+
+template <typename I, typename O>
+hipError_t convert_impl(const void *in, void *out, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_convert<I, O>), dim3(blocks_for(n, 256)), dim3(256), 0, st, (const I *)in, (O *)out, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+void init_sigma_kernels() {
+    if (g_lds_max > 0) return;
+    g_lds_max = 65536;
+    const void *fns[] = {(const void *)k_sigma_ab<double>, (const void *)k_sigma_ab<double2>};
+    bool ok = true;
+    for (const void *f : fns)
+        ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840) == hipSuccess;
+    if (ok) g_lds_max = 163840;  // a gfx950 CU's LDS
+    (void)hipGetLastError();
+}
+
+unsigned combine_grid(int64_t dim) {
+    const int64_t tiles = (dim + 1023) / 1024;  // upper bound on 32x32 tiles in use
+    return (unsigned)(tiles < 1 ? 1 : (tiles > 1024 ? 1024 : tiles));
+}
+
+int cadj_blocks(const PairOp &op, int64_t nsa, int64_t nsb) {
+    const CGrid g = cgrid_of(op, nsa, nsb);
+    return (int)(g.gx * g.gy);
+}
+
+hipError_t launch_crot(int vt, void *psi, const PairOp &op, const uint32_t *lists, const double *cs,
+                       int k, int64_t nsa, int64_t nsb, hipStream_t st) {
+    switch (vt) {
+    case V_C128: return crot_impl<double2>(psi, op, lists, cs, k, nsa, nsb, st);
+    case V_C64: return crot_impl<float2>(psi, op, lists, cs, k, nsa, nsb, st);
+    case V_F64: return crot_impl<double>(psi, op, lists, cs, k, nsa, nsb, st);
+    default: return crot_impl<float>(psi, op, lists, cs, k, nsa, nsb, st);
+    }
+}
+
+hipError_t launch_cadj(int vt, void *psi, void *lam, const PairOp &op, const uint32_t *lists,
+                       const double *cs, int k, int64_t nsa, int64_t nsb, double *partial,
+                       hipStream_t st) {
+    switch (vt) {
+    case V_C128: return cadj_impl<double2>(psi, lam, op, lists, cs, k, nsa, nsb, partial, st);
+    case V_C64: return cadj_impl<float2>(psi, lam, op, lists, cs, k, nsa, nsb, partial, st);
+    case V_F64: return cadj_impl<double>(psi, lam, op, lists, cs, k, nsa, nsb, partial, st);
+    default: return cadj_impl<float>(psi, lam, op, lists, cs, k, nsa, nsb, partial, st);
+    }
+}
+
+hipError_t launch_convert(int vi, const void *in, int vo, void *out, int64_t n, hipStream_t st) {
+    if (vi == V_F32 && vo == V_F64) return convert_impl<float, double>(in, out, n, st);
+    if (vi == V_F64 && vo == V_F32) return convert_impl<double, float>(in, out, n, st);
+    if (vi == V_C64 && vo == V_C128) return convert_impl<float2, double2>(in, out, n, st);
+    if (vi == V_C128 && vo == V_C64) return convert_impl<double2, float2>(in, out, n, st);
+    if (vi == V_F64 && vo == V_C128) return convert_impl<double, double2>(in, out, n, st);
+    if (vi == V_C128 && vo == V_F64) return convert_impl<double2, double>(in, out, n, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, void *S, void *CT, void *ST,
+                               double *epart, hipStream_t st) {
+    if (cplex)
+        return sigma_impl<double2>(T, (const double2 *)C, (double2 *)S, (double2 *)CT, (double2 *)ST, epart, st);
+    return sigma_impl<double>(T, (const double *)C, (double *)S, (double *)CT, (double *)ST, epart, st);
+}
+
+hipError_t launch_ctranspose(bool cplex, const void *in, void *out, int64_t rows, int64_t cols, hipStream_t st) {
+    const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+    if (cplex)
+        hipLaunchKernelGGL(k_transpose<double2>, grid, dim3(32, 8), 0, st, (const double2 *)in, (double2 *)out, rows, cols);
+    else
+        hipLaunchKernelGGL(k_transpose<double>, grid, dim3(32, 8), 0, st, (const double *)in, (double *)out, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_real(int precision, void *lam, const double *S, const uint64_t *Xa,
+                               const uint64_t *Xb, const uint32_t *sa, const uint32_t *PPb, int64_t nsa,
+                               int64_t nsb, hipStream_t st) {
+    const unsigned gx = blocks_for(nsb, 256) > 64 ? 64 : blocks_for(nsb, 256);
+    const dim3 grid(gx, (unsigned)nsa);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_scatter_real<double2>, grid, dim3(256), 0, st, (double2 *)lam, S, Xa, Xb, sa, PPb, nsb);
+    else
+        hipLaunchKernelGGL(k_scatter_real<float2>, grid, dim3(256), 0, st, (float2 *)lam, S, Xa, Xb, sa, PPb, nsb);
+    return hipGetLastError();
+}
+
+}  // namespace fsv

@@ -18,7 +18,9 @@ def fsv(gpu):
     return m
 
 
-def test_batch_mixed_small(fsv):
+@pytest.mark.parametrize("mode", ["phased", "persistent"])
+def test_batch_mixed_small(fsv, mode, monkeypatch):
+    monkeypatch.setenv("FSV_BATCH_MODE", mode)
     probs = []
     shapes = [(4, 2, 3), (6, 3, 10), (8, 4, 26), (8, 1, 5), (10, 7, 20), (12, 6, 40), (12, 4, 30),
               (10, 5, 0), (14, 7, 25), (6, 6, 0), (16, 9, 30)]
@@ -40,9 +42,11 @@ def test_batch_mixed_small(fsv):
             assert np.abs(g[i] - g_ref).max() < 1e-9, i
 
 
-def test_batch_c4_full(fsv):
+@pytest.mark.parametrize("mode", ["phased", "persistent"])
+def test_batch_c4_full(fsv, mode, monkeypatch):
+    monkeypatch.setenv("FSV_BATCH_MODE", mode)
     probs = batch_config()
-    say("batch C4: 256 instances")
+    say("batch C4: 256 instances", mode)
     b = fsv.Batch(probs)
     thetas = [p.theta for p in probs]
     e, g = b.energy_grad(thetas)
