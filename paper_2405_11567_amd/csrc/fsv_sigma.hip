@@ -245,6 +245,60 @@ __global__ __launch_bounds__(512) void k_sigma_ab(const uint32_t *__restrict__ e
     }
 }
 
+// Same term with each thread's beta-excitation list held in registers: a
+// workgroup of 1024 threads takes the output columns Ib in groups of 1024;
+// for each group it loads every thread's (J_f, rs_f, s_f) list once, then
+// streams the alpha excitations through LDS ec at a time.  The list is read
+// once per output element instead of once per LDS chunk.  MAXF bounds the
+// number of beta excitations per string (N (M - N + 1)).
+template <typename A, int MAXF, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_sigma_ab_reg(const uint32_t *__restrict__ excA, int nexcA,
+                                                       const uint32_t *__restrict__ excB, int nexcB,
+                                                       const double *__restrict__ g, int M,
+                                                       const A *__restrict__ C, A *__restrict__ S,
+                                                       int64_t nsb, int ec) {
+    extern __shared__ double smem_d[];
+    A *Rt = (A *)smem_d;                              // nsb * ec
+    double *Wt = (double *)(Rt + (int64_t)nsb * ec);  // M2 * ec
+    const int64_t Ia = blockIdx.x;
+    const int M2 = M * M;
+    for (int64_t ib0 = 0; ib0 < nsb; ib0 += blockDim.x) {
+        const int64_t Ib = ib0 + threadIdx.x;
+        const bool active = Ib < nsb;
+        uint32_t ex[MAXF];
+#pragma unroll
+        for (int f = 0; f < MAXF; ++f) ex[f] = (active && f < nexcB) ? excB[Ib * nexcB + f] : 0u;
+        A acc = zero<A>();
+        for (int e0 = 0; e0 < nexcA; e0 += ec) {
+            const int ne = min(ec, nexcA - e0);
+            __syncthreads();  // previous chunk fully consumed
+            for (int e = 0; e < ne; ++e) {
+                const uint32_t w = excA[Ia * nexcA + e0 + e];
+                const int64_t Ja = w & 0xFFFFu;
+                const int pq = (w >> 16) & 0x1FFu;
+                const double sa = (w >> 31) ? -1.0 : 1.0;
+                for (int64_t jb = threadIdx.x; jb < nsb; jb += blockDim.x) Rt[jb * ec + e] = C[Ja * nsb + jb];
+                for (int rs = threadIdx.x; rs < M2; rs += blockDim.x) Wt[rs * ec + e] = sa * g[pq * M2 + rs];
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int f = 0; f < MAXF; ++f) {
+                    if (f < nexcB) {
+                        const uint32_t eb = ex[f];
+                        const A *r = Rt + (int64_t)(eb & 0xFFFFu) * ec;
+                        const double *wr = Wt + (int)((eb >> 16) & 0x1FFu) * ec;
+                        A t = zero<A>();
+                        for (int e = 0; e < ne; ++e) axpy(t, wr[e], r[e]);
+                        acc = add(acc, neg_if((eb >> 31) != 0, t));
+                    }
+                }
+            }
+        }
+        if (active) S[Ia * nsb + Ib] = add(S[Ia * nsb + Ib], acc);
+    }
+}
+
 // Same term without LDS staging (rows too long for LDS): gathers from global.
 template <typename A>
 __global__ __launch_bounds__(256) void k_sigma_ab_global(const uint32_t *__restrict__ excA, int nexcA,
@@ -351,8 +405,17 @@ hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, doubl
         const int64_t per = nsb * (int64_t)sizeof(A) + (int64_t)T.M * T.M * (int64_t)sizeof(double);
         int64_t ec = lds / per;
         if (ec > T.nexcA) ec = T.nexcA;
-        if (ec >= 1)
-            hipLaunchKernelGGL(k_sigma_ab<A>, dim3((unsigned)nsa), dim3(512), (size_t)(ec * per), st, T.excA,
+        const size_t shm = (size_t)(ec * per);
+        // Register-resident lists pay off while each workgroup covers the row
+        // in at most two column groups (the staged rows are reloaded per group).
+        if (ec >= 1 && T.nexcB <= 48 && nsb <= 2048)
+            hipLaunchKernelGGL((k_sigma_ab_reg<A, 48, 1024>), dim3((unsigned)nsa), dim3(1024), shm, st, T.excA,
+                               T.nexcA, T.excB, T.nexcB, T.g, T.M, C, S, nsb, (int)ec);
+        else if (ec >= 1 && T.nexcB <= 64 && nsb <= 1024)
+            hipLaunchKernelGGL((k_sigma_ab_reg<A, 64, 512>), dim3((unsigned)nsa), dim3(512), shm, st, T.excA,
+                               T.nexcA, T.excB, T.nexcB, T.g, T.M, C, S, nsb, (int)ec);
+        else if (ec >= 1)
+            hipLaunchKernelGGL(k_sigma_ab<A>, dim3((unsigned)nsa), dim3(512), shm, st, T.excA,
                                T.nexcA, T.excB, T.nexcB, T.g, T.M, C, S, nsb, (int)ec);
         else  // a source row does not fit in LDS
             hipLaunchKernelGGL(k_sigma_ab_global<A>, dim3((unsigned)nsa), dim3(256), 0, st, T.excA, T.nexcA,
@@ -400,7 +463,11 @@ hipError_t convert_impl(const void *in, void *out, int64_t n, hipStream_t st) {
 void init_sigma_kernels() {
     if (g_lds_max > 0) return;
     g_lds_max = 65536;
-    const void *fns[] = {(const void *)k_sigma_ab<double>, (const void *)k_sigma_ab<double2>};
+    const void *fns[] = {(const void *)k_sigma_ab<double>, (const void *)k_sigma_ab<double2>,
+                         (const void *)k_sigma_ab_reg<double, 48, 1024>,
+                         (const void *)k_sigma_ab_reg<double2, 48, 1024>,
+                         (const void *)k_sigma_ab_reg<double, 64, 512>,
+                         (const void *)k_sigma_ab_reg<double2, 64, 512>};
     bool ok = true;
     for (const void *f : fns)
         ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840) == hipSuccess;
