@@ -119,6 +119,7 @@ struct fsv_plan {
     int engine = 0;  // 0 sector-compressed, 1 dense
     int svt = V_F64;  // storage of the sector state: real FP64, or real FP32 for precision 1
     SectorTabs tabs{};
+    int lr_R = 0;     // rank of the factorised alpha-beta product (0: direct)
     std::vector<PairOp> pops;
     uint32_t *d_plists = nullptr;
     int *d_ccount = nullptr;
@@ -411,9 +412,77 @@ PairOp build_pair_op(int M, const int32_t *op, const std::vector<uint32_t> &sa,
     return o;
 }
 
+// Pivoted Cholesky of a symmetric positive semidefinite n x n matrix G: the
+// largest remaining diagonal is taken as the next pivot until every residual
+// diagonal is below tol * max(diag).  Returns the rank R (L holds R rows of
+// length n, G ~ sum_k L_k L_k^T) or -1 when G is not positive semidefinite
+// within that tolerance.
+int pivoted_cholesky(int n, const double *G, double tol, std::vector<double> &L) {
+    std::vector<double> d(n);
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) {
+        d[i] = G[(size_t)i * n + i];
+        dmax = std::max(dmax, d[i]);
+    }
+    L.clear();
+    if (dmax <= 0.0) return 0;
+    const double cut = tol * dmax;
+    int R = 0;
+    while (R < n) {
+        int p = 0;
+        for (int i = 1; i < n; ++i)
+            if (d[i] > d[p]) p = i;
+        if (d[p] <= cut) break;
+        const double piv = std::sqrt(d[p]);
+        std::vector<double> ell(n);
+        for (int i = 0; i < n; ++i) {
+            double v = G[(size_t)i * n + p];
+            for (int k = 0; k < R; ++k) v -= L[(size_t)k * n + i] * L[(size_t)k * n + p];
+            ell[i] = v / piv;
+        }
+        for (int i = 0; i < n; ++i) d[i] -= ell[i] * ell[i];
+        L.insert(L.end(), ell.begin(), ell.end());
+        ++R;
+    }
+    for (int i = 0; i < n; ++i)
+        if (d[i] < -cut) return -1;
+    return R;
+}
+
 }  // namespace fsv
 
 namespace {
+
+// Choose the factorised alpha-beta product when (pq|rs) has a small exact
+// pivoted-Cholesky rank: per sector element it costs R (e_a + e_b) instead of
+// e_a e_b multiply-adds.  The factorisation must reproduce g to 1e-12 relative.
+void choose_sigma(fsv_plan &P, int &R_out, std::vector<double> &Lt_out) {
+    R_out = 0;
+    const char *mode = std::getenv("FSV_SIGMA");
+    if (mode && std::strcmp(mode, "direct") == 0) return;
+    const int M2 = P.M * P.M;
+    if (P.nexcA <= 0 || P.nexcB <= 0 || P.nexcA > 64 || M2 > 511) return;
+    std::vector<double> L;
+    const int R = pivoted_cholesky(M2, P.g.data(), 1e-14, L);
+    if (R <= 0 || R > 32) return;
+    double gmax = 0.0, err = 0.0;
+    for (int i = 0; i < M2; ++i)
+        for (int j = 0; j < M2; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < R; ++k) v += L[(size_t)k * M2 + i] * L[(size_t)k * M2 + j];
+            gmax = std::max(gmax, std::fabs(P.g[(size_t)i * M2 + j]));
+            err = std::max(err, std::fabs(v - P.g[(size_t)i * M2 + j]));
+        }
+    if (err > 1e-12 * std::max(1.0, gmax)) return;
+    const bool forced = mode && std::strcmp(mode, "lowrank") == 0;
+    if (!forced && (int64_t)R * (P.nexcA + P.nexcB) >= (int64_t)P.nexcA * P.nexcB) return;
+    // one factor row per workgroup LDS line: nsa complex values must fit
+    if (P.nsa * 16 + (int64_t)M2 * 8 > 163840) return;
+    R_out = R;
+    Lt_out.assign((size_t)M2 * R, 0.0);
+    for (int k = 0; k < R; ++k)
+        for (int i = 0; i < M2; ++i) Lt_out[(size_t)i * R + k] = L[(size_t)k * M2 + i];
+}
 
 int upload_hamiltonian_values(fsv_plan &P) {
     std::vector<double> ht(P.h);
@@ -811,8 +880,20 @@ int build_device(fsv_plan &P) {
     if ((rc = upload(P, P.d_hb_ptr, P.hb_ptr.data(), P.hb_ptr.size()))) return rc;
     if ((rc = upload(P, P.d_hb_col, P.hb_col.data(), P.hb_col.size()))) return rc;
     if ((rc = upload(P, P.d_hb_val, P.hb_val.data(), P.hb_val.size()))) return rc;
+    int R = 0;
+    std::vector<double> Lt;
+    choose_sigma(P, R, Lt);
+    double *d_Lt = nullptr;
+    double2 *d_YT = nullptr;
+    if (R > 0) {
+        if ((rc = dalloc(P, &d_Lt, Lt.size()))) return rc;
+        if ((rc = upload(P, d_Lt, Lt.data(), Lt.size()))) return rc;
+        if ((rc = dalloc(P, &d_YT, (size_t)R * P.dim))) return rc;  // complex-sized
+    }
+    P.lr_R = R;
     P.tabs = SectorTabs{P.nsa, P.nsb, M, P.nexcA, P.nexcB, P.d_ha_ptr, P.d_hb_ptr, P.d_ha_col,
-                        P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_g, P.ecore};
+                        P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_g, P.ecore,
+                        R, d_Lt, d_YT};
     return FSV_OK;
 }
 

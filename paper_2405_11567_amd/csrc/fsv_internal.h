@@ -117,6 +117,12 @@ struct SectorTabs {
     const uint32_t *excA, *excB;
     const double *g;
     double ecore;
+    // Optional exact factorisation (pq|rs) = sum_l L[l][pq] L[l][rs] of rank R
+    // (pivoted Cholesky of the pair supermatrix): Lt holds L transposed
+    // (M^2 x R) and YT is an R * nsa * nsb work array.  R = 0: direct product.
+    int R;
+    const double *Lt;
+    void *YT;
 };
 
 int cadj_blocks(const PairOp &op, int64_t nsa, int64_t nsb);  // partials written by launch_cadj

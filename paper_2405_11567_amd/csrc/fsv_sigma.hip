@@ -299,6 +299,87 @@ __global__ __launch_bounds__(BLOCK) void k_sigma_ab_reg(const uint32_t *__restri
     }
 }
 
+// ---- alpha-beta term through the factorisation (pq|rs) = sum_l L_l[pq] L_l[rs] ----
+// With B_l = sum_rs L_l[rs] E^b_rs and A_l = sum_pq L_l[pq] E^a_pq the term is
+// sum_l A_l (C B_l^T).  Step 1 forms Y_l = C B_l^T in the transposed layout
+// YT[l][Ib][Ja] = sum_{f in exc(Ib)} s_f L_l[rs_f] CT[J_f][Ja]: one workgroup
+// per (Ib, column group); the excitation entries and weights are uniform
+// across the workgroup, the CT rows are read coalesced.
+template <typename A, int RMAX>
+__global__ __launch_bounds__(256) void k_lr_beta(const A *__restrict__ CT, A *__restrict__ YT,
+                                                 const uint32_t *__restrict__ excB, int nexcB,
+                                                 const double *__restrict__ Lt, int R, int64_t nsa,
+                                                 int64_t nsb) {
+    const int64_t Ib = blockIdx.x;
+    const int64_t Ja = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    const bool active = Ja < nsa;
+    A acc[RMAX];
+#pragma unroll
+    for (int l = 0; l < RMAX; ++l) acc[l] = zero<A>();
+    for (int f = 0; f < nexcB; ++f) {
+        const uint32_t eb = excB[Ib * nexcB + f];
+        const int64_t Jb = eb & 0xFFFFu;
+        const double *lr = Lt + (int)((eb >> 16) & 0x1FFu) * R;
+        const A x = neg_if((eb >> 31) != 0, active ? CT[Jb * nsa + Ja] : zero<A>());
+#pragma unroll
+        for (int l = 0; l < RMAX; ++l)
+            if (l < R) axpy(acc[l], lr[l], x);
+    }
+    if (active) {
+#pragma unroll
+        for (int l = 0; l < RMAX; ++l)
+            if (l < R) YT[((int64_t)l * nsb + Ib) * nsa + Ja] = acc[l];
+    }
+}
+
+// Step 2: ST[Ib][Ia] += sum_l sum_{e in exc(Ia)} s_e L_l[pq_e] YT[l][Ib][J_e], one
+// workgroup per Ib.  The rows YT[l][Ib][:] are staged in LDS ec at a time
+// (interleaved Rt[Ja][l]), next to the matching columns of L; each thread
+// holds its Ia's alpha-excitation list in registers.
+template <typename A, int MAXE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_lr_alpha(const A *__restrict__ YT, A *__restrict__ ST,
+                                                    const uint32_t *__restrict__ excA, int nexcA,
+                                                    const double *__restrict__ Lt, int R, int M,
+                                                    int64_t nsa, int64_t nsb, int ec) {
+    extern __shared__ double smem_d[];
+    A *Rt = (A *)smem_d;                              // nsa * ec
+    double *Lc = (double *)(Rt + (int64_t)nsa * ec);  // M2 * ec
+    const int64_t Ib = blockIdx.x;
+    const int M2 = M * M;
+    for (int64_t ia0 = 0; ia0 < nsa; ia0 += blockDim.x) {
+        const int64_t Ia = ia0 + threadIdx.x;
+        const bool active = Ia < nsa;
+        uint32_t ex[MAXE];
+#pragma unroll
+        for (int e = 0; e < MAXE; ++e) ex[e] = (active && e < nexcA) ? excA[Ia * nexcA + e] : 0u;
+        A acc = zero<A>();
+        for (int l0 = 0; l0 < R; l0 += ec) {
+            const int nl = min(ec, R - l0);
+            __syncthreads();
+            for (int l = 0; l < nl; ++l) {
+                const A *row = YT + ((int64_t)(l0 + l) * nsb + Ib) * nsa;
+                for (int64_t ja = threadIdx.x; ja < nsa; ja += blockDim.x) Rt[ja * ec + l] = row[ja];
+                for (int pq = threadIdx.x; pq < M2; pq += blockDim.x) Lc[pq * ec + l] = Lt[pq * R + l0 + l];
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < MAXE; ++e) {
+                    if (e < nexcA) {
+                        const uint32_t w = ex[e];
+                        const A *r = Rt + (int64_t)(w & 0xFFFFu) * ec;
+                        const double *lc = Lc + (int)((w >> 16) & 0x1FFu) * ec;
+                        A t = zero<A>();
+                        for (int l = 0; l < nl; ++l) axpy(t, lc[l], r[l]);
+                        acc = add(acc, neg_if((w >> 31) != 0, t));
+                    }
+                }
+            }
+        }
+        if (active) ST[Ib * nsa + Ia] = add(ST[Ib * nsa + Ia], acc);
+    }
+}
+
 // Same term without LDS staging (rows too long for LDS): gathers from global.
 template <typename A>
 __global__ __launch_bounds__(256) void k_sigma_ab_global(const uint32_t *__restrict__ excA, int nexcA,
@@ -399,8 +480,8 @@ hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, doubl
         const dim3 grid((unsigned)nsa, (unsigned)((nsb + 255) / 256));
         hipLaunchKernelGGL(k_spmm<A>, grid, dim3(256), 0, st, T.ha_ptr, T.ha_col, T.ha_val, C, S, nsb);
     }
-    // alpha-beta part
-    if (T.nexcA > 0 && T.nexcB > 0) {
+    // alpha-beta part (direct; the factorised form is applied after the beta part)
+    if (T.nexcA > 0 && T.nexcB > 0 && T.R == 0) {
         const int lds = g_lds_max > 0 ? g_lds_max : 65536;
         const int64_t per = nsb * (int64_t)sizeof(A) + (int64_t)T.M * T.M * (int64_t)sizeof(double);
         int64_t ec = lds / per;
@@ -429,6 +510,32 @@ hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, doubl
     {
         const dim3 grid((unsigned)nsb, (unsigned)((nsa + 255) / 256));
         hipLaunchKernelGGL(k_spmm<A>, grid, dim3(256), 0, st, T.hb_ptr, T.hb_col, T.hb_val, CT, ST, nsa);
+    }
+    if (T.nexcA > 0 && T.nexcB > 0 && T.R > 0) {
+        A *YT = (A *)T.YT;
+        const dim3 g1((unsigned)nsb, (unsigned)((nsa + 255) / 256));
+        if (T.R <= 8)
+            hipLaunchKernelGGL((k_lr_beta<A, 8>), g1, dim3(256), 0, st, CT, YT, T.excB, T.nexcB, T.Lt, T.R, nsa, nsb);
+        else if (T.R <= 16)
+            hipLaunchKernelGGL((k_lr_beta<A, 16>), g1, dim3(256), 0, st, CT, YT, T.excB, T.nexcB, T.Lt, T.R, nsa, nsb);
+        else if (T.R <= 32)
+            hipLaunchKernelGGL((k_lr_beta<A, 32>), g1, dim3(256), 0, st, CT, YT, T.excB, T.nexcB, T.Lt, T.R, nsa, nsb);
+        else
+            return hipErrorInvalidValue;
+        const int lds = g_lds_max > 0 ? g_lds_max : 65536;
+        const int64_t per = nsa * (int64_t)sizeof(A) + (int64_t)T.M * T.M * (int64_t)sizeof(double);
+        int64_t ec = lds / per;
+        if (ec > T.R) ec = T.R;
+        if (ec < 1) return hipErrorInvalidValue;
+        const size_t shm = (size_t)(ec * per);
+        if (T.nexcA <= 48)
+            hipLaunchKernelGGL((k_lr_alpha<A, 48, 1024>), dim3((unsigned)nsb), dim3(1024), shm, st, YT, ST, T.excA,
+                               T.nexcA, T.Lt, T.R, T.M, nsa, nsb, (int)ec);
+        else if (T.nexcA <= 64)
+            hipLaunchKernelGGL((k_lr_alpha<A, 64, 512>), dim3((unsigned)nsb), dim3(512), shm, st, YT, ST, T.excA,
+                               T.nexcA, T.Lt, T.R, T.M, nsa, nsb, (int)ec);
+        else
+            return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k_combine<A>, dim3(combine_grid(nsa * nsb)), dim3(32, 8), 0, st, S, ST, C, T.ecore,
                        nsa, nsb, epart);
@@ -467,7 +574,11 @@ void init_sigma_kernels() {
                          (const void *)k_sigma_ab_reg<double, 48, 1024>,
                          (const void *)k_sigma_ab_reg<double2, 48, 1024>,
                          (const void *)k_sigma_ab_reg<double, 64, 512>,
-                         (const void *)k_sigma_ab_reg<double2, 64, 512>};
+                         (const void *)k_sigma_ab_reg<double2, 64, 512>,
+                         (const void *)k_lr_alpha<double, 48, 1024>,
+                         (const void *)k_lr_alpha<double2, 48, 1024>,
+                         (const void *)k_lr_alpha<double, 64, 512>,
+                         (const void *)k_lr_alpha<double2, 64, 512>};
     bool ok = true;
     for (const void *f : fns)
         ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840) == hipSuccess;

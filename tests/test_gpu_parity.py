@@ -223,3 +223,28 @@ def test_invalid_arguments(fsv):
     with pytest.raises(fsv.FsvError) as ei:
         plan.ansatz_apply(np.full(p.n_ops, np.nan))
     assert ei.value.code == -5
+
+
+@pytest.mark.parametrize("mode", ["direct", "lowrank", "auto"])
+@pytest.mark.parametrize("nfac", [8, 40])
+def test_sigma_paths(fsv, monkeypatch, mode, nfac):
+    # the alpha-beta product directly and through the pivoted-Cholesky factors
+    # of (pq|rs); nfac random symmetric factors set the rank of the supermatrix
+    p = random_problem(14, 7, 40, seed=600 + nfac, theta_std=0.3, replace=True)
+    m = p.n_orb
+    rng = np.random.default_rng(nfac)
+    g = np.zeros((m, m, m, m))
+    for _ in range(nfac):
+        l = rng.normal(0, 0.05, (m, m))
+        l = l + l.T
+        g += np.einsum("pq,rs->pqrs", l, l)
+    p.g = g
+    monkeypatch.setenv("FSV_SIGMA", mode)
+    say("sigma path", mode, nfac)
+    for engine in ENGINES:
+        plan = fsv.Plan(p, engine=engine)
+        e, gr = plan.energy_grad(p.theta)
+        e_ref, g_ref = oracle_energy_grad(p)
+        assert abs(e - e_ref) < 1e-10 and np.abs(gr - g_ref).max() < 1e-9
+        psi = plan.ansatz_apply(p.theta)
+        assert abs(plan.energy(psi) - e_ref) < 1e-10
