@@ -188,7 +188,7 @@ def bench_batch(args):
         "metric": "batched energy+gradient instance-evals/s (256 instances, 10-20 qubits)",
         "value": len(probs) / dt, "unit": "instance-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "C4: 256 instances, qubits uniform in 10..20 (even), electrons "
                                "n/2 +- 2, 50..150 operators each, energy + adjoint gradient",
                    "instances": len(probs), "total_ops": int(sum(p.n_ops for p in probs))},
@@ -290,7 +290,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if args.precision == 0 else "c64",
+        # the sector engine keeps the exactly real state as real numbers
+        "dtype": ({"sector": "f64", "dense": "c128"} if args.precision == 0
+                  else {"sector": "f32", "dense": "c64"})[args.engine],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {p.n_qubits} qubits, {p.n_alpha + p.n_beta} electrons, "
                                f"{k} sampled spin-conserving singles/doubles, energy + adjoint gradient",

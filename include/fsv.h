@@ -162,13 +162,18 @@ int fsv_autotune(fsv_plan *plan, void *psi_dev, void *lam_dev, const char **repo
 
 /* ---- batches: many independent instances in one graph launch ----
  * Each instance has its own problem (qubit count, electrons, integrals,
- * operators; at most 30 qubits); all must use complex128 (precision 0).  The
- * batch keeps each instance's sector state in a device arena that it owns.
+ * operators; at most 24 qubits: larger systems belong in a plan); all must use
+ * precision 0.  Real angles and integrals keep every amplitude real, so the
+ * batch stores each instance's sector state as real FP64 in a device arena
+ * that it owns.  H C runs as one workgroup per (instance, alpha string) with
+ * the row and the alpha-excitation source rows staged in LDS (rows too long
+ * for the LDS budget, or FSV_BATCH_SIGMA=global, read global memory only).
  * Two launch schemes, chosen by fsv_batch_autotune (or FSV_BATCH_MODE =
  * persistent | phased at creation): a persistent kernel whose workgroups take
  * whole instances from a device work queue, largest first; or phased launches
  * (one per operator index and phase, every instance in each) captured into
- * one graph.  Results are identical to rounding. */
+ * one graph.  Results are identical to rounding.  Errors: FSV_EINVAL for an
+ * invalid instance (the message names it), FSV_ENOMEM, FSV_EDEVICE. */
 int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count, void *hip_stream);
 int fsv_batch_destroy(fsv_batch *batch);
 /* theta_concat: host, sum_i K_i doubles in instance order.  E_out: host,
@@ -177,9 +182,11 @@ int fsv_batch_energy_grad(fsv_batch *batch, const double *theta_concat, double *
                           double *grad_concat);
 /* Device bytes the batch owns (arena + tables). */
 size_t fsv_batch_bytes(const fsv_batch *batch);
-/* Launch-shape tuning of the persistent batch kernel (workgroup size and
- * workgroups per CU), timed on this batch; *report (may be NULL) receives a
- * static summary string. */
+/* Autotuner: times every candidate on this batch through its own captured
+ * graph and keeps the fastest: launch scheme, persistent workgroup size and
+ * workgroups per CU, phased workgroups per instance, and the LDS budget of an
+ * H C workgroup (which sets how many alpha excitations it stages per pass).
+ * *report (may be NULL) receives a static summary string. */
 int fsv_batch_autotune(fsv_batch *batch, const char **report);
 
 #ifdef __cplusplus

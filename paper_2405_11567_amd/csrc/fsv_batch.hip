@@ -1,15 +1,23 @@
 // Batched evaluation: many independent instances (own qubit count, electrons,
-// integrals and operators), each getting energy + adjoint gradient, in one
-// persistent kernel launched from a captured HIP graph.
+// integrals and operators), each getting energy + adjoint gradient, from one
+// captured HIP graph.
 //
-// Each instance is processed by one workgroup on its (N_alpha, N_beta) sector
-// only, stored compactly as C[Ia][Ib] in the alpha-string-first product basis
-// (the JW basis of the blocked qubit ordering restricted to the sector).  In
-// that basis an excitation factorises into an alpha part and a beta part:
+// Each instance lives on its (N_alpha, N_beta) sector only, stored compactly
+// as C[Ia][Ib] in the alpha-string-first product basis (the JW basis of the
+// blocked qubit ordering restricted to the sector).  In that basis an
+// excitation factorises into an alpha part and a beta part:
 // tau|Ia Ib> = sign0 * s_a * s_b |Ia' Ib'>, so its active pairs are the
 // product of an alpha pair list and a beta pair list (or "all strings" when
-// the operator has no alpha / beta part).  Workgroups take instances from a
-// device counter in order of decreasing cost.
+// the operator has no alpha / beta part).  Angles and integrals are real, so
+// every amplitude stays real: the arena holds one double per amplitude.
+//
+// H C is evaluated row by row (one alpha string Ia per task):
+//   S[Ia][Ib] = e_core C[Ia][Ib] + sum_J Ha[Ia][J] C[J][Ib] + sum_J Hb[Ib][J] C[Ia][J]
+//             + sum_{e in exc(Ia)} sum_{f in exc(Ib)} s_e s_f (pq_e|rs_f) C[Ja_e][Jb_f]
+// with Ha, Hb the same-spin string Hamiltonians (Slater-Condon rules) and
+// exc(I) the single-excitation lists E_pq|J> = s |I>.  The task stages its own
+// row, the rows C[Ja_e][:] and the weights s_e (pq_e|rs) in LDS, so the
+// alpha-beta double sum reads LDS only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +28,7 @@
 #include <vector>
 
 #include "../../include/fsv.h"
+#include "fsv_device.h"
 #include "fsv_internal.h"
 
 using namespace fsv;
@@ -27,38 +36,40 @@ using namespace fsv;
 namespace {
 
 struct BInst {
-    int32_t M, nsa, nsb, nexcA, nexcB, K, ref, pad;
+    int32_t M, nsa, nsb, nexcA, nexcB, K, ref;
+    int32_t ec;   // alpha excitations staged per LDS pass (even); 0: global-memory sigma
+    int32_t wB;   // width of the beta string Hamiltonian in ELL form
+    int32_t pad;
     int64_t dim;
-    int64_t off_state;  // double2 offset of psi in the arena; lam follows psi
+    int64_t off_state;  // first double of psi in the arena; lam follows psi
     int64_t off_ops;    // first BOp
     int64_t off_k;      // first angle / gradient slot
     int64_t off_g;      // first double of (pq|rs)
-    int64_t off_ha, off_hb;    // first row pointer of the alpha / beta string Hamiltonian
-    int64_t off_excA, off_excB;
+    int64_t off_ha;     // first row pointer of the alpha string Hamiltonian (CSR)
+    int64_t off_hb;     // first entry of the beta string Hamiltonian (ELL, [slot][Ib])
+    int64_t off_excA;   // alpha excitation lists, [Ia][e]
+    int64_t off_excB;   // beta excitation lists transposed, [f][Ib]
+    int64_t off_task;   // first sigma task (row) of this instance
     double ecore;
+};
+
+// Flat device tables of all instances.
+struct BTabs {
+    const double *g;
+    const int64_t *hptr;
+    const int32_t *hcol;
+    const double *hval;
+    const int32_t *ellc;
+    const double *ellv;
+    const uint32_t *excA, *excBT;
 };
 
 using BOp = PairOp;
 
-constexpr int kWave = 64;
-
-__device__ double bsum(double v, double *red) {
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    const int nw = (blockDim.x + kWave - 1) / kWave;
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[w];
-    __syncthreads();
-    return s;
-}
-
 __device__ inline void pair_of(const BInst &I, const BOp &op, const uint32_t *__restrict__ lists,
-                               int64_t t, int64_t nb, int64_t &src, int64_t &dst, bool &neg) {
-    const int64_t u = t / nb, v = t - u * nb;
-    int64_t ia = u, ia2 = u, ib = v, ib2 = v;
+                               uint32_t t, uint32_t nb, int64_t &src, int64_t &dst, bool &neg) {
+    const uint32_t u = t / nb, v = t - u * nb;
+    uint32_t ia = u, ia2 = u, ib = v, ib2 = v;
     bool n = op.sign0 < 0;
     if (op.nA >= 0) {
         const uint32_t e = lists[op.offA + u];
@@ -72,20 +83,121 @@ __device__ inline void pair_of(const BInst &I, const BOp &op, const uint32_t *__
         ib2 = (e >> 15) & 0x7FFFu;
         n ^= (e >> 31) != 0;
     }
-    src = ia * I.nsb + ib;
-    dst = ia2 * I.nsb + ib2;
+    src = (int64_t)ia * I.nsb + ib;
+    dst = (int64_t)ia2 * I.nsb + ib2;
     neg = n;
 }
 
+__device__ inline uint32_t pairs_of(const BInst &I, const BOp &op) {
+    return (uint32_t)(op.nA >= 0 ? op.nA : I.nsa) * (uint32_t)(op.nB >= 0 ? op.nB : I.nsb);
+}
+
+// Row Ia of S = H C; returns this thread's share of sum_Ib C[Ia][Ib] S[Ia][Ib].
+// Called by every thread of the workgroup (it synchronises); lds holds at
+// least 2 nsb + (nsb + M^2) ec doubles when ec > 0.
+__device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C, double *__restrict__ S,
+                            const BTabs &T, double *lds) {
+    const int nsb = I.nsb, bs = blockDim.x, tid = threadIdx.x;
+    const int M2 = I.M * I.M;
+    const double *crowg = C + (int64_t)Ia * nsb;
+    const int64_t *pa = T.hptr + I.off_ha;
+    const int64_t q0 = pa[Ia], q1 = pa[Ia + 1];
+    const int32_t *elc = T.ellc + I.off_hb;
+    const double *elv = T.ellv + I.off_hb;
+    const uint32_t *exa = T.excA + I.off_excA + (int64_t)Ia * I.nexcA;
+    const uint32_t *exb = T.excBT + I.off_excB;
+    const double *g = T.g + I.off_g;
+    double eacc = 0.0;
+    if (I.ec == 0) {  // rows too long for LDS: everything from global memory
+        for (int ib = tid; ib < nsb; ib += bs) {
+            const double x0 = crowg[ib];
+            double a = I.ecore * x0;
+            for (int64_t q = q0; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
+            for (int q = 0; q < I.wB; ++q)
+                a += elv[(int64_t)q * nsb + ib] * crowg[elc[(int64_t)q * nsb + ib]];
+            for (int e = 0; e < I.nexcA; ++e) {
+                const uint32_t wa = exa[e];
+                const double *crj = C + (int64_t)(wa & 0xFFFFu) * nsb;
+                const double *gp = g + (int64_t)((wa >> 16) & 0x1FFu) * M2;
+                double b = 0.0;
+                for (int f = 0; f < I.nexcB; ++f) {
+                    const uint32_t wb = exb[(int64_t)f * nsb + ib];
+                    const double v = gp[(wb >> 16) & 0x1FFu] * crj[wb & 0xFFFFu];
+                    b += (wb >> 31) ? -v : v;
+                }
+                a += (wa >> 31) ? -b : b;
+            }
+            S[(int64_t)Ia * nsb + ib] = a;
+            eacc += x0 * a;
+        }
+        return eacc;
+    }
+    const int ec = I.ec;
+    double *crow = lds, *acc = lds + nsb, *Rt = lds + 2 * nsb, *Wt = Rt + (int64_t)nsb * ec;
+    __syncthreads();  // earlier readers of lds are done
+    for (int j = tid; j < nsb; j += bs) crow[j] = crowg[j];
+    __syncthreads();
+    for (int ib = tid; ib < nsb; ib += bs) {
+        double a = I.ecore * crow[ib];
+        for (int64_t q = q0; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
+        for (int q = 0; q < I.wB; ++q) a += elv[(int64_t)q * nsb + ib] * crow[elc[(int64_t)q * nsb + ib]];
+        acc[ib] = a;
+    }
+    for (int e0 = 0; e0 < I.nexcA; e0 += ec) {
+        const int ne = min(ec, I.nexcA - e0), nep = (ne + 1) & ~1;
+        __syncthreads();  // readers of the previous chunk are done
+        // Rt[Jb][e] = C[Ja_e][Jb] and Wt[rs][e] = s_e (pq_e|rs); an odd chunk is
+        // padded with a zero column so the dot products run over pairs
+        for (int t = tid; t < nep * nsb; t += bs) {
+            const int e = t / nsb, jb = t - e * nsb;
+            double v = 0.0;
+            if (e < ne) v = C[(int64_t)(exa[e0 + e] & 0xFFFFu) * nsb + jb];
+            Rt[jb * ec + e] = v;
+        }
+        for (int t = tid; t < nep * M2; t += bs) {
+            const int e = t / M2, rs = t - e * M2;
+            double v = 0.0;
+            if (e < ne) {
+                const uint32_t wa = exa[e0 + e];
+                v = g[(int64_t)((wa >> 16) & 0x1FFu) * M2 + rs];
+                if (wa >> 31) v = -v;
+            }
+            Wt[rs * ec + e] = v;
+        }
+        __syncthreads();
+        for (int ib = tid; ib < nsb; ib += bs) {
+            double s = 0.0;
+            for (int f = 0; f < I.nexcB; ++f) {
+                const uint32_t wb = exb[(int64_t)f * nsb + ib];
+                const double2 *r = (const double2 *)(Rt + (wb & 0xFFFFu) * ec);
+                const double2 *w = (const double2 *)(Wt + ((wb >> 16) & 0x1FFu) * ec);
+                double d = 0.0;
+                for (int e = 0; e < nep / 2; ++e) {
+                    const double2 x = r[e], y = w[e];
+                    d += x.x * y.x + x.y * y.y;
+                }
+                s += (wb >> 31) ? -d : d;
+            }
+            acc[ib] += s;
+        }
+    }
+    for (int ib = tid; ib < nsb; ib += bs) {  // same thread-to-column map as above
+        S[(int64_t)Ia * nsb + ib] = acc[ib];
+        eacc += crow[ib] * acc[ib];
+    }
+    return eacc;
+}
+
+// ---------------------------------------------------- persistent mode ----
+// Workgroups take whole instances from a device counter (largest first) and
+// run forward sweep, H C and the reverse adjoint sweep with workgroup
+// barriers between operators.
 __global__ __launch_bounds__(1024) void k_batch(
     const BInst *__restrict__ inst, const int *__restrict__ order, int count, int *counter,
     const BOp *__restrict__ ops, const uint32_t *__restrict__ lists, const double *__restrict__ cs,
-    const double *__restrict__ gint, const int64_t *__restrict__ hptr,
-    const int32_t *__restrict__ hcol, const double *__restrict__ hval,
-    const uint32_t *__restrict__ exc, double2 *__restrict__ arena, double *__restrict__ grad,
-    double *__restrict__ eout) {
+    BTabs T, double *__restrict__ arena, double *__restrict__ grad, double *__restrict__ eout) {
+    extern __shared__ double lds[];
     __shared__ int s_idx;
-    __shared__ double red[1024 / kWave];
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
         __syncthreads();
@@ -93,99 +205,51 @@ __global__ __launch_bounds__(1024) void k_batch(
         __syncthreads();
         if (idx >= count) break;  // every wave of the workgroup leaves here
         const BInst I = inst[order[idx]];
-        double2 *psi = arena + I.off_state;
-        double2 *lam = psi + I.dim;
-        const int64_t dim = I.dim;
+        double *psi = arena + I.off_state;
+        double *lam = psi + I.dim;
 
-        for (int64_t t = threadIdx.x; t < dim; t += blockDim.x) psi[t] = make_double2(0.0, 0.0);
-        __syncthreads();
-        if (threadIdx.x == 0) psi[I.ref] = make_double2(1.0, 0.0);
+        for (int64_t t = threadIdx.x; t < I.dim; t += blockDim.x) psi[t] = t == I.ref ? 1.0 : 0.0;
         __syncthreads();
 
-        // forward sweep
-        for (int k = 0; k < I.K; ++k) {
+        for (int k = 0; k < I.K; ++k) {  // forward sweep
             const BOp op = ops[I.off_ops + k];
             const double c = cs[2 * (I.off_k + k)], s = cs[2 * (I.off_k + k) + 1];
-            const int64_t na = op.nA >= 0 ? op.nA : I.nsa, nb = op.nB >= 0 ? op.nB : I.nsb;
-            for (int64_t t = threadIdx.x; t < na * nb; t += blockDim.x) {
+            const uint32_t np = pairs_of(I, op), nb = op.nB >= 0 ? op.nB : I.nsb;
+            for (uint32_t t = threadIdx.x; t < np; t += blockDim.x) {
                 int64_t xs, xd;
                 bool neg;
                 pair_of(I, op, lists, t, nb, xs, xd, neg);
                 const double sg = neg ? -s : s;
-                const double2 a = psi[xs], b = psi[xd];
-                psi[xs] = make_double2(c * a.x - sg * b.x, c * a.y - sg * b.y);
-                psi[xd] = make_double2(c * b.x + sg * a.x, c * b.y + sg * a.y);
+                const double a = psi[xs], b = psi[xd];
+                psi[xs] = c * a - sg * b;
+                psi[xd] = c * b + sg * a;
             }
             __syncthreads();
         }
 
-        // lam = H psi on the sector, and E = Re<psi|lam>
-        const int M2 = I.M * I.M;
-        const double *g = gint + I.off_g;
-        const int64_t *pa = hptr + I.off_ha, *pb = hptr + I.off_hb;
-        const uint32_t *ea = exc + I.off_excA, *eb = exc + I.off_excB;
-        double eacc = 0.0;
-        for (int64_t t = threadIdx.x; t < dim; t += blockDim.x) {
-            const int64_t Ia = t / I.nsb, Ib = t - Ia * I.nsb;
-            const double2 x0 = psi[t];
-            double ar = I.ecore * x0.x, ai = I.ecore * x0.y;
-            for (int64_t q = pa[Ia]; q < pa[Ia + 1]; ++q) {
-                const double v = hval[q];
-                const double2 x = psi[(int64_t)hcol[q] * I.nsb + Ib];
-                ar += v * x.x;
-                ai += v * x.y;
-            }
-            for (int64_t q = pb[Ib]; q < pb[Ib + 1]; ++q) {
-                const double v = hval[q];
-                const double2 x = psi[Ia * I.nsb + hcol[q]];
-                ar += v * x.x;
-                ai += v * x.y;
-            }
-            for (int e = 0; e < I.nexcA; ++e) {
-                const uint32_t wa = ea[Ia * I.nexcA + e];
-                const int64_t Ja = wa & 0xFFFFu;
-                const double *gp = g + ((wa >> 16) & 0x1FFu) * M2;
-                double br = 0.0, bi = 0.0;
-                for (int f = 0; f < I.nexcB; ++f) {
-                    const uint32_t wb = eb[Ib * I.nexcB + f];
-                    const double gv = (wb >> 31) ? -gp[(wb >> 16) & 0x1FFu] : gp[(wb >> 16) & 0x1FFu];
-                    const double2 x = psi[Ja * I.nsb + (wb & 0xFFFFu)];
-                    br += gv * x.x;
-                    bi += gv * x.y;
-                }
-                if (wa >> 31) {
-                    ar -= br;
-                    ai -= bi;
-                } else {
-                    ar += br;
-                    ai += bi;
-                }
-            }
-            lam[t] = make_double2(ar, ai);
-            eacc += x0.x * ar + x0.y * ai;
-        }
-        const double E = bsum(eacc, red);
+        double eacc = 0.0;  // lam = H psi, E = <psi|lam>
+        for (int Ia = 0; Ia < I.nsa; ++Ia) eacc += sigma_row(I, Ia, psi, lam, T, lds);
+        const double E = block_sum(eacc);  // also orders lam before the sweep
 
-        // reverse adjoint sweep
-        for (int k = I.K - 1; k >= 0; --k) {
+        for (int k = I.K - 1; k >= 0; --k) {  // reverse adjoint sweep
             const BOp op = ops[I.off_ops + k];
             const double c = cs[2 * (I.off_k + k)], s = cs[2 * (I.off_k + k) + 1];
-            const int64_t na = op.nA >= 0 ? op.nA : I.nsa, nb = op.nB >= 0 ? op.nB : I.nsb;
+            const uint32_t np = pairs_of(I, op), nb = op.nB >= 0 ? op.nB : I.nsb;
             double acc = 0.0;
-            for (int64_t t = threadIdx.x; t < na * nb; t += blockDim.x) {
+            for (uint32_t t = threadIdx.x; t < np; t += blockDim.x) {
                 int64_t xs, xd;
                 bool neg;
                 pair_of(I, op, lists, t, nb, xs, xd, neg);
-                const double2 a = psi[xs], b = psi[xd], la = lam[xs], lb = lam[xd];
-                const double o = lb.x * a.x + lb.y * a.y - la.x * b.x - la.y * b.y;
+                const double a = psi[xs], b = psi[xd], la = lam[xs], lb = lam[xd];
+                const double o = lb * a - la * b;
                 acc += neg ? -o : o;
                 const double sg = neg ? -s : s;
-                psi[xs] = make_double2(c * a.x + sg * b.x, c * a.y + sg * b.y);
-                psi[xd] = make_double2(c * b.x - sg * a.x, c * b.y - sg * a.y);
-                lam[xs] = make_double2(c * la.x + sg * lb.x, c * la.y + sg * lb.y);
-                lam[xd] = make_double2(c * lb.x - sg * la.x, c * lb.y - sg * la.y);
+                psi[xs] = c * a + sg * b;
+                psi[xd] = c * b - sg * a;
+                lam[xs] = c * la + sg * lb;
+                lam[xd] = c * lb - sg * la;
             }
-            const double gk = bsum(acc, red);  // also orders this op before the next
+            const double gk = block_sum(acc);  // also orders this op before the next
             if (threadIdx.x == 0) grad[I.off_k + k] = 2.0 * gk;
         }
         if (threadIdx.x == 0) eout[order[idx]] = E;
@@ -195,139 +259,82 @@ __global__ __launch_bounds__(1024) void k_batch(
 
 // ------------------------------------------------------- phased mode ----
 // One launch per phase and operator index across all instances: workgroup
-// (x, y) serves instance y, x of gridDim.x slices.  Kernel boundaries order
-// the phases; no workgroup ever waits on another.
+// (x, y) of a rotation launch serves instance y, slice x of gridDim.x; the
+// H C launch has one workgroup per (instance, alpha string).  Kernel
+// boundaries order the phases; no workgroup ever waits on another.
 
-__device__ inline double2 sigma_elem(const BInst &I, const double2 *__restrict__ psi, int64_t t,
-                                     const double *__restrict__ gint, const int64_t *__restrict__ hptr,
-                                     const int32_t *__restrict__ hcol, const double *__restrict__ hval,
-                                     const uint32_t *__restrict__ exc) {
-    const int M2 = I.M * I.M;
-    const double *g = gint + I.off_g;
-    const int64_t *pa = hptr + I.off_ha, *pb = hptr + I.off_hb;
-    const uint32_t *ea = exc + I.off_excA, *eb = exc + I.off_excB;
-    const int64_t Ia = t / I.nsb, Ib = t - Ia * I.nsb;
-    const double2 x0 = psi[t];
-    double ar = I.ecore * x0.x, ai = I.ecore * x0.y;
-    for (int64_t q = pa[Ia]; q < pa[Ia + 1]; ++q) {
-        const double v = hval[q];
-        const double2 x = psi[(int64_t)hcol[q] * I.nsb + Ib];
-        ar += v * x.x;
-        ai += v * x.y;
-    }
-    for (int64_t q = pb[Ib]; q < pb[Ib + 1]; ++q) {
-        const double v = hval[q];
-        const double2 x = psi[Ia * I.nsb + hcol[q]];
-        ar += v * x.x;
-        ai += v * x.y;
-    }
-    for (int e = 0; e < I.nexcA; ++e) {
-        const uint32_t wa = ea[Ia * I.nexcA + e];
-        const int64_t Ja = wa & 0xFFFFu;
-        const double *gp = g + ((wa >> 16) & 0x1FFu) * M2;
-        double br = 0.0, bi = 0.0;
-        for (int f = 0; f < I.nexcB; ++f) {
-            const uint32_t wb = eb[Ib * I.nexcB + f];
-            const double gv = (wb >> 31) ? -gp[(wb >> 16) & 0x1FFu] : gp[(wb >> 16) & 0x1FFu];
-            const double2 x = psi[Ja * I.nsb + (wb & 0xFFFFu)];
-            br += gv * x.x;
-            bi += gv * x.y;
-        }
-        if (wa >> 31) {
-            ar -= br;
-            ai -= bi;
-        } else {
-            ar += br;
-            ai += bi;
-        }
-    }
-    return make_double2(ar, ai);
-}
-
-__global__ __launch_bounds__(256) void k_pinit(const BInst *__restrict__ inst, double2 *__restrict__ arena) {
+__global__ __launch_bounds__(256) void k_pinit(const BInst *__restrict__ inst, double *__restrict__ arena) {
     const BInst I = inst[blockIdx.y];
-    double2 *psi = arena + I.off_state;
+    double *psi = arena + I.off_state;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < I.dim;
          t += (int64_t)gridDim.x * blockDim.x)
-        psi[t] = make_double2(t == I.ref ? 1.0 : 0.0, 0.0);
+        psi[t] = t == I.ref ? 1.0 : 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_pfwd(const BInst *__restrict__ inst, const BOp *__restrict__ ops,
                                               const uint32_t *__restrict__ lists,
-                                              const double *__restrict__ cs, double2 *__restrict__ arena,
+                                              const double *__restrict__ cs, double *__restrict__ arena,
                                               int k) {
     const BInst I = inst[blockIdx.y];
     if (k >= I.K) return;
     const BOp op = ops[I.off_ops + k];
     const double c = cs[2 * (I.off_k + k)], s = cs[2 * (I.off_k + k) + 1];
-    double2 *psi = arena + I.off_state;
-    const int64_t na = op.nA >= 0 ? op.nA : I.nsa, nb = op.nB >= 0 ? op.nB : I.nsb;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na * nb;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    double *psi = arena + I.off_state;
+    const uint32_t np = pairs_of(I, op), nb = op.nB >= 0 ? op.nB : I.nsb;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < np; t += gridDim.x * blockDim.x) {
         int64_t xs, xd;
         bool neg;
         pair_of(I, op, lists, t, nb, xs, xd, neg);
         const double sg = neg ? -s : s;
-        const double2 a = psi[xs], b = psi[xd];
-        psi[xs] = make_double2(c * a.x - sg * b.x, c * a.y - sg * b.y);
-        psi[xd] = make_double2(c * b.x + sg * a.x, c * b.y + sg * a.y);
+        const double a = psi[xs], b = psi[xd];
+        psi[xs] = c * a - sg * b;
+        psi[xd] = c * b + sg * a;
     }
 }
 
-__global__ __launch_bounds__(256) void k_psigma(const BInst *__restrict__ inst, const double *__restrict__ gint,
-                                                const int64_t *__restrict__ hptr,
-                                                const int32_t *__restrict__ hcol,
-                                                const double *__restrict__ hval,
-                                                const uint32_t *__restrict__ exc,
-                                                double2 *__restrict__ arena, double *__restrict__ epart) {
-    __shared__ double red[256 / kWave];
-    const BInst I = inst[blockIdx.y];
-    const double2 *psi = arena + I.off_state;
-    double2 *lam = arena + I.off_state + I.dim;
-    double acc = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < I.dim;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const double2 v = sigma_elem(I, psi, t, gint, hptr, hcol, hval, exc);
-        lam[t] = v;
-        const double2 x0 = psi[t];
-        acc += x0.x * v.x + x0.y * v.y;
-    }
-    acc = bsum(acc, red);
-    if (threadIdx.x == 0) epart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+__global__ __launch_bounds__(256) void k_psigma(const BInst *__restrict__ inst, const int32_t *__restrict__ tinst,
+                                                BTabs T, double *__restrict__ arena,
+                                                double *__restrict__ epart) {
+    extern __shared__ double lds[];
+    const int task = blockIdx.x;
+    const BInst I = inst[tinst[task]];
+    const double *psi = arena + I.off_state;
+    double *lam = arena + I.off_state + I.dim;
+    const double e = block_sum(sigma_row(I, task - (int)I.off_task, psi, lam, T, lds));
+    if (threadIdx.x == 0) epart[task] = e;
 }
 
 __global__ __launch_bounds__(256) void k_prev(const BInst *__restrict__ inst, const BOp *__restrict__ ops,
                                               const uint32_t *__restrict__ lists,
-                                              const double *__restrict__ cs, double2 *__restrict__ arena,
+                                              const double *__restrict__ cs, double *__restrict__ arena,
                                               int k, double *__restrict__ gpart) {
-    __shared__ double red[256 / kWave];
     const BInst I = inst[blockIdx.y];
     if (k >= I.K) return;  // uniform across the workgroup
     const BOp op = ops[I.off_ops + k];
     const double c = cs[2 * (I.off_k + k)], s = cs[2 * (I.off_k + k) + 1];
-    double2 *psi = arena + I.off_state;
-    double2 *lam = psi + I.dim;
-    const int64_t na = op.nA >= 0 ? op.nA : I.nsa, nb = op.nB >= 0 ? op.nB : I.nsb;
+    double *psi = arena + I.off_state;
+    double *lam = psi + I.dim;
+    const uint32_t np = pairs_of(I, op), nb = op.nB >= 0 ? op.nB : I.nsb;
     double acc = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na * nb;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < np; t += gridDim.x * blockDim.x) {
         int64_t xs, xd;
         bool neg;
         pair_of(I, op, lists, t, nb, xs, xd, neg);
-        const double2 a = psi[xs], b = psi[xd], la = lam[xs], lb = lam[xd];
-        const double o = lb.x * a.x + lb.y * a.y - la.x * b.x - la.y * b.y;
+        const double a = psi[xs], b = psi[xd], la = lam[xs], lb = lam[xd];
+        const double o = lb * a - la * b;
         acc += neg ? -o : o;
         const double sg = neg ? -s : s;
-        psi[xs] = make_double2(c * a.x + sg * b.x, c * a.y + sg * b.y);
-        psi[xd] = make_double2(c * b.x - sg * a.x, c * b.y - sg * a.y);
-        lam[xs] = make_double2(c * la.x + sg * lb.x, c * la.y + sg * lb.y);
-        lam[xd] = make_double2(c * lb.x - sg * la.x, c * lb.y - sg * la.y);
+        psi[xs] = c * a + sg * b;
+        psi[xd] = c * b - sg * a;
+        lam[xs] = c * la + sg * lb;
+        lam[xd] = c * lb - sg * la;
     }
-    acc = bsum(acc, red);
+    acc = block_sum(acc);
     if (threadIdx.x == 0) gpart[(I.off_k + k) * gridDim.x + blockIdx.x] = acc;
 }
 
-// Ordered per-instance sums of the partials: E and 2 * per-operator sums.
+// Ordered per-instance sums of the partials: E over the instance's row tasks
+// and 2 * the per-operator sums.
 __global__ __launch_bounds__(64) void k_preduce(const BInst *__restrict__ inst, int gx,
                                                 const double *__restrict__ epart,
                                                 const double *__restrict__ gpart,
@@ -336,7 +343,7 @@ __global__ __launch_bounds__(64) void k_preduce(const BInst *__restrict__ inst, 
     const BInst I = inst[y];
     if (threadIdx.x == 0) {
         double e = 0.0;
-        for (int x = 0; x < gx; ++x) e += epart[(int64_t)y * gx + x];
+        for (int r = 0; r < I.nsa; ++r) e += epart[I.off_task + r];
         eout[y] = e;
     }
     for (int k = threadIdx.x; k < I.K; k += blockDim.x) {
@@ -369,6 +376,7 @@ int dmalloc(std::vector<void *> &owned, T **out, size_t count) {
 struct fsv_batch {
     int count = 0;
     int64_t total_k = 0;
+    int64_t ntasks = 0;  // sigma row tasks = sum of the alpha string counts
     std::vector<BInst> inst;
     std::vector<int> order;
     std::vector<void *> owned;
@@ -377,21 +385,28 @@ struct fsv_batch {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     BInst *d_inst = nullptr;
     int *d_order = nullptr, *d_counter = nullptr;
+    int32_t *d_tinst = nullptr;
     BOp *d_ops = nullptr;
-    uint32_t *d_lists = nullptr, *d_exc = nullptr;
-    double *d_cs = nullptr, *d_g = nullptr, *d_hval = nullptr, *d_grad = nullptr, *d_e = nullptr;
+    uint32_t *d_lists = nullptr, *d_excA = nullptr, *d_excBT = nullptr;
+    double *d_cs = nullptr, *d_g = nullptr, *d_hval = nullptr, *d_ellv = nullptr;
+    double *d_grad = nullptr, *d_e = nullptr;
     int64_t *d_hptr = nullptr;
-    int32_t *d_hcol = nullptr;
-    double2 *d_arena = nullptr;
+    int32_t *d_hcol = nullptr, *d_ellc = nullptr;
+    double *d_arena = nullptr;
     double *h_pin = nullptr;  // cs (2 total_k) | grad (total_k) | E (count)
     int block = 256, per_cu = 2, cus = 256;
     int mode = 1;       // 0 persistent work-queue kernel, 1 phased launches
-    int gx = 32;        // phased mode: workgroups per instance per launch
+    int gx = 32;        // phased mode: workgroups per instance per rotation launch
+    size_t lds_budget = 65536;  // LDS bytes a sigma workgroup may stage
+    size_t lds_max = 65536;     // largest dynamic LDS the sigma kernels accept
+    size_t lds_bytes = 0;       // dynamic LDS of the sigma kernels (max over instances)
+    bool force_global = false;  // sigma from global memory only (FSV_BATCH_SIGMA=global)
     int kmax = 0;
     double *d_epart = nullptr, *d_gpart = nullptr;
-    size_t part_cap = 0;  // workgroups per instance the partial buffers hold
+    size_t part_cap = 0;  // workgroups per instance the gradient partials hold
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;
+    BTabs tabs() const { return BTabs{d_g, d_hptr, d_hcol, d_hval, d_ellc, d_ellv, d_excA, d_excBT}; }
     ~fsv_batch() {
         if (work) (void)hipStreamSynchronize(work);
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -412,7 +427,30 @@ namespace {
             return fail(FSV_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
     } while (0)
 
+// Per-instance alpha-excitation chunk for an LDS budget (bytes): the largest
+// even ec with 2 nsb + (nsb + M^2) ec doubles within the budget, capped at the
+// whole list; 0 (global-memory sigma) when not even two fit.  Uploads the
+// instance table.
+int set_lds_budget(fsv_batch &B, size_t budget) {
+    budget = std::min(budget, B.lds_max);
+    size_t need = 0;
+    for (BInst &I : B.inst) {
+        const int64_t nsb = I.nsb, M2 = (int64_t)I.M * I.M;
+        const int64_t room = (int64_t)(budget / 8) - 2 * nsb;
+        int64_t ec = room > 0 ? (room / (nsb + M2)) & ~1LL : 0;
+        ec = std::min<int64_t>(ec, (I.nexcA + 1) & ~1);
+        if (B.force_global || ec < 2) ec = 0;
+        I.ec = (int32_t)ec;
+        if (ec) need = std::max(need, (size_t)(8 * (2 * nsb + (nsb + M2) * ec)));
+    }
+    B.lds_budget = budget;
+    B.lds_bytes = need;
+    BHIP(hipMemcpy(B.d_inst, B.inst.data(), sizeof(BInst) * B.inst.size(), hipMemcpyHostToDevice));
+    return FSV_OK;
+}
+
 int enqueue(fsv_batch &B) {
+    const BTabs T = B.tabs();
     if (B.mode == 1) {
         const dim3 grid((unsigned)B.gx, (unsigned)B.count);
         hipLaunchKernelGGL(k_pinit, grid, dim3(256), 0, B.work, B.d_inst, B.d_arena);
@@ -422,8 +460,8 @@ int enqueue(fsv_batch &B) {
                                B.d_arena, k);
             BHIP(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_psigma, grid, dim3(256), 0, B.work, B.d_inst, B.d_g, B.d_hptr, B.d_hcol,
-                           B.d_hval, B.d_exc, B.d_arena, B.d_epart);
+        hipLaunchKernelGGL(k_psigma, dim3((unsigned)B.ntasks), dim3(256), B.lds_bytes, B.work, B.d_inst,
+                           B.d_tinst, T, B.d_arena, B.d_epart);
         BHIP(hipGetLastError());
         for (int k = B.kmax - 1; k >= 0; --k) {
             hipLaunchKernelGGL(k_prev, grid, dim3(256), 0, B.work, B.d_inst, B.d_ops, B.d_lists, B.d_cs,
@@ -438,9 +476,8 @@ int enqueue(fsv_batch &B) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, B.work, B.d_counter);
     BHIP(hipGetLastError());
     const int grid = std::max(1, std::min(B.count, B.cus * B.per_cu));
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(B.block), 0, B.work, B.d_inst, B.d_order, B.count,
-                       B.d_counter, B.d_ops, B.d_lists, B.d_cs, B.d_g, B.d_hptr, B.d_hcol, B.d_hval,
-                       B.d_exc, B.d_arena, B.d_grad, B.d_e);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(B.block), B.lds_bytes, B.work, B.d_inst, B.d_order,
+                       B.count, B.d_counter, B.d_ops, B.d_lists, B.d_cs, T, B.d_arena, B.d_grad, B.d_e);
     BHIP(hipGetLastError());
     return FSV_OK;
 }
@@ -504,8 +541,10 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     for (int i = 0; i < count; ++i) {
         int rc = validate_problem(&problems[i]);
         if (rc) return fail(rc, "instance %d: %s", i, fsv_last_error());
-        if (problems[i].precision != 0) return fail(FSV_EINVAL, "instance %d: batches are complex128 only", i);
-        if (problems[i].n_qubits > 30) return fail(FSV_EINVAL, "instance %d: batches take at most 30 qubits", i);
+        if (problems[i].precision != 0)
+            return fail(FSV_EINVAL, "instance %d: batches compute in FP64 (precision 0)", i);
+        if (problems[i].n_qubits > 24)
+            return fail(FSV_EINVAL, "instance %d: batches take at most 24 qubits (use a plan)", i);
     }
     fsv_batch *B = new (std::nothrow) fsv_batch();
     if (!B) return fail(FSV_ENOMEM, "batch allocation failed");
@@ -513,12 +552,13 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     B->user = (hipStream_t)hip_stream;
     B->use_graph = std::getenv("FSV_NO_GRAPH") == nullptr;
     if (const char *m = std::getenv("FSV_BATCH_MODE")) B->mode = std::strcmp(m, "persistent") == 0 ? 0 : 1;
+    if (const char *m = std::getenv("FSV_BATCH_SIGMA")) B->force_global = std::strcmp(m, "global") == 0;
 
     std::vector<BOp> ops;
-    std::vector<uint32_t> lists, excs;
-    std::vector<double> gall, hval;
+    std::vector<uint32_t> lists, excA, excBT;
+    std::vector<double> gall, hval, ellv;
     std::vector<int64_t> hptr;
-    std::vector<int32_t> hcol;
+    std::vector<int32_t> hcol, ellc;
     std::vector<double> cost(count);
     int64_t state = 0, kk = 0;
     for (int i = 0; i < count; ++i) {
@@ -543,25 +583,43 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         I.ecore = p.e_core;
         I.off_g = (int64_t)gall.size();
         gall.insert(gall.end(), p.g, p.g + (size_t)M * M * M * M);
-        // string Hamiltonians (row pointers are global indices into hcol / hval)
-        for (int s = 0; s < 2; ++s) {
-            std::vector<int64_t> ptr;
-            std::vector<int32_t> col;
-            std::vector<double> val;
-            build_string_h(M, s ? sb : sa, s ? rb : ra, p.h, p.g, ptr, col, val);
-            const int64_t base = (int64_t)hcol.size();
-            (s ? I.off_hb : I.off_ha) = (int64_t)hptr.size();
-            for (int64_t v : ptr) hptr.push_back(v + base);
-            hcol.insert(hcol.end(), col.begin(), col.end());
-            hval.insert(hval.end(), val.begin(), val.end());
-        }
+        // alpha string Hamiltonian as CSR (row pointers index hcol / hval globally)
+        std::vector<int64_t> ptr;
+        std::vector<int32_t> col;
+        std::vector<double> val;
+        build_string_h(M, sa, ra, p.h, p.g, ptr, col, val);
+        const int64_t base = (int64_t)hcol.size();
+        I.off_ha = (int64_t)hptr.size();
+        for (int64_t v : ptr) hptr.push_back(v + base);
+        hcol.insert(hcol.end(), col.begin(), col.end());
+        hval.insert(hval.end(), val.begin(), val.end());
+        const double nnz_a = (double)col.size() / std::max(1, I.nsa);
+        // beta string Hamiltonian as transposed ELL: slot q of row Ib at [q][Ib],
+        // padded with zero weights on the diagonal
+        build_string_h(M, sb, rb, p.h, p.g, ptr, col, val);
+        int w = 0;
+        for (int r = 0; r < I.nsb; ++r) w = std::max<int>(w, (int)(ptr[r + 1] - ptr[r]));
+        I.wB = w;
+        I.off_hb = (int64_t)ellc.size();
+        ellc.resize(ellc.size() + (size_t)w * I.nsb);
+        ellv.resize(ellv.size() + (size_t)w * I.nsb, 0.0);
+        for (int r = 0; r < I.nsb; ++r)
+            for (int q = 0; q < w; ++q) {
+                const int64_t at = I.off_hb + (int64_t)q * I.nsb + r, src = ptr[r] + q;
+                const bool real = src < ptr[r + 1];
+                ellc[at] = real ? col[src] : r;
+                ellv[at] = real ? val[src] : 0.0;
+            }
         std::vector<uint32_t> ea, eb;
         build_exc(M, sa, ra, ea, I.nexcA);
         build_exc(M, sb, rb, eb, I.nexcB);
-        I.off_excA = (int64_t)excs.size();
-        excs.insert(excs.end(), ea.begin(), ea.end());
-        I.off_excB = (int64_t)excs.size();
-        excs.insert(excs.end(), eb.begin(), eb.end());
+        I.off_excA = (int64_t)excA.size();
+        excA.insert(excA.end(), ea.begin(), ea.end());
+        I.off_excB = (int64_t)excBT.size();
+        excBT.resize(excBT.size() + (size_t)I.nexcB * I.nsb);
+        for (int r = 0; r < I.nsb; ++r)
+            for (int f = 0; f < I.nexcB; ++f)
+                excBT[I.off_excB + (int64_t)f * I.nsb + r] = eb[(size_t)r * I.nexcB + f];
         // operators in the alpha-first basis = the blocked JW ordering
         double pairs = 0.0;
         for (int k = 0; k < p.n_ops; ++k) {
@@ -569,9 +627,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
             pairs += (double)(o.nA >= 0 ? o.nA : I.nsa) * (double)(o.nB >= 0 ? o.nB : I.nsb);
             ops.push_back(o);
         }
-        const double nnz = (double)(hptr[I.off_ha + I.nsa] - hptr[I.off_ha]) / std::max(1, I.nsa) +
-                           (double)(hptr[I.off_hb + I.nsb] - hptr[I.off_hb]) / std::max(1, I.nsb);
-        cost[i] = (double)I.dim * (nnz + (double)I.nexcA * I.nexcB) + 3.0 * pairs;
+        cost[i] = (double)I.dim * (nnz_a + w + (double)I.nexcA * I.nexcB) + 3.0 * pairs;
         B->inst.push_back(I);
     }
     B->total_k = kk;
@@ -580,6 +636,14 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     B->order.resize(count);
     std::iota(B->order.begin(), B->order.end(), 0);
     std::stable_sort(B->order.begin(), B->order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    // sigma row tasks, most expensive instances first; each instance's rows
+    // are contiguous so its energy partials sum in a fixed order
+    std::vector<int32_t> tinst;
+    for (int i : B->order) {
+        B->inst[i].off_task = (int64_t)tinst.size();
+        tinst.insert(tinst.end(), (size_t)B->inst[i].nsa, i);
+    }
+    B->ntasks = (int64_t)tinst.size();
 
     int rc = FSV_OK;
     auto fin = [&](int code) {
@@ -603,35 +667,55 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         delete B;
         return fail(FSV_ENOMEM, "pinned host buffer");
     }
+    // dynamic LDS limit of the sigma kernels: a CU's 160 KiB less their static
+    // LDS, or the default 64 KiB if the attribute cannot be raised
+    B->lds_max = 163840;
+    for (const void *f : {(const void *)k_psigma, (const void *)k_batch}) {
+        hipFuncAttributes fa;
+        size_t lim = 163840;
+        if (hipFuncGetAttributes(&fa, f) == hipSuccess) lim -= fa.sharedSizeBytes;
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess) {
+            (void)hipGetLastError();
+            lim = 65536 - (lim < 163840 ? 163840 - lim : 0);
+        }
+        B->lds_max = std::min(B->lds_max, lim);
+    }
     auto& o = B->owned;
     if ((rc = dmalloc(o, &B->d_inst, B->inst.size())) || (rc = dmalloc(o, &B->d_order, count)) ||
-        (rc = dmalloc(o, &B->d_counter, 4)) || (rc = dmalloc(o, &B->d_ops, ops.size())) ||
-        (rc = dmalloc(o, &B->d_lists, lists.size())) || (rc = dmalloc(o, &B->d_exc, excs.size())) ||
+        (rc = dmalloc(o, &B->d_counter, 4)) || (rc = dmalloc(o, &B->d_tinst, tinst.size())) ||
+        (rc = dmalloc(o, &B->d_ops, ops.size())) || (rc = dmalloc(o, &B->d_lists, lists.size())) ||
+        (rc = dmalloc(o, &B->d_excA, excA.size())) || (rc = dmalloc(o, &B->d_excBT, excBT.size())) ||
         (rc = dmalloc(o, &B->d_cs, 2 * (size_t)kk)) || (rc = dmalloc(o, &B->d_g, gall.size())) ||
         (rc = dmalloc(o, &B->d_hval, hval.size())) || (rc = dmalloc(o, &B->d_hptr, hptr.size())) ||
-        (rc = dmalloc(o, &B->d_hcol, hcol.size())) || (rc = dmalloc(o, &B->d_grad, (size_t)kk)) ||
+        (rc = dmalloc(o, &B->d_hcol, hcol.size())) || (rc = dmalloc(o, &B->d_ellc, ellc.size())) ||
+        (rc = dmalloc(o, &B->d_ellv, ellv.size())) || (rc = dmalloc(o, &B->d_grad, (size_t)kk)) ||
         (rc = dmalloc(o, &B->d_e, (size_t)count)) || (rc = dmalloc(o, &B->d_arena, (size_t)state)) ||
-        (rc = dmalloc(o, &B->d_epart, (size_t)count * B->part_cap)) ||
+        (rc = dmalloc(o, &B->d_epart, (size_t)B->ntasks)) ||
         (rc = dmalloc(o, &B->d_gpart, (size_t)kk * B->part_cap)))
         return fin(rc);
-    B->bytes = sizeof(BInst) * B->inst.size() + sizeof(int) * (count + 4) + sizeof(BOp) * ops.size() +
-               4 * (lists.size() + excs.size()) + 8 * (2 * kk + gall.size() + hval.size() + hptr.size() + kk + count) +
-               4 * hcol.size() + 16 * (size_t)state;
+    B->bytes = sizeof(BInst) * B->inst.size() + sizeof(int) * (count + 4) + 4 * tinst.size() +
+               sizeof(BOp) * ops.size() + 4 * (lists.size() + excA.size() + excBT.size() + hcol.size() + ellc.size()) +
+               8 * (2 * kk + gall.size() + hval.size() + hptr.size() + ellv.size() + kk + count) +
+               8 * ((size_t)B->ntasks + (size_t)kk * B->part_cap) + 8 * (size_t)state;
     struct Up { void *d; const void *h; size_t n; };
     const Up ups[] = {
-        {B->d_inst, B->inst.data(), sizeof(BInst) * B->inst.size()},
         {B->d_order, B->order.data(), sizeof(int) * count},
+        {B->d_tinst, tinst.data(), 4 * tinst.size()},
         {B->d_ops, ops.data(), sizeof(BOp) * ops.size()},
         {B->d_lists, lists.data(), 4 * lists.size()},
-        {B->d_exc, excs.data(), 4 * excs.size()},
+        {B->d_excA, excA.data(), 4 * excA.size()},
+        {B->d_excBT, excBT.data(), 4 * excBT.size()},
         {B->d_g, gall.data(), 8 * gall.size()},
         {B->d_hval, hval.data(), 8 * hval.size()},
         {B->d_hptr, hptr.data(), 8 * hptr.size()},
         {B->d_hcol, hcol.data(), 4 * hcol.size()},
+        {B->d_ellc, ellc.data(), 4 * ellc.size()},
+        {B->d_ellv, ellv.data(), 8 * ellv.size()},
     };
     for (const Up &u : ups)
         if (u.n && hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice) != hipSuccess)
             return fin(fail(FSV_EDEVICE, "upload failed"));
+    if ((rc = set_lds_budget(*B, B->lds_budget))) return fin(rc);
     *out = B;
     clear_error();
     return FSV_OK;
@@ -660,40 +744,55 @@ int fsv_batch_autotune(fsv_batch *B, const char **report) {
         if (rc) return rc;
     }
     // candidates: persistent kernel (workgroup size x workgroups per CU) and
-    // phased launches (workgroups per instance)
-    struct Cand { int mode, block, per_cu, gx; };
+    // phased launches (workgroups per instance per rotation launch); both with
+    // the LDS budget of a sigma workgroup, which sets the chunk of alpha
+    // excitations staged per pass
+    struct Cand { int mode, block, per_cu, gx; size_t lds; };
     std::vector<Cand> cands;
-    for (int blk : {256, 512, 1024})
-        for (int per : {1, 2, 4}) cands.push_back({0, blk, per, B->gx});
-    for (int gx : {8, 16, 32, 64})
-        if ((size_t)gx <= B->part_cap) cands.push_back({1, B->block, B->per_cu, gx});
+    for (size_t lds : {32768, 65536, 98304, 147456}) {
+        if (lds > B->lds_max) continue;
+        for (int blk : {256, 512, 1024})
+            for (int per : {1, 2}) cands.push_back({0, blk, per, B->gx, lds});
+        for (int gx : {8, 16, 32, 64})
+            if ((size_t)gx <= B->part_cap) cands.push_back({1, B->block, B->per_cu, gx, lds});
+    }
     float best = 1e30f;
-    Cand bestc{B->mode, B->block, B->per_cu, B->gx};
+    const Cand keep{B->mode, B->block, B->per_cu, B->gx, B->lds_budget};
+    Cand bestc = keep;
     hipEvent_t e0, e1;
     BHIP(hipEventCreate(&e0));
     BHIP(hipEventCreate(&e1));
     rep.clear();
-    char line[128];
-    const bool graph = B->use_graph;
-    B->use_graph = false;
-    for (const Cand &c : cands) {
+    char line[160];
+    auto apply = [&](const Cand &c) {
         B->mode = c.mode;
         B->block = c.block;
         B->per_cu = c.per_cu;
         B->gx = c.gx;
-        float ms = 0.f;
-        for (int r = 0; r < 2; ++r) {
-            BHIP(hipEventRecord(e0, B->work));
-            int rc = enqueue(*B);
-            if (rc) return rc;
-            BHIP(hipEventRecord(e1, B->work));
-            BHIP(hipEventSynchronize(e1));
-            BHIP(hipEventElapsedTime(&ms, e0, e1));
+        if (B->graph) (void)hipGraphExecDestroy(B->graph);
+        B->graph = nullptr;
+        return set_lds_budget(*B, c.lds);
+    };
+    int rc = FSV_OK;
+    for (const Cand &c : cands) {
+        if ((rc = apply(c))) break;
+        float ms = 1e30f;
+        for (int r = 0; r < 3 && !rc; ++r) {  // the first run also captures the graph
+            float t = 0.f;
+            if (hipEventRecord(e0, B->work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
+            if (!rc) rc = launch(*B);
+            if (!rc && (hipEventRecord(e1, B->work) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                rc = fail(FSV_EDEVICE, "event timing failed");
+            if (r > 0) ms = std::min(ms, t);
         }
+        if (rc) break;
         if (c.mode == 0)
-            snprintf(line, sizeof line, "persistent: block %d x %d per CU: %.3f ms\n", c.block, c.per_cu, ms);
+            snprintf(line, sizeof line, "persistent: block %d x %d per CU, LDS %zu KiB: %.3f ms\n", c.block,
+                     c.per_cu, c.lds / 1024, ms);
         else
-            snprintf(line, sizeof line, "phased: %d workgroups per instance: %.3f ms\n", c.gx, ms);
+            snprintf(line, sizeof line, "phased: %d workgroups per instance, LDS %zu KiB: %.3f ms\n", c.gx,
+                     c.lds / 1024, ms);
         rep += line;
         if (ms < best) {
             best = ms;
@@ -702,15 +801,11 @@ int fsv_batch_autotune(fsv_batch *B, const char **report) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    B->use_graph = graph;
-    B->mode = bestc.mode;
-    B->block = bestc.block;
-    B->per_cu = bestc.per_cu;
-    B->gx = bestc.gx;
-    if (B->graph) (void)hipGraphExecDestroy(B->graph);
-    B->graph = nullptr;
-    snprintf(line, sizeof line, "chosen: %s block %d per_cu %d gx %d\n", bestc.mode ? "phased" : "persistent",
-             bestc.block, bestc.per_cu, bestc.gx);
+    const int rc2 = apply(rc ? keep : bestc);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    snprintf(line, sizeof line, "chosen: %s block %d per_cu %d gx %d LDS %zu KiB\n",
+             bestc.mode ? "phased" : "persistent", bestc.block, bestc.per_cu, bestc.gx, bestc.lds / 1024);
     rep += line;
     if (report) *report = rep.c_str();
     return FSV_OK;

@@ -89,3 +89,23 @@ def test_null_arguments(lib):
     assert lib.energy_grad(None, None, None, None, None, None) == -1
     assert lib.rdm1(None, None, None) == -1
     assert lib.set_onebody_potential(None, None) == -1
+
+
+def test_batch_rejects_before_device(lib):
+    # validation runs before any device call: empty batch, single precision,
+    # an instance above the batch size limit, and a bad instance among good ones
+    out = ctypes.c_void_p()
+    assert lib.fsv_batch_create(ctypes.byref(out), None, 0, None) == -1
+    cp, keep = _problem(precision=1)
+    assert lib.fsv_batch_create(ctypes.byref(out), ctypes.byref(cp), 1, None) == -1
+    assert b"FP64" in lib.fsv_last_error()
+    cp, keep = _problem(n=26, na=3, nb=3)
+    assert lib.fsv_batch_create(ctypes.byref(out), ctypes.byref(cp), 1, None) == -1
+    assert b"24 qubits" in lib.fsv_last_error()
+    from paper_2405_11567_amd import _lib
+    good, k1 = _problem()
+    bad, k2 = _problem(ops=[[0, 2, 1, 3]])
+    arr = (_lib.Problem * 2)(good, bad)
+    assert lib.fsv_batch_create(ctypes.byref(out), arr, 2, None) == -1
+    assert b"instance 1" in lib.fsv_last_error()
+    assert out.value is None

@@ -1,4 +1,5 @@
-"""Batched persistent-kernel path vs the FP64 oracle, instance by instance."""
+"""Batched path (phased launches and the persistent work-queue kernel) vs the
+FP64 oracle, instance by instance."""
 
 import time
 
@@ -18,9 +19,14 @@ def fsv(gpu):
     return m
 
 
+@pytest.mark.parametrize("sigma", ["lds", "global"])
 @pytest.mark.parametrize("mode", ["phased", "persistent"])
-def test_batch_mixed_small(fsv, mode, monkeypatch):
+def test_batch_mixed_small(fsv, mode, sigma, monkeypatch):
+    # H C with rows staged in LDS, and from global memory only (the path taken
+    # by rows too long for LDS)
     monkeypatch.setenv("FSV_BATCH_MODE", mode)
+    if sigma == "global":
+        monkeypatch.setenv("FSV_BATCH_SIGMA", "global")
     probs = []
     shapes = [(4, 2, 3), (6, 3, 10), (8, 4, 26), (8, 1, 5), (10, 7, 20), (12, 6, 40), (12, 4, 30),
               (10, 5, 0), (14, 7, 25), (6, 6, 0), (16, 9, 30)]
@@ -32,7 +38,7 @@ def test_batch_mixed_small(fsv, mode, monkeypatch):
             p.theta = np.zeros(0)
         p.e_core = 0.1 * i
         probs.append(p)
-    say("batch mixed", len(probs))
+    say("batch mixed", len(probs), mode, sigma)
     b = fsv.Batch(probs)
     e, g = b.energy_grad([p.theta for p in probs])
     for i, p in enumerate(probs):
