@@ -103,6 +103,19 @@ int fsv_plan_info(const fsv_plan *plan, int64_t *n_alpha_strings, int64_t *n_bet
  * rounding.  The environment variable FSV_ENGINE=dense selects 1 at creation. */
 int fsv_plan_set_engine(fsv_plan *plan, int engine);
 
+/* Operator runs of the sector engine's forward sweep (adjoint = 0) or adjoint
+ * sweep (adjoint = 1).  An excitation changes occupations only in the
+ * orbitals it names, so consecutive operators can be applied together, tile
+ * by tile in LDS, on tiles that the whole run maps onto themselves (alpha
+ * strings that agree outside the run's alpha orbitals x a block of beta
+ * strings); runs are chosen from an LDS budget and a cost model (FSV_NO_FUSE:
+ * never, FSV_FORCE_FUSE: every run of two or more) and retuned by
+ * fsv_autotune.  run_start[k] receives the first operator of the run holding
+ * operator k, fused_tiles[k] the tiles of its fused launch or 0 when k is
+ * applied alone (host arrays of K int32, either may be NULL).  Returns the
+ * number of runs (>= 0) or a negative status. */
+int fsv_plan_runs(const fsv_plan *plan, int adjoint, int32_t *run_start, int32_t *fused_tiles);
+
 /* psi_dev <- U_K(theta_K) ... U_1(theta_1) |ref> (ansatz preparation on the
  * GPU emulator, Fig. 1).  theta: host, K doubles.  Every amplitude of psi_dev
  * is written (zero outside the sector). */
@@ -154,10 +167,13 @@ int fsv_reverse_async(fsv_plan *plan, void *psi_dev, void *lam_dev);
 /* Reduce the partial sums, copy E and grad to the host and wait. */
 int fsv_finish(fsv_plan *plan, double *E_out, double *grad_out);
 
-/* Launch-shape tuning: time the rotation and adjoint kernels of this plan over
- * the candidate shapes and keep the fastest (cached per shape class in the
- * file named by FSV_TUNE_CACHE when set).  psi_dev and lam_dev are work
- * buffers.  *report (may be NULL) receives a static summary string. */
+/* Autotuner.  Sector engine: time whole energy + gradient evaluations for
+ * candidate LDS budgets of the fused operator runs (and for one launch per
+ * operator) and keep the fastest.  Dense engine: time the rotation and adjoint
+ * kernels over candidate launch shapes and keep the fastest (cached per shape
+ * class in the file named by FSV_TUNE_CACHE when set).  psi_dev and lam_dev
+ * are distinct work buffers.  *report (may be NULL) receives a static summary
+ * string. */
 int fsv_autotune(fsv_plan *plan, void *psi_dev, void *lam_dev, const char **report);
 
 /* ---- batches: many independent instances in one graph launch ----

@@ -80,6 +80,18 @@ class Plan:
         check(self._lib.fsv_plan_set_engine(self._h, self.ENGINES[engine]))
         self.engine = engine
 
+    def runs(self, adjoint: bool = False):
+        """Operator runs of the sector engine's forward (or adjoint) sweep:
+        (run_start, fused_tiles), two int32 arrays of length K (fused_tiles 0
+        for an operator applied alone)."""
+        k = self.n_ops
+        start = np.zeros(max(k, 1), dtype=np.int32)
+        tiles = np.zeros(max(k, 1), dtype=np.int32)
+        rc = self._lib.fsv_plan_runs(self._h, int(bool(adjoint)), _iptr(start), _iptr(tiles))
+        if rc < 0:
+            check(rc)
+        return start[:k], tiles[:k]
+
     # -- buffers ---------------------------------------------------------
     @property
     def dtype(self):

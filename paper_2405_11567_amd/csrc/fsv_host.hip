@@ -121,8 +121,14 @@ struct fsv_plan {
     SectorTabs tabs{};
     int lr_R = 0;     // rank of the factorised alpha-beta product (0: direct)
     std::vector<PairOp> pops;
+    std::vector<uint32_t> h_plists;  // host copy of the pair lists (fused-run tables are built from it)
     uint32_t *d_plists = nullptr;
+    PairOp *d_pops = nullptr;
     int *d_ccount = nullptr;
+    // fused operator runs of the forward and adjoint sweeps (LDS budget per tile)
+    FusedSched ffwd, frev;
+    size_t fuse_budget_fwd = 65536, fuse_budget_rev = 98304;
+    int fuse_mode = 0;  // 0 cost model, 1 never (FSV_NO_FUSE), 2 every run (FSV_FORCE_FUSE)
 
     // graphs
     bool use_graph = true;
@@ -616,8 +622,15 @@ int enq_forward_sector(fsv_plan &P, void *c) {
     // The reference is string 0 x string 0.  Its alpha-first amplitude carries
     // the ordering sign so that the dense image starts at exactly +1 |ref>.
     HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
-    for (int k = 0; k < P.K; ++k)
-        HIPCHECK(launch_crot(P.svt, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
+    for (const FGroup &g : P.ffwd.groups) {
+        if (g.fused) {
+            HIPCHECK(launch_fused(P.svt, false, c, nullptr, P.ffwd, g, P.d_pops, P.d_cs, P.nsb, nullptr, 0,
+                                  P.work));
+            continue;
+        }
+        for (int k = g.k0; k < g.k0 + g.nops; ++k)
+            HIPCHECK(launch_crot(P.svt, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
+    }
     return FSV_OK;
 }
 
@@ -633,9 +646,17 @@ int enq_sigma_sector(fsv_plan &P, const void *c, void *lam_c) {
 
 int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
     const int G = max_grid();
-    for (int k = P.K - 1; k >= 0; --k)
-        HIPCHECK(launch_cadj(P.svt, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
-                             P.d_gpart + (size_t)k * G, P.work));
+    for (auto it = P.frev.groups.rbegin(); it != P.frev.groups.rend(); ++it) {
+        const FGroup &g = *it;
+        if (g.fused) {
+            HIPCHECK(launch_fused(P.svt, true, c, lam_c, P.frev, g, P.d_pops, P.d_cs, P.nsb, P.d_gpart, G,
+                                  P.work));
+            continue;
+        }
+        for (int k = g.k0 + g.nops - 1; k >= g.k0; --k)
+            HIPCHECK(launch_cadj(P.svt, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
+                                 P.d_gpart + (size_t)k * G, P.work));
+    }
     HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_ccount, G, P.K, 2.0, P.d_out + 1, P.work));
     return FSV_OK;
 }
@@ -761,6 +782,34 @@ int launch_energy_only(fsv_plan &P, void *psi) {
     return FSV_OK;
 }
 
+// Fused runs of both sweeps for the current LDS budgets, and the gradient
+// partial counts of the adjoint sweep that they imply.
+int rebuild_fused(fsv_plan &P) {
+    FusedOpts o;
+    o.es = vtype_bytes(P.svt);
+    o.mode = P.fuse_mode;
+    o.max_tiles = max_grid();
+    const size_t lim = fused_lds_limit();
+    o.lds_limit = lim;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        o.cus = cus;
+    (void)hipGetLastError();
+    o.arrays = 1;
+    o.budget = std::min(P.fuse_budget_fwd, lim);
+    int rc = build_fused(P.M, P.sa, P.sb, P.pops, P.h_plists, P.ops, o, P.ffwd);
+    if (rc) return rc;
+    o.arrays = 2;
+    o.budget = std::min(P.fuse_budget_rev, lim);
+    if ((rc = build_fused(P.M, P.sa, P.sb, P.pops, P.h_plists, P.ops, o, P.frev))) return rc;
+    std::vector<int> ccount(std::max(P.K, 1), 0);
+    for (int k = 0; k < P.K; ++k)
+        ccount[k] = P.frev.count[k] >= 0 ? P.frev.count[k] : cadj_blocks(P.pops[k], P.nsa, P.nsb);
+    drop_graphs(P);
+    return upload(P, P.d_ccount, ccount.data(), (size_t)P.K);
+}
+
 int build_device(fsv_plan &P) {
     int rc;
     init_kernels();
@@ -811,17 +860,19 @@ int build_device(fsv_plan &P) {
     std::vector<int32_t> boA, biA, boB, biB;
     build_bins(M, excA, P.nexcA, boA, biA);
     build_bins(M, excB, P.nexcB, boB, biB);
-    std::vector<uint32_t> plists;
-    std::vector<int> ccount(std::max(P.K, 1), 0);
+    std::vector<uint32_t> &plists = P.h_plists;
+    plists.clear();
     P.pops.clear();
-    for (int k = 0; k < P.K; ++k) {
+    for (int k = 0; k < P.K; ++k)
         P.pops.push_back(build_pair_op(M, P.ops.data() + 4 * k, P.sa, ra, P.sb, rb, plists));
-        ccount[k] = cadj_blocks(P.pops.back(), P.nsa, P.nsb);
-    }
     if ((rc = dalloc(P, &P.d_plists, plists.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_pops, (size_t)P.K))) return rc;
     if ((rc = dalloc(P, &P.d_ccount, (size_t)std::max(P.K, 1)))) return rc;
     if ((rc = upload(P, P.d_plists, plists.data(), plists.size()))) return rc;
-    if ((rc = upload(P, P.d_ccount, ccount.data(), (size_t)P.K))) return rc;
+    if ((rc = upload(P, P.d_pops, P.pops.data(), P.pops.size()))) return rc;
+    if (const char *e = std::getenv("FSV_NO_FUSE")) P.fuse_mode = e[0] ? 1 : 0;
+    if (std::getenv("FSV_FORCE_FUSE")) P.fuse_mode = 2;
+    if ((rc = rebuild_fused(P))) return rc;
 
     if ((rc = dalloc(P, &P.d_rot, P.K))) return rc;
     if ((rc = dalloc(P, &P.d_cs, 2 * (size_t)P.K))) return rc;
@@ -908,6 +959,72 @@ fsv_plan::~fsv_plan() {
     if (work) (void)hipStreamDestroy(work);
 }
 
+namespace {
+
+// Sector engine: time whole energy + gradient evaluations (graph launches)
+// for candidate LDS budgets of the fused runs, and keep the fastest.
+int autotune_sector(fsv_plan &P, void *psi, void *lam, std::string &rep) {
+    struct Cand { int mode; size_t fwd, rev; };
+    const Cand cands[] = {{1, 0, 0},          {0, 32768, 65536},   {0, 49152, 98304},
+                          {0, 65536, 98304},  {0, 65536, 131072},  {0, 98304, 163840},
+                          {0, 163840, 163840}};
+    const Cand keep{P.fuse_mode, P.fuse_budget_fwd, P.fuse_budget_rev};
+    std::vector<double> th(P.K, 0.1);
+    int rc;
+    if ((rc = upload_theta(P, th.data()))) return rc;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    auto apply = [&](const Cand &c) {
+        P.fuse_mode = c.mode;
+        P.fuse_budget_fwd = c.fwd ? c.fwd : keep.fwd;
+        P.fuse_budget_rev = c.rev ? c.rev : keep.rev;
+        return rebuild_fused(P);
+    };
+    rep.clear();
+    char line[200];
+    float best = 1e30f;
+    Cand bestc = keep;
+    for (const Cand &c : cands) {
+        if ((rc = apply(c))) break;
+        float ms = 1e30f;
+        for (int r = 0; r < 4 && !rc; ++r) {  // the first launch also captures the graph
+            float t = 0.f;
+            if (hipEventRecord(e0, P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
+            if (!rc) rc = launch_energy_grad(P, psi, lam);
+            if (!rc && (hipEventRecord(e1, P.work) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                rc = fail(FSV_EDEVICE, "event timing failed");
+            if (r > 0) ms = std::min(ms, t);
+        }
+        if (rc) break;
+        int fo = 0, ro = 0;
+        const int fr = fused_runs(P.ffwd, &fo), rr = fused_runs(P.frev, &ro);
+        if (c.mode == 1)
+            snprintf(line, sizeof line, "one launch per operator: %.3f ms\n", ms);
+        else
+            snprintf(line, sizeof line,
+                     "fused runs, LDS %zu / %zu KiB: forward %d runs (%d ops), adjoint %d runs (%d ops): %.3f ms\n",
+                     c.fwd / 1024, c.rev / 1024, fr, fo, rr, ro, ms);
+        rep += line;
+        if (ms < best) {
+            best = ms;
+            bestc = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int rc2 = apply(rc ? keep : bestc);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    snprintf(line, sizeof line, "chosen: %s, LDS %zu / %zu KiB\n", bestc.mode == 1 ? "per operator" : "fused runs",
+             P.fuse_budget_fwd / 1024, P.fuse_budget_rev / 1024);
+    rep += line;
+    return FSV_OK;
+}
+
+}  // namespace
+
 // ==================================================================== C ABI ==
 extern "C" {
 
@@ -983,6 +1100,18 @@ int fsv_plan_set_engine(fsv_plan *P, int engine) {
         P->engine = engine;
     }
     return FSV_OK;
+}
+
+int fsv_plan_runs(const fsv_plan *P, int adjoint, int32_t *run_start, int32_t *fused_tiles) {
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    if (adjoint != 0 && adjoint != 1) return fail(FSV_EINVAL, "adjoint must be 0 or 1");
+    const FusedSched &S = adjoint ? P->frev : P->ffwd;
+    for (const FGroup &g : S.groups)
+        for (int k = g.k0; k < g.k0 + g.nops; ++k) {
+            if (run_start) run_start[k] = g.k0;
+            if (fused_tiles) fused_tiles[k] = g.fused ? g.n_orbits * g.n_blocks : 0;
+        }
+    return (int)S.groups.size();
 }
 
 int fsv_set_theta(fsv_plan *P, const double *theta) {
@@ -1137,8 +1266,14 @@ int set_onebody_potential(fsv_plan *P, const double *v) {
 int fsv_autotune(fsv_plan *P, void *psi, void *lam, const char **report) {
     static thread_local std::string rep;
     if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
+    if (psi == lam) return fail(FSV_EINVAL, "psi and lam must be distinct buffers");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if (P->engine == 0) {
+        if ((rc = autotune_sector(*P, psi, lam, rep))) return rc;
+        if (report) *report = rep.c_str();
+        return fence_out(*P);
+    }
     const char *cache = std::getenv("FSV_TUNE_CACHE");
     char key[128];
     snprintf(key, sizeof key, "n%d_p%d_o%d_K%d", P->n, P->precision, P->ordering, P->K);

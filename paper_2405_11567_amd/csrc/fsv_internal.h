@@ -147,4 +147,56 @@ hipError_t launch_scatter_real(int precision, void *lam, const double *S, const 
                                int64_t nsa, int64_t nsb, hipStream_t st);
 void init_sigma_kernels();
 
+// ---- fused operator runs on the sector state (fsv_fused.hip) ----
+// A run of consecutive operators applied tile by tile in LDS (fused = 1), or
+// a single operator left to the per-operator kernels (fused = 0, nops = 1).
+// A fused run keeps, per alpha orbit, a program of astride words (row count,
+// row ranks, per-operator local alpha pairs) and, per beta block, one of
+// bstride words (first column, width, per-operator local beta pairs).
+struct FGroup {
+    int32_t k0, nops, fused;
+    int32_t n_orbits, n_blocks;  // tiles = n_orbits x n_blocks
+    int32_t rmax, lmax;          // largest orbit (rows) and block (columns)
+    int32_t astride, bstride;
+    int64_t aprog_off, bprog_off;
+    size_t lds;                  // dynamic LDS bytes of one tile workgroup
+};
+
+struct FusedOpts {
+    size_t budget = 65536;       // LDS bytes of tile data per workgroup
+    size_t lds_limit = 65536;    // dynamic LDS a workgroup may use
+    int es = 8;                  // bytes per stored amplitude
+    int arrays = 1;              // 1: forward (psi); 2: adjoint (psi and lam)
+    int mode = 0;                // 0 fuse where the cost model gains, 1 never, 2 every run of >= 2
+    int cus = 256;               // compute units (tiles resident at once scale with it)
+    int min_block = 32;          // columns per block when blocks are split for more tiles
+    int max_ops = 32;            // operators per run
+    int64_t max_tiles = 8192;    // tiles per run (gradient partial slots per operator)
+};
+
+struct FusedSched {
+    std::vector<FGroup> groups;  // in operator order
+    std::vector<int> count;      // per operator: tiles of its fused run, -1 if not fused
+    uint32_t *d_aprog = nullptr, *d_bprog = nullptr;
+    std::vector<void *> mem;
+    void release();
+    FusedSched() = default;
+    FusedSched(const FusedSched &) = delete;
+    FusedSched &operator=(const FusedSched &) = delete;
+    ~FusedSched() { release(); }
+};
+
+// Runs and tiles for the operators (K x 4 spin-orbital labels in ops, their
+// pair ops and host pair lists) under o.  Returns an FSV_ status.
+int build_fused(int M, const std::vector<uint32_t> &sa, const std::vector<uint32_t> &sb,
+                const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
+                const std::vector<int32_t> &ops, const FusedOpts &o, FusedSched &S);
+int fused_runs(const FusedSched &S, int *n_fused_ops);
+void init_fused_kernels();
+size_t fused_lds_limit();
+// Forward (psi) or adjoint (psi, lam, gradient partials gpart[k * gstride + tile]).
+hipError_t launch_fused(int vtype, bool adjoint, void *psi, void *lam, const FusedSched &S, const FGroup &g,
+                        const PairOp *d_pops, const double *cs, int64_t nsb, double *gpart, int gstride,
+                        hipStream_t st);
+
 }  // namespace fsv

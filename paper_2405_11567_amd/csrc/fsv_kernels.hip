@@ -321,7 +321,10 @@ hipError_t adj_dispatch(void *psi, void *lam, const RotOp &op, const double *cs,
 
 int max_grid() { return kMaxGrid; }
 
-void init_kernels() { init_sigma_kernels(); }
+void init_kernels() {
+    init_sigma_kernels();
+    init_fused_kernels();
+}
 
 unsigned rot_grid(uint64_t npairs, Shape sh) {
     const uint64_t per = (uint64_t)sh.block * (uint64_t)sh.ppt;

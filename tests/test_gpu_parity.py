@@ -248,3 +248,48 @@ def test_sigma_paths(fsv, monkeypatch, mode, nfac):
         assert abs(e - e_ref) < 1e-10 and np.abs(gr - g_ref).max() < 1e-9
         psi = plan.ansatz_apply(p.theta)
         assert abs(plan.energy(psi) - e_ref) < 1e-10
+
+
+@pytest.mark.parametrize("mode", ["auto", "none", "force"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_runs_sector(fsv, monkeypatch, mode, precision):
+    # runs of operators applied tile by tile in LDS against one launch per
+    # operator; draws with replacement from the whole pool mix alpha-only,
+    # beta-only and alpha-beta operators in every run
+    p = random_problem(16, 8, 120, seed=801, theta_std=0.5, replace=True, ordering=1)
+    if mode == "none":
+        monkeypatch.setenv("FSV_NO_FUSE", "1")
+    if mode == "force":
+        monkeypatch.setenv("FSV_FORCE_FUSE", "1")
+    say("fused runs", mode, precision)
+    plan = fsv.Plan(p, precision=precision)
+    start, tiles = plan.runs()
+    rstart, rtiles = plan.runs(adjoint=True)
+    assert start[0] == 0 and np.all(np.diff(start) >= 0) and np.all(start <= np.arange(p.n_ops))
+    if mode == "none":
+        assert not tiles.any() and not rtiles.any()
+    else:
+        assert tiles.any() and rtiles.any()
+    psi = _np(plan.ansatz_apply(p.theta))
+    ref, _ = dense_from_sector(oracle_state(p), p)
+    e, g = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p)
+    if precision == 0:
+        assert np.abs(psi - ref).max() < 1e-12
+        assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+    else:
+        assert np.abs(psi - ref).max() < 2e-5
+        assert abs(e - e_ref) < 1e-4 and np.abs(g - g_ref).max() < 1e-3
+
+
+def test_sector_autotune(fsv):
+    # every candidate LDS budget is run and timed; the chosen schedule keeps parity
+    p = config("C2")
+    plan = fsv.Plan(p)
+    psi, lam = plan.new_state(), plan.new_state()
+    rep = plan.autotune(psi, lam)
+    say(rep)
+    assert "chosen" in rep and rep.count("ms") >= 7
+    e, g = plan.energy_grad(p.theta, psi, lam)
+    e_ref, g_ref = oracle_energy_grad(p)
+    assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
