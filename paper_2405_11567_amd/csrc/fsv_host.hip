@@ -2,6 +2,7 @@
 // string tables, same-spin string Hamiltonians (Slater-Condon rules), graph
 // capture of the energy/gradient pass, finite differences and launch tuning.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -104,7 +105,7 @@ struct fsv_plan {
     double *d_cs = nullptr, *d_gpart = nullptr, *d_epart = nullptr, *d_out = nullptr;
     int *d_gcount = nullptr, *d_ecount = nullptr;
     uint64_t *d_Xa = nullptr, *d_Xb = nullptr;
-    uint32_t *d_sa = nullptr, *d_PPb = nullptr, *d_excA = nullptr, *d_excB = nullptr;
+    uint32_t *d_sa = nullptr, *d_PPb = nullptr, *d_excA = nullptr, *d_excB = nullptr, *d_excBT = nullptr;
     double *d_g = nullptr;
     int64_t *d_ha_ptr = nullptr, *d_hb_ptr = nullptr;
     int32_t *d_ha_col = nullptr, *d_hb_col = nullptr;
@@ -120,6 +121,9 @@ struct fsv_plan {
     int svt = V_F64;  // storage of the sector state: real FP64, or real FP32 for precision 1
     SectorTabs tabs{};
     int lr_R = 0;     // rank of the factorised alpha-beta product (0: direct)
+    // dense same-spin string Hamiltonians (FP64 GEMM on the matrix cores)
+    rocblas_handle blas = nullptr;
+    double *d_ha_dense = nullptr, *d_hb_dense = nullptr;
     std::vector<PairOp> pops;
     std::vector<uint32_t> h_plists;  // host copy of the pair lists (fused-run tables are built from it)
     uint32_t *d_plists = nullptr;
@@ -462,12 +466,14 @@ namespace {
 // Choose the factorised alpha-beta product when (pq|rs) has a small exact
 // pivoted-Cholesky rank: per sector element it costs R (e_a + e_b) instead of
 // e_a e_b multiply-adds.  The factorisation must reproduce g to 1e-12 relative.
+int lr_pad(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : 32); }
+
 void choose_sigma(fsv_plan &P, int &R_out, std::vector<double> &Lt_out) {
     R_out = 0;
     const char *mode = std::getenv("FSV_SIGMA");
     if (mode && std::strcmp(mode, "direct") == 0) return;
     const int M2 = P.M * P.M;
-    if (P.nexcA <= 0 || P.nexcB <= 0 || P.nexcA > 64 || M2 > 511) return;
+    if (P.nexcA <= 0 || P.nexcB <= 0 || M2 > 511) return;
     std::vector<double> L;
     const int R = pivoted_cholesky(M2, P.g.data(), 1e-14, L);
     if (R <= 0 || R > 32) return;
@@ -482,12 +488,39 @@ void choose_sigma(fsv_plan &P, int &R_out, std::vector<double> &Lt_out) {
     if (err > 1e-12 * std::max(1.0, gmax)) return;
     const bool forced = mode && std::strcmp(mode, "lowrank") == 0;
     if (!forced && (int64_t)R * (P.nexcA + P.nexcB) >= (int64_t)P.nexcA * P.nexcB) return;
-    // one factor row per workgroup LDS line: nsa complex values must fit
-    if (P.nsa * 16 + (int64_t)M2 * 8 > 163840) return;
+    // the beta step stages one row of the intermediate (complex for the dense
+    // engine) with one factor column in LDS
+    const int rp = lr_pad(R);
+    if (P.nsb * 16 + (int64_t)M2 * 8 > 163840) return;
     R_out = R;
-    Lt_out.assign((size_t)M2 * R, 0.0);
+    Lt_out.assign((size_t)M2 * rp, 0.0);  // M^2 x rp, zero beyond column R
     for (int k = 0; k < R; ++k)
-        for (int i = 0; i < M2; ++i) Lt_out[(size_t)i * R + k] = L[(size_t)k * M2 + i];
+        for (int i = 0; i < M2; ++i) Lt_out[(size_t)i * rp + k] = L[(size_t)k * M2 + i];
+}
+
+// Dense copies of the same-spin string Hamiltonians, rebuilt on the device
+// from the CSR rows whenever the one-body part changes.
+int refresh_dense_same_spin(fsv_plan &P) {
+    if (!P.d_ha_dense) return FSV_OK;
+    HIPCHECK(launch_csr_dense(P.d_ha_ptr, P.d_ha_col, P.d_ha_val, P.d_ha_dense, P.nsa, P.work));
+    HIPCHECK(launch_csr_dense(P.d_hb_ptr, P.d_hb_col, P.d_hb_val, P.d_hb_dense, P.nsb, P.work));
+    HIPCHECK(hipStreamSynchronize(P.work));
+    return FSV_OK;
+}
+
+// Same-spin products as dense FP64 GEMMs when the string Hamiltonian is
+// dense enough that the matrix cores beat gathering its rows: per output
+// element a sparse row costs nnz 8-byte gathers at ~10 TB/s, a dense row
+// 2 nsa flops at ~40 TFLOP/s (FSV_SAME_SPIN = dense | sparse overrides).
+bool want_dense_same_spin(const fsv_plan &P) {
+    const char *m = std::getenv("FSV_SAME_SPIN");
+    if (m && std::strcmp(m, "sparse") == 0) return false;
+    const double bytes = 8.0 * ((double)P.nsa * P.nsa + (double)P.nsb * P.nsb);
+    if (bytes > 16e9) return false;
+    if (m && std::strcmp(m, "dense") == 0) return true;
+    if (P.nsa * P.nsb < 4096) return false;
+    const double nnz_a = (double)P.ha_col.size() / (double)P.nsa, nnz_b = (double)P.hb_col.size() / (double)P.nsb;
+    return nnz_a * 16.0 > (double)P.nsa && nnz_b * 16.0 > (double)P.nsb;
 }
 
 int upload_hamiltonian_values(fsv_plan &P) {
@@ -501,7 +534,7 @@ int upload_hamiltonian_values(fsv_plan &P) {
     int rc;
     if ((rc = upload(P, P.d_ha_val, P.ha_val.data(), P.ha_val.size()))) return rc;
     if ((rc = upload(P, P.d_hb_val, P.hb_val.data(), P.hb_val.size()))) return rc;
-    return FSV_OK;
+    return refresh_dense_same_spin(P);
 }
 
 // Byte model of one pair kernel (read + write of the touched 128-byte lines).
@@ -887,6 +920,7 @@ int build_device(fsv_plan &P) {
     if ((rc = dalloc(P, &P.d_PPb, P.nsb))) return rc;
     if ((rc = dalloc(P, &P.d_excA, excA.size()))) return rc;
     if ((rc = dalloc(P, &P.d_excB, excB.size()))) return rc;
+    if ((rc = dalloc(P, &P.d_excBT, excB.size()))) return rc;
     if ((rc = dalloc(P, &P.d_g, M2 * M2))) return rc;
     if ((rc = dalloc(P, &P.d_binA_off, boA.size()))) return rc;
     if ((rc = dalloc(P, &P.d_binA_idx, biA.size()))) return rc;
@@ -906,6 +940,12 @@ int build_device(fsv_plan &P) {
     if ((rc = upload(P, P.d_PPb, PPb.data(), PPb.size()))) return rc;
     if ((rc = upload(P, P.d_excA, excA.data(), excA.size()))) return rc;
     if ((rc = upload(P, P.d_excB, excB.data(), excB.size()))) return rc;
+    {
+        std::vector<uint32_t> excBT(excB.size());
+        for (int64_t r = 0; r < P.nsb; ++r)
+            for (int f = 0; f < P.nexcB; ++f) excBT[(size_t)f * P.nsb + r] = excB[(size_t)r * P.nexcB + f];
+        if ((rc = upload(P, P.d_excBT, excBT.data(), excBT.size()))) return rc;
+    }
     if ((rc = upload(P, P.d_g, P.g.data(), P.g.size()))) return rc;
     if ((rc = upload(P, P.d_binA_off, boA.data(), boA.size()))) return rc;
     if ((rc = upload(P, P.d_binA_idx, biA.data(), biA.size()))) return rc;
@@ -939,12 +979,32 @@ int build_device(fsv_plan &P) {
     if (R > 0) {
         if ((rc = dalloc(P, &d_Lt, Lt.size()))) return rc;
         if ((rc = upload(P, d_Lt, Lt.data(), Lt.size()))) return rc;
-        if ((rc = dalloc(P, &d_YT, (size_t)R * P.dim))) return rc;  // complex-sized
+        if ((rc = dalloc(P, &d_YT, (size_t)lr_pad(R) * P.dim))) return rc;  // complex-sized
     }
     P.lr_R = R;
+    if (want_dense_same_spin(P)) {
+        if (rocblas_create_handle(&P.blas) != rocblas_status_success) {
+            P.blas = nullptr;
+            return fail(FSV_EDEVICE, "rocblas_create_handle failed");
+        }
+        if (rocblas_set_atomics_mode(P.blas, rocblas_atomics_not_allowed) != rocblas_status_success)
+            return fail(FSV_EDEVICE, "rocblas_set_atomics_mode failed");
+        if ((rc = dalloc(P, &P.d_ha_dense, (size_t)P.nsa * P.nsa))) return rc;
+        if ((rc = dalloc(P, &P.d_hb_dense, (size_t)P.nsb * P.nsb))) return rc;
+        if ((rc = refresh_dense_same_spin(P))) return rc;
+    }
     P.tabs = SectorTabs{P.nsa, P.nsb, M, P.nexcA, P.nexcB, P.d_ha_ptr, P.d_hb_ptr, P.d_ha_col,
-                        P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_g, P.ecore,
-                        R, d_Lt, d_YT};
+                        P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_excBT, P.d_g, P.ecore,
+                        R, d_Lt, d_YT, P.d_ha_dense, P.d_hb_dense, (void *)P.blas};
+    if (P.blas) {
+        // one eager product per amplitude type, outside any graph capture, so
+        // that the library has loaded its kernels and sized its workspace
+        // before the first capture (the work buffers hold no state yet)
+        HIPCHECK(launch_fill_zero(P.d_C, (size_t)P.dim * sizeof(double2), P.work));
+        HIPCHECK(launch_sector_sigma(false, P.tabs, P.d_C, P.d_S, P.d_CT, P.d_ST, P.d_epart, P.work));
+        HIPCHECK(launch_sector_sigma(true, P.tabs, P.d_C, P.d_S, P.d_CT, P.d_ST, P.d_epart, P.work));
+        HIPCHECK(hipStreamSynchronize(P.work));
+    }
     return FSV_OK;
 }
 
@@ -952,6 +1012,7 @@ int build_device(fsv_plan &P) {
 
 fsv_plan::~fsv_plan() {
     drop_graphs(*this);
+    if (blas) (void)rocblas_destroy_handle(blas);
     for (auto &b : bufs) (void)hipFree(b.p);
     if (h_pin) (void)hipHostFree(h_pin);
     if (ev_in) (void)hipEventDestroy(ev_in);

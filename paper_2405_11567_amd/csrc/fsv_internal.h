@@ -115,14 +115,21 @@ struct SectorTabs {
     const int32_t *ha_col, *hb_col;
     const double *ha_val, *hb_val;
     const uint32_t *excA, *excB;
+    const uint32_t *excBT;  // excB transposed: [f][Ib]
     const double *g;
     double ecore;
     // Optional exact factorisation (pq|rs) = sum_l L[l][pq] L[l][rs] of rank R
-    // (pivoted Cholesky of the pair supermatrix): Lt holds L transposed
-    // (M^2 x R) and YT is an R * nsa * nsb work array.  R = 0: direct product.
+    // (pivoted Cholesky of the pair supermatrix): Lt holds L transposed and
+    // padded to RP = 8, 16 or 32 columns (M^2 x RP, zero beyond R) and YT is an
+    // RP * nsa * nsb work array (complex-sized).  R = 0: direct product.
     int R;
     const double *Lt;
     void *YT;
+    // Optional dense same-spin string Hamiltonians (nsa x nsa, nsb x nsb,
+    // row-major) applied as FP64 GEMMs through the rocBLAS handle blas;
+    // nullptr: the CSR rows above.
+    const double *ha_dense, *hb_dense;
+    void *blas;
 };
 
 int cadj_blocks(const PairOp &op, int64_t nsa, int64_t nsb);  // partials written by launch_cadj
@@ -138,6 +145,9 @@ hipError_t launch_convert(int vt_in, const void *in, int vt_out, void *out, int6
 unsigned combine_grid(int64_t dim);
 hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, void *S, void *CT,
                                void *ST, double *epart, hipStream_t st);
+// Dense row-major copy (n x n) of an n-row CSR matrix.
+hipError_t launch_csr_dense(const int64_t *rowptr, const int32_t *col, const double *val, double *out, int64_t n,
+                            hipStream_t st);
 // Transpose of a compact vector (rows x cols -> cols x rows), complex or real.
 hipError_t launch_ctranspose(bool cplex, const void *in, void *out, int64_t rows, int64_t cols,
                              hipStream_t st);

@@ -7,6 +7,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <rocblas/rocblas.h>
+
+#include <vector>
+
 #include "fsv_device.h"
 #include "fsv_internal.h"
 
@@ -201,6 +205,35 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ rowptr
     out[I * ncols + c] = acc;
 }
 
+// Dense copy of a CSR matrix (one workgroup per row; columns within a row are
+// distinct, so the scatter needs no ordering).
+__global__ __launch_bounds__(256) void k_csr_dense(const int64_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col,
+                                                   const double *__restrict__ val, double *__restrict__ out,
+                                                   int64_t n) {
+    const int64_t I = blockIdx.x;
+    double *row = out + I * n;
+    for (int64_t c = threadIdx.x; c < n; c += blockDim.x) row[c] = 0.0;
+    __syncthreads();
+    for (int64_t k = rowptr[I] + threadIdx.x; k < rowptr[I + 1]; k += blockDim.x) row[col[k]] = val[k];
+}
+
+// Same-spin product on the matrix cores: out (rows x w*ncols, row-major) =
+// H (rows x rows, row-major, symmetric) * in (rows x w*ncols), as the
+// column-major product in' * H of rocBLAS (in' = in viewed column-major).
+// Atomics stay disallowed on the handle, so the result is deterministic and no
+// memset enters a captured graph.
+hipError_t dense_same_spin(void *blas, const double *H, const double *in, double *out, int64_t rows,
+                           int64_t wcols, hipStream_t st) {
+    rocblas_handle h = (rocblas_handle)blas;
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_set_stream(h, st) != rocblas_status_success) return hipErrorInvalidHandle;
+    const rocblas_status rs = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)wcols,
+                                            (rocblas_int)rows, (rocblas_int)rows, &one, in, (rocblas_int)wcols, H,
+                                            (rocblas_int)rows, &zero, out, (rocblas_int)wcols);
+    return rs == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
 // Alpha-beta two-body term, one workgroup per output row Ia:
 //   S[Ia][Ib] += sum_{e in exc(Ia)} sum_{f in exc(Ib)} s_e s_f (pq_e|rs_f) C[J_e][J_f].
 // The alpha excitations are taken ec at a time.  Their source rows are staged
@@ -299,84 +332,89 @@ __global__ __launch_bounds__(BLOCK) void k_sigma_ab_reg(const uint32_t *__restri
     }
 }
 
-// ---- alpha-beta term through the factorisation (pq|rs) = sum_l L_l[pq] L_l[rs] ----
-// With B_l = sum_rs L_l[rs] E^b_rs and A_l = sum_pq L_l[pq] E^a_pq the term is
-// sum_l A_l (C B_l^T).  Step 1 forms Y_l = C B_l^T in the transposed layout
-// YT[l][Ib][Ja] = sum_{f in exc(Ib)} s_f L_l[rs_f] CT[J_f][Ja]: one workgroup
-// per (Ib, column group); the excitation entries and weights are uniform
-// across the workgroup, the CT rows are read coalesced.
-template <typename A, int RMAX>
-__global__ __launch_bounds__(256) void k_lr_beta(const A *__restrict__ CT, A *__restrict__ YT,
-                                                 const uint32_t *__restrict__ excB, int nexcB,
-                                                 const double *__restrict__ Lt, int R, int64_t nsa,
-                                                 int64_t nsb) {
-    const int64_t Ib = blockIdx.x;
-    const int64_t Ja = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-    const bool active = Ja < nsa;
-    A acc[RMAX];
+// Factorised alpha-beta term, (pq|rs) = sum_l L_l[pq] L_l[rs] (l < R, padded
+// to RP = 8, 16 or 32 with zero columns of Lt, which is M^2 x RP):
+//   S[Ia][Ib] += sum_l (A_l C B_l^T)[Ia][Ib],  A_l = sum_pq L_l[pq] E^alpha_pq,
+//   B_l = sum_rs L_l[rs] E^beta_rs,
+// in two steps through Y[Ia][Jb][l] = (A_l C)[Ia][Jb] (l fastest).
+//
+// Step 1 gathers whole rows of C: a workgroup is one alpha string Ia and 256
+// beta strings Jb, so Ia's excitation list and the factor row of each
+// excitation are workgroup-uniform and every coalesced load of C feeds RP
+// multiply-adds.
+template <typename A, int RP>
+__global__ __launch_bounds__(256) void k_lr_a(const A *__restrict__ C, A *__restrict__ Y,
+                                              const uint32_t *__restrict__ excA, int nexcA,
+                                              const double *__restrict__ Lt, int64_t nsb) {
+    const int64_t Ia = blockIdx.x;
+    const int64_t Jb = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    const bool active = Jb < nsb;
+    const int64_t jb = active ? Jb : nsb - 1;
+    const uint32_t *ex = excA + Ia * nexcA;
+    A acc[RP];
 #pragma unroll
-    for (int l = 0; l < RMAX; ++l) acc[l] = zero<A>();
-    for (int f = 0; f < nexcB; ++f) {
-        const uint32_t eb = excB[Ib * nexcB + f];
-        const int64_t Jb = eb & 0xFFFFu;
-        const double *lr = Lt + (int)((eb >> 16) & 0x1FFu) * R;
-        const A x = neg_if((eb >> 31) != 0, active ? CT[Jb * nsa + Ja] : zero<A>());
+    for (int l = 0; l < RP; ++l) acc[l] = zero<A>();
+    int e = 0;
+    for (; e + 4 <= nexcA; e += 4) {
+        A x[4];
 #pragma unroll
-        for (int l = 0; l < RMAX; ++l)
-            if (l < R) axpy(acc[l], lr[l], x);
+        for (int u = 0; u < 4; ++u) x[u] = C[(int64_t)(ex[e + u] & 0xFFFFu) * nsb + jb];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t ea = ex[e + u];
+            const double *lr = Lt + ((ea >> 16) & 0x1FFu) * RP;
+            const A xv = neg_if((ea >> 31) != 0, x[u]);
+#pragma unroll
+            for (int l = 0; l < RP; ++l) axpy(acc[l], lr[l], xv);
+        }
+    }
+    for (; e < nexcA; ++e) {
+        const uint32_t ea = ex[e];
+        const double *lr = Lt + ((ea >> 16) & 0x1FFu) * RP;
+        const A xv = neg_if((ea >> 31) != 0, C[(int64_t)(ea & 0xFFFFu) * nsb + jb]);
+#pragma unroll
+        for (int l = 0; l < RP; ++l) axpy(acc[l], lr[l], xv);
     }
     if (active) {
+        A *y = Y + (Ia * nsb + Jb) * RP;
 #pragma unroll
-        for (int l = 0; l < RMAX; ++l)
-            if (l < R) YT[((int64_t)l * nsb + Ib) * nsa + Ja] = acc[l];
+        for (int l = 0; l < RP; ++l) y[l] = acc[l];
     }
 }
 
-// Step 2: ST[Ib][Ia] += sum_l sum_{e in exc(Ia)} s_e L_l[pq_e] YT[l][Ib][J_e], one
-// workgroup per Ib.  The rows YT[l][Ib][:] are staged in LDS ec at a time
-// (interleaved Rt[Ja][l]), next to the matching columns of L; each thread
-// holds its Ia's alpha-excitation list in registers.
-template <typename A, int MAXE, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_lr_alpha(const A *__restrict__ YT, A *__restrict__ ST,
-                                                    const uint32_t *__restrict__ excA, int nexcA,
-                                                    const double *__restrict__ Lt, int R, int M,
-                                                    int64_t nsa, int64_t nsb, int ec) {
+// Step 2, row-local: S[Ia][Ib] += sum_{f in exc(Ib)} s_f sum_l L_l[rs_f]
+// Y[Ia][Jb_f][l].  One workgroup per Ia stages its Y row (nsb x lc values)
+// and the matching lc columns of Lt in LDS, lc of the RP values at a time;
+// the beta lists are read transposed (excBT[f][Ib]) so the lanes' loads
+// coalesce.
+template <typename A>
+__global__ __launch_bounds__(1024) void k_lr_b(const A *__restrict__ Y, A *__restrict__ S,
+                                               const uint32_t *__restrict__ excBT, int nexcB,
+                                               const double *__restrict__ Lt, int M2, int RP, int64_t nsb,
+                                               int lc) {
     extern __shared__ double smem_d[];
-    A *Rt = (A *)smem_d;                              // nsa * ec
-    double *Lc = (double *)(Rt + (int64_t)nsa * ec);  // M2 * ec
-    const int64_t Ib = blockIdx.x;
-    const int M2 = M * M;
-    for (int64_t ia0 = 0; ia0 < nsa; ia0 += blockDim.x) {
-        const int64_t Ia = ia0 + threadIdx.x;
-        const bool active = Ia < nsa;
-        uint32_t ex[MAXE];
-#pragma unroll
-        for (int e = 0; e < MAXE; ++e) ex[e] = (active && e < nexcA) ? excA[Ia * nexcA + e] : 0u;
-        A acc = zero<A>();
-        for (int l0 = 0; l0 < R; l0 += ec) {
-            const int nl = min(ec, R - l0);
-            __syncthreads();
-            for (int l = 0; l < nl; ++l) {
-                const A *row = YT + ((int64_t)(l0 + l) * nsb + Ib) * nsa;
-                for (int64_t ja = threadIdx.x; ja < nsa; ja += blockDim.x) Rt[ja * ec + l] = row[ja];
-                for (int pq = threadIdx.x; pq < M2; pq += blockDim.x) Lc[pq * ec + l] = Lt[pq * R + l0 + l];
+    double *lt = smem_d;               // M2 x lc
+    A *yr = (A *)(lt + M2 * lc);       // nsb x lc
+    const int64_t Ia = blockIdx.x;
+    const A *yrow = Y + Ia * nsb * RP;
+    A *srow = S + Ia * nsb;
+    for (int l0 = 0; l0 < RP; l0 += lc) {
+        __syncthreads();  // readers of the previous chunk are done
+        for (int i = threadIdx.x; i < M2 * lc; i += blockDim.x) lt[i] = Lt[(i / lc) * RP + l0 + i % lc];
+        for (int64_t i = threadIdx.x; i < nsb * lc; i += blockDim.x) yr[i] = yrow[(i / lc) * RP + l0 + i % lc];
+        __syncthreads();
+        for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
+            A acc = zero<A>();
+            for (int f = 0; f < nexcB; ++f) {
+                const uint32_t eb = excBT[(int64_t)f * nsb + Ib];
+                const double *w = lt + ((eb >> 16) & 0x1FFu) * lc;
+                const A *y = yr + (int64_t)(eb & 0xFFFFu) * lc;
+                A t = zero<A>();
+                for (int l = 0; l < lc; ++l) axpy(t, w[l], y[l]);
+                acc = add(acc, neg_if((eb >> 31) != 0, t));
             }
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int e = 0; e < MAXE; ++e) {
-                    if (e < nexcA) {
-                        const uint32_t w = ex[e];
-                        const A *r = Rt + (int64_t)(w & 0xFFFFu) * ec;
-                        const double *lc = Lc + (int)((w >> 16) & 0x1FFu) * ec;
-                        A t = zero<A>();
-                        for (int l = 0; l < nl; ++l) axpy(t, lc[l], r[l]);
-                        acc = add(acc, neg_if((w >> 31) != 0, t));
-                    }
-                }
-            }
+            srow[Ib] = add(srow[Ib], acc);
         }
-        if (active) ST[Ib * nsa + Ia] = add(ST[Ib * nsa + Ia], acc);
     }
 }
 
@@ -472,15 +510,44 @@ __global__ void k_scatter_real(O *__restrict__ lam,
 
 int g_lds_max = -1;
 
+// LDS chunk of the factor columns for step 2 (0: a row does not fit).
+template <typename A>
+int lr_chunk(const SectorTabs &T, int rp) {
+    const size_t lim = g_lds_max > 0 ? (size_t)g_lds_max : 65536;
+    const size_t per = (size_t)T.M * T.M * sizeof(double) + (size_t)T.nsb * sizeof(A);
+    int lc = rp;
+    while (lc > 0 && (size_t)lc * per > lim) lc >>= 1;
+    return lc;
+}
+
+template <typename A, int RP>
+hipError_t lr_launch(const SectorTabs &T, const A *C, A *S, hipStream_t st) {
+    A *Y = (A *)T.YT;
+    const int lc = lr_chunk<A>(T, RP);
+    if (lc < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_lr_a<A, RP>), dim3((unsigned)T.nsa, (unsigned)((T.nsb + 255) / 256)), dim3(256), 0, st,
+                       C, Y, T.excA, T.nexcA, T.Lt, T.nsb);
+    const int M2 = T.M * T.M;
+    const size_t shm = (size_t)lc * ((size_t)M2 * sizeof(double) + (size_t)T.nsb * sizeof(A));
+    hipLaunchKernelGGL((k_lr_b<A>), dim3((unsigned)T.nsa), dim3(1024), shm, st, Y, S, T.excBT, T.nexcB, T.Lt, M2,
+                       RP, T.nsb, lc);
+    return hipGetLastError();
+}
+
 template <typename A>
 hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, double *epart, hipStream_t st) {
     const int64_t nsa = T.nsa, nsb = T.nsb;
-    // same-spin alpha part (with the alpha one-body terms)
-    {
-        const dim3 grid((unsigned)nsa, (unsigned)((nsb + 255) / 256));
-        hipLaunchKernelGGL(k_spmm<A>, grid, dim3(256), 0, st, T.ha_ptr, T.ha_col, T.ha_val, C, S, nsb);
+    constexpr int64_t w = sizeof(A) / sizeof(double);  // doubles per amplitude
+    // same-spin alpha part (with the alpha one-body terms): dense on the
+    // matrix cores, or sparse rows
+    if (T.ha_dense) {
+        const hipError_t e = dense_same_spin(T.blas, T.ha_dense, (const double *)C, (double *)S, nsa, w * nsb, st);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_spmm<A>, dim3((unsigned)nsa, (unsigned)((nsb + 255) / 256)), dim3(256), 0, st,
+                           T.ha_ptr, T.ha_col, T.ha_val, C, S, nsb);
     }
-    // alpha-beta part (direct; the factorised form is applied after the beta part)
+    // alpha-beta part, directly or through the factors of (pq|rs)
     if (T.nexcA > 0 && T.nexcB > 0 && T.R == 0) {
         const int lds = g_lds_max > 0 ? g_lds_max : 65536;
         const int64_t per = nsb * (int64_t)sizeof(A) + (int64_t)T.M * T.M * (int64_t)sizeof(double);
@@ -502,40 +569,22 @@ hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, doubl
             hipLaunchKernelGGL(k_sigma_ab_global<A>, dim3((unsigned)nsa), dim3(256), 0, st, T.excA, T.nexcA,
                                T.excB, T.nexcB, T.g, T.M, C, S, nsb);
     }
+    if (T.nexcA > 0 && T.nexcB > 0 && T.R > 0) {
+        hipError_t e = T.R <= 8 ? lr_launch<A, 8>(T, C, S, st)
+                                : (T.R <= 16 ? lr_launch<A, 16>(T, C, S, st) : lr_launch<A, 32>(T, C, S, st));
+        if (e != hipSuccess) return e;
+    }
     // same-spin beta part on the transpose, then combine
     {
         const dim3 grid((unsigned)((nsb + 31) / 32), (unsigned)((nsa + 31) / 32));
         hipLaunchKernelGGL(k_transpose<A>, grid, dim3(32, 8), 0, st, C, CT, nsa, nsb);
     }
-    {
-        const dim3 grid((unsigned)nsb, (unsigned)((nsa + 255) / 256));
-        hipLaunchKernelGGL(k_spmm<A>, grid, dim3(256), 0, st, T.hb_ptr, T.hb_col, T.hb_val, CT, ST, nsa);
-    }
-    if (T.nexcA > 0 && T.nexcB > 0 && T.R > 0) {
-        A *YT = (A *)T.YT;
-        const dim3 g1((unsigned)nsb, (unsigned)((nsa + 255) / 256));
-        if (T.R <= 8)
-            hipLaunchKernelGGL((k_lr_beta<A, 8>), g1, dim3(256), 0, st, CT, YT, T.excB, T.nexcB, T.Lt, T.R, nsa, nsb);
-        else if (T.R <= 16)
-            hipLaunchKernelGGL((k_lr_beta<A, 16>), g1, dim3(256), 0, st, CT, YT, T.excB, T.nexcB, T.Lt, T.R, nsa, nsb);
-        else if (T.R <= 32)
-            hipLaunchKernelGGL((k_lr_beta<A, 32>), g1, dim3(256), 0, st, CT, YT, T.excB, T.nexcB, T.Lt, T.R, nsa, nsb);
-        else
-            return hipErrorInvalidValue;
-        const int lds = g_lds_max > 0 ? g_lds_max : 65536;
-        const int64_t per = nsa * (int64_t)sizeof(A) + (int64_t)T.M * T.M * (int64_t)sizeof(double);
-        int64_t ec = lds / per;
-        if (ec > T.R) ec = T.R;
-        if (ec < 1) return hipErrorInvalidValue;
-        const size_t shm = (size_t)(ec * per);
-        if (T.nexcA <= 48)
-            hipLaunchKernelGGL((k_lr_alpha<A, 48, 1024>), dim3((unsigned)nsb), dim3(1024), shm, st, YT, ST, T.excA,
-                               T.nexcA, T.Lt, T.R, T.M, nsa, nsb, (int)ec);
-        else if (T.nexcA <= 64)
-            hipLaunchKernelGGL((k_lr_alpha<A, 64, 512>), dim3((unsigned)nsb), dim3(512), shm, st, YT, ST, T.excA,
-                               T.nexcA, T.Lt, T.R, T.M, nsa, nsb, (int)ec);
-        else
-            return hipErrorInvalidValue;
+    if (T.hb_dense) {
+        const hipError_t e = dense_same_spin(T.blas, T.hb_dense, (const double *)CT, (double *)ST, nsb, w * nsa, st);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_spmm<A>, dim3((unsigned)nsb, (unsigned)((nsa + 255) / 256)), dim3(256), 0, st,
+                           T.hb_ptr, T.hb_col, T.hb_val, CT, ST, nsa);
     }
     hipLaunchKernelGGL(k_combine<A>, dim3(combine_grid(nsa * nsb)), dim3(32, 8), 0, st, S, ST, C, T.ecore,
                        nsa, nsb, epart);
@@ -570,15 +619,12 @@ hipError_t convert_impl(const void *in, void *out, int64_t n, hipStream_t st) {
 void init_sigma_kernels() {
     if (g_lds_max > 0) return;
     g_lds_max = 65536;
-    const void *fns[] = {(const void *)k_sigma_ab<double>, (const void *)k_sigma_ab<double2>,
-                         (const void *)k_sigma_ab_reg<double, 48, 1024>,
-                         (const void *)k_sigma_ab_reg<double2, 48, 1024>,
-                         (const void *)k_sigma_ab_reg<double, 64, 512>,
-                         (const void *)k_sigma_ab_reg<double2, 64, 512>,
-                         (const void *)k_lr_alpha<double, 48, 1024>,
-                         (const void *)k_lr_alpha<double2, 48, 1024>,
-                         (const void *)k_lr_alpha<double, 64, 512>,
-                         (const void *)k_lr_alpha<double2, 64, 512>};
+    std::vector<const void *> fns = {(const void *)k_sigma_ab<double>, (const void *)k_sigma_ab<double2>,
+                                     (const void *)k_sigma_ab_reg<double, 48, 1024>,
+                                     (const void *)k_sigma_ab_reg<double2, 48, 1024>,
+                                     (const void *)k_sigma_ab_reg<double, 64, 512>,
+                                     (const void *)k_sigma_ab_reg<double2, 64, 512>,
+                                     (const void *)k_lr_b<double>, (const void *)k_lr_b<double2>};
     bool ok = true;
     for (const void *f : fns)
         ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840) == hipSuccess;
@@ -632,6 +678,12 @@ hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, v
     if (cplex)
         return sigma_impl<double2>(T, (const double2 *)C, (double2 *)S, (double2 *)CT, (double2 *)ST, epart, st);
     return sigma_impl<double>(T, (const double *)C, (double *)S, (double *)CT, (double *)ST, epart, st);
+}
+
+hipError_t launch_csr_dense(const int64_t *rowptr, const int32_t *col, const double *val, double *out, int64_t n,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_csr_dense, dim3((unsigned)n), dim3(256), 0, st, rowptr, col, val, out, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_ctranspose(bool cplex, const void *in, void *out, int64_t rows, int64_t cols, hipStream_t st) {

@@ -226,7 +226,7 @@ def test_invalid_arguments(fsv):
 
 
 @pytest.mark.parametrize("mode", ["direct", "lowrank", "auto"])
-@pytest.mark.parametrize("nfac", [8, 40])
+@pytest.mark.parametrize("nfac", [8, 12, 40])
 def test_sigma_paths(fsv, monkeypatch, mode, nfac):
     # the alpha-beta product directly and through the pivoted-Cholesky factors
     # of (pq|rs); nfac random symmetric factors set the rank of the supermatrix
@@ -293,3 +293,27 @@ def test_sector_autotune(fsv):
     e, g = plan.energy_grad(p.theta, psi, lam)
     e_ref, g_ref = oracle_energy_grad(p)
     assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+
+
+@pytest.mark.parametrize("same_spin", ["dense", "sparse"])
+def test_same_spin_paths_and_replays(fsv, monkeypatch, same_spin):
+    # same-spin products as FP64 GEMMs or sparse rows; each energy_grad call
+    # replays the captured graph, with eager work between the replays, and
+    # every replay must match the oracle and the first replay bit for bit
+    monkeypatch.setenv("FSV_SAME_SPIN", same_spin)
+    p = config("C2", ordering=1)
+    e_ref, g_ref = oracle_energy_grad(p)
+    for engine in ENGINES:
+        say("same-spin", same_spin, engine)
+        plan = fsv.Plan(p, engine=engine)
+        psi, lam = plan.new_state(), plan.new_state()
+        first = None
+        for _ in range(4):
+            e, g = plan.energy_grad(p.theta, psi, lam)
+            assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+            if first is None:
+                first = (e, g)
+            else:
+                assert e == first[0] and np.array_equal(g, first[1])
+            psi2 = plan.ansatz_apply(p.theta)
+            assert abs(plan.energy(psi2) - e_ref) < 1e-10
