@@ -1,8 +1,9 @@
 """Benchmark: energy + adjoint-gradient evaluations per second of the 24-qubit
-workload (12 electrons, 200 sampled excitations, FP64 amplitudes) on one GPU,
-the HBM roofline fraction of its dominant kernel (the adjoint reverse step),
-the per-parameter finite-difference gradient on the same GPU, and the FP64
-CPU oracle timed on the host cores.
+workload (12 electrons, 200 sampled excitations, FP64) on one GPU, the HBM
+roofline fraction of the per-operator adjoint kernel (k_cadj, timed live on a
+plan without fused runs, so that every reverse launch is that kernel), the
+per-parameter finite-difference gradient on the same GPU, and the FP64 CPU
+oracle timed on the host cores.
 
 Prints one JSON line.
 """
@@ -134,15 +135,69 @@ def time_engine(fsv, torch, p, precision, engine, steps, warmup, stream, psi, la
     return plan, ms, steps / (t1 - t0), stages, e, g
 
 
-def roofline_of(mb, stages, k, kernel):
-    """Reverse-step kernel: algorithmic bytes per launch over its average launch
+def roofline_of(mb, stages, k, kernel, traffic=None):
+    """Adjoint-step kernel: algorithmic bytes per launch over its average launch
     duration (the reverse stage's HIP-event time over its K launches)."""
     launch_ms = stages["reverse"] / k
     per_launch = mb["reverse"] / k
     achieved = per_launch / (launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
             "avg_launch_us": launch_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
+
+
+ROTATION_SOURCE = os.path.join(ROOT, "paper_2405_11567_amd", "csrc", "fsv_sigma.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_cadj_sector_24q_fp64.md")
+
+
+def rotation_source_hash():
+    """sha256 (16 hex digits) of the rotation-kernel section of the sector
+    kernel file: the launch-grid helper, pair decoding, k_crot and k_cadj."""
+    import hashlib
+    text = open(ROTATION_SOURCE).read()
+    a = text.index("// ------------------------------------------------------------ rotations ----")
+    b = text.index("// ---------------------------------------------------------------- sigma ----")
+    return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
+
+
+def traffic_from_profile(workload):
+    """HBM bytes per k_cadj launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE x calibration + WRITE_SIZE), when it was taken on the current
+    kernel source and this workload; otherwise None."""
+    try:
+        fields = {}
+        for line in open(TRAFFIC_PROFILE):
+            if ":" in line and line.startswith("- "):
+                key, val = line[2:].split(":", 1)
+                fields[key.strip()] = val.strip().strip("`")
+        if fields.get("source_sha256") != rotation_source_hash() or fields.get("workload") != workload:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def unfused_reverse(fsv, torch, p, precision, stream, psi, lam, reps=5):
+    """Reverse-stage HIP-event time of a plan without fused runs: K launches of
+    the per-operator adjoint kernel."""
+    os.environ["FSV_NO_FUSE"] = "1"
+    try:
+        plan = fsv.Plan(p, precision=precision, device=psi.device)
+    finally:
+        os.environ.pop("FSV_NO_FUSE", None)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for _ in range(reps + 1):
+        plan.set_theta(p.theta)
+        plan.forward_async(psi)
+        plan.sigma_async(psi, lam)
+        ev[0].record(stream)
+        plan.reverse_async(psi, lam)
+        ev[1].record(stream)
+        plan.finish()
+        torch.cuda.synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    return float(np.median(times[1:]))
 
 
 def bench_batch(args):
@@ -255,8 +310,14 @@ def main():
     # the sector engine stores the (exactly real) state as real FP64 / FP32
     mb_sector = sector_model_bytes(p, amp_bytes // 2)
     mb = mb_sector if args.engine == "sector" else mb_dense
-    roof = roofline_of(mb, stages, k, "k_cadj (sector adjoint step)" if args.engine == "sector"
-                       else "k_adj (dense adjoint step)")
+    if args.engine == "sector":
+        rev_ms = unfused_reverse(fsv, torch, p, args.precision, stream, psi, lam)
+        print(f"[bench] per-operator adjoint sweep (no fused runs): {rev_ms:.3f} ms", file=sys.stderr, flush=True)
+        traffic = traffic_from_profile(args.config) if args.precision == 0 else None
+        roof = roofline_of(mb, {"reverse": rev_ms}, k, "k_cadj<double> (sector adjoint step)"
+                           if args.precision == 0 else "k_cadj<float> (sector adjoint step)", traffic)
+    else:
+        roof = roofline_of(mb, stages, k, "k_adj (dense adjoint step)")
 
     dense = None
     if args.engine == "sector" and not args.no_dense:
