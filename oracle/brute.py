@@ -4,7 +4,8 @@ Every fermionic operator is a 2^n x 2^n sparse matrix built from Kronecker
 products of Jordan-Wigner factors: a_j = I x ... x I x sigma^- x Z x ... x Z,
 with Z on every qubit below j (bit j of the basis index is qubit j, so the
 rightmost Kronecker factor acts on qubit 0).  Rotations are matrix
-exponentials exp(theta T) of T = tau - tau^+, and the FCI energy (the
+exponentials exp(theta T) of T = tau - tau^+ (for qubit excitations the
+same products with the Z strings left out), and the FCI energy (the
 finite-basis minimum of the energy functional, Density-based basis-set
 correction section) is the lowest eigenvalue of H restricted to the
 (N_alpha, N_beta) sector.  Independent of the bit-manipulation route of T1/T3.
@@ -42,18 +43,34 @@ def creator(j: int, n: int) -> sp.csr_matrix:
     return annihilator(j, n).conj().T.tocsr()
 
 
+@lru_cache(maxsize=64)
+def qubit_lowering(j: int, n: int) -> sp.csr_matrix:
+    """|0><1| on qubit j, identity elsewhere (no Z string)."""
+    mat = sp.identity(1, format="csr", dtype=np.complex128)
+    for qubit in range(n - 1, -1, -1):
+        mat = sp.kron(mat, _LOWER if qubit == j else _I, format="csr")
+    return mat
+
+
+def qubit_raising(j: int, n: int) -> sp.csr_matrix:
+    return qubit_lowering(j, n).conj().T.tocsr()
+
+
 def _q(so, m, ordering):
     p, s = divmod(int(so), 2)
     return int(so) if ordering == 0 else p + s * m
 
 
-def tau_matrix(op, n: int, ordering: int) -> sp.csr_matrix:
+def tau_matrix(op, n: int, ordering: int, excitation: int = 0) -> sp.csr_matrix:
+    """tau = a^+_a a^+_b a_j a_i (excitation 0) or Q^+_a Q^+_b Q_j Q_i with
+    qubit raising / lowering operators (excitation 1)."""
     a, b, j, i = (int(v) for v in op)
     m = n // 2
+    up, down = (creator, annihilator) if excitation == 0 else (qubit_raising, qubit_lowering)
     if b < 0:
-        return (creator(_q(a, m, ordering), n) @ annihilator(_q(i, m, ordering), n)).tocsr()
-    return (creator(_q(a, m, ordering), n) @ creator(_q(b, m, ordering), n)
-            @ annihilator(_q(j, m, ordering), n) @ annihilator(_q(i, m, ordering), n)).tocsr()
+        return (up(_q(a, m, ordering), n) @ down(_q(i, m, ordering), n)).tocsr()
+    return (up(_q(a, m, ordering), n) @ up(_q(b, m, ordering), n)
+            @ down(_q(j, m, ordering), n) @ down(_q(i, m, ordering), n)).tocsr()
 
 
 def hamiltonian_matrix(h, g, e_core, n: int, ordering: int) -> sp.csr_matrix:
@@ -89,11 +106,11 @@ def reference_index(n, n_alpha, n_beta, ordering) -> int:
     return x
 
 
-def ansatz_state(n, n_alpha, n_beta, ops, theta, ordering=0) -> np.ndarray:
+def ansatz_state(n, n_alpha, n_beta, ops, theta, ordering=0, excitation=0) -> np.ndarray:
     psi = np.zeros(1 << n, dtype=np.complex128)
     psi[reference_index(n, n_alpha, n_beta, ordering)] = 1.0
     for op, t in zip(ops, theta):
-        tau = tau_matrix(op, n, ordering).toarray()
+        tau = tau_matrix(op, n, ordering, excitation).toarray()
         U = scipy.linalg.expm(float(t) * (tau - tau.conj().T))
         psi = U @ psi
     return psi

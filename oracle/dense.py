@@ -13,6 +13,11 @@ over all basis states.
 
 Spin-orbital label so = 2p + s (s = 0 alpha, 1 beta); the qubit holding it is
 so for ordering 0 (interleaved) and p + s*M for ordering 1 (blocked).
+
+Excitation kinds: 0 fermionic (the factors above, with their JW signs);
+1 qubit excitation (the QEB operators of the paper's ADAPT pool, Computational
+Details): the same factor list applied with qubit raising / lowering
+operators, which flip the bit without any parity sign.
 """
 
 from __future__ import annotations
@@ -25,9 +30,10 @@ def qubit_of(so: int, n_orb: int, ordering: int) -> int:
     return int(so) if ordering == 0 else p + s * n_orb
 
 
-def apply_string(x: np.ndarray, factors):
+def apply_string(x: np.ndarray, factors, excitation: int = 0):
     """Apply operator factors (dagger, qubit) in the listed order (the first
-    listed acts first) to every basis index in x.  Returns (x', sign, ok)."""
+    listed acts first) to every basis index in x.  Returns (x', sign, ok).
+    excitation 1: qubit raising / lowering operators (no parity sign)."""
     x = x.copy()
     sign = np.ones(x.shape, dtype=np.int64)
     ok = np.ones(x.shape, dtype=bool)
@@ -35,8 +41,9 @@ def apply_string(x: np.ndarray, factors):
         bit = np.int64(1) << np.int64(q)
         occ = (x & bit) != 0
         ok &= (~occ) if dag else occ
-        par = np.bitwise_count(x & (bit - 1)) & 1
-        sign *= 1 - 2 * par.astype(np.int64)
+        if excitation == 0:
+            par = np.bitwise_count(x & (bit - 1)) & 1
+            sign *= 1 - 2 * par.astype(np.int64)
         x ^= bit
     return x, sign, ok
 
@@ -63,10 +70,10 @@ def tau_factors(op, n_orb: int, ordering: int, adjoint: bool = False):
     return f
 
 
-def apply_operator(psi: np.ndarray, factors, coeff=1.0) -> np.ndarray:
+def apply_operator(psi: np.ndarray, factors, coeff=1.0, excitation: int = 0) -> np.ndarray:
     """coeff * (operator string) psi as a new vector."""
     x = np.arange(psi.size, dtype=np.int64)
-    xp, s, ok = apply_string(x, factors)
+    xp, s, ok = apply_string(x, factors, excitation)
     out = np.zeros_like(psi)
     out[xp[ok]] = coeff * s[ok] * psi[x[ok]]
     return out
@@ -86,12 +93,12 @@ def reference_state(n_qubits: int, n_alpha: int, n_beta: int, ordering: int) -> 
     return psi
 
 
-def rotate(psi: np.ndarray, op, theta: float, n_orb: int, ordering: int) -> np.ndarray:
+def rotate(psi: np.ndarray, op, theta: float, n_orb: int, ordering: int, excitation: int = 0) -> np.ndarray:
     """exp(theta (tau - tau^+)) psi.  On each pair tau|x> = s|x'>:
     psi'_x = cos psi_x - s sin psi_x',  psi'_x' = cos psi_x' + s sin psi_x."""
     psi = psi.copy()
     x = np.arange(psi.size, dtype=np.int64)
-    xp, s, ok = apply_string(x, tau_factors(op, n_orb, ordering))
+    xp, s, ok = apply_string(x, tau_factors(op, n_orb, ordering), excitation)
     src, dst, sg = x[ok], xp[ok], s[ok]
     a, b = psi[src].copy(), psi[dst].copy()
     c, sn = np.cos(theta), np.sin(theta)
@@ -100,18 +107,18 @@ def rotate(psi: np.ndarray, op, theta: float, n_orb: int, ordering: int) -> np.n
     return psi
 
 
-def apply_T(psi: np.ndarray, op, n_orb: int, ordering: int) -> np.ndarray:
+def apply_T(psi: np.ndarray, op, n_orb: int, ordering: int, excitation: int = 0) -> np.ndarray:
     """(tau - tau^+) psi, both terms applied as operator strings."""
-    return (apply_operator(psi, tau_factors(op, n_orb, ordering))
-            - apply_operator(psi, tau_factors(op, n_orb, ordering, adjoint=True)))
+    return (apply_operator(psi, tau_factors(op, n_orb, ordering), excitation=excitation)
+            - apply_operator(psi, tau_factors(op, n_orb, ordering, adjoint=True), excitation=excitation))
 
 
-def ansatz_state(n_qubits, n_alpha, n_beta, ops, theta, ordering=0):
+def ansatz_state(n_qubits, n_alpha, n_beta, ops, theta, ordering=0, excitation=0):
     """|psi(theta)> = U_K ... U_1 |ref>, first listed operator first."""
     m = n_qubits // 2
     psi = reference_state(n_qubits, n_alpha, n_beta, ordering)
     for op, t in zip(ops, theta):
-        psi = rotate(psi, op, float(t), m, ordering)
+        psi = rotate(psi, op, float(t), m, ordering, excitation)
     return psi
 
 
@@ -160,30 +167,41 @@ def rdm1(psi, n_orb: int, ordering=0) -> np.ndarray:
     return gam
 
 
-def energy_grad(n_qubits, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0):
+def energy_grad(n_qubits, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, excitation=0):
     """Energy and dE/dtheta_k = 2 Re <lam_k| T_k |psi_k>, with every forward
     state psi_k stored and lam_k = U_{k+1}^+ ... U_K^+ H psi_K."""
     m = n_qubits // 2
     states = [reference_state(n_qubits, n_alpha, n_beta, ordering)]
     for op, t in zip(ops, theta):
-        states.append(rotate(states[-1], op, float(t), m, ordering))
+        states.append(rotate(states[-1], op, float(t), m, ordering, excitation))
     lam = hamiltonian_apply(states[-1], h, g, e_core, ordering)
     e = float(np.real(np.vdot(states[-1], lam)))
     grad = np.zeros(len(ops))
     for k in range(len(ops) - 1, -1, -1):
-        grad[k] = 2.0 * np.real(np.vdot(lam, apply_T(states[k + 1], ops[k], m, ordering)))
-        lam = rotate(lam, ops[k], -float(theta[k]), m, ordering)
+        grad[k] = 2.0 * np.real(np.vdot(lam, apply_T(states[k + 1], ops[k], m, ordering, excitation)))
+        lam = rotate(lam, ops[k], -float(theta[k]), m, ordering, excitation)
     return e, grad
 
 
-def energy_fd_grad(n_qubits, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, step=1e-5):
+def energy_fd_grad(n_qubits, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, step=1e-5,
+                   excitation=0):
     """Central finite differences of the energy, step h = 1e-5."""
     theta = np.asarray(theta, dtype=np.float64)
     grad = np.zeros(len(theta))
     for k in range(len(theta)):
         tp = theta.copy(); tp[k] += step
         tm = theta.copy(); tm[k] -= step
-        ep = energy(ansatz_state(n_qubits, n_alpha, n_beta, ops, tp, ordering), h, g, e_core, ordering)
-        em = energy(ansatz_state(n_qubits, n_alpha, n_beta, ops, tm, ordering), h, g, e_core, ordering)
+        ep = energy(ansatz_state(n_qubits, n_alpha, n_beta, ops, tp, ordering, excitation), h, g, e_core, ordering)
+        em = energy(ansatz_state(n_qubits, n_alpha, n_beta, ops, tm, ordering, excitation), h, g, e_core, ordering)
         grad[k] = (ep - em) / (2 * step)
     return grad
+
+
+def pool_gradients(psi, h, g, e_core, pool, n_orb, ordering=0, excitation=0):
+    """ADAPT screening of an operator pool at the state psi: for every pool
+    operator, the derivative of the energy with respect to its angle when it
+    is appended to the ansatz at angle 0,
+        g_op = <psi| [H, T_op] |psi> = 2 Re <H psi| T_op |psi>
+    (real H, anti-Hermitian T_op)."""
+    lam = hamiltonian_apply(psi, h, g, e_core, ordering)
+    return np.array([2.0 * np.real(np.vdot(lam, apply_T(psi, op, n_orb, ordering, excitation))) for op in pool])

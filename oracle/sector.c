@@ -10,6 +10,11 @@
  *    obtained by applying the operators one at a time in this way.
  *  - Excitation rotations U = exp(theta (tau - tau^+)), tau = a^+_a a^+_b a_j a_i
  *    (singles a^+_a a_i); U acts on the pairs (x, x') with tau|x> = s|x'>.
+ *    Excitation kind 1 (qubit excitations, the QEB pool of the paper's ADAPT
+ *    runs, Computational Details) applies the same factors as qubit raising /
+ *    lowering operators: the bit flips without a parity sign.
+ *  - ADAPT pool screening: for each pool operator the energy derivative of
+ *    appending it at angle 0, <psi|[H, T]|psi> = 2 Re <H psi| T |psi>.
  *  - The Hamiltonian with the Strategy-2 one-body potential folded into h:
  *      H = E_core + sum_{pq,s} h_pq a^+_{ps} a_{qs}
  *             + 1/2 sum_{pqrs,st} (pq|rs) a^+_{ps} a^+_{rt} a_{st} a_{qs}
@@ -48,6 +53,7 @@ typedef struct {
     int32_t *ranka, *rankb; /* 2^M lookup, -1 when not in list */
     uint64_t *xa, *xb;      /* qubit string of each alpha / beta string */
     int qa[32], qb[32];     /* qubit of orbital p for each spin */
+    int exc;                /* excitation kind: 0 fermionic, 1 qubit */
 } sec_t;
 
 static int popc64(uint64_t v) { return __builtin_popcountll(v); }
@@ -57,15 +63,16 @@ static int qubit_of(int M, int ordering, int p, int s) {
 }
 
 /* Apply a^+_q (dag=1) or a_q (dag=0) to the string *x in place.  Returns the
- * JW sign (+1/-1) or 0 when the operator annihilates the string. */
-static int jw(uint64_t *x, int dag, int q) {
+ * JW sign (+1/-1) or 0 when the operator annihilates the string.  qubit = 1:
+ * the qubit raising / lowering operator instead (sign +1). */
+static int jw(uint64_t *x, int dag, int q, int qubit) {
     uint64_t bit = 1ull << q;
     if (dag) {
         if (*x & bit) return 0;
     } else {
         if (!(*x & bit)) return 0;
     }
-    int par = popc64(*x & (bit - 1)) & 1;
+    int par = qubit ? 0 : (popc64(*x & (bit - 1)) & 1);
     *x ^= bit;
     return par ? -1 : 1;
 }
@@ -153,7 +160,7 @@ static int apply_tau(const sec_t *S, const int32_t *op, int adjoint, uint64_t *x
 #undef SOQ
     int sign = 1;
     for (int k = 0; k < cnt; ++k) {
-        int s = jw(x, d[k], q[k]);
+        int s = jw(x, d[k], q[k], S->exc);
         if (!s) return 0;
         sign *= s;
     }
@@ -213,11 +220,12 @@ static void set_reference(const sec_t *S, double *psi) {
 
 /* psi = U_K(theta_K) ... U_1(theta_1) |reference>; first listed op first. */
 int or_ansatz(int M, int na, int nb, int ordering, int K, const int32_t *ops,
-              const double *theta, double *psi) {
+              const double *theta, int excitation, double *psi) {
     sec_t S;
     if (check_ops(M, K, ops)) return -1;
     int rc = sec_init(&S, M, na, nb, ordering);
     if (rc) return rc;
+    S.exc = excitation;
     set_reference(&S, psi);
     for (int k = 0; k < K; ++k) rotate(&S, ops + 4 * k, theta[k], psi);
     sec_free(&S);
@@ -226,11 +234,12 @@ int or_ansatz(int M, int na, int nb, int ordering, int K, const int32_t *ops,
 
 /* Apply the listed rotations in order to a given sector vector. */
 int or_apply_rotations(int M, int na, int nb, int ordering, int K, const int32_t *ops,
-                       const double *theta, double *psi) {
+                       const double *theta, int excitation, double *psi) {
     sec_t S;
     if (check_ops(M, K, ops)) return -1;
     int rc = sec_init(&S, M, na, nb, ordering);
     if (rc) return rc;
+    S.exc = excitation;
     for (int k = 0; k < K; ++k) rotate(&S, ops + 4 * k, theta[k], psi);
     sec_free(&S);
     return 0;
@@ -261,9 +270,9 @@ static int build_exc(int M, const uint32_t *str, const int32_t *rank, long ns, e
         for (int p = 0; p < M; ++p)
             for (int q = 0; q < M; ++q) {
                 uint64_t x = str[J];
-                int s = jw(&x, 0, q);
+                int s = jw(&x, 0, q, 0);
                 if (!s) continue;
-                int s2 = jw(&x, 1, p);
+                int s2 = jw(&x, 1, p, 0);
                 if (!s2) continue;
                 cnt[rank[x] + 1]++;
             }
@@ -275,9 +284,9 @@ static int build_exc(int M, const uint32_t *str, const int32_t *rank, long ns, e
         for (int p = 0; p < M; ++p)
             for (int q = 0; q < M; ++q) {
                 uint64_t x = str[J];
-                int s = jw(&x, 0, q);
+                int s = jw(&x, 0, q, 0);
                 if (!s) continue;
-                int s2 = jw(&x, 1, p);
+                int s2 = jw(&x, 1, p, 0);
                 if (!s2) continue;
                 long I = rank[x];
                 exc_t t = {(int32_t)J, (int16_t)p, (int16_t)q, (int8_t)(s * s2)};
@@ -301,28 +310,28 @@ static int build_same_spin(int M, const uint32_t *str, const int32_t *rank, long
         for (int p = 0; p < M; ++p)
             for (int q = 0; q < M; ++q) {
                 uint64_t x = str[J];
-                int s = jw(&x, 0, q);
+                int s = jw(&x, 0, q, 0);
                 if (!s) continue;
-                int s2 = jw(&x, 1, p);
+                int s2 = jw(&x, 1, p, 0);
                 if (!s2) continue;
                 dense[(size_t)rank[x] * ns + J] += h[p * M + q] * s * s2;
             }
         /* a^+_p a^+_r a_s a_q: a_q acts first, then a_s, a^+_r, a^+_p */
         for (int q = 0; q < M; ++q) {
             uint64_t x1 = str[J];
-            int t1 = jw(&x1, 0, q);
+            int t1 = jw(&x1, 0, q, 0);
             if (!t1) continue;
             for (int s_ = 0; s_ < M; ++s_) {
                 uint64_t x2 = x1;
-                int t2 = jw(&x2, 0, s_);
+                int t2 = jw(&x2, 0, s_, 0);
                 if (!t2) continue;
                 for (int r = 0; r < M; ++r) {
                     uint64_t x3 = x2;
-                    int t3 = jw(&x3, 1, r);
+                    int t3 = jw(&x3, 1, r, 0);
                     if (!t3) continue;
                     for (int p = 0; p < M; ++p) {
                         uint64_t x4 = x3;
-                        int t4 = jw(&x4, 1, p);
+                        int t4 = jw(&x4, 1, p, 0);
                         if (!t4) continue;
                         double v = 0.5 * g[p * M3 + q * M2 + r * M + s_];
                         dense[(size_t)rank[x4] * ns + J] += v * t1 * t2 * t3 * t4;
@@ -459,9 +468,9 @@ int or_rdm1(int M, int na, int nb, int ordering, const double *psi, double *gamm
 #pragma omp parallel for reduction(+ : re, im) schedule(static)
                 for (long r = 0; r < dim; ++r) {
                     uint64_t x = S.xa[r / nsb] | S.xb[r % nsb];
-                    int t1 = jw(&x, 0, qq);
+                    int t1 = jw(&x, 0, qq, 0);
                     if (!t1) continue;
-                    int t2 = jw(&x, 1, qp);
+                    int t2 = jw(&x, 1, qp, 0);
                     if (!t2) continue;
                     long rp = sec_index(&S, x);
                     /* conj(psi[rp]) * sign * psi[r] */
@@ -507,13 +516,14 @@ static double overlap_T(const sec_t *S, const int32_t *op, const double *lam, co
  * state when the reverse pass reaches it (stride = 1 recomputes one operator).
  */
 int or_energy_grad(int M, int na, int nb, int ordering, const double *h, const double *g,
-                   double e_core, int K, const int32_t *ops, const double *theta,
+                   double e_core, int K, const int32_t *ops, const double *theta, int excitation,
                    int stride, double *E, double *grad) {
     sec_t S;
     if (check_ops(M, K, ops)) return -1;
     if (stride < 1) stride = 1;
     int rc = sec_init(&S, M, na, nb, ordering);
     if (rc) return rc;
+    S.exc = excitation;
     const long dim = S.dim;
     const size_t vb = sizeof(double) * 2 * dim;
     const int nstore = K / stride + 1;
@@ -561,6 +571,26 @@ int or_energy_grad(int M, int na, int nb, int ordering, const double *h, const d
 done:
     if (store) for (int i = 0; i < nstore; ++i) free(store[i]);
     free(store); free(psi); free(lam); free(seg);
+    sec_free(&S);
+    return rc;
+}
+
+/* ADAPT screening: grad[t] = 2 Re <H psi| T_t |psi> for the P pool operators
+ * (kind `excitation`) at the sector state psi. */
+int or_pool_gradients(int M, int na, int nb, int ordering, const double *h, const double *g,
+                      double e_core, const double *psi, int P, const int32_t *pool, int excitation,
+                      double *grad) {
+    sec_t S;
+    if (check_ops(M, P, pool)) return -1;
+    int rc = sec_init(&S, M, na, nb, ordering);
+    if (rc) return rc;
+    S.exc = excitation;
+    double *lam = (double *)malloc(sizeof(double) * 2 * S.dim);
+    if (!lam) { sec_free(&S); return -2; }
+    rc = or_sigma(M, na, nb, ordering, h, g, e_core, psi, lam);
+    if (!rc)
+        for (int t = 0; t < P; ++t) grad[t] = 2.0 * overlap_T(&S, pool + 4 * t, lam, psi);
+    free(lam);
     sec_free(&S);
     return rc;
 }

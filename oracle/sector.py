@@ -43,12 +43,14 @@ def _load():
         lib.or_dim.restype = ctypes.c_long
         lib.or_dim.argtypes = [c_int, c_int, c_int]
         lib.or_sector_qubit_index.argtypes = [c_int, c_int, c_int, c_int, u64]
-        lib.or_ansatz.argtypes = [c_int, c_int, c_int, c_int, c_int, i32, d, d]
-        lib.or_apply_rotations.argtypes = [c_int, c_int, c_int, c_int, c_int, i32, d, d]
+        lib.or_ansatz.argtypes = [c_int, c_int, c_int, c_int, c_int, i32, d, c_int, d]
+        lib.or_apply_rotations.argtypes = [c_int, c_int, c_int, c_int, c_int, i32, d, c_int, d]
         lib.or_sigma.argtypes = [c_int, c_int, c_int, c_int, d, d, ctypes.c_double, d, d]
         lib.or_rdm1.argtypes = [c_int, c_int, c_int, c_int, d, d]
         lib.or_energy_grad.argtypes = [c_int, c_int, c_int, c_int, d, d, ctypes.c_double,
-                                       c_int, i32, d, c_int, d, d]
+                                       c_int, i32, d, c_int, c_int, d, d]
+        lib.or_pool_gradients.argtypes = [c_int, c_int, c_int, c_int, d, d, ctypes.c_double, d,
+                                          c_int, i32, c_int, d]
         lib.or_num_threads.restype = c_int
         _lib = lib
     return _lib
@@ -87,21 +89,23 @@ def _ops(ops):
     return np.ascontiguousarray(np.asarray(ops, dtype=np.int32).reshape(-1, 4))
 
 
-def ansatz(n_orb, n_alpha, n_beta, ops, theta, ordering=0) -> np.ndarray:
+def ansatz(n_orb, n_alpha, n_beta, ops, theta, ordering=0, excitation=0) -> np.ndarray:
+    """Sector vector of U_K ... U_1 |ref> (excitation 0 fermionic, 1 qubit)."""
     ops = _ops(ops)
     theta = np.ascontiguousarray(theta, dtype=np.float64)
     psi = np.zeros(dim(n_orb, n_alpha, n_beta), dtype=np.complex128)
     _check(_load().or_ansatz(n_orb, n_alpha, n_beta, ordering, len(ops), _ip(ops), _dp(theta),
-                             _dp(psi.view(np.float64))), "ansatz")
+                             int(excitation), _dp(psi.view(np.float64))), "ansatz")
     return psi
 
 
-def apply_rotations(psi, n_orb, n_alpha, n_beta, ops, theta, ordering=0) -> np.ndarray:
+def apply_rotations(psi, n_orb, n_alpha, n_beta, ops, theta, ordering=0, excitation=0) -> np.ndarray:
     ops = _ops(ops)
     theta = np.ascontiguousarray(theta, dtype=np.float64)
     psi = np.ascontiguousarray(psi, dtype=np.complex128).copy()
     _check(_load().or_apply_rotations(n_orb, n_alpha, n_beta, ordering, len(ops), _ip(ops),
-                                      _dp(theta), _dp(psi.view(np.float64))), "apply_rotations")
+                                      _dp(theta), int(excitation), _dp(psi.view(np.float64))),
+           "apply_rotations")
     return psi
 
 
@@ -129,7 +133,8 @@ def rdm1(psi, n_orb, n_alpha, n_beta, ordering=0) -> np.ndarray:
     return gam
 
 
-def energy_grad(n_orb, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, stride=None):
+def energy_grad(n_orb, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, stride=None,
+                excitation=0):
     """Stored-state adjoint: the state before every `stride`-th operator is
     kept and each segment is recomputed once (default: all states when they fit
     in 4 GiB, else stride ~ sqrt(K))."""
@@ -146,9 +151,25 @@ def energy_grad(n_orb, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, st
     e = ctypes.c_double(0.0)
     grad = np.zeros(k, dtype=np.float64)
     _check(_load().or_energy_grad(n_orb, n_alpha, n_beta, ordering, _dp(h), _dp(g), float(e_core),
-                                  k, _ip(ops), _dp(theta), int(stride), ctypes.byref(e), _dp(grad)),
+                                  k, _ip(ops), _dp(theta), int(excitation), int(stride),
+                                  ctypes.byref(e), _dp(grad)),
            "energy_grad")
     return float(e.value), grad
+
+
+def pool_gradients(psi, h, g, e_core, pool, n_alpha, n_beta, ordering=0, excitation=0) -> np.ndarray:
+    """ADAPT screening at the sector state psi: 2 Re <H psi| T_op |psi> for every
+    pool operator (see sector.c)."""
+    m = h.shape[0]
+    pool = _ops(pool)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    out = np.zeros(len(pool), dtype=np.float64)
+    _check(_load().or_pool_gradients(m, n_alpha, n_beta, ordering, _dp(h), _dp(g), float(e_core),
+                                     _dp(psi.view(np.float64)), len(pool), _ip(pool), int(excitation),
+                                     _dp(out)), "pool_gradients")
+    return out
 
 
 def fci_energy(h, g, e_core, n_alpha, n_beta, ordering=0, k=1) -> float:
