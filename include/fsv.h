@@ -19,7 +19,9 @@
  *  - An operator is four int32 {a, b, j, i}: tau = a^+_a a^+_b a_j a_i; a
  *    single excitation is {a, -1, -1, i}: tau = a^+_a a_i.  Indices are
  *    spin-orbital labels; they must be distinct, in range and conserve the
- *    number of alpha and of beta electrons.  U_k = exp(theta_k (tau - tau^+)),
+ *    number of alpha and of beta electrons.  With excitation = 1 the same four
+ *    labels name a qubit excitation (the factors act as qubit raising /
+ *    lowering operators, without JW signs).  U_k = exp(theta_k (tau - tau^+)),
  *    theta in radians, and the ansatz is U_K ... U_1 |ref>: the first listed
  *    operator acts first.  |ref> fills the lowest n_alpha alpha and n_beta beta
  *    orbitals with amplitude +1 (the paper's HF initial state).
@@ -61,6 +63,7 @@ extern "C" {
 
 typedef struct fsv_plan fsv_plan;
 typedef struct fsv_batch fsv_batch;
+typedef struct fsv_pool fsv_pool;
 
 typedef struct {
     int32_t n_qubits;   /* 2 .. 34, even */
@@ -73,6 +76,10 @@ typedef struct {
     double e_core;      /* constant added through H (0 for synthetic inputs) */
     int32_t n_ops;      /* K >= 0 */
     const int32_t *ops; /* host, K x 4 {a, b, j, i}, copied at plan creation */
+    int32_t excitation; /* 0 fermionic excitations (JW signs); 1 qubit excitations
+                           (QEB: Q^+_a Q^+_b Q_j Q_i on the plan's qubits, every
+                           pair sign +1 in the qubit basis; the pool of the
+                           paper's ADAPT runs, Computational Details) */
 } fsv_problem;
 
 /* Message of the last failure on this thread ("" when none). */
@@ -175,6 +182,25 @@ int fsv_finish(fsv_plan *plan, double *E_out, double *grad_out);
  * are distinct work buffers.  *report (may be NULL) receives a static summary
  * string. */
 int fsv_autotune(fsv_plan *plan, void *psi_dev, void *lam_dev, const char **report);
+
+/* ---- ADAPT operator-pool screening ----
+ * ADAPT grows the ansatz by the pool operator with the largest energy
+ * derivative (Computational Details: ADAPT-VQE with a QEB pool).  For an
+ * operator T appended at angle 0 to the plan's ansatz at theta that
+ * derivative is <psi| [H, T] |psi> = 2 Re <H psi| T |psi>, psi = psi(theta).
+ * fsv_pool_create compiles a pool for a plan (the plan must outlive the pool
+ * and use the sector engine): ops is host, n_ops x 4 {a, b, j, i} in the
+ * plan's conventions, excitation 0 fermionic / 1 qubit (as in fsv_problem).
+ * Errors: FSV_EINVAL for an invalid operator, FSV_ESTATE for a dense-engine
+ * plan, FSV_ENOMEM, FSV_EDEVICE. */
+int fsv_pool_create(fsv_pool **out, fsv_plan *plan, const int32_t *ops, int32_t n_ops, int32_t excitation);
+int fsv_pool_destroy(fsv_pool *pool);
+/* Prepare psi(theta), lam = H psi, then screen every pool operator in one
+ * launch: grad_out[t] = 2 Re <lam| T_t |psi> (host, n_ops doubles); *E_out
+ * (may be NULL) receives E(theta).  theta: host, K doubles of the plan.
+ * psi_dev and lam_dev are distinct work buffers of fsv_state_bytes each. */
+int fsv_pool_gradients(fsv_pool *pool, const double *theta, void *psi_dev, void *lam_dev, double *E_out,
+                       double *grad_out);
 
 /* ---- batches: many independent instances in one graph launch ----
  * Each instance has its own problem (qubit count, electrons, integrals,

@@ -13,7 +13,7 @@ import numpy as np
 
 from ._lib import FsvError, Problem as _CProblem, check, load  # noqa: F401
 
-__all__ = ["Plan", "Batch", "EnergyFn", "FsvError", "load"]
+__all__ = ["Plan", "Pool", "Batch", "EnergyFn", "FsvError", "load"]
 
 
 def _dptr(a: np.ndarray):
@@ -29,19 +29,20 @@ def _torch():
     return torch
 
 
-def _cproblem(n_qubits, n_alpha, n_beta, h, g, ops, e_core, ordering, precision, keep):
+def _cproblem(n_qubits, n_alpha, n_beta, h, g, ops, e_core, ordering, precision, keep, excitation=0):
     h = np.ascontiguousarray(h, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
     ops = np.ascontiguousarray(np.asarray(ops, dtype=np.int32).reshape(-1, 4))
     keep.extend([h, g, ops])
     return _CProblem(int(n_qubits), int(n_alpha), int(n_beta), int(ordering), int(precision),
-                     _dptr(h), _dptr(g), float(e_core), int(ops.shape[0]), _iptr(ops))
+                     _dptr(h), _dptr(g), float(e_core), int(ops.shape[0]), _iptr(ops), int(excitation))
 
 
 class Plan:
     """One problem (qubits, electrons, integrals, operator list) bound to one
     HIP stream.  `problem` is any object with the attributes of
-    workloads.Problem (n_qubits, n_alpha, n_beta, h, g, ops, e_core, ordering)."""
+    workloads.Problem (n_qubits, n_alpha, n_beta, h, g, ops, e_core, ordering,
+    excitation: 0 fermionic / 1 qubit excitations)."""
 
     ENGINES = {"sector": 0, "dense": 1}
 
@@ -58,8 +59,10 @@ class Plan:
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         keep = []
+        self.excitation = int(getattr(problem, "excitation", 0))
         cp = _cproblem(problem.n_qubits, problem.n_alpha, problem.n_beta, problem.h, problem.g,
-                       problem.ops, getattr(problem, "e_core", 0.0), self.ordering, self.precision, keep)
+                       problem.ops, getattr(problem, "e_core", 0.0), self.ordering, self.precision, keep,
+                       self.excitation)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(lib.fsv_plan_create(ctypes.byref(handle), ctypes.byref(cp),
@@ -79,6 +82,11 @@ class Plan:
         sector, compactly; 'dense': every active pair of the 2^n vector."""
         check(self._lib.fsv_plan_set_engine(self._h, self.ENGINES[engine]))
         self.engine = engine
+
+    def pool(self, ops, excitation: int | None = None):
+        """An operator pool for ADAPT screening on this plan (sector engine);
+        excitation defaults to the plan's own."""
+        return Pool(self, ops, self.excitation if excitation is None else excitation)
 
     def runs(self, adjoint: bool = False):
         """Operator runs of the sector engine's forward (or adjoint) sweep:
@@ -199,6 +207,49 @@ class Plan:
             pass
 
 
+class Pool:
+    """ADAPT operator-pool screening on a plan: for each pool operator T,
+    2 Re <H psi| T |psi> at psi = psi(theta), one launch for the whole pool."""
+
+    def __init__(self, plan, ops, excitation: int = 0):
+        self.plan = plan
+        self.ops = np.ascontiguousarray(np.asarray(ops, dtype=np.int32).reshape(-1, 4))
+        self.n = int(self.ops.shape[0])
+        self.excitation = int(excitation)
+        handle = ctypes.c_void_p()
+        torch = _torch()
+        with torch.cuda.device(plan.device):
+            check(plan._lib.fsv_pool_create(ctypes.byref(handle), plan._h, _iptr(self.ops), self.n,
+                                            self.excitation))
+        self._h = handle
+        self._lib = plan._lib
+
+    def gradients(self, theta, psi=None, lam=None):
+        """(E(theta), screening values) with psi / lam work buffers of the
+        plan (allocated when not given)."""
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if th.size != self.plan.n_ops:
+            raise ValueError(f"theta must have {self.plan.n_ops} entries")
+        psi = self.plan.new_state() if psi is None else psi
+        lam = self.plan.new_state() if lam is None else lam
+        e = ctypes.c_double(0.0)
+        g = np.zeros(self.n)
+        check(self._lib.fsv_pool_gradients(self._h, _dptr(th), self.plan._check_state(psi),
+                                           self.plan._check_state(lam), ctypes.byref(e), _dptr(g)))
+        return float(e.value), g
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(self._lib.fsv_pool_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Many independent problems evaluated together (energy + adjoint gradient
     of each) in one persistent graph launch."""
@@ -214,7 +265,7 @@ class Batch:
         self.n_ops = []
         for i, p in enumerate(problems):
             arr[i] = _cproblem(p.n_qubits, p.n_alpha, p.n_beta, p.h, p.g, p.ops,
-                               getattr(p, "e_core", 0.0), p.ordering, 0, keep)
+                               getattr(p, "e_core", 0.0), p.ordering, 0, keep, getattr(p, "excitation", 0))
             self.n_ops.append(int(np.asarray(p.ops).reshape(-1, 4).shape[0]))
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -37,6 +37,7 @@ class Problem(ctypes.Structure):
         ("e_core", ctypes.c_double),
         ("n_ops", ctypes.c_int32),
         ("ops", ctypes.POINTER(ctypes.c_int32)),
+        ("excitation", ctypes.c_int32),
     ]
 
 
@@ -46,7 +47,7 @@ EXPORTS = [
     "ansatz_apply", "energy", "energy_grad", "energy_grad_fd", "rdm1", "set_onebody_potential",
     "fsv_set_theta", "fsv_forward_async", "fsv_sigma_async", "fsv_reverse_async", "fsv_finish",
     "fsv_autotune", "fsv_batch_create", "fsv_batch_destroy", "fsv_batch_energy_grad",
-    "fsv_batch_bytes", "fsv_batch_autotune",
+    "fsv_batch_bytes", "fsv_batch_autotune", "fsv_pool_create", "fsv_pool_destroy", "fsv_pool_gradients",
 ]
 
 _lib = None
@@ -89,6 +90,9 @@ def load():
     lib.fsv_batch_bytes.restype = ctypes.c_size_t
     lib.fsv_batch_bytes.argtypes = [vp]
     lib.fsv_batch_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p)]
+    lib.fsv_pool_create.argtypes = [ctypes.POINTER(vp), vp, i32, ctypes.c_int32, ctypes.c_int32]
+    lib.fsv_pool_destroy.argtypes = [vp]
+    lib.fsv_pool_gradients.argtypes = [vp, d, vp, vp, d, d]
     for name in EXPORTS:
         if name not in ("fsv_last_error", "fsv_state_bytes", "fsv_batch_bytes"):
             getattr(lib, name).restype = c_int

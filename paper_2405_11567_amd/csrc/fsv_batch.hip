@@ -620,10 +620,12 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         for (int r = 0; r < I.nsb; ++r)
             for (int f = 0; f < I.nexcB; ++f)
                 excBT[I.off_excB + (int64_t)f * I.nsb + r] = eb[(size_t)r * I.nexcB + f];
-        // operators in the alpha-first basis = the blocked JW ordering
+        // operators in the alpha-first basis = the blocked JW ordering (qubit
+        // excitations carry the signs of the instance's own qubit ordering)
         double pairs = 0.0;
         for (int k = 0; k < p.n_ops; ++k) {
-            const BOp o = build_pair_op(M, p.ops + 4 * k, sa, ra, sb, rb, lists);
+            const BOp o = p.excitation ? build_pair_op_qeb(M, p.ordering, p.ops + 4 * k, sa, ra, sb, rb, lists)
+                                       : build_pair_op(M, p.ops + 4 * k, sa, ra, sb, rb, lists);
             pairs += (double)(o.nA >= 0 ? o.nA : I.nsa) * (double)(o.nB >= 0 ? o.nB : I.nsb);
             ops.push_back(o);
         }

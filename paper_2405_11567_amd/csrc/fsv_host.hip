@@ -118,6 +118,7 @@ struct fsv_plan {
 
     // sector-compressed engine (default for energy_grad / ansatz_apply)
     int engine = 0;  // 0 sector-compressed, 1 dense
+    int excitation = 0;  // 0 fermionic, 1 qubit excitations
     int svt = V_F64;  // storage of the sector state: real FP64, or real FP32 for precision 1
     SectorTabs tabs{};
     int lr_R = 0;     // rank of the factorised alpha-beta product (0: direct)
@@ -135,6 +136,7 @@ struct fsv_plan {
     int fuse_mode = 0;  // 0 cost model, 1 never (FSV_NO_FUSE), 2 every run (FSV_FORCE_FUSE)
 
     // graphs
+    uint64_t gen = 0;  // bumped whenever captured launches may have changed
     bool use_graph = true;
     hipGraphExec_t g_eg = nullptr;
     const void *g_eg_psi = nullptr, *g_eg_lam = nullptr;
@@ -142,6 +144,26 @@ struct fsv_plan {
     const void *g_e_psi = nullptr;
 
     ~fsv_plan();
+};
+
+// An operator pool compiled for one plan's sector (ADAPT screening).
+struct fsv_pool {
+    fsv_plan *plan = nullptr;
+    int n = 0, gx = 1;
+    PairOp *d_ops = nullptr;
+    uint32_t *d_lists = nullptr;
+    double *d_part = nullptr, *d_out = nullptr;
+    int *d_counts = nullptr;
+    double *h_pin = nullptr;  // E, then the n screening values
+    hipGraphExec_t graph = nullptr;
+    const void *g_psi = nullptr, *g_lam = nullptr;
+    uint64_t gen = 0;
+    std::vector<void *> mem;
+    ~fsv_pool() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        for (void *p : mem) (void)hipFree(p);
+        if (h_pin) (void)hipHostFree(h_pin);
+    }
 };
 
 namespace {
@@ -208,9 +230,14 @@ int fsv::validate_problem(const fsv_problem *p) {
                     if (std::fabs(x - y1) > tol || std::fabs(x - y2) > tol || std::fabs(x - y3) > tol)
                         return fail(FSV_EINVAL, "g lacks 8-fold symmetry at (%d%d|%d%d)", q, r, s, t);
                 }
-    const int n = p->n_qubits;
-    for (int k = 0; k < p->n_ops; ++k) {
-        const int32_t *o = p->ops + 4 * k;
+    if (p->excitation != 0 && p->excitation != 1) return fail(FSV_EINVAL, "excitation must be 0 or 1");
+    return validate_ops(p->n_qubits, p->n_ops, p->ops);
+}
+
+int fsv::validate_ops(int n, int n_ops, const int32_t *ops) {
+    if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(FSV_EINVAL, "bad n_ops/ops");
+    for (int k = 0; k < n_ops; ++k) {
+        const int32_t *o = ops + 4 * k;
         const int a = o[0], b = o[1], j = o[2], i = o[3];
         const bool single = (b < 0);
         if (single) {
@@ -234,8 +261,9 @@ int fsv::validate_problem(const fsv_problem *p) {
 
 // Compile one operator for a given qubit ordering: sorted target qubits,
 // source/destination patterns, the parity mask of non-target bits and the
-// constant sign of the JW string of tau.
-RotOp fsv::compile_op(int M, int ordering, const int32_t *o) {
+// constant sign of the JW string of tau (excitation 1: a qubit excitation,
+// sign +1 on every pair).
+RotOp fsv::compile_op(int M, int ordering, const int32_t *o, int excitation) {
     auto qubit = [&](int so) { return ordering == 0 ? so : so / 2 + (so % 2) * M; };
     RotOp r{};
     const bool single = o[1] < 0;
@@ -265,10 +293,10 @@ RotOp fsv::compile_op(int M, int ordering, const int32_t *o) {
     sg *= jw_step(x, true, qa);
     r.src = src;
     r.dst = dst;
-    r.par = par;
+    r.par = excitation ? 0ull : par;  // a qubit excitation has no JW string
     for (int t = 0; t < 4; ++t) r.q[t] = t < nt ? (uint32_t)qs[t] : 0u;
     r.nt = nt;
-    r.sign0 = sg;
+    r.sign0 = excitation ? 1 : sg;
     return r;
 }
 
@@ -419,6 +447,77 @@ PairOp build_pair_op(int M, const int32_t *op, const std::vector<uint32_t> &sa,
     make((uint32_t)(r.src & mask), (uint32_t)(r.dst & mask), (uint32_t)(r.par & mask), sa, ra, o.nA, o.offA);
     make((uint32_t)((r.src >> M) & mask), (uint32_t)((r.dst >> M) & mask), (uint32_t)((r.par >> M) & mask),
          sb, rb, o.nB, o.offB);
+    return o;
+}
+
+// Pair lists of one qubit excitation Q^+_a Q^+_b Q_j Q_i (sign +1 on every
+// pair in the plan's qubit basis).  The alpha-first sector basis differs from
+// the qubit basis by phi(A, B) = (-1)^N(A, B), N(A, B) = #{(q in A, r in B):
+// qubit(r, beta) < qubit(q, alpha)}, so a pair (x, x') carries phi(x) phi(x').
+// N is bilinear, hence N(A', B') + N(A, B) = D1(B') + D2(A) mod 2 with
+//   D1(B') = sum over the alpha orbitals q the operator changes of
+//            #{r in B': qubit(r, beta) < qubit(q, alpha)},
+//   D2(A)  = sum over the beta orbitals r it changes of
+//            #{q in A: qubit(r, beta) < qubit(q, alpha)},
+// an alpha-source factor times a beta-destination factor.  A spin that the
+// operator leaves alone gets an explicit diagonal list when its factor is not
+// constant (interleaved ordering); in the blocked ordering every factor is 1.
+PairOp build_pair_op_qeb(int M, int ordering, const int32_t *op, const std::vector<uint32_t> &sa,
+                         const std::vector<int32_t> &ra, const std::vector<uint32_t> &sb,
+                         const std::vector<int32_t> &rb, std::vector<uint32_t> &lists) {
+    auto qa = [&](int p) { return ordering == 0 ? 2 * p : p; };
+    auto qb = [&](int p) { return ordering == 0 ? 2 * p + 1 : p + M; };
+    uint32_t ann[2] = {0, 0}, cre[2] = {0, 0};
+    for (int t = 2; t < 4; ++t)
+        if (op[t] >= 0) ann[op[t] % 2] |= 1u << (op[t] / 2);
+    for (int t = 0; t < 2; ++t)
+        if (op[t] >= 0) cre[op[t] % 2] |= 1u << (op[t] / 2);
+    const uint32_t chA = ann[0] | cre[0], chB = ann[1] | cre[1];
+    std::vector<uint32_t> lowB(M, 0), highA(M, 0);  // {r : qb(r) < qa(q)}, {q : qb(r) < qa(q)}
+    for (int q = 0; q < M; ++q)
+        for (int r = 0; r < M; ++r)
+            if (qb(r) < qa(q)) {
+                lowB[q] |= 1u << r;
+                highA[r] |= 1u << q;
+            }
+    auto d1 = [&](uint32_t B) {
+        int c = 0;
+        for (int q = 0; q < M; ++q)
+            if (chA >> q & 1u) c += __builtin_popcount(B & lowB[q]);
+        return c & 1;
+    };
+    auto d2 = [&](uint32_t A) {
+        int c = 0;
+        for (int r = 0; r < M; ++r)
+            if (chB >> r & 1u) c += __builtin_popcount(A & highA[r]);
+        return c & 1;
+    };
+    PairOp o{};
+    o.sign0 = 1;
+    auto part = [&](uint32_t an, uint32_t cr, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
+                    bool src_factor, int32_t &n, int64_t &off) {
+        off = (int64_t)lists.size();
+        if (an | cr) {
+            for (uint32_t s : str) {
+                if ((s & an) != an || (s & cr) != 0) continue;
+                const uint32_t d = s ^ an ^ cr;
+                lists.push_back(pack_pair((uint32_t)rank[s], (uint32_t)rank[d], src_factor ? d2(s) : d1(d)));
+            }
+        } else {
+            bool any = false;
+            for (uint32_t s : str) any = any || (src_factor ? d2(s) : d1(s));
+            if (!any) {
+                n = -1;
+                off = 0;
+                return;
+            }
+            for (uint32_t s : str)
+                lists.push_back(pack_pair((uint32_t)rank[s], (uint32_t)rank[s], src_factor ? d2(s) : d1(s)));
+        }
+        n = (int32_t)((int64_t)lists.size() - off);
+    };
+    part(ann[0], cre[0], sa, ra, true, o.nA, o.offA);
+    part(ann[1], cre[1], sb, rb, false, o.nB, o.offB);
     return o;
 }
 
@@ -582,6 +681,7 @@ int upload_counts(fsv_plan &P) {
 }
 
 void drop_graphs(fsv_plan &P) {
+    ++P.gen;  // graphs of pools built on this plan are stale too
     if (P.g_eg) (void)hipGraphExecDestroy(P.g_eg);
     if (P.g_e) (void)hipGraphExecDestroy(P.g_e);
     P.g_eg = nullptr;
@@ -897,7 +997,8 @@ int build_device(fsv_plan &P) {
     plists.clear();
     P.pops.clear();
     for (int k = 0; k < P.K; ++k)
-        P.pops.push_back(build_pair_op(M, P.ops.data() + 4 * k, P.sa, ra, P.sb, rb, plists));
+        P.pops.push_back(P.excitation ? build_pair_op_qeb(M, P.ordering, P.ops.data() + 4 * k, P.sa, ra, P.sb, rb, plists)
+                                      : build_pair_op(M, P.ops.data() + 4 * k, P.sa, ra, P.sb, rb, plists));
     if ((rc = dalloc(P, &P.d_plists, plists.size()))) return rc;
     if ((rc = dalloc(P, &P.d_pops, (size_t)P.K))) return rc;
     if ((rc = dalloc(P, &P.d_ccount, (size_t)std::max(P.K, 1)))) return rc;
@@ -1117,8 +1218,9 @@ int fsv_plan_create(fsv_plan **out, const fsv_problem *p, void *hip_stream) {
     P->user = (hipStream_t)hip_stream;
     P->use_graph = std::getenv("FSV_NO_GRAPH") == nullptr;
     if (const char *e = std::getenv("FSV_ENGINE")) P->engine = std::strcmp(e, "dense") == 0 ? 1 : 0;
+    P->excitation = p->excitation;
     for (int k = 0; k < P->K; ++k) {
-        P->rot.push_back(compile_op(P->M, P->ordering, P->ops.data() + 4 * k));
+        P->rot.push_back(compile_op(P->M, P->ordering, P->ops.data() + 4 * k, P->excitation));
         P->npairs.push_back(1ull << (P->n - P->rot.back().nt));
     }
     plan_segments(*P);
@@ -1413,6 +1515,112 @@ int fsv_autotune(fsv_plan *P, void *psi, void *lam, const char **report) {
     }
     if (report) *report = rep.c_str();
     return fence_out(*P);
+}
+
+// ------------------------------------------------------------ pools ----
+int fsv_pool_create(fsv_pool **out, fsv_plan *P, const int32_t *ops, int32_t n_ops, int32_t excitation) {
+    if (!out) return fail(FSV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    if (n_ops < 1 || n_ops > 65535) return fail(FSV_EINVAL, "a pool holds 1 .. 65535 operators");
+    if (excitation != 0 && excitation != 1) return fail(FSV_EINVAL, "excitation must be 0 or 1");
+    int rc = validate_ops(P->n, n_ops, ops);
+    if (rc) return rc;
+    if (P->engine != 0) return fail(FSV_ESTATE, "pool screening runs on the sector engine");
+    fsv_pool *Q = new (std::nothrow) fsv_pool();
+    if (!Q) return fail(FSV_ENOMEM, "pool allocation failed");
+    Q->plan = P;
+    Q->n = n_ops;
+    std::vector<int32_t> ra((size_t)1 << P->M, -1), rb((size_t)1 << P->M, -1);
+    for (size_t i = 0; i < P->sa.size(); ++i) ra[P->sa[i]] = (int32_t)i;
+    for (size_t i = 0; i < P->sb.size(); ++i) rb[P->sb[i]] = (int32_t)i;
+    std::vector<PairOp> pops;
+    std::vector<uint32_t> lists;
+    double maxpairs = 1.0;
+    for (int t = 0; t < n_ops; ++t) {
+        const int32_t *o = ops + 4 * t;
+        const PairOp po = excitation ? build_pair_op_qeb(P->M, P->ordering, o, P->sa, ra, P->sb, rb, lists)
+                                     : build_pair_op(P->M, o, P->sa, ra, P->sb, rb, lists);
+        maxpairs = std::max(maxpairs, (double)(po.nA >= 0 ? po.nA : P->nsa) * (double)(po.nB >= 0 ? po.nB : P->nsb));
+        pops.push_back(po);
+    }
+    // workgroups per operator: ~16 pairs per thread for the largest, at most 64
+    Q->gx = (int)std::min(64.0, std::max(1.0, std::ceil(maxpairs / (256.0 * 16.0))));
+    auto dal = [&](void **p, size_t bytes) -> int {
+        if (hipMalloc(p, std::max<size_t>(bytes, 4)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FSV_ENOMEM, "hipMalloc of %zu bytes for the pool failed", bytes);
+        }
+        Q->mem.push_back(*p);
+        return FSV_OK;
+    };
+    std::vector<int> counts(n_ops, Q->gx);
+    if ((rc = dal((void **)&Q->d_ops, sizeof(PairOp) * pops.size())) ||
+        (rc = dal((void **)&Q->d_lists, 4 * lists.size())) ||
+        (rc = dal((void **)&Q->d_part, sizeof(double) * (size_t)n_ops * Q->gx)) ||
+        (rc = dal((void **)&Q->d_out, sizeof(double) * (size_t)n_ops)) ||
+        (rc = dal((void **)&Q->d_counts, sizeof(int) * (size_t)n_ops))) {
+        delete Q;
+        return rc;
+    }
+    if (hipMemcpy(Q->d_ops, pops.data(), sizeof(PairOp) * pops.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (!lists.empty() && hipMemcpy(Q->d_lists, lists.data(), 4 * lists.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(Q->d_counts, counts.data(), sizeof(int) * counts.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipHostMalloc((void **)&Q->h_pin, sizeof(double) * ((size_t)n_ops + 1), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete Q;
+        return fail(FSV_EDEVICE, "pool upload failed");
+    }
+    *out = Q;
+    clear_error();
+    return FSV_OK;
+}
+
+int fsv_pool_destroy(fsv_pool *Q) {
+    if (!Q) return FSV_OK;
+    if (Q->plan && Q->plan->work) (void)hipStreamSynchronize(Q->plan->work);
+    delete Q;
+    return FSV_OK;
+}
+
+int fsv_pool_gradients(fsv_pool *Q, const double *theta, void *psi, void *lam, double *E_out, double *grad_out) {
+    if (!Q || !psi || !lam || !grad_out) return fail(FSV_EINVAL, "pool, psi, lam or grad_out is NULL");
+    if (psi == lam) return fail(FSV_EINVAL, "psi and lam must be distinct buffers");
+    fsv_plan &P = *Q->plan;
+    if (P.engine != 0) return fail(FSV_ESTATE, "pool screening runs on the sector engine");
+    int rc;
+    if ((rc = fence_in(P))) return rc;
+    if ((rc = upload_theta(P, theta))) return rc;
+    auto body = [&]() -> int {
+        int r;
+        if ((r = enq_forward(P, psi))) return r;
+        if ((r = enq_sigma(P, psi, lam))) return r;
+        HIPCHECK(launch_pool(P.svt, psi, lam, Q->d_ops, Q->d_lists, Q->n, Q->gx, P.nsa, P.nsb, Q->d_part, P.work));
+        HIPCHECK(launch_reduce_rows(Q->d_part, Q->d_counts, Q->gx, Q->n, 2.0, Q->d_out, P.work));
+        return FSV_OK;
+    };
+    if (!P.use_graph) {
+        if ((rc = body())) return rc;
+    } else {
+        if (!Q->graph || Q->g_psi != psi || Q->g_lam != lam || Q->gen != P.gen) {
+            if (Q->graph) (void)hipGraphExecDestroy(Q->graph);
+            Q->graph = nullptr;
+            if ((rc = capture(P, body, &Q->graph))) {
+                Q->graph = nullptr;
+                return rc;
+            }
+            Q->g_psi = psi;
+            Q->g_lam = lam;
+            Q->gen = P.gen;
+        }
+        HIPCHECK(hipGraphLaunch(Q->graph, P.work));
+    }
+    HIPCHECK(hipMemcpyAsync(Q->h_pin, P.d_out, sizeof(double), hipMemcpyDeviceToHost, P.work));
+    HIPCHECK(hipMemcpyAsync(Q->h_pin + 1, Q->d_out, sizeof(double) * Q->n, hipMemcpyDeviceToHost, P.work));
+    HIPCHECK(hipStreamSynchronize(P.work));
+    if (E_out) *E_out = Q->h_pin[0];
+    std::memcpy(grad_out, Q->h_pin + 1, sizeof(double) * Q->n);
+    return fence_out(P);
 }
 
 // Batches are built in fsv_batch.hip.

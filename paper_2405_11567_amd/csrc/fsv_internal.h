@@ -53,7 +53,9 @@ __host__ __device__ inline uint32_t pack_exc(uint32_t J, uint32_t pq, int neg) {
 int fail(int code, const char *fmt, ...);
 void clear_error();
 int validate_problem(const fsv_problem *p);
-RotOp compile_op(int M, int ordering, const int32_t *op);
+int validate_ops(int n_qubits, int n_ops, const int32_t *ops);
+// excitation 1: a qubit excitation (no JW string: sign +1 on every pair)
+RotOp compile_op(int M, int ordering, const int32_t *op, int excitation = 0);
 std::vector<uint32_t> strings_of(int M, int N);  // popcount-N masks, ascending
 void build_string_h(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
                     const double *ht, const double *g, std::vector<int64_t> &ptr,
@@ -64,6 +66,10 @@ void build_exc(int M, const std::vector<uint32_t> &str, const std::vector<int32_
 PairOp build_pair_op(int M, const int32_t *op, const std::vector<uint32_t> &sa,
                      const std::vector<int32_t> &ra, const std::vector<uint32_t> &sb,
                      const std::vector<int32_t> &rb, std::vector<uint32_t> &lists);
+// The same for a qubit excitation in the given qubit ordering.
+PairOp build_pair_op_qeb(int M, int ordering, const int32_t *op, const std::vector<uint32_t> &sa,
+                         const std::vector<int32_t> &ra, const std::vector<uint32_t> &sb,
+                         const std::vector<int32_t> &rb, std::vector<uint32_t> &lists);
 
 // ---- launchers (fsv_kernels.hip) ----
 // precision: 0 complex128, 1 complex64.  Each returns the hipError_t of the launch.
@@ -145,6 +151,10 @@ hipError_t launch_convert(int vt_in, const void *in, int vt_out, void *out, int6
 unsigned combine_grid(int64_t dim);
 hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, void *S, void *CT,
                                void *ST, double *epart, hipStream_t st);
+// ADAPT pool screening on a real sector state (V_F64 / V_F32): grid (gx, n_ops),
+// partial[t * gx + x] = workgroup x's share of Re<lam|T_t|psi> for pool op t.
+hipError_t launch_pool(int vtype, const void *psi, const void *lam, const PairOp *ops, const uint32_t *lists,
+                       int n_ops, int gx, int64_t nsa, int64_t nsb, double *partial, hipStream_t st);
 // Dense row-major copy (n x n) of an n-row CSR matrix.
 hipError_t launch_csr_dense(const int64_t *rowptr, const int32_t *col, const double *val, double *out, int64_t n,
                             hipStream_t st);

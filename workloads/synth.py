@@ -46,6 +46,7 @@ class Problem:
     ordering: int = 0             # 0 interleaved (qubit 2p+s), 1 blocked (p + s*M)
     name: str = ""
     meta: dict = field(default_factory=dict)
+    excitation: int = 0           # 0 fermionic excitations, 1 qubit excitations
 
     @property
     def n_orb(self) -> int:
