@@ -200,6 +200,37 @@ def unfused_reverse(fsv, torch, p, precision, stream, psi, lam, reps=5):
     return float(np.median(times[1:]))
 
 
+def bench_pool(fsv, torch, p, psi, lam, stages, reps=10):
+    """ADAPT screening of the whole UCCSD pool at psi(theta): forward sweep,
+    H psi, and every pool operator's 2 Re<H psi|T|psi> in one launch;
+    fermionic and qubit-excitation pools."""
+    from workloads import uccsd_pool
+    pool_ops = np.asarray(uccsd_pool(p.n_orb, p.n_alpha, p.n_beta), dtype=np.int32)
+    plan = fsv.Plan(p, device=psi.device)
+    from math import comb
+    m, na, nb = p.n_orb, p.n_alpha, p.n_beta
+    pair_bytes = sum(4 * 8 * sector_pairs(op, m, na, nb) for op in pool_ops)  # read psi, lam at both ends
+    out = {"pool_ops": int(len(pool_ops))}
+    for exc, name in ((0, "fermionic"), (1, "qubit")):
+        pool = plan.pool(pool_ops, excitation=exc)
+        pool.gradients(p.theta, psi, lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            e, g = pool.gradients(p.theta, psi, lam)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        screen_ms = max(ms - stages["forward"] - stages["sigma"], 1e-6)
+        out[name] = {"ms_per_screening": ms, "screen_ms_beyond_state": screen_ms,
+                     "pool_gradients_per_s": len(pool_ops) / (ms * 1e-3),
+                     "screen_algorithmic_GBs": pair_bytes / (screen_ms * 1e-3) / 1e9,
+                     "max_abs_grad": float(np.abs(g).max())}
+        print(f"[bench] {name} pool of {len(pool_ops)}: {ms:.3f} ms per screening", file=sys.stderr, flush=True)
+        pool.close()
+    plan.close()
+    return out
+
+
 def bench_batch(args):
     """C4: 256 independent instances (10..20 qubits), energy + adjoint gradient
     of every instance per step, in one persistent graph launch; compared with
@@ -265,6 +296,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-engine comparison run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--no-pool", action="store_true", help="skip the ADAPT pool-screening measurement")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (the known-size "
@@ -339,6 +371,15 @@ def main():
         print(f"[bench] FD gradient {fd_s:.3f} s ({2*k+1} energies), adjoint {ms:.3f} ms: "
               f"{fd['adjoint_speedup']:.0f}x", file=sys.stderr, flush=True)
 
+    pool = None
+    if args.engine == "sector" and args.precision == 0 and not args.no_pool:
+        pool = bench_pool(fsv, torch, p, psi, lam, stages)
+        if fd is not None:
+            # screening by finite differences: two energies of the ansatz with
+            # each pool operator appended at +-h
+            e_ms = fd["gradient_s"] / fd["energies"] * 1e3
+            pool["fd_screening_s_estimate"] = 2 * pool["pool_ops"] * e_ms / 1e3
+
     cpu = None if args.no_cpu else cpu_baseline(p)
     out = {
         "metric": "energy+gradient evals/s and achieved HBM GB/s at 24 qubits vs plain FD method",
@@ -366,6 +407,7 @@ def main():
         "dense_engine": dense,
         "energy": e,
         "fd_baseline": fd,
+        "adapt_pool_screening": pool,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
