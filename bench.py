@@ -297,6 +297,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--no-pool", action="store_true", help="skip the ADAPT pool-screening measurement")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-amplitude variant")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (the known-size "
@@ -371,6 +372,17 @@ def main():
         print(f"[bench] FD gradient {fd_s:.3f} s ({2*k+1} energies), adjoint {ms:.3f} ms: "
               f"{fd['adjoint_speedup']:.0f}x", file=sys.stderr, flush=True)
 
+    fp32 = None
+    if args.precision == 0 and not args.no_fp32:
+        # the FP32-amplitude variant on the same workload, its energy error
+        # against the FP64 result (which matches the FP64 oracle to 1e-10 Ha)
+        p32, ms32, evals32, st32, e32, g32 = time_engine(fsv, torch, p, 1, args.engine, max(3, args.steps // 3), 1,
+                                                         stream, psi.view(torch.float64)[: psi.numel()].view(torch.complex64),
+                                                         lam.view(torch.float64)[: lam.numel()].view(torch.complex64))
+        fp32 = {"evals_s": evals32, "ms_per_eval": ms32, "stage_ms": st32, "energy": e32,
+                "abs_energy_error_vs_fp64_Ha": abs(e32 - e), "max_abs_grad_error_vs_fp64": float(np.abs(g32 - g).max())}
+        del p32
+
     pool = None
     if args.engine == "sector" and args.precision == 0 and not args.no_pool:
         pool = bench_pool(fsv, torch, p, psi, lam, stages)
@@ -407,6 +419,7 @@ def main():
         "dense_engine": dense,
         "energy": e,
         "fd_baseline": fd,
+        "fp32_variant": fp32,
         "adapt_pool_screening": pool,
         "cpu_baseline": cpu,
     }
