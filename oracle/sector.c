@@ -509,7 +509,8 @@ static double overlap_T(const sec_t *S, const int32_t *op, const double *lam, co
 
 /*
  * Energy and gradient by the adjoint method with stored forward states:
- *   psi_k = U_k ... U_1 |ref>, lam_k = U_{k+1}^+ ... U_K^+ H psi_K,
+ *   psi_k = U_k ... U_1 psi_0 (psi_0 = |ref>, or the given initial sector
+ *   vector), lam_k = U_{k+1}^+ ... U_K^+ H psi_K,
  *   dE/dtheta_k = 2 Re <lam_k| T_k |psi_k>.
  * The states before operators 0, stride, 2*stride, ... are kept; each
  * segment's intermediate states are recomputed forward once from its kept
@@ -517,7 +518,7 @@ static double overlap_T(const sec_t *S, const int32_t *op, const double *lam, co
  */
 int or_energy_grad(int M, int na, int nb, int ordering, const double *h, const double *g,
                    double e_core, int K, const int32_t *ops, const double *theta, int excitation,
-                   int stride, double *E, double *grad) {
+                   const double *psi0, int stride, double *E, double *grad) {
     sec_t S;
     if (check_ops(M, K, ops)) return -1;
     if (stride < 1) stride = 1;
@@ -535,7 +536,8 @@ int or_energy_grad(int M, int na, int nb, int ordering, const double *h, const d
         store[i] = (double *)malloc(vb);
         if (!store[i]) { rc = -2; goto done; }
     }
-    set_reference(&S, psi);
+    if (psi0) memcpy(psi, psi0, vb); /* a given initial state instead of |ref> */
+    else set_reference(&S, psi);
     for (int k = 0; k < K; ++k) {
         if (k % stride == 0) memcpy(store[k / stride], psi, vb);
         rotate(&S, ops + 4 * k, theta[k], psi);

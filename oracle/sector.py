@@ -48,7 +48,7 @@ def _load():
         lib.or_sigma.argtypes = [c_int, c_int, c_int, c_int, d, d, ctypes.c_double, d, d]
         lib.or_rdm1.argtypes = [c_int, c_int, c_int, c_int, d, d]
         lib.or_energy_grad.argtypes = [c_int, c_int, c_int, c_int, d, d, ctypes.c_double,
-                                       c_int, i32, d, c_int, c_int, d, d]
+                                       c_int, i32, d, c_int, d, c_int, d, d]
         lib.or_pool_gradients.argtypes = [c_int, c_int, c_int, c_int, d, d, ctypes.c_double, d,
                                           c_int, i32, c_int, d]
         lib.or_num_threads.restype = c_int
@@ -87,6 +87,17 @@ def sector_qubit_index(n_orb, n_alpha, n_beta, ordering=0) -> np.ndarray:
 
 def _ops(ops):
     return np.ascontiguousarray(np.asarray(ops, dtype=np.int32).reshape(-1, 4))
+
+
+def determinants_vector(n_orb, n_alpha, n_beta, dets, coef, ordering=0) -> np.ndarray:
+    """Sector vector of sum_i coef_i |dets_i> for qubit strings dets (bit j =
+    qubit j in the ordering); every determinant must lie in the sector."""
+    idx = sector_qubit_index(n_orb, n_alpha, n_beta, ordering)
+    pos = {int(x): r for r, x in enumerate(idx)}
+    out = np.zeros(idx.size, dtype=np.complex128)
+    for x, c in zip(dets, coef):
+        out[pos[int(x)]] += c
+    return out
 
 
 def ansatz(n_orb, n_alpha, n_beta, ops, theta, ordering=0, excitation=0) -> np.ndarray:
@@ -134,10 +145,11 @@ def rdm1(psi, n_orb, n_alpha, n_beta, ordering=0) -> np.ndarray:
 
 
 def energy_grad(n_orb, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, stride=None,
-                excitation=0):
+                excitation=0, psi0=None):
     """Stored-state adjoint: the state before every `stride`-th operator is
     kept and each segment is recomputed once (default: all states when they fit
-    in 4 GiB, else stride ~ sqrt(K))."""
+    in 4 GiB, else stride ~ sqrt(K)).  psi0: initial sector vector (default
+    the reference determinant)."""
     ops = _ops(ops)
     theta = np.ascontiguousarray(theta, dtype=np.float64)
     h = np.ascontiguousarray(h, dtype=np.float64)
@@ -150,8 +162,14 @@ def energy_grad(n_orb, n_alpha, n_beta, ops, theta, h, g, e_core, ordering=0, st
             stride = max(1, int(np.ceil(np.sqrt(k))))
     e = ctypes.c_double(0.0)
     grad = np.zeros(k, dtype=np.float64)
+    p0 = None
+    if psi0 is not None:
+        p0 = np.ascontiguousarray(psi0, dtype=np.complex128)
+        if p0.size != dim(n_orb, n_alpha, n_beta):
+            raise ValueError("psi0 must be a sector vector")
     _check(_load().or_energy_grad(n_orb, n_alpha, n_beta, ordering, _dp(h), _dp(g), float(e_core),
-                                  k, _ip(ops), _dp(theta), int(excitation), int(stride),
+                                  k, _ip(ops), _dp(theta), int(excitation),
+                                  _dp(p0.view(np.float64)) if p0 is not None else None, int(stride),
                                   ctypes.byref(e), _dp(grad)),
            "energy_grad")
     return float(e.value), grad

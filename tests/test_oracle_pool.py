@@ -1,5 +1,6 @@
-"""Pins of the oracle's qubit-excitation (QEB) operators and of ADAPT pool
-screening against brute force, finite differences and exact relations.
+"""Pins of the oracle's qubit-excitation (QEB) operators, ADAPT pool screening,
+multi-determinant initial states and one-body properties
+against brute force, finite differences and exact relations.
 
 ADAPT screening value of a pool operator T at a state psi: the derivative of
 the energy when U = exp(theta T) is appended to the ansatz, at theta = 0,
@@ -125,3 +126,75 @@ def test_qubit_single_without_crossing_equals_fermionic():
     a = sector.apply_rotations(psi, m, p.n_alpha, p.n_beta, op, [0.7], 1, excitation=0)
     b = sector.apply_rotations(psi, m, p.n_alpha, p.n_beta, op, [0.7], 1, excitation=1)
     assert np.abs(a - b).max() < 1e-15
+
+
+# --------------------------------------------------------------- P13-P15 -----
+def _random_dets(p, n_det, seed):
+    """n_det distinct sector determinants (qubit strings) and normalised real
+    coefficients, the reference first."""
+    idx = sector.sector_qubit_index(p.n_orb, p.n_alpha, p.n_beta, p.ordering).astype(np.int64)
+    rng = np.random.default_rng(seed)
+    pick = np.r_[0, 1 + rng.choice(idx.size - 1, n_det - 1, replace=False)]
+    coef = rng.normal(size=n_det)
+    coef[0] += 3.0
+    return idx[pick], coef / np.linalg.norm(coef)
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_multideterminant_start_brute_force(ordering):
+    # a multi-determinant initial state: energy at theta = 0 is Phi^T H Phi
+    # (brute-force matrix), and the rotations applied to it match expm products
+    p = random_problem(8, 4, 12, seed=71, theta_std=0.4, ordering=ordering)
+    m, n = p.n_orb, 8
+    dets, coef = _random_dets(p, 6, 72)
+    phi = np.zeros(1 << n, dtype=np.complex128)
+    phi[dets] = coef
+    H = brute.hamiltonian_matrix(p.h, p.g, 0.3, n, ordering)
+    psi0 = sector.determinants_vector(m, p.n_alpha, p.n_beta, dets, coef, ordering)
+    e0, _ = sector.energy_grad(m, p.n_alpha, p.n_beta, p.ops[:0], np.zeros(0), p.h, p.g, 0.3, ordering,
+                               psi0=psi0)
+    assert abs(e0 - np.real(np.vdot(phi, H @ phi))) < 1e-12
+    psi_b = phi.copy()
+    for op, t in zip(p.ops, p.theta):
+        tau = brute.tau_matrix(op, n, ordering).toarray()
+        psi_b = scipy.linalg.expm(float(t) * (tau - tau.conj().T)) @ psi_b
+    psi_s = sector.apply_rotations(psi0, m, p.n_alpha, p.n_beta, p.ops, p.theta, ordering)
+    assert np.abs(psi_b[_idx(p)] - psi_s).max() < 1e-13
+    e, _ = sector.energy_grad(m, p.n_alpha, p.n_beta, p.ops, p.theta, p.h, p.g, 0.3, ordering, psi0=psi0)
+    assert abs(e - np.real(np.vdot(psi_b, H @ psi_b))) < 1e-12
+
+
+def test_multideterminant_gradient_finite_difference():
+    p = random_problem(10, 5, 15, seed=73, theta_std=0.4, ordering=0)
+    m = p.n_orb
+    dets, coef = _random_dets(p, 12, 74)
+    psi0 = sector.determinants_vector(m, p.n_alpha, p.n_beta, dets, coef, 0)
+    e, g = sector.energy_grad(m, p.n_alpha, p.n_beta, p.ops, p.theta, p.h, p.g, 0.0, 0, psi0=psi0)
+    h = 1e-5
+    for k in range(p.n_ops):
+        tp, tm = p.theta.copy(), p.theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        ep = sector.energy(sector.apply_rotations(psi0, m, p.n_alpha, p.n_beta, p.ops, tp, 0), p.h, p.g, 0.0,
+                           p.n_alpha, p.n_beta, 0)
+        em = sector.energy(sector.apply_rotations(psi0, m, p.n_alpha, p.n_beta, p.ops, tm, 0), p.h, p.g, 0.0,
+                           p.n_alpha, p.n_beta, 0)
+        assert abs((ep - em) / (2 * h) - g[k]) < 1e-8
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_onebody_property_brute_force(ordering):
+    # a first-order property <psi|D|psi>, D = sum_{pq,s} d_pq a^+_{ps} a_{qs}
+    # (a dipole component for dipole integrals d), equals tr(d (gamma_a + gamma_b))
+    p = random_problem(8, 3, 10, seed=75, theta_std=0.5, ordering=ordering)
+    m, n = p.n_orb, 8
+    rng = np.random.default_rng(76)
+    d = rng.normal(size=(m, m))  # need not be symmetric
+    psi_s = sector.ansatz(m, p.n_alpha, p.n_beta, p.ops, p.theta, ordering)
+    gam = sector.rdm1(psi_s, m, p.n_alpha, p.n_beta, ordering)
+    val = np.sum(d * (gam[0] + gam[1]))
+    D = sum(d[a, b] * (brute.creator(brute._q(2 * a + s, m, ordering), n)
+                       @ brute.annihilator(brute._q(2 * b + s, m, ordering), n))
+            for a in range(m) for b in range(m) for s in (0, 1))
+    psi_b = brute.ansatz_state(n, p.n_alpha, p.n_beta, p.ops, p.theta, ordering)
+    assert abs(val - np.vdot(psi_b, D @ psi_b)) < 1e-12
