@@ -183,6 +183,26 @@ int fsv_finish(fsv_plan *plan, double *E_out, double *grad_out);
  * string. */
 int fsv_autotune(fsv_plan *plan, void *psi_dev, void *lam_dev, const char **report);
 
+/* Start the ansatz from a multi-determinant state instead of |ref> (the
+ * paper warm-starts its runs from CIPSI wavefunctions, Computational
+ * Details): sum_d coef[d] |dets[d]>, dets = qubit strings (host, n_det
+ * uint64; bit j = qubit j in the plan's ordering), each in the
+ * (n_alpha, n_beta) sector and listed once; coef: host, n_det real values,
+ * used as given (not normalised).  n_det = 0 restores |ref>.  Later
+ * ansatz_apply, energy_grad, energy_grad_fd, the stage calls and pools start
+ * from it (captured graphs are rebuilt).  Errors: FSV_EINVAL (a determinant
+ * outside the sector, repeated, or with bits above the last qubit),
+ * FSV_ENONFINITE, FSV_ENOMEM. */
+int fsv_set_initial_state(fsv_plan *plan, int32_t n_det, const uint64_t *dets, const double *coef);
+
+/* First-order property <psi| D |psi> of a spin-independent one-body operator
+ * D = sum_{pq,s} d_pq a^+_{ps} a_{qs} (e.g. a dipole component with d the
+ * dipole integrals, evaluated from the Strategy-2 density as tr(d gamma)):
+ * out[0] + i out[1] = sum_pq d_pq (gamma_alpha + gamma_beta)_pq, from the
+ * 1-RDM of psi_dev (read only).  d: host, n_orb x n_orb real, row-major, need
+ * not be symmetric.  out: host, 2 doubles. */
+int onebody_expectation(fsv_plan *plan, const void *psi_dev, const double *d, double *out);
+
 /* ---- ADAPT operator-pool screening ----
  * ADAPT grows the ansatz by the pool operator with the largest energy
  * derivative (Computational Details: ADAPT-VQE with a QEB pool).  For an

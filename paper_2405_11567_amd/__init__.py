@@ -160,6 +160,28 @@ class Plan:
         check(self._lib.rdm1(self._h, self._check_state(psi), _dptr(gam.view(np.float64))))
         return gam
 
+    def set_initial_state(self, dets=None, coef=None):
+        """Start the ansatz from sum_d coef[d] |dets[d]> (qubit strings in the
+        plan's ordering, each in the sector); no arguments: the reference."""
+        if dets is None:
+            check(self._lib.fsv_set_initial_state(self._h, 0, None, None))
+            return
+        x = np.ascontiguousarray(np.asarray(dets, dtype=np.uint64).reshape(-1))
+        c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).reshape(-1))
+        if x.size != c.size:
+            raise ValueError("dets and coef differ in length")
+        check(self._lib.fsv_set_initial_state(self._h, int(x.size),
+                                              x.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _dptr(c)))
+
+    def onebody_expectation(self, psi, d) -> complex:
+        """<psi| sum_{pq,s} d_pq a^+_{ps} a_{qs} |psi> (e.g. a dipole component)."""
+        dd = np.ascontiguousarray(d, dtype=np.float64)
+        if dd.shape != (self.n_orb, self.n_orb):
+            raise ValueError("d must be n_orb x n_orb")
+        out = np.zeros(2)
+        check(self._lib.onebody_expectation(self._h, self._check_state(psi), _dptr(dd), _dptr(out)))
+        return complex(out[0], out[1])
+
     def set_onebody_potential(self, v=None):
         if v is None:
             check(self._lib.set_onebody_potential(self._h, None))

@@ -48,6 +48,7 @@ EXPORTS = [
     "fsv_set_theta", "fsv_forward_async", "fsv_sigma_async", "fsv_reverse_async", "fsv_finish",
     "fsv_autotune", "fsv_batch_create", "fsv_batch_destroy", "fsv_batch_energy_grad",
     "fsv_batch_bytes", "fsv_batch_autotune", "fsv_pool_create", "fsv_pool_destroy", "fsv_pool_gradients",
+    "fsv_set_initial_state", "onebody_expectation",
 ]
 
 _lib = None
@@ -93,6 +94,8 @@ def load():
     lib.fsv_pool_create.argtypes = [ctypes.POINTER(vp), vp, i32, ctypes.c_int32, ctypes.c_int32]
     lib.fsv_pool_destroy.argtypes = [vp]
     lib.fsv_pool_gradients.argtypes = [vp, d, vp, vp, d, d]
+    lib.fsv_set_initial_state.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), d]
+    lib.onebody_expectation.argtypes = [vp, vp, d, d]
     for name in EXPORTS:
         if name not in ("fsv_last_error", "fsv_state_bytes", "fsv_batch_bytes"):
             getattr(lib, name).restype = c_int

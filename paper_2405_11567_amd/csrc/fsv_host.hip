@@ -119,6 +119,14 @@ struct fsv_plan {
     // sector-compressed engine (default for energy_grad / ansatz_apply)
     int engine = 0;  // 0 sector-compressed, 1 dense
     int excitation = 0;  // 0 fermionic, 1 qubit excitations
+    // multi-determinant start (n_init = 0: the reference determinant):
+    // sector index and signed value for the sector engine, qubit index and
+    // value for the dense engine
+    int n_init = 0;
+    int64_t *d_init_sidx = nullptr, *d_init_didx = nullptr;
+    double *d_init_sval = nullptr, *d_init_dval = nullptr;
+    std::vector<void *> init_mem;
+    std::vector<uint32_t> PPb;  // per-beta-string prefix parity (host copy)
     int svt = V_F64;  // storage of the sector state: real FP64, or real FP32 for precision 1
     SectorTabs tabs{};
     int lr_R = 0;     // rank of the factorised alpha-beta product (0: direct)
@@ -704,7 +712,11 @@ int fence_out(fsv_plan &P) {
 // ---- enqueue helpers (no synchronisation; usable under stream capture) ----
 int enq_forward_dense(fsv_plan &P, void *psi) {
     HIPCHECK(launch_fill_zero(psi, ((size_t)1 << P.n) * P.amp_bytes, P.work));
-    HIPCHECK(launch_set_amp(psi, P.precision == 0 ? V_C128 : V_C64, P.ref_index, 1.0, P.work));
+    if (P.n_init)
+        HIPCHECK(launch_set_list(psi, P.precision == 0 ? V_C128 : V_C64, P.d_init_didx, P.d_init_dval, P.n_init,
+                                 P.work));
+    else
+        HIPCHECK(launch_set_amp(psi, P.precision == 0 ? V_C128 : V_C64, P.ref_index, 1.0, P.work));
     for (const auto &sg : P.segs) {
         if (sg.fused) {
             HIPCHECK(launch_rot_fused(P.precision, psi, P.d_rot, P.d_cs, sg.k0, sg.k1, P.tile_bits,
@@ -754,7 +766,10 @@ int enq_forward_sector(fsv_plan &P, void *c) {
     HIPCHECK(launch_fill_zero(c, (size_t)P.dim * vtype_bytes(P.svt), P.work));
     // The reference is string 0 x string 0.  Its alpha-first amplitude carries
     // the ordering sign so that the dense image starts at exactly +1 |ref>.
-    HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
+    if (P.n_init)
+        HIPCHECK(launch_set_list(c, P.svt, P.d_init_sidx, P.d_init_sval, P.n_init, P.work));
+    else
+        HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
     for (const FGroup &g : P.ffwd.groups) {
         if (g.fused) {
             HIPCHECK(launch_fused(P.svt, false, c, nullptr, P.ffwd, g, P.d_pops, P.d_cs, P.nsb, nullptr, 0,
@@ -985,6 +1000,7 @@ int build_device(fsv_plan &P) {
         Xb[i] = x;
         PPb[i] = pp;
     }
+    P.PPb = PPb;
     P.ref_index = Xa[0] | Xb[0];  // strings are ascending: index 0 fills the lowest orbitals
     P.ref_phase = (__builtin_popcount(P.sa[0] & PPb[0]) & 1) ? -1.0 : 1.0;
     std::vector<uint32_t> excA, excB;
@@ -1113,6 +1129,7 @@ int build_device(fsv_plan &P) {
 
 fsv_plan::~fsv_plan() {
     drop_graphs(*this);
+    for (void *p : init_mem) (void)hipFree(p);
     if (blas) (void)rocblas_destroy_handle(blas);
     for (auto &b : bufs) (void)hipFree(b.p);
     if (h_pin) (void)hipHostFree(h_pin);
@@ -1515,6 +1532,93 @@ int fsv_autotune(fsv_plan *P, void *psi, void *lam, const char **report) {
     }
     if (report) *report = rep.c_str();
     return fence_out(*P);
+}
+
+// ------------------------------------------------- initial state, properties ----
+int fsv_set_initial_state(fsv_plan *P, int32_t n_det, const uint64_t *dets, const double *coef) {
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    if (n_det < 0 || (n_det > 0 && (!dets || !coef))) return fail(FSV_EINVAL, "bad n_det / dets / coef");
+    if (n_det > 0 && (int64_t)n_det > P->dim) return fail(FSV_EINVAL, "more determinants than the sector holds");
+    if (!finite_all(coef, (size_t)n_det)) return fail(FSV_ENONFINITE, "non-finite coefficient");
+    const int M = P->M;
+    std::vector<int32_t> ra((size_t)1 << M, -1), rb((size_t)1 << M, -1);
+    for (size_t i = 0; i < P->sa.size(); ++i) ra[P->sa[i]] = (int32_t)i;
+    for (size_t i = 0; i < P->sb.size(); ++i) rb[P->sb[i]] = (int32_t)i;
+    std::vector<int64_t> sidx(n_det), didx(n_det);
+    std::vector<double> sval(n_det), dval(n_det);
+    for (int d = 0; d < n_det; ++d) {
+        const uint64_t x = dets[d];
+        if (P->n < 64 && (x >> P->n) != 0) return fail(FSV_EINVAL, "determinant %d has bits above qubit %d", d, P->n - 1);
+        uint32_t a = 0, b = 0;
+        for (int p = 0; p < M; ++p) {
+            a |= (uint32_t)((x >> qubit_of(*P, 2 * p)) & 1u) << p;
+            b |= (uint32_t)((x >> qubit_of(*P, 2 * p + 1)) & 1u) << p;
+        }
+        if (ra[a] < 0 || rb[b] < 0)
+            return fail(FSV_EINVAL, "determinant %d lies outside the (%d, %d) sector", d, P->na, P->nb);
+        sidx[d] = (int64_t)ra[a] * P->nsb + rb[b];
+        // the alpha-first sector amplitude is the qubit-basis amplitude times
+        // (-1)^popcount(alpha string & beta prefix parity)
+        sval[d] = (__builtin_popcount(a & P->PPb[rb[b]]) & 1) ? -coef[d] : coef[d];
+        didx[d] = (int64_t)x;
+        dval[d] = coef[d];
+    }
+    {
+        std::vector<int64_t> srt(sidx);
+        std::sort(srt.begin(), srt.end());
+        for (size_t i = 1; i < srt.size(); ++i)
+            if (srt[i] == srt[i - 1]) return fail(FSV_EINVAL, "a determinant is listed twice");
+    }
+    if (P->work) HIPCHECK(hipStreamSynchronize(P->work));
+    drop_graphs(*P);  // captured launches point at the old list
+    for (void *q : P->init_mem) (void)hipFree(q);
+    P->init_mem.clear();
+    P->n_init = 0;
+    P->d_init_sidx = P->d_init_didx = nullptr;
+    P->d_init_sval = P->d_init_dval = nullptr;
+    if (n_det == 0) {
+        clear_error();
+        return FSV_OK;
+    }
+    void *bufs[4] = {nullptr, nullptr, nullptr, nullptr};
+    const size_t bytes = 8 * (size_t)n_det;
+    for (int i = 0; i < 4; ++i) {
+        if (hipMalloc(&bufs[i], bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < i; ++j) (void)hipFree(bufs[j]);
+            return fail(FSV_ENOMEM, "hipMalloc of the initial state list failed");
+        }
+    }
+    P->init_mem.assign(bufs, bufs + 4);
+    P->d_init_sidx = (int64_t *)bufs[0];
+    P->d_init_sval = (double *)bufs[1];
+    P->d_init_didx = (int64_t *)bufs[2];
+    P->d_init_dval = (double *)bufs[3];
+    HIPCHECK(hipMemcpy(P->d_init_sidx, sidx.data(), bytes, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(P->d_init_sval, sval.data(), bytes, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(P->d_init_didx, didx.data(), bytes, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(P->d_init_dval, dval.data(), bytes, hipMemcpyHostToDevice));
+    P->n_init = n_det;
+    clear_error();
+    return FSV_OK;
+}
+
+int onebody_expectation(fsv_plan *P, const void *psi, const double *d, double *out) {
+    if (!P || !psi || !d || !out) return fail(FSV_EINVAL, "plan, psi, d or out is NULL");
+    const int M = P->M;
+    if (!finite_all(d, (size_t)M * M)) return fail(FSV_ENONFINITE, "non-finite d");
+    std::vector<double> gam(4 * (size_t)M * M);
+    int rc = rdm1(P, psi, gam.data());
+    if (rc) return rc;
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < 2; ++s)
+        for (int pq = 0; pq < M * M; ++pq) {
+            re += d[pq] * gam[2 * ((size_t)s * M * M + pq)];
+            im += d[pq] * gam[2 * ((size_t)s * M * M + pq) + 1];
+        }
+    out[0] = re;
+    out[1] = im;
+    return FSV_OK;
 }
 
 // ------------------------------------------------------------ pools ----

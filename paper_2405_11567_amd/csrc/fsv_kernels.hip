@@ -58,6 +58,21 @@ __global__ void k_set_amp(void *psi, int vt, uint64_t x, double re) {
     }
 }
 
+// A list of amplitudes psi[idx[i]] = (val[i], 0) (a multi-determinant start).
+__global__ void k_set_list(void *psi, int vt, const int64_t *__restrict__ idx, const double *__restrict__ val,
+                           int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int64_t x = idx[i];
+        const double re = val[i];
+        switch (vt) {
+        case V_C128: ((double2 *)psi)[x] = make_double2(re, 0.0); break;
+        case V_C64: ((float2 *)psi)[x] = make_float2((float)re, 0.f); break;
+        case V_F64: ((double *)psi)[x] = re; break;
+        default: ((float *)psi)[x] = (float)re; break;
+        }
+    }
+}
+
 // ------------------------------------------------------------ rotations ----
 // psi'_src = c psi_src - s sg psi_dst ; psi'_dst = c psi_dst + s sg psi_src
 template <typename R, typename Idx, int PPT>
@@ -351,6 +366,11 @@ hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st) {
 
 hipError_t launch_set_amp(void *psi, int vt, uint64_t x, double re, hipStream_t st) {
     hipLaunchKernelGGL(k_set_amp, dim3(1), dim3(64), 0, st, psi, vt, x, re);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_list(void *psi, int vt, const int64_t *idx, const double *val, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_list, dim3(blocks_for(n, 256)), dim3(256), 0, st, psi, vt, idx, val, n);
     return hipGetLastError();
 }
 
