@@ -187,33 +187,6 @@ __global__ __launch_bounds__(256) void k_cadj(V *__restrict__ psi, V *__restrict
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
-// ADAPT pool screening, one launch for the whole pool: workgroup (x, t)
-// accumulates, over its share of pool operator t's pairs, the real part of
-// <lam| T_t |psi> = sum s (lam[x'] psi[x] - lam[x] psi[x']); psi and lam are
-// only read.  partial[t * gridDim.x + x].
-template <typename V>
-__global__ __launch_bounds__(256) void k_pool(const V *__restrict__ psi, const V *__restrict__ lam,
-                                              const PairOp *__restrict__ ops,
-                                              const uint32_t *__restrict__ lists, int64_t nsa, int64_t nsb,
-                                              double *__restrict__ partial) {
-    const PairOp op = ops[blockIdx.y];
-    const uint32_t na = (uint32_t)(op.nA >= 0 ? op.nA : nsa), nb = (uint32_t)(op.nB >= 0 ? op.nB : nsb);
-    const uint32_t np = na * nb;
-    double acc = 0.0;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < np; t += gridDim.x * blockDim.x) {
-        const uint32_t u = t / nb, v = t - u * nb;
-        int64_t ia, ia2, ib, ib2;
-        bool neg;
-        pair_row(op, lists, u, ia, ia2, neg);
-        pair_col(op, lists, v, ib, ib2, neg);
-        const int64_t xs = ia * nsb + ib, xd = ia2 * nsb + ib2;
-        const double o = dotre(lam[xd], psi[xs]) - dotre(lam[xs], psi[xd]);
-        acc += neg ? -o : o;
-    }
-    acc = block_sum(acc);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
-}
-
 // ---------------------------------------------------------------- sigma ----
 // out[I][:] = sum_k val[k] in[col[k]][:].  Blocks are dispatched row-fastest
 // over one column tile at a time (blockIdx.x = row, blockIdx.y = tile), so the
@@ -443,6 +416,34 @@ __global__ __launch_bounds__(1024) void k_lr_b(const A *__restrict__ Y, A *__res
             srow[Ib] = add(srow[Ib], acc);
         }
     }
+}
+
+// ------------------------------------------------------------ screening ----
+// ADAPT pool screening, one launch for the whole pool: workgroup (x, t)
+// accumulates, over its share of pool operator t's pairs, the real part of
+// <lam| T_t |psi> = sum s (lam[x'] psi[x] - lam[x] psi[x']); psi and lam are
+// only read.  partial[t * gridDim.x + x].
+template <typename V>
+__global__ __launch_bounds__(256) void k_pool(const V *__restrict__ psi, const V *__restrict__ lam,
+                                              const PairOp *__restrict__ ops,
+                                              const uint32_t *__restrict__ lists, int64_t nsa, int64_t nsb,
+                                              double *__restrict__ partial) {
+    const PairOp op = ops[blockIdx.y];
+    const uint32_t na = (uint32_t)(op.nA >= 0 ? op.nA : nsa), nb = (uint32_t)(op.nB >= 0 ? op.nB : nsb);
+    const uint32_t np = na * nb;
+    double acc = 0.0;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < np; t += gridDim.x * blockDim.x) {
+        const uint32_t u = t / nb, v = t - u * nb;
+        int64_t ia, ia2, ib, ib2;
+        bool neg;
+        pair_row(op, lists, u, ia, ia2, neg);
+        pair_col(op, lists, v, ib, ib2, neg);
+        const int64_t xs = ia * nsb + ib, xd = ia2 * nsb + ib2;
+        const double o = dotre(lam[xd], psi[xs]) - dotre(lam[xs], psi[xd]);
+        acc += neg ? -o : o;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
 // Same term without LDS staging (rows too long for LDS): gathers from global.
