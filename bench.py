@@ -11,6 +11,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -98,10 +99,19 @@ def cpu_baseline(p, max_seconds=30.0):
                       f"(sector-compressed FP64 C/OpenMP oracle), {el:.1f} s"}
 
 
+def quiet_gc():
+    """Collect, then move every live object out of the collector's reach: a
+    full collection over torch's objects stalls the host for ~35 ms, which a
+    timed loop of ~1 ms steps would otherwise absorb at random."""
+    gc.collect()
+    gc.freeze()
+
+
 def time_engine(fsv, torch, p, precision, engine, steps, warmup, stream, psi, lam):
     """Timed energy+gradient passes of one engine, then per-stage HIP-event
     timing on the plan's stream."""
     plan = fsv.Plan(p, precision=precision, device=psi.device, engine=engine)
+    quiet_gc()
     for _ in range(warmup):
         plan.energy_grad(p.theta, psi, lam)
     torch.cuda.synchronize()
@@ -148,6 +158,8 @@ def roofline_of(mb, stages, k, kernel, traffic=None):
 
 ROTATION_SOURCE = os.path.join(ROOT, "paper_2405_11567_amd", "csrc", "fsv_sigma.hip")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_cadj_sector_24q_fp64.md")
+PACKET_SOURCE = os.path.join(ROOT, "paper_2405_11567_amd", "csrc", "fsv_packet.hip")
+PACKET_PROFILE = os.path.join(ROOT, "profiles", "k_pkt_adjoint_24q_fp64.md")
 
 
 def rotation_source_hash():
@@ -160,21 +172,98 @@ def rotation_source_hash():
     return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
 
 
-def traffic_from_profile(workload):
-    """HBM bytes per k_cadj launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE x calibration + WRITE_SIZE), when it was taken on the current
-    kernel source and this workload; otherwise None."""
+def packet_source_hash():
+    """sha256 (16 hex digits) of the packet kernel's device code (the file up
+    to its host-side union-find)."""
+    import hashlib
+    text = open(PACKET_SOURCE).read()
+    return hashlib.sha256(text[: text.index("// ---- host: union-find")].encode()).hexdigest()[:16]
+
+
+def traffic_from_profile(workload, path=TRAFFIC_PROFILE, source_hash=rotation_source_hash):
+    """HBM bytes per launch of a profiled kernel from its committed rocprofv3
+    counter summary (FETCH_SIZE x calibration + WRITE_SIZE), when it was taken
+    on the current kernel source and this workload; otherwise None."""
     try:
         fields = {}
-        for line in open(TRAFFIC_PROFILE):
+        for line in open(path):
             if ":" in line and line.startswith("- "):
                 key, val = line[2:].split(":", 1)
                 fields[key.strip()] = val.strip().strip("`")
-        if fields.get("source_sha256") != rotation_source_hash() or fields.get("workload") != workload:
+        if fields.get("source_sha256") != source_hash() or fields.get("workload") != workload:
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def sector_strings(m, n):
+    from itertools import combinations
+    return np.array(sorted(sum(1 << b for b in c) for c in combinations(range(m), n)), dtype=np.int64)
+
+
+def run_touched(p, k0, k1):
+    """Sector amplitudes (alpha string rank * n_beta_strings + beta rank) that
+    the operators k0..k1-1 pair: the amplitudes a fused run must move."""
+    m, na, nb = p.n_orb, p.n_alpha, p.n_beta
+    sa, sb = sector_strings(m, na), sector_strings(m, nb)
+    rank = {0: np.full(1 << m, -1, np.int64), 1: np.full(1 << m, -1, np.int64)}
+    rank[0][sa] = np.arange(len(sa))
+    rank[1][sb] = np.arange(len(sb))
+    strs = {0: sa, 1: sb}
+    out = []
+    for op in p.ops[k0:k1]:
+        a, b, j, i = (int(v) for v in op)
+        ends = []
+        for sp in (0, 1):
+            ann = sum(1 << (v // 2) for v in (i, j) if v >= 0 and v % 2 == sp)
+            cre = sum(1 << (v // 2) for v in (a, b) if v >= 0 and v % 2 == sp)
+            S = strs[sp]
+            if not ann and not cre:
+                ends.append((np.arange(len(S)), np.arange(len(S))))
+                continue
+            src = S[((S & ann) == ann) & ((S & (cre & ~ann)) == 0)]
+            ends.append((rank[sp][src], rank[sp][(src & ~ann) | cre]))
+        nsb = len(sb)
+        for t in (0, 1):
+            out.append((ends[0][t][:, None] * nsb + ends[1][t][None, :]).ravel())
+    return int(len(np.unique(np.concatenate(out)))) if out else 0
+
+
+def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps=5):
+    """Roofline of the adjoint packet-run kernel: the adjoint sweep is launched
+    eagerly with HIP events around every run (fsv_time_runs); achieved =
+    algorithmic bytes of the packet runs (their touched amplitudes, psi and
+    lam, read and written) over their measured time.  None when the plan has
+    no packet runs."""
+    start, tiles = plan.runs(adjoint=True)
+    k = len(start)
+    firsts = [t for t in range(k) if t == 0 or start[t] != start[t - 1]]
+    groups = [(k0, (firsts[n + 1] if n + 1 < len(firsts) else k)) for n, k0 in enumerate(firsts)]
+    fused = [n for n, (k0, k1) in enumerate(groups) if tiles[k0] > 0 and k1 - k0 >= 2]
+    if not fused:
+        return None
+    times = []
+    for _ in range(reps + 1):
+        plan.set_theta(p.theta)
+        plan.forward_async(psi)
+        plan.sigma_async(psi, lam)
+        times.append(plan.time_runs(psi, lam, adjoint=True))
+        torch.cuda.synchronize()
+    med = np.median(np.array(times[1:]), axis=0)
+    es = 8 if precision == 0 else 4
+    amps = [run_touched(p, *groups[n]) for n in fused]
+    byts = [4.0 * es * a for a in amps]  # psi and lam, read and written
+    ms = [float(med[n]) for n in fused]
+    achieved = sum(byts) / (sum(ms) * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_pkt<%s, true> (adjoint packet run)" % ("double" if precision == 0 else "float"),
+            "avg_launch_us": float(np.mean(ms)) * 1e3,
+            "algorithmic_bytes_per_launch": float(np.mean(byts)),
+            "launches_per_eval": len(fused), "operators_fused": int(sum(groups[n][1] - groups[n][0] for n in fused)),
+            "mean_touched_amplitudes": float(np.mean(amps)),
+            "adjoint_sweep_ms": float(med.sum())}
 
 
 def unfused_reverse(fsv, torch, p, precision, stream, psi, lam, reps=5):
@@ -207,6 +296,7 @@ def bench_pool(fsv, torch, p, psi, lam, stages, reps=10):
     from workloads import uccsd_pool
     pool_ops = np.asarray(uccsd_pool(p.n_orb, p.n_alpha, p.n_beta), dtype=np.int32)
     plan = fsv.Plan(p, device=psi.device)
+    quiet_gc()
     from math import comb
     m, na, nb = p.n_orb, p.n_alpha, p.n_beta
     pair_bytes = sum(4 * 8 * sector_pairs(op, m, na, nb) for op in pool_ops)  # read psi, lam at both ends
@@ -257,6 +347,7 @@ def bench_multidet(fsv, torch, p, psi, lam, n_det=10000, reps=10):
     coef /= np.linalg.norm(coef)
     plan = fsv.Plan(p, device=psi.device)
     plan.set_initial_state(np.array(dets, dtype=np.uint64), coef)
+    quiet_gc()
     plan.energy_grad(p.theta, psi, lam)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -292,6 +383,7 @@ def bench_batch(args):
     tune = b.autotune() if args.tune else ""
     if tune:
         print(tune, file=sys.stderr, flush=True)
+    quiet_gc()
     for _ in range(args.warmup):
         b.energy_grad(thetas)
     torch.cuda.synchronize()
@@ -388,12 +480,22 @@ def main():
     # the sector engine stores the (exactly real) state as real FP64 / FP32
     mb_sector = sector_model_bytes(p, amp_bytes // 2)
     mb = mb_sector if args.engine == "sector" else mb_dense
+    per_op = None
     if args.engine == "sector":
         rev_ms = unfused_reverse(fsv, torch, p, args.precision, stream, psi, lam)
         print(f"[bench] per-operator adjoint sweep (no fused runs): {rev_ms:.3f} ms", file=sys.stderr, flush=True)
         traffic = traffic_from_profile(args.config) if args.precision == 0 else None
-        roof = roofline_of(mb, {"reverse": rev_ms}, k, "k_cadj<double> (sector adjoint step)"
-                           if args.precision == 0 else "k_cadj<float> (sector adjoint step)", traffic)
+        per_op = roofline_of(mb, {"reverse": rev_ms}, k, "k_cadj<double> (sector adjoint step)"
+                             if args.precision == 0 else "k_cadj<float> (sector adjoint step)", traffic)
+        pk_traffic = (traffic_from_profile(args.config, PACKET_PROFILE, packet_source_hash)
+                      if args.precision == 0 else None)
+        roof = packet_roofline(fsv, torch, plan, p, args.precision, psi, lam, pk_traffic)
+        if roof is None:
+            roof, per_op = per_op, None
+        else:
+            print(f"[bench] adjoint packet runs: {roof['launches_per_eval']} launches, "
+                  f"{roof['avg_launch_us']:.1f} us each, {roof['achieved']:.0f} GB/s algorithmic",
+                  file=sys.stderr, flush=True)
     else:
         roof = roofline_of(mb, stages, k, "k_adj (dense adjoint step)")
 
@@ -462,6 +564,7 @@ def main():
                    "n_qubits": p.n_qubits, "n_ops": k, "precision": args.precision,
                    "engine": args.engine},
         "roofline": roof,
+        "per_operator_kernel": per_op,
         "eval_model": {"engine_bytes_per_eval": mb["eval"], "stage_ms": stages,
                        "dense_line_model_bytes_per_eval": mb_dense["eval"],
                        "dense_model_hbm_frac": mb_dense["eval"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

@@ -111,17 +111,36 @@ int fsv_plan_info(const fsv_plan *plan, int64_t *n_alpha_strings, int64_t *n_bet
 int fsv_plan_set_engine(fsv_plan *plan, int engine);
 
 /* Operator runs of the sector engine's forward sweep (adjoint = 0) or adjoint
- * sweep (adjoint = 1).  An excitation changes occupations only in the
- * orbitals it names, so consecutive operators can be applied together, tile
- * by tile in LDS, on tiles that the whole run maps onto themselves (alpha
- * strings that agree outside the run's alpha orbitals x a block of beta
- * strings); runs are chosen from an LDS budget and a cost model (FSV_NO_FUSE:
- * never, FSV_FORCE_FUSE: every run of two or more) and retuned by
- * fsv_autotune.  run_start[k] receives the first operator of the run holding
- * operator k, fused_tiles[k] the tiles of its fused launch or 0 when k is
+ * sweep (adjoint = 1).  Each rotation exp(theta (tau - tau^+)) mixes only
+ * the two amplitudes of each of its active pairs, so consecutive operators can
+ * be applied together in one launch:
+ *  - component packets (the default for sector states of at most 2^22
+ *    amplitudes; FSV_FUSE=packets): the connected components of the graph
+ *    joining the amplitudes that some operator of the run pairs are mutually
+ *    independent; runs are extended while every component has at most 256
+ *    amplitudes, and whole components are packed into 256-amplitude packets,
+ *    one wavefront each;
+ *  - LDS tiles (larger states, FSV_FUSE=tiles): tiles that the whole run maps
+ *    onto themselves (alpha strings that agree outside the run's alpha
+ *    orbitals x a block of beta strings), chosen from an LDS budget.
+ * A cost model decides which runs are fused (FSV_NO_FUSE: none,
+ * FSV_FORCE_FUSE: every tile run of two or more); fsv_autotune retunes.
+ * run_start[k] receives the first operator of the run holding operator k,
+ * fused_tiles[k] the tiles or packets of its fused launch, or 0 when k is
  * applied alone (host arrays of K int32, either may be NULL).  Returns the
  * number of runs (>= 0) or a negative status. */
 int fsv_plan_runs(const fsv_plan *plan, int adjoint, int32_t *run_start, int32_t *fused_tiles);
+
+/* Profiling: the sector engine's forward sweep (adjoint = 0: psi is
+ * initialised, then every run) or adjoint sweep (adjoint = 1: psi and lam must
+ * hold the final state and H psi, as after fsv_forward_async and
+ * fsv_sigma_async; the runs are applied last to first and the gradient is
+ * reduced into the plan's output, readable with fsv_finish) launched without a
+ * graph, with HIP events around every run.  ms (host, one float per run of
+ * fsv_plan_runs, operator order) receives each run's time in milliseconds.
+ * Synchronises the plan's stream.  Returns the number of runs (>= 0), or -1
+ * for NULL arguments, -4 on the dense engine, -3 on a HIP error. */
+int fsv_time_runs(fsv_plan *plan, int adjoint, void *psi_dev, void *lam_dev, float *ms);
 
 /* psi_dev <- U_K(theta_K) ... U_1(theta_1) |ref> (ansatz preparation on the
  * GPU emulator, Fig. 1).  theta: host, K doubles.  Every amplitude of psi_dev

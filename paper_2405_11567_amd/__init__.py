@@ -205,6 +205,22 @@ class Plan:
     def reverse_async(self, psi, lam):
         check(self._lib.fsv_reverse_async(self._h, self._check_state(psi), self._check_state(lam)))
 
+    def time_runs(self, psi, lam=None, adjoint: bool = False):
+        """Per-run times (ms, operator order) of the sector engine's forward
+        sweep, or of its adjoint sweep when adjoint is set (psi and lam must
+        then hold the final state and H psi, e.g. after forward_async and
+        sigma_async), launched eagerly with HIP events around every run."""
+        import ctypes
+        start, _ = self.runs(adjoint)
+        n = len(np.unique(start)) if len(start) else 0
+        ms = np.zeros(max(n, 1), dtype=np.float32)
+        rc = self._lib.fsv_time_runs(self._h, int(bool(adjoint)), self._check_state(psi),
+                                     self._check_state(lam) if lam is not None else None,
+                                     ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        if rc < 0:
+            check(rc)
+        return ms[:rc]
+
     def finish(self):
         grad = np.zeros(self.n_ops)
         e = ctypes.c_double()

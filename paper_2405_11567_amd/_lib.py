@@ -43,7 +43,7 @@ class Problem(ctypes.Structure):
 
 EXPORTS = [
     "fsv_last_error", "fsv_plan_create", "fsv_plan_destroy", "fsv_state_bytes", "fsv_plan_info",
-    "fsv_plan_set_engine", "fsv_plan_runs",
+    "fsv_plan_set_engine", "fsv_plan_runs", "fsv_time_runs",
     "ansatz_apply", "energy", "energy_grad", "energy_grad_fd", "rdm1", "set_onebody_potential",
     "fsv_set_theta", "fsv_forward_async", "fsv_sigma_async", "fsv_reverse_async", "fsv_finish",
     "fsv_autotune", "fsv_batch_create", "fsv_batch_destroy", "fsv_batch_energy_grad",
@@ -73,6 +73,7 @@ def load():
                                   ctypes.POINTER(ctypes.c_uint64)]
     lib.fsv_plan_set_engine.argtypes = [vp, c_int]
     lib.fsv_plan_runs.argtypes = [vp, c_int, i32, i32]
+    lib.fsv_time_runs.argtypes = [vp, c_int, vp, vp, ctypes.POINTER(ctypes.c_float)]
     lib.ansatz_apply.argtypes = [vp, d, vp]
     lib.energy.argtypes = [vp, vp, d]
     lib.energy_grad.argtypes = [vp, d, vp, vp, d, d]

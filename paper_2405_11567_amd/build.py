@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libfsv.so")
-SOURCES = ["fsv_kernels.hip", "fsv_sigma.hip", "fsv_fused.hip", "fsv_host.hip", "fsv_batch.hip"]
+SOURCES = ["fsv_kernels.hip", "fsv_sigma.hip", "fsv_fused.hip", "fsv_packet.hip", "fsv_host.hip", "fsv_batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

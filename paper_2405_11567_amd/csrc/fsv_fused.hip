@@ -275,7 +275,6 @@ uint32_t spin_mask(const int32_t *op, int spin) {
 }  // namespace
 
 void FusedSched::release() {
-    for (void *p : mem) (void)hipFree(p);
     mem.clear();
     groups.clear();
     count.clear();
@@ -468,7 +467,7 @@ int build_fused(int M, const std::vector<uint32_t> &sa, const std::vector<uint32
             (void)hipGetLastError();
             return fail(FSV_ENOMEM, "hipMalloc of %zu bytes for fused programs failed", bytes);
         }
-        S.mem.push_back(p);
+        S.mem.emplace_back(p, [](void *q) { (void)hipFree(q); });
         if (!vec.empty() && hipMemcpy(p, vec.data(), vec.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
             return fail(FSV_EDEVICE, "upload of fused programs failed");
         *dst = (uint32_t *)p;
@@ -526,6 +525,7 @@ size_t fused_lds_limit() {
 hipError_t launch_fused(int vtype, bool adjoint, void *psi, void *lam, const FusedSched &S, const FGroup &g,
                         const PairOp *d_pops, const double *cs, int64_t nsb, double *gpart, int gstride,
                         hipStream_t st) {
+    if (g.fused == 2) return launch_packets(vtype, adjoint, psi, lam, S, g, cs, gpart, gstride, st);
     FArgs a;
     a.k0 = g.k0;
     a.nops = g.nops;

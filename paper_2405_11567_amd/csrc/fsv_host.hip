@@ -141,7 +141,10 @@ struct fsv_plan {
     // fused operator runs of the forward and adjoint sweeps (LDS budget per tile)
     FusedSched ffwd, frev;
     size_t fuse_budget_fwd = 65536, fuse_budget_rev = 98304;
-    int fuse_mode = 0;  // 0 cost model, 1 never (FSV_NO_FUSE), 2 every run (FSV_FORCE_FUSE)
+    // 0 LDS tiles where the cost model gains, 1 never (FSV_NO_FUSE), 2 every tile
+    // run (FSV_FORCE_FUSE), 3 component packets where the cost model gains (the
+    // default for states of at most packet_max_dim() amplitudes)
+    int fuse_mode = 0;
 
     // graphs
     uint64_t gen = 0;  // bumped whenever captured launches may have changed
@@ -759,6 +762,31 @@ int enq_reverse_dense(fsv_plan &P, void *psi, void *lam) {
     return FSV_OK;
 }
 
+// One group of the forward sweep: a fused run in one launch, or its single
+// operator.
+int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g) {
+    if (g.fused) {
+        HIPCHECK(launch_fused(P.svt, false, c, nullptr, P.ffwd, g, P.d_pops, P.d_cs, P.nsb, nullptr, 0, P.work));
+        return FSV_OK;
+    }
+    for (int k = g.k0; k < g.k0 + g.nops; ++k)
+        HIPCHECK(launch_crot(P.svt, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
+    return FSV_OK;
+}
+
+// One group of the adjoint sweep (operators last to first).
+int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g) {
+    const int G = max_grid();
+    if (g.fused) {
+        HIPCHECK(launch_fused(P.svt, true, c, lam_c, P.frev, g, P.d_pops, P.d_cs, P.nsb, P.d_gpart, G, P.work));
+        return FSV_OK;
+    }
+    for (int k = g.k0 + g.nops - 1; k >= g.k0; --k)
+        HIPCHECK(launch_cadj(P.svt, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
+                             P.d_gpart + (size_t)k * G, P.work));
+    return FSV_OK;
+}
+
 // ---- sector-compressed engine: the state is C[Ia][Ib] in the first
 // nsa*nsb amplitudes of the caller's buffer.  With real angles and real
 // integrals every amplitude stays real, so it is stored real (FP64 or FP32). ----
@@ -771,13 +799,8 @@ int enq_forward_sector(fsv_plan &P, void *c) {
     else
         HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
     for (const FGroup &g : P.ffwd.groups) {
-        if (g.fused) {
-            HIPCHECK(launch_fused(P.svt, false, c, nullptr, P.ffwd, g, P.d_pops, P.d_cs, P.nsb, nullptr, 0,
-                                  P.work));
-            continue;
-        }
-        for (int k = g.k0; k < g.k0 + g.nops; ++k)
-            HIPCHECK(launch_crot(P.svt, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
+        const int rc = enq_group_fwd(P, c, g);
+        if (rc) return rc;
     }
     return FSV_OK;
 }
@@ -795,18 +818,50 @@ int enq_sigma_sector(fsv_plan &P, const void *c, void *lam_c) {
 int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
     const int G = max_grid();
     for (auto it = P.frev.groups.rbegin(); it != P.frev.groups.rend(); ++it) {
-        const FGroup &g = *it;
-        if (g.fused) {
-            HIPCHECK(launch_fused(P.svt, true, c, lam_c, P.frev, g, P.d_pops, P.d_cs, P.nsb, P.d_gpart, G,
-                                  P.work));
-            continue;
-        }
-        for (int k = g.k0 + g.nops - 1; k >= g.k0; --k)
-            HIPCHECK(launch_cadj(P.svt, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
-                                 P.d_gpart + (size_t)k * G, P.work));
+        const int rc = enq_group_rev(P, c, lam_c, *it);
+        if (rc) return rc;
     }
     HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_ccount, G, P.K, 2.0, P.d_out + 1, P.work));
     return FSV_OK;
+}
+
+// The forward (adjoint = 0: initial state, then the groups) or adjoint sweep
+// (adjoint = 1: groups last to first on psi, lam, then the gradient reduction)
+// launched eagerly with HIP events around every group; ms[i] = time of group i
+// (operator order).  Synchronises the work stream.
+int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms) {
+    const FusedSched &S = adjoint ? P.frev : P.ffwd;
+    const int n = (int)S.groups.size();
+    std::vector<hipEvent_t> ev(n + 1, nullptr);
+    int rc = FSV_OK;
+    for (auto &e : ev)
+        if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(FSV_EDEVICE, "hipEventCreate failed");
+    if (!rc && !adjoint) {
+        if (hipSuccess != launch_fill_zero(c, (size_t)P.dim * vtype_bytes(P.svt), P.work))
+            rc = fail(FSV_EDEVICE, "fill launch failed");
+        else if (P.n_init && hipSuccess != launch_set_list(c, P.svt, P.d_init_sidx, P.d_init_sval, P.n_init, P.work))
+            rc = fail(FSV_EDEVICE, "initial-state launch failed");
+        else if (!P.n_init && hipSuccess != launch_set_amp(c, P.svt, 0, P.ref_phase, P.work))
+            rc = fail(FSV_EDEVICE, "initial-state launch failed");
+    }
+    if (!rc && hipEventRecord(ev[0], P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
+    for (int t = 0; t < n && !rc; ++t) {
+        const int i = adjoint ? n - 1 - t : t;
+        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i]) : enq_group_fwd(P, c, S.groups[i]);
+        if (!rc && hipEventRecord(ev[t + 1], P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
+    }
+    if (!rc && adjoint &&
+        hipSuccess != launch_reduce_rows(P.d_gpart, P.d_ccount, max_grid(), P.K, 2.0, P.d_out + 1, P.work))
+        rc = fail(FSV_EDEVICE, "reduction launch failed");
+    if (!rc && hipStreamSynchronize(P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "stream synchronize failed");
+    for (int t = 0; t < n && !rc; ++t) {
+        float v = 0.f;
+        if (hipEventElapsedTime(&v, ev[t], ev[t + 1]) != hipSuccess) rc = fail(FSV_EDEVICE, "event timing failed");
+        ms[adjoint ? n - 1 - t : t] = v;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
 }
 
 int enq_forward(fsv_plan &P, void *psi) {
@@ -944,13 +999,22 @@ int rebuild_fused(fsv_plan &P) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         o.cus = cus;
     (void)hipGetLastError();
-    o.arrays = 1;
-    o.budget = std::min(P.fuse_budget_fwd, lim);
-    int rc = build_fused(P.M, P.sa, P.sb, P.pops, P.h_plists, P.ops, o, P.ffwd);
-    if (rc) return rc;
-    o.arrays = 2;
-    o.budget = std::min(P.fuse_budget_rev, lim);
-    if ((rc = build_fused(P.M, P.sa, P.sb, P.pops, P.h_plists, P.ops, o, P.frev))) return rc;
+    int rc;
+    if (P.fuse_mode == 3 && P.dim <= packet_max_dim()) {
+        // both sweeps run the same packet runs
+        o.mode = 0;
+        o.arrays = 2;
+        if ((rc = build_packets(P.nsa, P.nsb, P.pops, P.h_plists, o, P.frev))) return rc;
+        P.ffwd.share(P.frev);
+    } else {
+        if (o.mode == 3) o.mode = 0;
+        o.arrays = 1;
+        o.budget = std::min(P.fuse_budget_fwd, lim);
+        if ((rc = build_fused(P.M, P.sa, P.sb, P.pops, P.h_plists, P.ops, o, P.ffwd))) return rc;
+        o.arrays = 2;
+        o.budget = std::min(P.fuse_budget_rev, lim);
+        if ((rc = build_fused(P.M, P.sa, P.sb, P.pops, P.h_plists, P.ops, o, P.frev))) return rc;
+    }
     std::vector<int> ccount(std::max(P.K, 1), 0);
     for (int k = 0; k < P.K; ++k)
         ccount[k] = P.frev.count[k] >= 0 ? P.frev.count[k] : cadj_blocks(P.pops[k], P.nsa, P.nsb);
@@ -1020,7 +1084,12 @@ int build_device(fsv_plan &P) {
     if ((rc = dalloc(P, &P.d_ccount, (size_t)std::max(P.K, 1)))) return rc;
     if ((rc = upload(P, P.d_plists, plists.data(), plists.size()))) return rc;
     if ((rc = upload(P, P.d_pops, P.pops.data(), P.pops.size()))) return rc;
-    if (const char *e = std::getenv("FSV_NO_FUSE")) P.fuse_mode = e[0] ? 1 : 0;
+    P.fuse_mode = P.dim <= packet_max_dim() ? 3 : 0;
+    if (const char *e = std::getenv("FSV_FUSE")) {
+        if (!std::strcmp(e, "tiles")) P.fuse_mode = 0;
+        if (!std::strcmp(e, "packets")) P.fuse_mode = 3;
+    }
+    if (const char *e = std::getenv("FSV_NO_FUSE")) P.fuse_mode = e[0] ? 1 : P.fuse_mode;
     if (std::getenv("FSV_FORCE_FUSE")) P.fuse_mode = 2;
     if ((rc = rebuild_fused(P))) return rc;
 
@@ -1144,9 +1213,10 @@ namespace {
 // for candidate LDS budgets of the fused runs, and keep the fastest.
 int autotune_sector(fsv_plan &P, void *psi, void *lam, std::string &rep) {
     struct Cand { int mode; size_t fwd, rev; };
-    const Cand cands[] = {{1, 0, 0},          {0, 32768, 65536},   {0, 49152, 98304},
-                          {0, 65536, 98304},  {0, 65536, 131072},  {0, 98304, 163840},
-                          {0, 163840, 163840}};
+    std::vector<Cand> cands = {{1, 0, 0},          {0, 32768, 65536},   {0, 49152, 98304},
+                               {0, 65536, 98304},  {0, 65536, 131072},  {0, 98304, 163840},
+                               {0, 163840, 163840}};
+    if (P.dim <= packet_max_dim()) cands.push_back({3, 0, 0});
     const Cand keep{P.fuse_mode, P.fuse_budget_fwd, P.fuse_budget_rev};
     std::vector<double> th(P.K, 0.1);
     int rc;
@@ -1181,6 +1251,8 @@ int autotune_sector(fsv_plan &P, void *psi, void *lam, std::string &rep) {
         const int fr = fused_runs(P.ffwd, &fo), rr = fused_runs(P.frev, &ro);
         if (c.mode == 1)
             snprintf(line, sizeof line, "one launch per operator: %.3f ms\n", ms);
+        else if (c.mode == 3)
+            snprintf(line, sizeof line, "component packets: %d runs (%d ops): %.3f ms\n", rr, ro, ms);
         else
             snprintf(line, sizeof line,
                      "fused runs, LDS %zu / %zu KiB: forward %d runs (%d ops), adjoint %d runs (%d ops): %.3f ms\n",
@@ -1196,7 +1268,8 @@ int autotune_sector(fsv_plan &P, void *psi, void *lam, std::string &rep) {
     const int rc2 = apply(rc ? keep : bestc);
     if (rc) return rc;
     if (rc2) return rc2;
-    snprintf(line, sizeof line, "chosen: %s, LDS %zu / %zu KiB\n", bestc.mode == 1 ? "per operator" : "fused runs",
+    snprintf(line, sizeof line, "chosen: %s, LDS %zu / %zu KiB\n",
+             bestc.mode == 1 ? "per operator" : (bestc.mode == 3 ? "component packets" : "fused runs"),
              P.fuse_budget_fwd / 1024, P.fuse_budget_rev / 1024);
     rep += line;
     return FSV_OK;
@@ -1289,9 +1362,21 @@ int fsv_plan_runs(const fsv_plan *P, int adjoint, int32_t *run_start, int32_t *f
     for (const FGroup &g : S.groups)
         for (int k = g.k0; k < g.k0 + g.nops; ++k) {
             if (run_start) run_start[k] = g.k0;
-            if (fused_tiles) fused_tiles[k] = g.fused ? g.n_orbits * g.n_blocks : 0;
+            if (fused_tiles)
+                fused_tiles[k] = g.fused == 2 ? g.n_packets : (g.fused ? g.n_orbits * g.n_blocks : 0);
         }
     return (int)S.groups.size();
+}
+
+int fsv_time_runs(fsv_plan *P, int adjoint, void *psi, void *lam, float *ms) {
+    if (!P || !psi || !ms || (adjoint && !lam)) return fail(FSV_EINVAL, "plan, psi, lam or ms is NULL");
+    if (adjoint != 0 && adjoint != 1) return fail(FSV_EINVAL, "adjoint must be 0 or 1");
+    if (P->engine != 0) return fail(FSV_ESTATE, "per-run timing is available on the sector engine only");
+    int rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = time_sweep_sector(*P, adjoint, psi, lam, ms))) return rc;
+    if ((rc = fence_out(*P))) return rc;
+    return (int)(adjoint ? P->frev : P->ffwd).groups.size();
 }
 
 int fsv_set_theta(fsv_plan *P, const double *theta) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <vector>
 
 #include "../../include/fsv.h"
@@ -169,19 +170,23 @@ hipError_t launch_scatter_real(int precision, void *lam, const double *S, const 
                                int64_t nsa, int64_t nsb, hipStream_t st);
 void init_sigma_kernels();
 
-// ---- fused operator runs on the sector state (fsv_fused.hip) ----
-// A run of consecutive operators applied tile by tile in LDS (fused = 1), or
-// a single operator left to the per-operator kernels (fused = 0, nops = 1).
-// A fused run keeps, per alpha orbit, a program of astride words (row count,
-// row ranks, per-operator local alpha pairs) and, per beta block, one of
-// bstride words (first column, width, per-operator local beta pairs).
+// ---- fused operator runs on the sector state (fsv_fused.hip, fsv_packet.hip) ----
+// A run of consecutive operators applied tile by tile in LDS (fused = 1), by
+// connected-component packets (fused = 2), or a single operator left to the
+// per-operator kernels (fused = 0, nops = 1).  A tile run keeps, per alpha
+// orbit, a program of astride words (row count, row ranks, per-operator local
+// alpha pairs) and, per beta block, one of bstride words (first column, width,
+// per-operator local beta pairs).  A packet run keeps n_packets index lists
+// (at ent_off, 256 words each) and regions of wr words (at reg_off).
 struct FGroup {
     int32_t k0, nops, fused;
     int32_t n_orbits, n_blocks;  // tiles = n_orbits x n_blocks
     int32_t rmax, lmax;          // largest orbit (rows) and block (columns)
     int32_t astride, bstride;
     int64_t aprog_off, bprog_off;
-    size_t lds;                  // dynamic LDS bytes of one tile workgroup
+    size_t lds;                  // dynamic LDS bytes of one tile / packet workgroup
+    int32_t n_packets, wr;
+    int64_t ent_off, reg_off;
 };
 
 struct FusedOpts {
@@ -198,10 +203,18 @@ struct FusedOpts {
 
 struct FusedSched {
     std::vector<FGroup> groups;  // in operator order
-    std::vector<int> count;      // per operator: tiles of its fused run, -1 if not fused
-    uint32_t *d_aprog = nullptr, *d_bprog = nullptr;
-    std::vector<void *> mem;
+    std::vector<int> count;      // per operator: gradient partials of its fused run, -1 if not fused
+    uint32_t *d_aprog = nullptr, *d_bprog = nullptr;  // packet runs: index lists, regions
+    std::vector<std::shared_ptr<void>> mem;  // device buffers (shared by schedules that alias them)
     void release();
+    void share(const FusedSched &o) {  // the same runs and device tables as o
+        release();
+        groups = o.groups;
+        count = o.count;
+        d_aprog = o.d_aprog;
+        d_bprog = o.d_bprog;
+        mem = o.mem;
+    }
     FusedSched() = default;
     FusedSched(const FusedSched &) = delete;
     FusedSched &operator=(const FusedSched &) = delete;
@@ -214,6 +227,15 @@ int build_fused(int M, const std::vector<uint32_t> &sa, const std::vector<uint32
                 const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
                 const std::vector<int32_t> &ops, const FusedOpts &o, FusedSched &S);
 int fused_runs(const FusedSched &S, int *n_fused_ops);
+// Packet runs (fused = 2) for sector states of at most packet_max_dim()
+// amplitudes; o.es, o.mode (0 cost model, 1 never, otherwise every run of >= 2)
+// and o.max_ops are used.  count[k] = gradient partials of operator k's run.
+int64_t packet_max_dim();
+int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
+                  const FusedOpts &o, FusedSched &S);
+// One packet run: forward (psi) or adjoint (psi, lam, gpart[k * gstride + workgroup]).
+hipError_t launch_packets(int vtype, bool adjoint, void *psi, void *lam, const FusedSched &S, const FGroup &g,
+                          const double *cs, double *gpart, int gstride, hipStream_t st);
 void init_fused_kernels();
 size_t fused_lds_limit();
 // Forward (psi) or adjoint (psi, lam, gradient partials gpart[k * gstride + tile]).

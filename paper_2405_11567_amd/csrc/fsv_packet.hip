@@ -1,0 +1,436 @@
+// Fused runs of excitation rotations on the sector state, by connected
+// components ("packets").
+//
+// The rotation of one operator mixes the two amplitudes of each of its active
+// pairs and leaves every other amplitude alone.  For a run of consecutive
+// operators, join two amplitudes whenever some operator of the run pairs them:
+// the connected components of that graph are independent of each other, so
+// each can be carried through the whole run on its own.  For the 24-qubit
+// workloads (853,776 sector amplitudes, random singles and doubles) runs of
+// about a dozen operators still have every component at or below 256
+// amplitudes, while a single operator moves only ~15% of the state: a run
+// becomes one launch over the ~85% of the state it touches instead of a dozen
+// latency-bound launches.
+//
+// The host computes the components (union-find with union by size and
+// rollback, so that a run is extended operator by operator while its largest
+// component fits) and packs whole components into packets of at most 256
+// amplitudes, in order of their smallest index.  Per packet it stores the
+// global indices of its amplitudes (ascending) and a region holding a header
+// (amplitude count, then the cumulative pair count after each operator) and,
+// operator by operator, the packet-local pairs (source | partner << 8 |
+// negative sign << 31, the operator's sign already folded in).  One wavefront
+// per packet: it loads the indices and the region in one round, gathers the
+// amplitudes into LDS (lane l holds slots l, l + 64, l + 128, l + 192, so
+// each load instruction covers 64 consecutive sorted indices), applies the run there (forward:
+// rotations in order; adjoint: for the last operator back to the first, the
+// gradient contribution, then psi and lam un-rotated) and scatters them back.
+// Untouched amplitudes are never read.  Consecutive workgroup ids go to
+// different XCDs, so packet numbers are remapped to give each XCD a contiguous
+// range: packets with nearby amplitudes then share that XCD's L2.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <memory>
+#include <vector>
+
+#include "fsv_device.h"
+#include "fsv_internal.h"
+
+namespace fsv {
+
+namespace {
+
+constexpr int kPkt = 256;            // amplitudes per packet (4 per lane)
+constexpr int kPktHdr = 32;          // header words of a region
+constexpr int kPktMaxOps = 15;       // operators per run: 15 x 128 pairs + header <= kPktMaxWords
+constexpr int kPktMaxWords = 2048;   // region words (header + pairs)
+constexpr uint32_t kNone = 0xFFFFFFFFu;  // padding of the index list
+constexpr int kPktScalars = 2 * 16 + 16;  // LDS doubles: angles of <= 16 operators, gradient sums
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct PArgs {
+    int32_t k0, m, wr, n_packets, gstride;
+    const double *cs;
+};
+
+// Packet of workgroup slot v: XCD v % 8 gets a contiguous range of packets.
+__device__ __forceinline__ int xcd_packet(int v, int n) {
+    const int per = n >> 3, rem = n & 7, x = v & 7, i = v >> 3;
+    return x * per + min(x, rem) + i;
+}
+
+template <typename T>
+__device__ __forceinline__ void rotp(T &a, T &b, T c, T s) {
+    const T t = a;
+    a = c * a - s * b;
+    b = c * b + s * t;
+}
+
+template <typename T, bool ADJ, int NQ>
+__global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restrict__ lam,
+                                               const uint32_t *__restrict__ ent,
+                                               const uint32_t *__restrict__ reg, PArgs a,
+                                               double *__restrict__ gpart) {
+    extern __shared__ double lds[];
+    double *scs = lds;       // cos, sin of the run's operators
+    double *red = lds + 32;  // per-operator gradient sums of this workgroup's packets
+    T *tp = (T *)(lds + kPktScalars);
+    T *tl = tp + kPkt;
+    uint32_t *rg = (uint32_t *)(tp + (ADJ ? 2 : 1) * kPkt);
+    const int l = threadIdx.x;
+    {
+        const int t = min(l, 2 * a.m - 1);
+        const double v = a.cs[2 * a.k0 + t];
+        if (l < 2 * a.m) scs[l] = v;
+        if (ADJ && l < a.m) red[l] = 0.0;
+    }
+    const int nq = a.wr >> 2;
+    for (int v = blockIdx.x; v < a.n_packets; v += gridDim.x) {
+        const int p = xcd_packet(v, a.n_packets);
+        // one round: indices and region (clamped, so every load is in flight at once)
+        const uint32_t *es = ent + (size_t)p * kPkt;
+        const u32x4 *rs = (const u32x4 *)(reg + (size_t)p * a.wr);
+        uint32_t x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = es[l + i * kWave];  // slot l + 64 i
+        u32x4 q[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) q[i] = rs[min(l + i * kWave, nq - 1)];
+        T v0[4], v1[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t xi = x[i] == kNone ? 0u : x[i];
+            v0[i] = psi[xi];
+            if (ADJ) v1[i] = lam[xi];
+        }
+        __syncthreads();  // the previous packet is out of LDS
+        // Unconditional LDS writes: a clamped lane writes the value its
+        // neighbour writes, and padding slots are never named by a pair.
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) ((u32x4 *)rg)[min(l + i * kWave, nq - 1)] = q[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            tp[l + i * kWave] = v0[i];
+            if (ADJ) tl[l + i * kWave] = v1[i];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < a.m; ++jj) {
+            const int j = ADJ ? a.m - 1 - jj : jj;
+            const uint32_t o0 = j ? rg[j] : 0u, o1 = rg[1 + j];
+            const T c = (T)scs[2 * j], s = (T)scs[2 * j + 1];
+            double acc = 0.0;
+            for (uint32_t t = o0 + l; t < o1; t += kWave) {
+                const uint32_t w = rg[kPktHdr + t];
+                const int xs = (int)(w & 0xFFu), xd = (int)((w >> 8) & 0xFFu);
+                const bool neg = (w >> 31) != 0;
+                T va = tp[xs], vb = tp[xd];
+                if (ADJ) {
+                    T la = tl[xs], lb = tl[xd];
+                    const double ov = (double)lb * (double)va - (double)la * (double)vb;
+                    acc += neg ? -ov : ov;
+                    const T sg = neg ? s : -s;  // U^+ = U(-theta)
+                    rotp(va, vb, c, sg);
+                    rotp(la, lb, c, sg);
+                    tl[xs] = la;
+                    tl[xd] = lb;
+                } else {
+                    rotp(va, vb, c, neg ? -s : s);
+                }
+                tp[xs] = va;
+                tp[xd] = vb;
+            }
+            if (ADJ) {
+                acc = wave_sum(acc);
+                if (l == 0) red[j] += acc;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (x[i] != kNone) {
+                psi[x[i]] = tp[l + i * kWave];
+                if (ADJ) lam[x[i]] = tl[l + i * kWave];
+            }
+    }
+    if (ADJ) {
+        __syncthreads();
+        if (l < a.m) gpart[(size_t)(a.k0 + l) * a.gstride + blockIdx.x] = red[l];
+    }
+}
+
+// ---- host: union-find over the amplitudes touched by a run ----
+struct UnionFind {
+    std::vector<int32_t> parent, size, comp;
+    std::vector<uint8_t> seen;
+    std::vector<int32_t> touched, log;
+    explicit UnionFind(int64_t n) : parent(n), size(n, 1), comp(n, -1), seen(n, 0) {
+        for (int64_t i = 0; i < n; ++i) parent[i] = (int32_t)i;
+    }
+    int32_t find(int32_t x) const {  // union by size keeps the depth <= log2(kPkt)
+        while (parent[x] != x) x = parent[x];
+        return x;
+    }
+    void mark(int32_t x) {
+        if (!seen[x]) {
+            seen[x] = 1;
+            touched.push_back(x);
+        }
+    }
+    int32_t unite(int32_t x, int32_t y) {  // size of the joined component
+        int32_t rx = find(x), ry = find(y);
+        if (rx == ry) return size[rx];
+        if (size[rx] < size[ry]) std::swap(rx, ry);
+        parent[ry] = rx;
+        size[rx] += size[ry];
+        log.push_back(ry);
+        return size[rx];
+    }
+    void rollback(size_t lmark, size_t tmark) {
+        for (size_t t = log.size(); t-- > lmark;) {
+            const int32_t ry = log[t], rx = parent[ry];
+            size[rx] -= size[ry];
+            parent[ry] = ry;
+        }
+        log.resize(lmark);
+        for (size_t t = tmark; t < touched.size(); ++t) seen[touched[t]] = 0;
+        touched.resize(tmark);
+    }
+    void reset() {
+        for (int32_t x : touched) {
+            parent[x] = x;
+            size[x] = 1;
+            comp[x] = -1;
+            seen[x] = 0;
+        }
+        touched.clear();
+        log.clear();
+    }
+};
+
+// Calls f(src, dst, neg) for every active pair of operator op; stops early
+// when f returns false.
+template <typename F>
+bool for_pairs(const PairOp &op, const std::vector<uint32_t> &lists, int64_t nsa, int64_t nsb, F &&f) {
+    const int64_t na = op.nA >= 0 ? op.nA : nsa, nb = op.nB >= 0 ? op.nB : nsb;
+    for (int64_t u = 0; u < na; ++u) {
+        int64_t ia = u, ia2 = u;
+        bool nrow = op.sign0 < 0;
+        if (op.nA >= 0) {
+            const uint32_t e = lists[op.offA + u];
+            ia = e & 0x7FFFu;
+            ia2 = (e >> 15) & 0x7FFFu;
+            nrow ^= (e >> 31) != 0;
+        }
+        for (int64_t v = 0; v < nb; ++v) {
+            int64_t ib = v, ib2 = v;
+            bool neg = nrow;
+            if (op.nB >= 0) {
+                const uint32_t e = lists[op.offB + v];
+                ib = e & 0x7FFFu;
+                ib2 = (e >> 15) & 0x7FFFu;
+                neg ^= (e >> 31) != 0;
+            }
+            if (!f((int32_t)(ia * nsb + ib), (int32_t)(ia2 * nsb + ib2), neg)) return false;
+        }
+    }
+    return true;
+}
+
+int upload_words(const std::vector<uint32_t> &vec, FusedSched &S, uint32_t **dst) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(vec.size(), 1) * 4;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FSV_ENOMEM, "hipMalloc of %zu bytes for packet programs failed", bytes);
+    }
+    S.mem.emplace_back(p, [](void *q) { (void)hipFree(q); });
+    if (!vec.empty() && hipMemcpy(p, vec.data(), vec.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FSV_EDEVICE, "upload of packet programs failed");
+    *dst = (uint32_t *)p;
+    return FSV_OK;
+}
+
+}  // namespace
+
+int64_t packet_max_dim() { return (int64_t)1 << 22; }
+
+int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
+                  const FusedOpts &o, FusedSched &S) {
+    S.release();
+    const int K = (int)pops.size();
+    S.count.assign(K, -1);
+    const int64_t N = nsa * nsb;
+    if (K == 0) return FSV_OK;
+    if (N > packet_max_dim()) return fail(FSV_EINVAL, "internal: packet runs need at most %lld amplitudes",
+                                          (long long)packet_max_dim());
+    UnionFind uf(N);
+    auto pairs_of = [&](const PairOp &p) {
+        return (double)(p.nA >= 0 ? p.nA : nsa) * (double)(p.nB >= 0 ? p.nB : nsb);
+    };
+    // cost model (adjoint sweep, per-operator launches ~5 us each; a packet
+    // run ~6 us of launch and load chain plus its bytes at ~2 TB/s)
+    const double bw = 4.0e12, bw_pk = 2.0e12, t_launch = 5.0e-6, t_chain = 6.0e-6;
+    const double amp = (double)o.es * 2;  // psi and lam
+    const int max_ops = std::min(o.max_ops, kPktMaxOps);
+    std::vector<uint32_t> ent, reg;
+    std::vector<int32_t> csize, pk_of, pfill, cnt, cur;
+    std::vector<int32_t> slot(N, 0);
+    auto single = [&](int k) {
+        FGroup s{};
+        s.k0 = k;
+        s.nops = 1;
+        S.groups.push_back(s);
+    };
+    int i = 0;
+    while (i < K) {
+        int j = i;
+        while (j < K && j - i < max_ops) {
+            const size_t lmark = uf.log.size(), tmark = uf.touched.size();
+            const bool ok = for_pairs(pops[j], lists, nsa, nsb, [&](int32_t s, int32_t d, bool) {
+                uf.mark(s);
+                uf.mark(d);
+                return uf.unite(s, d) <= kPkt;
+            });
+            if (!ok) {
+                uf.rollback(lmark, tmark);
+                break;
+            }
+            ++j;
+        }
+        const int m = j - i;
+        bool fuse = m >= 2 && o.mode != 1 && !uf.touched.empty();
+        double npairs = 0.0;
+        for (int k = i; k < j; ++k) npairs += pairs_of(pops[k]);
+        if (fuse && o.mode == 0) {
+            const double t_ops = m * t_launch + npairs * 4.0 * amp / bw;
+            const double t_pk = t_chain + ((double)uf.touched.size() * (2.0 * amp + 4.0) + npairs * 4.0) / bw_pk;
+            fuse = t_pk < t_ops;
+        }
+        if (!fuse) {
+            for (int k = i; k < j; ++k) single(k);
+            uf.reset();
+            i = j;
+            continue;
+        }
+        // components in order of their smallest amplitude, packed greedily
+        std::vector<int32_t> &tv = uf.touched;
+        std::sort(tv.begin(), tv.end());
+        csize.clear();
+        for (int32_t x : tv) {
+            const int32_t r = uf.find(x);
+            if (uf.comp[r] < 0) {
+                uf.comp[r] = (int32_t)csize.size();
+                csize.push_back(uf.size[r]);
+            }
+        }
+        pk_of.assign(csize.size(), 0);
+        int npk = 0, fill = kPkt;
+        for (size_t c = 0; c < csize.size(); ++c) {
+            if (fill + csize[c] > kPkt) {
+                ++npk;
+                fill = 0;
+            }
+            pk_of[c] = npk - 1;
+            fill += csize[c];
+        }
+        const size_t e0 = ent.size();
+        ent.resize(e0 + (size_t)npk * kPkt, kNone);
+        pfill.assign(npk, 0);
+        for (int32_t x : tv) {
+            const int pk = pk_of[uf.comp[uf.find(x)]];
+            const int sl = pfill[pk]++;
+            ent[e0 + (size_t)pk * kPkt + sl] = (uint32_t)x;
+            slot[x] = sl;
+        }
+        // per packet and operator pair counts, then the regions
+        cnt.assign((size_t)npk * m, 0);
+        for (int jj = 0; jj < m; ++jj)
+            for_pairs(pops[i + jj], lists, nsa, nsb, [&](int32_t s, int32_t, bool) {
+                ++cnt[(size_t)pk_of[uf.comp[uf.find(s)]] * m + jj];
+                return true;
+            });
+        int maxp = 0;
+        for (int pk = 0; pk < npk; ++pk) {
+            int t = 0;
+            for (int jj = 0; jj < m; ++jj) t += cnt[(size_t)pk * m + jj];
+            maxp = std::max(maxp, t);
+        }
+        const int wr = (kPktHdr + maxp + 3) & ~3;
+        if (wr > kPktMaxWords) return fail(FSV_EINVAL, "internal: packet region of %d words", wr);
+        const size_t r0 = reg.size();
+        reg.resize(r0 + (size_t)npk * wr, 0u);
+        cur.assign((size_t)npk * m, 0);
+        for (int pk = 0; pk < npk; ++pk) {
+            uint32_t *h = &reg[r0 + (size_t)pk * wr];
+            h[0] = (uint32_t)pfill[pk];
+            int t = 0;
+            for (int jj = 0; jj < m; ++jj) {
+                cur[(size_t)pk * m + jj] = t;
+                t += cnt[(size_t)pk * m + jj];
+                h[1 + jj] = (uint32_t)t;
+            }
+        }
+        for (int jj = 0; jj < m; ++jj)
+            for_pairs(pops[i + jj], lists, nsa, nsb, [&](int32_t s, int32_t d, bool neg) {
+                const int pk = pk_of[uf.comp[uf.find(s)]];
+                const int at = cur[(size_t)pk * m + jj]++;
+                reg[r0 + (size_t)pk * wr + kPktHdr + at] =
+                    (uint32_t)slot[s] | ((uint32_t)slot[d] << 8) | (neg ? 0x80000000u : 0u);
+                return true;
+            });
+        FGroup g{};
+        g.k0 = i;
+        g.nops = m;
+        g.fused = 2;
+        g.n_packets = npk;
+        g.wr = wr;
+        g.ent_off = (int64_t)e0;
+        g.reg_off = (int64_t)r0;
+        g.lds = sizeof(double) * kPktScalars + (size_t)kPkt * 2 * o.es + (size_t)wr * 4;
+        const int grid = std::min(npk, max_grid());
+        for (int k = i; k < j; ++k) S.count[k] = grid;
+        S.groups.push_back(g);
+        uf.reset();
+        i = j;
+    }
+    int rc;
+    if ((rc = upload_words(ent, S, &S.d_aprog)) || (rc = upload_words(reg, S, &S.d_bprog))) {
+        S.release();
+        return rc;
+    }
+    return FSV_OK;
+}
+
+namespace {
+
+template <typename T, bool ADJ>
+hipError_t pkt_impl(void *psi, void *lam, const FusedSched &S, const FGroup &g, const double *cs, double *gpart,
+                    int gstride, hipStream_t st) {
+    PArgs a{g.k0, g.nops, g.wr, g.n_packets, gstride, cs};
+    const uint32_t *ent = S.d_aprog + g.ent_off, *reg = S.d_bprog + g.reg_off;
+    const size_t shm = sizeof(double) * kPktScalars + (size_t)kPkt * (ADJ ? 2 : 1) * sizeof(T) + (size_t)g.wr * 4;
+    const dim3 grid((unsigned)std::min(g.n_packets, max_grid())), block(kWave);
+    if (g.wr <= 4 * kWave * 2)
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 2>), grid, block, shm, st, (T *)psi, (T *)lam, ent, reg, a, gpart);
+    else if (g.wr <= 4 * kWave * 4)
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 4>), grid, block, shm, st, (T *)psi, (T *)lam, ent, reg, a, gpart);
+    else
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 8>), grid, block, shm, st, (T *)psi, (T *)lam, ent, reg, a, gpart);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_packets(int vtype, bool adjoint, void *psi, void *lam, const FusedSched &S, const FGroup &g,
+                          const double *cs, double *gpart, int gstride, hipStream_t st) {
+    if (vtype == V_F64)
+        return adjoint ? pkt_impl<double, true>(psi, lam, S, g, cs, gpart, gstride, st)
+                       : pkt_impl<double, false>(psi, lam, S, g, cs, gpart, gstride, st);
+    return adjoint ? pkt_impl<float, true>(psi, lam, S, g, cs, gpart, gstride, st)
+                   : pkt_impl<float, false>(psi, lam, S, g, cs, gpart, gstride, st);
+}
+
+}  // namespace fsv

@@ -250,17 +250,20 @@ def test_sigma_paths(fsv, monkeypatch, mode, nfac):
         assert abs(plan.energy(psi) - e_ref) < 1e-10
 
 
-@pytest.mark.parametrize("mode", ["auto", "none", "force"])
+@pytest.mark.parametrize("mode", ["auto", "none", "force", "tiles", "packets"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_fused_runs_sector(fsv, monkeypatch, mode, precision):
-    # runs of operators applied tile by tile in LDS against one launch per
-    # operator; draws with replacement from the whole pool mix alpha-only,
-    # beta-only and alpha-beta operators in every run
+    # runs of operators applied tile by tile in LDS or by component packets
+    # (the default at this size) against one launch per operator; draws with
+    # replacement from the whole pool mix alpha-only, beta-only and alpha-beta
+    # operators in every run
     p = random_problem(16, 8, 120, seed=801, theta_std=0.5, replace=True, ordering=1)
     if mode == "none":
         monkeypatch.setenv("FSV_NO_FUSE", "1")
     if mode == "force":
         monkeypatch.setenv("FSV_FORCE_FUSE", "1")
+    if mode in ("tiles", "packets"):
+        monkeypatch.setenv("FSV_FUSE", mode)
     say("fused runs", mode, precision)
     plan = fsv.Plan(p, precision=precision)
     start, tiles = plan.runs()
