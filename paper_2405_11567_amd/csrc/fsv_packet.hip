@@ -15,7 +15,7 @@
 // The host computes the components (union-find with union by size and
 // rollback, so that a run is extended operator by operator while its largest
 // component fits) and packs whole components into packets of at most 256
-// amplitudes, in order of their smallest index.  Per packet it stores the
+// amplitudes, row group by row group (rows that some component joins).  Per packet it stores the
 // global indices of its amplitudes (ascending) and a region holding a header
 // (amplitude count, then the cumulative pair count after each operator) and,
 // operator by operator, the packet-local pairs (source | partner << 8 |
@@ -27,7 +27,8 @@
 // gradient contribution, then psi and lam un-rotated) and scatters them back.
 // Untouched amplitudes are never read.  Consecutive workgroup ids go to
 // different XCDs, so packet numbers are remapped to give each XCD a contiguous
-// range: packets with nearby amplitudes then share that XCD's L2.
+// range of packets: with packets laid out by row group, the packets that
+// share a cache line then share that XCD's L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -47,7 +48,7 @@ constexpr int kPktHdr = 32;          // header words of a region
 constexpr int kPktMaxOps = 15;       // operators per run: 15 x 128 pairs + header <= kPktMaxWords
 constexpr int kPktMaxWords = 2048;   // region words (header + pairs)
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // padding of the index list
-constexpr int kPktScalars = 2 * 16 + 16;  // LDS doubles: angles of <= 16 operators, gradient sums
+constexpr int kPktScalars = 2 * 16;  // LDS doubles: angles of <= 16 operators
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -75,8 +76,7 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
                                                const uint32_t *__restrict__ reg, PArgs a,
                                                double *__restrict__ gpart) {
     extern __shared__ double lds[];
-    double *scs = lds;       // cos, sin of the run's operators
-    double *red = lds + 32;  // per-operator gradient sums of this workgroup's packets
+    double *scs = lds;  // cos, sin of the run's operators
     T *tp = (T *)(lds + kPktScalars);
     T *tl = tp + kPkt;
     uint32_t *rg = (uint32_t *)(tp + (ADJ ? 2 : 1) * kPkt);
@@ -85,8 +85,10 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
         const int t = min(l, 2 * a.m - 1);
         const double v = a.cs[2 * a.k0 + t];
         if (l < 2 * a.m) scs[l] = v;
-        if (ADJ && l < a.m) red[l] = 0.0;
     }
+    double acc[kPktMaxOps];  // this lane's share of each operator's gradient term (sweep order)
+#pragma unroll
+    for (int jj = 0; jj < kPktMaxOps; ++jj) acc[jj] = 0.0;
     const int nq = a.wr >> 2;
     for (int v = blockIdx.x; v < a.n_packets; v += gridDim.x) {
         const int p = xcd_packet(v, a.n_packets);
@@ -117,36 +119,48 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
             if (ADJ) tl[l + i * kWave] = v1[i];
         }
         __syncthreads();
-        for (int jj = 0; jj < a.m; ++jj) {
+        // Operator jj of the sweep order (adjoint: last to first).  Its pair
+        // range and each lane's first pair word are read before the loop, so
+        // a step waits only for its amplitudes; gradient contributions stay
+        // per lane in registers and are reduced once, after the packets.
+        uint32_t ob[kPktMaxOps], oe[kPktMaxOps], w0[kPktMaxOps];
+#pragma unroll
+        for (int jj = 0; jj < kPktMaxOps; ++jj) {
             const int j = ADJ ? a.m - 1 - jj : jj;
-            const uint32_t o0 = j ? rg[j] : 0u, o1 = rg[1 + j];
-            const T c = (T)scs[2 * j], s = (T)scs[2 * j + 1];
-            double acc = 0.0;
-            for (uint32_t t = o0 + l; t < o1; t += kWave) {
-                const uint32_t w = rg[kPktHdr + t];
-                const int xs = (int)(w & 0xFFu), xd = (int)((w >> 8) & 0xFFu);
-                const bool neg = (w >> 31) != 0;
-                T va = tp[xs], vb = tp[xd];
-                if (ADJ) {
-                    T la = tl[xs], lb = tl[xd];
-                    const double ov = (double)lb * (double)va - (double)la * (double)vb;
-                    acc += neg ? -ov : ov;
-                    const T sg = neg ? s : -s;  // U^+ = U(-theta)
-                    rotp(va, vb, c, sg);
-                    rotp(la, lb, c, sg);
-                    tl[xs] = la;
-                    tl[xd] = lb;
-                } else {
-                    rotp(va, vb, c, neg ? -s : s);
+            const int jc = max(j, 0);
+            ob[jj] = jc ? rg[jc] : 0u;
+            oe[jj] = rg[1 + jc];
+        }
+#pragma unroll
+        for (int jj = 0; jj < kPktMaxOps; ++jj) w0[jj] = rg[kPktHdr + min(ob[jj] + l, (uint32_t)(a.wr - kPktHdr - 1))];
+#pragma unroll
+        for (int jj = 0; jj < kPktMaxOps; ++jj) {
+            if (jj < a.m) {
+                const int j = ADJ ? a.m - 1 - jj : jj;
+                const T c = (T)scs[2 * j], s = (T)scs[2 * j + 1];
+                uint32_t w = w0[jj];
+                for (uint32_t t = ob[jj] + l; t < oe[jj]; t += kWave) {
+                    if (t != ob[jj] + l) w = rg[kPktHdr + t];
+                    const int xs = (int)(w & 0xFFu), xd = (int)((w >> 8) & 0xFFu);
+                    const bool neg = (w >> 31) != 0;
+                    T va = tp[xs], vb = tp[xd];
+                    if (ADJ) {
+                        T la = tl[xs], lb = tl[xd];
+                        const double ov = (double)lb * (double)va - (double)la * (double)vb;
+                        acc[jj] += neg ? -ov : ov;
+                        const T sg = neg ? s : -s;  // U^+ = U(-theta)
+                        rotp(va, vb, c, sg);
+                        rotp(la, lb, c, sg);
+                        tl[xs] = la;
+                        tl[xd] = lb;
+                    } else {
+                        rotp(va, vb, c, neg ? -s : s);
+                    }
+                    tp[xs] = va;
+                    tp[xd] = vb;
                 }
-                tp[xs] = va;
-                tp[xd] = vb;
+                __syncthreads();
             }
-            if (ADJ) {
-                acc = wave_sum(acc);
-                if (l == 0) red[j] += acc;
-            }
-            __syncthreads();
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -156,8 +170,14 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
             }
     }
     if (ADJ) {
-        __syncthreads();
-        if (l < a.m) gpart[(size_t)(a.k0 + l) * a.gstride + blockIdx.x] = red[l];
+        // one butterfly for all operators: independent shuffles per step
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int jj = 0; jj < kPktMaxOps; ++jj) acc[jj] += __shfl_xor(acc[jj], off, kWave);
+#pragma unroll
+        for (int jj = 0; jj < kPktMaxOps; ++jj)
+            if (jj < a.m && l == 0) gpart[(size_t)(a.k0 + a.m - 1 - jj) * a.gstride + blockIdx.x] = acc[jj];
     }
 }
 
@@ -276,8 +296,8 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
     const double amp = (double)o.es * 2;  // psi and lam
     const int max_ops = std::min(o.max_ops, kPktMaxOps);
     std::vector<uint32_t> ent, reg;
-    std::vector<int32_t> csize, pk_of, pfill, cnt, cur;
-    std::vector<int32_t> slot(N, 0);
+    std::vector<int32_t> csize, crow, order, pk_of, pfill, cnt, cur;
+    std::vector<int32_t> slot(N, 0), rpar(nsa);
     auto single = [&](int k) {
         FGroup s{};
         s.k0 = k;
@@ -315,20 +335,41 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
             i = j;
             continue;
         }
-        // components in order of their smallest amplitude, packed greedily
+        // Components, numbered in order of their smallest amplitude.
         std::vector<int32_t> &tv = uf.touched;
         std::sort(tv.begin(), tv.end());
         csize.clear();
+        crow.clear();
         for (int32_t x : tv) {
             const int32_t r = uf.find(x);
             if (uf.comp[r] < 0) {
                 uf.comp[r] = (int32_t)csize.size();
                 csize.push_back(uf.size[r]);
+                crow.push_back((int32_t)(x / nsb));
             }
         }
+        // Row groups: rows joined whenever one component has amplitudes in
+        // both.  Every component touching a row lies in that row's group, so
+        // a cache line (a segment of one row) is only ever touched by packets
+        // of one group.  Packets are laid out group by group (groups in order
+        // of their first row), and the kernel gives each XCD a contiguous
+        // range of packets, so most lines live in one XCD's L2.
+        for (int64_t r = 0; r < nsa; ++r) rpar[r] = (int32_t)r;
+        auto rfind = [&](int32_t r) {
+            while (rpar[r] != r) r = rpar[r] = rpar[rpar[r]];
+            return r;
+        };
+        for (int32_t x : tv) {
+            const int32_t a = rfind(crow[uf.comp[uf.find(x)]]), b = rfind((int32_t)(x / nsb));
+            if (a != b) rpar[std::max(a, b)] = std::min(a, b);  // root = smallest row
+        }
+        order.resize(csize.size());
+        for (size_t c = 0; c < order.size(); ++c) order[c] = (int32_t)c;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t u, int32_t v) { return rfind(crow[u]) < rfind(crow[v]); });
         pk_of.assign(csize.size(), 0);
         int npk = 0, fill = kPkt;
-        for (size_t c = 0; c < csize.size(); ++c) {
+        for (int32_t c : order) {
             if (fill + csize[c] > kPkt) {
                 ++npk;
                 fill = 0;

@@ -386,29 +386,33 @@ __global__ __launch_bounds__(256) void k_lr_a(const A *__restrict__ C, A *__rest
 // Y[Ia][Jb_f][l].  One workgroup per Ia stages its Y row (nsb x lc values)
 // and the matching lc columns of Lt in LDS, lc of the RP values at a time;
 // the beta lists are read transposed (excBT[f][Ib]) so the lanes' loads
-// coalesce.
+// coalesce.  The staged rows are ys (Y) and ws (Lt) elements apart: with
+// lc = 8 a 64-byte stride would start every lane's 16-byte LDS read in one
+// of only 4 bank groups, so the host pads the strides by 16 bytes.
 template <typename A>
 __global__ __launch_bounds__(1024) void k_lr_b(const A *__restrict__ Y, A *__restrict__ S,
                                                const uint32_t *__restrict__ excBT, int nexcB,
                                                const double *__restrict__ Lt, int M2, int RP, int64_t nsb,
-                                               int lc) {
+                                               int lc, int ys, int ws) {
     extern __shared__ double smem_d[];
-    double *lt = smem_d;               // M2 x lc
-    A *yr = (A *)(lt + M2 * lc);       // nsb x lc
+    double *lt = smem_d;               // M2 x ws
+    A *yr = (A *)(lt + M2 * ws);       // nsb x ys
     const int64_t Ia = blockIdx.x;
     const A *yrow = Y + Ia * nsb * RP;
     A *srow = S + Ia * nsb;
     for (int l0 = 0; l0 < RP; l0 += lc) {
         __syncthreads();  // readers of the previous chunk are done
-        for (int i = threadIdx.x; i < M2 * lc; i += blockDim.x) lt[i] = Lt[(i / lc) * RP + l0 + i % lc];
-        for (int64_t i = threadIdx.x; i < nsb * lc; i += blockDim.x) yr[i] = yrow[(i / lc) * RP + l0 + i % lc];
+        for (int i = threadIdx.x; i < M2 * lc; i += blockDim.x)
+            lt[(i / lc) * ws + i % lc] = Lt[(i / lc) * RP + l0 + i % lc];
+        for (int64_t i = threadIdx.x; i < nsb * lc; i += blockDim.x)
+            yr[(i / lc) * ys + i % lc] = yrow[(i / lc) * RP + l0 + i % lc];
         __syncthreads();
         for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
             A acc = zero<A>();
             for (int f = 0; f < nexcB; ++f) {
                 const uint32_t eb = excBT[(int64_t)f * nsb + Ib];
-                const double *w = lt + ((eb >> 16) & 0x1FFu) * lc;
-                const A *y = yr + (int64_t)(eb & 0xFFFFu) * lc;
+                const double *w = lt + ((eb >> 16) & 0x1FFu) * ws;
+                const A *y = yr + (int64_t)(eb & 0xFFFFu) * ys;
                 A t = zero<A>();
                 for (int l = 0; l < lc; ++l) axpy(t, w[l], y[l]);
                 acc = add(acc, neg_if((eb >> 31) != 0, t));
@@ -548,6 +552,21 @@ int lr_chunk(const SectorTabs &T, int rp) {
     return lc;
 }
 
+// Padded LDS strides (in elements) of k_lr_b's staged rows for lc values per
+// row: 16 bytes more than the row when lc >= 4 and the padded rows still fit.
+template <typename A>
+void lr_strides(const SectorTabs &T, int lc, int &ys, int &ws) {
+    const size_t lim = g_lds_max > 0 ? (size_t)g_lds_max : 65536;
+    ys = lc;
+    ws = lc;
+    if (lc < 4) return;
+    const int py = lc + (int)(16 / sizeof(A)), pw = lc + 2;
+    if ((size_t)T.M * T.M * pw * sizeof(double) + (size_t)T.nsb * py * sizeof(A) <= lim) {
+        ys = py;
+        ws = pw;
+    }
+}
+
 template <typename A, int RP>
 hipError_t lr_launch(const SectorTabs &T, const A *C, A *S, hipStream_t st) {
     A *Y = (A *)T.YT;
@@ -556,9 +575,11 @@ hipError_t lr_launch(const SectorTabs &T, const A *C, A *S, hipStream_t st) {
     hipLaunchKernelGGL((k_lr_a<A, RP>), dim3((unsigned)T.nsa, (unsigned)((T.nsb + 255) / 256)), dim3(256), 0, st,
                        C, Y, T.excA, T.nexcA, T.Lt, T.nsb);
     const int M2 = T.M * T.M;
-    const size_t shm = (size_t)lc * ((size_t)M2 * sizeof(double) + (size_t)T.nsb * sizeof(A));
+    int ys, ws;
+    lr_strides<A>(T, lc, ys, ws);
+    const size_t shm = (size_t)M2 * ws * sizeof(double) + (size_t)T.nsb * ys * sizeof(A);
     hipLaunchKernelGGL((k_lr_b<A>), dim3((unsigned)T.nsa), dim3(1024), shm, st, Y, S, T.excBT, T.nexcB, T.Lt, M2,
-                       RP, T.nsb, lc);
+                       RP, T.nsb, lc, ys, ws);
     return hipGetLastError();
 }
 

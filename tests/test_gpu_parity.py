@@ -285,6 +285,21 @@ def test_fused_runs_sector(fsv, monkeypatch, mode, precision):
         assert abs(e - e_ref) < 1e-4 and np.abs(g - g_ref).max() < 1e-3
 
 
+def test_packet_runs_many_packets(fsv):
+    # 26 qubits (2.9 M sector amplitudes): runs hold more packets than the
+    # launch grid, so workgroups carry several packets each
+    p = random_problem(26, 12, 60, seed=1201, theta_std=0.3, replace=True)
+    say("packets, 26 qubits")
+    plan = fsv.Plan(p)
+    start, tiles = plan.runs(adjoint=True)
+    assert tiles.max() > 8192
+    e, g = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p)
+    assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+    e2, g2 = plan.energy_grad(p.theta)
+    assert e2 == e and np.array_equal(g2, g)
+
+
 def test_sector_autotune(fsv):
     # every candidate LDS budget is run and timed; the chosen schedule keeps parity
     p = config("C2")
