@@ -18,8 +18,11 @@
 // amplitudes, row group by row group (rows that some component joins).  Per packet it stores the
 // global indices of its amplitudes (ascending) and a region holding a header
 // (amplitude count, then the cumulative pair count after each operator) and,
-// operator by operator, the packet-local pairs (source | partner << 8 |
-// negative sign << 31, the operator's sign already folded in).  One wavefront
+// operator by operator, the packet-local pairs as 16-bit words (first slot |
+// second slot << 8).  The pair's sign is carried by the order of the slots:
+// swapping the two amplitudes of a pair turns a rotation by -theta into one
+// by +theta, and negates its gradient term, so every stored pair is applied
+// with the positive sign.  One wavefront
 // per packet: it loads the indices and the region in one round, gathers the
 // amplitudes into LDS (lane l holds slots l, l + 64, l + 128, l + 192, so
 // each load instruction covers 64 consecutive sorted indices), applies the run there (forward:
@@ -45,9 +48,11 @@ namespace {
 
 constexpr int kPkt = 256;            // amplitudes per packet (4 per lane)
 constexpr int kPktHdr = 32;          // header words of a region
-constexpr int kPktMaxOps = 15;       // operators per run: 15 x 128 pairs + header <= kPktMaxWords
-constexpr int kPktMaxWords = 2048;   // region words (header + pairs)
+constexpr int kPktMaxOps = 15;       // operators per run: 15 x 128 16-bit pairs + header <= kPktMaxWords
+constexpr int kPktMaxWords = 1024;   // region words (header + pairs)
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // padding of the index list
+// an operator's pairs in one packet are disjoint: at most kPkt / 2 of them
+static_assert(kPktHdr + kPktMaxOps * (kPkt / 2) / 2 <= kPktMaxWords, "packet region bound");
 constexpr int kPktScalars = 2 * 16;  // LDS doubles: angles of <= 16 operators
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -123,6 +128,9 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
         // range and each lane's first pair word are read before the loop, so
         // a step waits only for its amplitudes; gradient contributions stay
         // per lane in registers and are reduced once, after the packets.
+        const uint32_t *rp = rg + kPktHdr;  // the pairs, two 16-bit words per 32-bit word
+        const uint32_t npmax = 2u * (uint32_t)(a.wr - kPktHdr) - 1u;
+        auto pair_at = [&](uint32_t t) { return (rp[t >> 1] >> ((t & 1u) << 4)) & 0xFFFFu; };
         uint32_t ob[kPktMaxOps], oe[kPktMaxOps], w0[kPktMaxOps];
 #pragma unroll
         for (int jj = 0; jj < kPktMaxOps; ++jj) {
@@ -132,7 +140,7 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
             oe[jj] = rg[1 + jc];
         }
 #pragma unroll
-        for (int jj = 0; jj < kPktMaxOps; ++jj) w0[jj] = rg[kPktHdr + min(ob[jj] + l, (uint32_t)(a.wr - kPktHdr - 1))];
+        for (int jj = 0; jj < kPktMaxOps; ++jj) w0[jj] = pair_at(min(ob[jj] + l, npmax));
 #pragma unroll
         for (int jj = 0; jj < kPktMaxOps; ++jj) {
             if (jj < a.m) {
@@ -140,21 +148,18 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
                 const T c = (T)scs[2 * j], s = (T)scs[2 * j + 1];
                 uint32_t w = w0[jj];
                 for (uint32_t t = ob[jj] + l; t < oe[jj]; t += kWave) {
-                    if (t != ob[jj] + l) w = rg[kPktHdr + t];
-                    const int xs = (int)(w & 0xFFu), xd = (int)((w >> 8) & 0xFFu);
-                    const bool neg = (w >> 31) != 0;
+                    if (t != ob[jj] + l) w = pair_at(t);
+                    const int xs = (int)(w & 0xFFu), xd = (int)(w >> 8);
                     T va = tp[xs], vb = tp[xd];
                     if (ADJ) {
                         T la = tl[xs], lb = tl[xd];
-                        const double ov = (double)lb * (double)va - (double)la * (double)vb;
-                        acc[jj] += neg ? -ov : ov;
-                        const T sg = neg ? s : -s;  // U^+ = U(-theta)
-                        rotp(va, vb, c, sg);
-                        rotp(la, lb, c, sg);
+                        acc[jj] += (double)lb * (double)va - (double)la * (double)vb;
+                        rotp(va, vb, c, -s);  // U^+ = U(-theta)
+                        rotp(la, lb, c, -s);
                         tl[xs] = la;
                         tl[xd] = lb;
                     } else {
-                        rotp(va, vb, c, neg ? -s : s);
+                        rotp(va, vb, c, s);
                     }
                     tp[xs] = va;
                     tp[xd] = vb;
@@ -399,7 +404,7 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
             for (int jj = 0; jj < m; ++jj) t += cnt[(size_t)pk * m + jj];
             maxp = std::max(maxp, t);
         }
-        const int wr = (kPktHdr + maxp + 3) & ~3;
+        const int wr = (kPktHdr + (maxp + 1) / 2 + 3) & ~3;
         if (wr > kPktMaxWords) return fail(FSV_EINVAL, "internal: packet region of %d words", wr);
         const size_t r0 = reg.size();
         reg.resize(r0 + (size_t)npk * wr, 0u);
@@ -418,8 +423,8 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
             for_pairs(pops[i + jj], lists, nsa, nsb, [&](int32_t s, int32_t d, bool neg) {
                 const int pk = pk_of[uf.comp[uf.find(s)]];
                 const int at = cur[(size_t)pk * m + jj]++;
-                reg[r0 + (size_t)pk * wr + kPktHdr + at] =
-                    (uint32_t)slot[s] | ((uint32_t)slot[d] << 8) | (neg ? 0x80000000u : 0u);
+                const uint32_t v = neg ? (uint32_t)(slot[d] | (slot[s] << 8)) : (uint32_t)(slot[s] | (slot[d] << 8));
+                reg[r0 + (size_t)pk * wr + kPktHdr + (at >> 1)] |= v << ((at & 1) << 4);
                 return true;
             });
         FGroup g{};
@@ -456,10 +461,8 @@ hipError_t pkt_impl(void *psi, void *lam, const FusedSched &S, const FGroup &g, 
     const dim3 grid((unsigned)std::min(g.n_packets, max_grid())), block(kWave);
     if (g.wr <= 4 * kWave * 2)
         hipLaunchKernelGGL((k_pkt<T, ADJ, 2>), grid, block, shm, st, (T *)psi, (T *)lam, ent, reg, a, gpart);
-    else if (g.wr <= 4 * kWave * 4)
+    else  // wr <= kPktMaxWords
         hipLaunchKernelGGL((k_pkt<T, ADJ, 4>), grid, block, shm, st, (T *)psi, (T *)lam, ent, reg, a, gpart);
-    else
-        hipLaunchKernelGGL((k_pkt<T, ADJ, 8>), grid, block, shm, st, (T *)psi, (T *)lam, ent, reg, a, gpart);
     return hipGetLastError();
 }
 
