@@ -132,7 +132,7 @@ struct fsv_plan {
     int lr_R = 0;     // rank of the factorised alpha-beta product (0: direct)
     // dense same-spin string Hamiltonians (FP64 GEMM on the matrix cores)
     rocblas_handle blas = nullptr;
-    double *d_ha_dense = nullptr, *d_hb_dense = nullptr;
+    double *d_ha_dense = nullptr, *d_hb_dense = nullptr, *d_hb_dense_t = nullptr;
     std::vector<PairOp> pops;
     std::vector<uint32_t> h_plists;  // host copy of the pair lists (fused-run tables are built from it)
     uint32_t *d_plists = nullptr;
@@ -614,6 +614,7 @@ int refresh_dense_same_spin(fsv_plan &P) {
     if (!P.d_ha_dense) return FSV_OK;
     HIPCHECK(launch_csr_dense(P.d_ha_ptr, P.d_ha_col, P.d_ha_val, P.d_ha_dense, P.nsa, P.work));
     HIPCHECK(launch_csr_dense(P.d_hb_ptr, P.d_hb_col, P.d_hb_val, P.d_hb_dense, P.nsb, P.work));
+    HIPCHECK(launch_ctranspose(false, P.d_hb_dense, P.d_hb_dense_t, P.nsb, P.nsb, P.work));
     HIPCHECK(hipStreamSynchronize(P.work));
     return FSV_OK;
 }
@@ -1177,11 +1178,12 @@ int build_device(fsv_plan &P) {
             return fail(FSV_EDEVICE, "rocblas_set_atomics_mode failed");
         if ((rc = dalloc(P, &P.d_ha_dense, (size_t)P.nsa * P.nsa))) return rc;
         if ((rc = dalloc(P, &P.d_hb_dense, (size_t)P.nsb * P.nsb))) return rc;
+        if ((rc = dalloc(P, &P.d_hb_dense_t, (size_t)P.nsb * P.nsb))) return rc;
         if ((rc = refresh_dense_same_spin(P))) return rc;
     }
     P.tabs = SectorTabs{P.nsa, P.nsb, M, P.nexcA, P.nexcB, P.d_ha_ptr, P.d_hb_ptr, P.d_ha_col,
                         P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_excBT, P.d_g, P.ecore,
-                        R, d_Lt, d_YT, P.d_ha_dense, P.d_hb_dense, (void *)P.blas};
+                        R, d_Lt, d_YT, P.d_ha_dense, P.d_hb_dense, (void *)P.blas, P.d_hb_dense_t};
     if (P.blas) {
         // one eager product per amplitude type, outside any graph capture, so
         // that the library has loaded its kernels and sized its workspace

@@ -139,6 +139,9 @@ struct SectorTabs {
     // nullptr: the CSR rows above.
     const double *ha_dense, *hb_dense;
     void *blas;
+    // hb_dense transposed (its column-major form): real states add the beta
+    // product into S with one untransposed GEMM on it
+    const double *hb_dense_t;
 };
 
 int cadj_blocks(const PairOp &op, int64_t nsa, int64_t nsb);  // partials written by launch_cadj

@@ -9,6 +9,7 @@
 
 #include <rocblas/rocblas.h>
 
+#include <cstdlib>
 #include <vector>
 
 #include "fsv_device.h"
@@ -234,6 +235,21 @@ hipError_t dense_same_spin(void *blas, const double *H, const double *in, double
     return rs == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }
 
+// Same-spin beta part of a real state accumulated in place, with no
+// transposes of the state: S[Ia][Ib] += sum_Jb Hb[Ib][Jb] C[Ia][Jb].  Read
+// column-major, the row-major S and C are nsb x nsa matrices and the
+// row-major Hb^T (HbT) is Hb, so this is S += Hb x C, one untransposed GEMM.
+hipError_t dense_beta_accumulate(void *blas, const double *HbT, const double *C, double *S, int64_t nsa,
+                                 int64_t nsb, hipStream_t st) {
+    rocblas_handle h = (rocblas_handle)blas;
+    const double one = 1.0;
+    if (rocblas_set_stream(h, st) != rocblas_status_success) return hipErrorInvalidHandle;
+    const rocblas_status rs =
+        rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)nsb, (rocblas_int)nsa,
+                      (rocblas_int)nsb, &one, HbT, (rocblas_int)nsb, C, (rocblas_int)nsb, &one, S, (rocblas_int)nsb);
+    return rs == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
 // Alpha-beta two-body term, one workgroup per output row Ia:
 //   S[Ia][Ib] += sum_{e in exc(Ia)} sum_{f in exc(Ib)} s_e s_f (pq_e|rs_f) C[J_e][J_f].
 // The alpha excitations are taken ec at a time.  Their source rows are staged
@@ -422,6 +438,71 @@ __global__ __launch_bounds__(1024) void k_lr_b(const A *__restrict__ Y, A *__res
     }
 }
 
+// Both steps in one workgroup per alpha string Ia (real states, RP = 8, the
+// Y row in LDS): the row Y[Ia][:][:] is built from Ia's alpha excitations
+// (each thread one Jb; the excitation words and factor rows are
+// workgroup-uniform, so they come through scalar loads) straight into LDS,
+// then step 2 runs on it as in k_lr_b.  Y never goes to memory.  Rows are
+// kLrStride = 9 doubles apart (72 bytes: lanes' 8-byte reads start in 32
+// different bank pairs), which keeps two workgroups per CU at 24 qubits.
+constexpr int kLrStride = 9;
+
+__global__ __launch_bounds__(1024) void k_lr_ab(const double *__restrict__ C, double *__restrict__ S,
+                                                const uint32_t *__restrict__ excA, int nexcA,
+                                                const uint32_t *__restrict__ excBT, int nexcB,
+                                                const double *__restrict__ Lt, int M2, int64_t nsb) {
+    constexpr int RP = 8;
+    extern __shared__ double smem_d[];
+    double *lt = smem_d;                // M2 x kLrStride
+    double *yr = lt + M2 * kLrStride;   // nsb x kLrStride
+    const int64_t Ia = blockIdx.x;
+    for (int i = threadIdx.x; i < M2 * RP; i += blockDim.x) lt[(i / RP) * kLrStride + i % RP] = Lt[i];
+    const uint32_t *ex = excA + Ia * nexcA;
+    for (int64_t Jb = threadIdx.x; Jb < nsb; Jb += blockDim.x) {
+        double acc[RP];
+#pragma unroll
+        for (int l = 0; l < RP; ++l) acc[l] = 0.0;
+        int e = 0;
+        for (; e + 4 <= nexcA; e += 4) {
+            double x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = C[(int64_t)(ex[e + u] & 0xFFFFu) * nsb + Jb];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t ea = ex[e + u];
+                const double *lr = Lt + ((ea >> 16) & 0x1FFu) * RP;
+                const double xv = neg_if((ea >> 31) != 0, x[u]);
+#pragma unroll
+                for (int l = 0; l < RP; ++l) axpy(acc[l], lr[l], xv);
+            }
+        }
+        for (; e < nexcA; ++e) {
+            const uint32_t ea = ex[e];
+            const double *lr = Lt + ((ea >> 16) & 0x1FFu) * RP;
+            const double xv = neg_if((ea >> 31) != 0, C[(int64_t)(ea & 0xFFFFu) * nsb + Jb]);
+#pragma unroll
+            for (int l = 0; l < RP; ++l) axpy(acc[l], lr[l], xv);
+        }
+#pragma unroll
+        for (int l = 0; l < RP; ++l) yr[Jb * kLrStride + l] = acc[l];
+    }
+    __syncthreads();
+    double *srow = S + Ia * nsb;
+    for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
+        double acc = 0.0;
+        for (int f = 0; f < nexcB; ++f) {
+            const uint32_t eb = excBT[(int64_t)f * nsb + Ib];
+            const double *w = lt + ((eb >> 16) & 0x1FFu) * kLrStride;
+            const double *y = yr + (int64_t)(eb & 0xFFFFu) * kLrStride;
+            double t = 0.0;
+#pragma unroll
+            for (int l = 0; l < RP; ++l) axpy(t, w[l], y[l]);
+            acc += neg_if((eb >> 31) != 0, t);
+        }
+        srow[Ib] += acc;
+    }
+}
+
 // ------------------------------------------------------------ screening ----
 // ADAPT pool screening, one launch for the whole pool: workgroup (x, t)
 // accumulates, over its share of pool operator t's pairs, the real part of
@@ -524,6 +605,22 @@ __global__ void k_combine(A *__restrict__ S, const A *__restrict__ ST, const A *
     if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.x] = acc;
 }
 
+// S += ecore C and this workgroup's share of <C|S> (real states whose beta
+// part went straight into S).
+__global__ __launch_bounds__(256) void k_ecore_dot(double *__restrict__ S, const double *__restrict__ C, double ecore,
+                                                   int64_t dim, double *__restrict__ partial) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += (int64_t)gridDim.x * blockDim.x) {
+        const double c = C[i];
+        double s = S[i];
+        axpy(s, ecore, c);
+        S[i] = s;
+        acc += c * s;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 template <typename O>  // O = double2 or float2 (dense complex amplitude)
 __global__ void k_scatter_real(O *__restrict__ lam,
                                const double *__restrict__ S, const uint64_t *__restrict__ Xa,
@@ -552,6 +649,14 @@ int lr_chunk(const SectorTabs &T, int rp) {
     return lc;
 }
 
+// The one-kernel form applies to real states with RP = 8 whose LDS rows fit
+// two workgroups per CU.
+template <typename A, int RP>
+bool lr_fused_ok(const SectorTabs &T) {
+    if (sizeof(A) != sizeof(double) || RP != 8 || std::getenv("FSV_LR_SPLIT")) return false;
+    return (size_t)(T.M * T.M + T.nsb) * kLrStride * sizeof(double) * 2 <= 163840 && g_lds_max >= 81920;
+}
+
 // Padded LDS strides (in elements) of k_lr_b's staged rows for lc values per
 // row: 16 bytes more than the row when lc >= 4 and the padded rows still fit.
 template <typename A>
@@ -569,6 +674,12 @@ void lr_strides(const SectorTabs &T, int lc, int &ys, int &ws) {
 
 template <typename A, int RP>
 hipError_t lr_launch(const SectorTabs &T, const A *C, A *S, hipStream_t st) {
+    if (lr_fused_ok<A, RP>(T)) {
+        const size_t shm = (size_t)(T.M * T.M + T.nsb) * kLrStride * sizeof(double);
+        hipLaunchKernelGGL(k_lr_ab, dim3((unsigned)T.nsa), dim3(1024), shm, st, (const double *)C, (double *)S,
+                           T.excA, T.nexcA, T.excBT, T.nexcB, T.Lt, T.M * T.M, T.nsb);
+        return hipGetLastError();
+    }
     A *Y = (A *)T.YT;
     const int lc = lr_chunk<A>(T, RP);
     if (lc < 1) return hipErrorInvalidValue;
@@ -623,6 +734,14 @@ hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, doubl
                                 : (T.R <= 16 ? lr_launch<A, 16>(T, C, S, st) : lr_launch<A, 32>(T, C, S, st));
         if (e != hipSuccess) return e;
     }
+    if (T.hb_dense_t && sizeof(A) == sizeof(double)) {
+        // real state: the beta GEMM accumulates into S directly
+        const hipError_t e = dense_beta_accumulate(T.blas, T.hb_dense_t, (const double *)C, (double *)S, nsa, nsb, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_ecore_dot, dim3(combine_grid(nsa * nsb)), dim3(256), 0, st, (double *)S,
+                           (const double *)C, T.ecore, nsa * nsb, epart);
+        return hipGetLastError();
+    }
     // same-spin beta part on the transpose, then combine
     {
         const dim3 grid((unsigned)((nsb + 31) / 32), (unsigned)((nsa + 31) / 32));
@@ -673,7 +792,8 @@ void init_sigma_kernels() {
                                      (const void *)k_sigma_ab_reg<double2, 48, 1024>,
                                      (const void *)k_sigma_ab_reg<double, 64, 512>,
                                      (const void *)k_sigma_ab_reg<double2, 64, 512>,
-                                     (const void *)k_lr_b<double>, (const void *)k_lr_b<double2>};
+                                     (const void *)k_lr_b<double>, (const void *)k_lr_b<double2>,
+                                     (const void *)k_lr_ab};
     bool ok = true;
     for (const void *f : fns)
         ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 163840) == hipSuccess;
