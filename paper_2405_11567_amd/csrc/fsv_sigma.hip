@@ -398,6 +398,9 @@ __global__ __launch_bounds__(256) void k_lr_a(const A *__restrict__ C, A *__rest
     }
 }
 
+constexpr int kExcBatch = 8;    // beta-list words loaded together in the step-2 loop of k_lr_b
+constexpr int kExcBatchAB = 4;  // and of k_lr_ab (which must stay within 64 VGPRs: two workgroups per CU)
+
 // Step 2, row-local: S[Ia][Ib] += sum_{f in exc(Ib)} s_f sum_l L_l[rs_f]
 // Y[Ia][Jb_f][l].  One workgroup per Ia stages its Y row (nsb x lc values)
 // and the matching lc columns of Lt in LDS, lc of the RP values at a time;
@@ -425,14 +428,22 @@ __global__ __launch_bounds__(1024) void k_lr_b(const A *__restrict__ Y, A *__res
         __syncthreads();
         for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
             A acc = zero<A>();
-            for (int f = 0; f < nexcB; ++f) {
-                const uint32_t eb = excBT[(int64_t)f * nsb + Ib];
+            auto step = [&](uint32_t eb) {
                 const double *w = lt + ((eb >> 16) & 0x1FFu) * ws;
                 const A *y = yr + (int64_t)(eb & 0xFFFFu) * ys;
                 A t = zero<A>();
                 for (int l = 0; l < lc; ++l) axpy(t, w[l], y[l]);
                 acc = add(acc, neg_if((eb >> 31) != 0, t));
+            };
+            int f = 0;
+            for (; f + kExcBatch <= nexcB; f += kExcBatch) {  // the list words in flight together
+                uint32_t eb[kExcBatch];
+#pragma unroll
+                for (int u = 0; u < kExcBatch; ++u) eb[u] = excBT[(int64_t)(f + u) * nsb + Ib];
+#pragma unroll
+                for (int u = 0; u < kExcBatch; ++u) step(eb[u]);
             }
+            for (; f < nexcB; ++f) step(excBT[(int64_t)f * nsb + Ib]);
             srow[Ib] = add(srow[Ib], acc);
         }
     }
@@ -490,15 +501,23 @@ __global__ __launch_bounds__(1024) void k_lr_ab(const double *__restrict__ C, do
     double *srow = S + Ia * nsb;
     for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
         double acc = 0.0;
-        for (int f = 0; f < nexcB; ++f) {
-            const uint32_t eb = excBT[(int64_t)f * nsb + Ib];
+        auto step = [&](uint32_t eb) {
             const double *w = lt + ((eb >> 16) & 0x1FFu) * kLrStride;
             const double *y = yr + (int64_t)(eb & 0xFFFFu) * kLrStride;
             double t = 0.0;
 #pragma unroll
             for (int l = 0; l < RP; ++l) axpy(t, w[l], y[l]);
             acc += neg_if((eb >> 31) != 0, t);
+        };
+        int f = 0;
+        for (; f + kExcBatchAB <= nexcB; f += kExcBatchAB) {
+            uint32_t eb[kExcBatchAB];
+#pragma unroll
+            for (int u = 0; u < kExcBatchAB; ++u) eb[u] = excBT[(int64_t)(f + u) * nsb + Ib];
+#pragma unroll
+            for (int u = 0; u < kExcBatchAB; ++u) step(eb[u]);
         }
+        for (; f < nexcB; ++f) step(excBT[(int64_t)f * nsb + Ib]);
         srow[Ib] += acc;
     }
 }
@@ -658,14 +677,16 @@ bool lr_fused_ok(const SectorTabs &T) {
 }
 
 // Padded LDS strides (in elements) of k_lr_b's staged rows for lc values per
-// row: 16 bytes more than the row when lc >= 4 and the padded rows still fit.
+// row, when the padded rows still fit: 16 bytes more than the row for lc >= 4
+// (16-byte reads); an odd number of doubles for real rows of lc < 4 (8-byte
+// reads, 32 distinct bank pairs instead of 16).
 template <typename A>
 void lr_strides(const SectorTabs &T, int lc, int &ys, int &ws) {
     const size_t lim = g_lds_max > 0 ? (size_t)g_lds_max : 65536;
     ys = lc;
     ws = lc;
-    if (lc < 4) return;
-    const int py = lc + (int)(16 / sizeof(A)), pw = lc + 2;
+    if (lc < 4 && sizeof(A) != sizeof(double)) return;
+    const int py = lc < 4 ? lc + 1 : lc + (int)(16 / sizeof(A)), pw = lc < 4 ? lc + 1 : lc + 2;
     if ((size_t)T.M * T.M * pw * sizeof(double) + (size_t)T.nsb * py * sizeof(A) <= lim) {
         ys = py;
         ws = pw;
