@@ -314,15 +314,20 @@ def test_sector_autotune(fsv):
 
 
 @pytest.mark.parametrize("same_spin", ["dense", "sparse"])
-def test_same_spin_paths_and_replays(fsv, monkeypatch, same_spin):
-    # same-spin products as FP64 GEMMs or sparse rows; each energy_grad call
-    # replays the captured graph, with eager work between the replays, and
-    # every replay must match the oracle and the first replay bit for bit
+@pytest.mark.parametrize("lr", ["fused", "split"])
+def test_same_spin_paths_and_replays(fsv, monkeypatch, same_spin, lr):
+    # same-spin products as FP64 GEMMs (the beta one accumulated in place for
+    # real states) or sparse rows, and the factorised alpha-beta term in one
+    # kernel or in two; each energy_grad call replays the captured graph, with
+    # eager work between the replays, and every replay must match the oracle
+    # and the first replay bit for bit
     monkeypatch.setenv("FSV_SAME_SPIN", same_spin)
+    if lr == "split":
+        monkeypatch.setenv("FSV_LR_SPLIT", "1")
     p = config("C2", ordering=1)
     e_ref, g_ref = oracle_energy_grad(p)
     for engine in ENGINES:
-        say("same-spin", same_spin, engine)
+        say("same-spin", same_spin, lr, engine)
         plan = fsv.Plan(p, engine=engine)
         psi, lam = plan.new_state(), plan.new_state()
         first = None
