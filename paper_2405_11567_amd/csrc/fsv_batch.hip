@@ -353,6 +353,27 @@ __global__ __launch_bounds__(64) void k_preduce(const BInst *__restrict__ inst, 
     }
 }
 
+// The same sums for packet runs: operator k's partials are its run's packets,
+// count[k] of them at gpart[k * pstride + slot].
+__global__ __launch_bounds__(64) void k_preduce_pk(const BInst *__restrict__ inst, const int32_t *__restrict__ count,
+                                                   int pstride, const double *__restrict__ epart,
+                                                   const double *__restrict__ gpart, double *__restrict__ grad,
+                                                   double *__restrict__ eout) {
+    const int y = blockIdx.x;
+    const BInst I = inst[y];
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int r = 0; r < I.nsa; ++r) e += epart[I.off_task + r];
+        eout[y] = e;
+    }
+    for (int k = threadIdx.x; k < I.K; k += blockDim.x) {
+        const int64_t kk = I.off_k + k;
+        double s = 0.0;
+        for (int x = 0; x < count[kk]; ++x) s += gpart[kk * pstride + x];
+        grad[kk] = 2.0 * s;
+    }
+}
+
 __global__ void k_zero_int(int *p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
@@ -395,7 +416,7 @@ struct fsv_batch {
     double *d_arena = nullptr;
     double *h_pin = nullptr;  // cs (2 total_k) | grad (total_k) | E (count)
     int block = 256, per_cu = 2, cus = 256;
-    int mode = 1;       // 0 persistent work-queue kernel, 1 phased launches
+    int mode = 1;       // 0 persistent work-queue kernel, 1 phased launches, 2 packet runs
     int gx = 32;        // phased mode: workgroups per instance per rotation launch
     size_t lds_budget = 65536;  // LDS bytes a sigma workgroup may stage
     size_t lds_max = 65536;     // largest dynamic LDS the sigma kernels accept
@@ -406,6 +427,12 @@ struct fsv_batch {
     size_t part_cap = 0;  // workgroups per instance the gradient partials hold
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;
+    // packet runs (mode 2): one launch per run index, the runs of all instances
+    BatchPackets pk;
+    bool pk_ok = false;
+    uint32_t *d_pent = nullptr, *d_preg = nullptr;
+    int32_t *d_pcount = nullptr;
+    double *d_pgpart = nullptr;
     BTabs tabs() const { return BTabs{d_g, d_hptr, d_hcol, d_hval, d_ellc, d_ellv, d_excA, d_excBT}; }
     ~fsv_batch() {
         if (work) (void)hipStreamSynchronize(work);
@@ -451,6 +478,25 @@ int set_lds_budget(fsv_batch &B, size_t budget) {
 
 int enqueue(fsv_batch &B) {
     const BTabs T = B.tabs();
+    if (B.mode == 2) {
+        hipLaunchKernelGGL(k_pinit, dim3((unsigned)B.gx, (unsigned)B.count), dim3(256), 0, B.work, B.d_inst,
+                           B.d_arena);
+        BHIP(hipGetLastError());
+        const BatchPackets &P = B.pk;
+        for (int r = 0; r < P.runs; ++r)
+            BHIP(launch_batch_packets(false, B.d_arena, B.d_pent + P.ent_off[r], B.d_preg + P.reg_off[r], P.wr[r],
+                                      P.npk[r], B.d_cs, nullptr, P.pstride, B.work));
+        hipLaunchKernelGGL(k_psigma, dim3((unsigned)B.ntasks), dim3(256), B.lds_bytes, B.work, B.d_inst,
+                           B.d_tinst, T, B.d_arena, B.d_epart);
+        BHIP(hipGetLastError());
+        for (int r = P.runs - 1; r >= 0; --r)
+            BHIP(launch_batch_packets(true, B.d_arena, B.d_pent + P.ent_off[r], B.d_preg + P.reg_off[r], P.wr[r],
+                                      P.npk[r], B.d_cs, B.d_pgpart, P.pstride, B.work));
+        hipLaunchKernelGGL(k_preduce_pk, dim3((unsigned)B.count), dim3(64), 0, B.work, B.d_inst, B.d_pcount,
+                           P.pstride, B.d_epart, B.d_pgpart, B.d_grad, B.d_e);
+        BHIP(hipGetLastError());
+        return FSV_OK;
+    }
     if (B.mode == 1) {
         const dim3 grid((unsigned)B.gx, (unsigned)B.count);
         hipLaunchKernelGGL(k_pinit, grid, dim3(256), 0, B.work, B.d_inst, B.d_arena);
@@ -551,7 +597,9 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     B->count = count;
     B->user = (hipStream_t)hip_stream;
     B->use_graph = std::getenv("FSV_NO_GRAPH") == nullptr;
-    if (const char *m = std::getenv("FSV_BATCH_MODE")) B->mode = std::strcmp(m, "persistent") == 0 ? 0 : 1;
+    int env_mode = -1;
+    if (const char *m = std::getenv("FSV_BATCH_MODE"))
+        env_mode = std::strcmp(m, "persistent") == 0 ? 0 : (std::strcmp(m, "packets") == 0 ? 2 : 1);
     if (const char *m = std::getenv("FSV_BATCH_SIGMA")) B->force_global = std::strcmp(m, "global") == 0;
 
     std::vector<BOp> ops;
@@ -718,6 +766,27 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         if (u.n && hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice) != hipSuccess)
             return fin(fail(FSV_EDEVICE, "upload failed"));
     if ((rc = set_lds_budget(*B, B->lds_budget))) return fin(rc);
+    // packet runs, when every instance is small enough (the default mode then)
+    bool small = true;
+    for (const BInst &I : B->inst) small = small && I.dim <= packet_max_dim();
+    if (small && kk > 0) {
+        std::vector<BatchPacketInst> pi;
+        for (const BInst &I : B->inst) pi.push_back({I.nsa, I.nsb, I.off_state, I.off_ops, I.off_k, I.K});
+        if ((rc = build_batch_packets(pi, ops, lists, B->pk))) return fin(rc);
+        const BatchPackets &P = B->pk;
+        if ((rc = dmalloc(o, &B->d_pent, std::max<size_t>(P.ent.size(), 1))) ||
+            (rc = dmalloc(o, &B->d_preg, std::max<size_t>(P.reg.size(), 1))) ||
+            (rc = dmalloc(o, &B->d_pcount, (size_t)kk)) || (rc = dmalloc(o, &B->d_pgpart, (size_t)kk * P.pstride)))
+            return fin(rc);
+        if ((!P.ent.empty() && hipMemcpy(B->d_pent, P.ent.data(), 4 * P.ent.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+            (!P.reg.empty() && hipMemcpy(B->d_preg, P.reg.data(), 4 * P.reg.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+            hipMemcpy(B->d_pcount, P.count.data(), 4 * (size_t)kk, hipMemcpyHostToDevice) != hipSuccess)
+            return fin(fail(FSV_EDEVICE, "upload of packet runs failed"));
+        B->bytes += 4 * (P.ent.size() + P.reg.size() + (size_t)kk) + 8 * (size_t)kk * P.pstride;
+        B->pk_ok = true;
+        B->mode = 2;
+    }
+    if (env_mode >= 0) B->mode = env_mode == 2 && !B->pk_ok ? 1 : env_mode;
     *out = B;
     clear_error();
     return FSV_OK;
@@ -757,6 +826,7 @@ int fsv_batch_autotune(fsv_batch *B, const char **report) {
             for (int per : {1, 2}) cands.push_back({0, blk, per, B->gx, lds});
         for (int gx : {8, 16, 32, 64})
             if ((size_t)gx <= B->part_cap) cands.push_back({1, B->block, B->per_cu, gx, lds});
+        if (B->pk_ok) cands.push_back({2, B->block, B->per_cu, B->gx, lds});
     }
     float best = 1e30f;
     const Cand keep{B->mode, B->block, B->per_cu, B->gx, B->lds_budget};
@@ -792,6 +862,9 @@ int fsv_batch_autotune(fsv_batch *B, const char **report) {
         if (c.mode == 0)
             snprintf(line, sizeof line, "persistent: block %d x %d per CU, LDS %zu KiB: %.3f ms\n", c.block,
                      c.per_cu, c.lds / 1024, ms);
+        else if (c.mode == 2)
+            snprintf(line, sizeof line, "packet runs (%d launches per sweep), LDS %zu KiB: %.3f ms\n", B->pk.runs,
+                     c.lds / 1024, ms);
         else
             snprintf(line, sizeof line, "phased: %d workgroups per instance, LDS %zu KiB: %.3f ms\n", c.gx,
                      c.lds / 1024, ms);
@@ -807,7 +880,8 @@ int fsv_batch_autotune(fsv_batch *B, const char **report) {
     if (rc) return rc;
     if (rc2) return rc2;
     snprintf(line, sizeof line, "chosen: %s block %d per_cu %d gx %d LDS %zu KiB\n",
-             bestc.mode ? "phased" : "persistent", bestc.block, bestc.per_cu, bestc.gx, bestc.lds / 1024);
+             bestc.mode == 2 ? "packet runs" : (bestc.mode ? "phased" : "persistent"), bestc.block, bestc.per_cu,
+             bestc.gx, bestc.lds / 1024);
     rep += line;
     if (report) *report = rep.c_str();
     return FSV_OK;

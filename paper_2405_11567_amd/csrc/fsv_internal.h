@@ -230,6 +230,38 @@ int build_fused(int M, const std::vector<uint32_t> &sa, const std::vector<uint32
                 const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
                 const std::vector<int32_t> &ops, const FusedOpts &o, FusedSched &S);
 int fused_runs(const FusedSched &S, int *n_fused_ops);
+// Host side of packet runs: groups (fused = 2 for packet runs, 0 for
+// operators left alone), per-operator partial counts, and the index lists and
+// regions (FGroup::ent_off / reg_off index ent / reg).  every_run: every run,
+// a single operator's included, becomes a packet run.
+struct PacketPlan {
+    std::vector<FGroup> groups;
+    std::vector<int> count;
+    std::vector<uint32_t> ent, reg;
+};
+int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
+                 const FusedOpts &o, bool every_run, PacketPlan &S);
+// Batched packet runs over independent instances (real FP64 states in one
+// arena): launch r carries run r - (R - runs_i) of every instance i (runs
+// aligned at the end, so the adjoint sweep runs the same launches backwards).
+struct BatchPacketInst {
+    int64_t nsa, nsb, off_state, off_ops, off_k;
+    int32_t K;
+};
+struct BatchPackets {
+    int runs = 0;
+    int pstride = 1;                       // gradient partial slots per operator
+    std::vector<int64_t> ent_off, reg_off;  // per launch
+    std::vector<int32_t> wr, npk;           // per launch: region stride, packets
+    std::vector<uint32_t> ent, reg;
+    std::vector<int32_t> count;             // per operator (global index): partials of its run
+};
+int build_batch_packets(const std::vector<BatchPacketInst> &insts, const std::vector<PairOp> &ops,
+                        const std::vector<uint32_t> &lists, BatchPackets &B);
+size_t batch_packet_lds(int wr, bool adjoint);
+hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent, const uint32_t *reg, int wr,
+                                int npk, const double *cs, double *gpart, int pstride, hipStream_t st);
+
 // Packet runs (fused = 2) for sector states of at most packet_max_dim()
 // amplitudes; o.es, o.mode (0 cost model, 1 never, otherwise every run of >= 2)
 // and o.max_ops are used.  count[k] = gradient partials of operator k's run.

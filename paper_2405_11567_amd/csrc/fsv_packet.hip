@@ -186,6 +186,111 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
     }
 }
 
+// Batched form: one launch carries one run of many independent instances.
+// Each packet's header also holds (word kBHdr + ...) its instance's first
+// amplitude in the arena (two words), the instance dimension (lam follows
+// psi), the global index of the run's first operator (angles, gradients), the
+// run length and the packet's gradient slot within its run; the gradient
+// terms of each packet go to gpart[op * pstride + slot].
+constexpr int kBHdr = 16;
+static_assert(kBHdr > kPktMaxOps, "batched header fields follow the pair offsets");
+
+template <bool ADJ, int NQ>
+__global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, const uint32_t *__restrict__ ent,
+                                                const uint32_t *__restrict__ reg, int wr, int n_packets,
+                                                const double *__restrict__ cs, double *__restrict__ gpart,
+                                                int pstride) {
+    extern __shared__ double lds[];
+    double *scs = lds;
+    double *tp = lds + kPktScalars;
+    double *tl = tp + kPkt;
+    uint32_t *rg = (uint32_t *)(tp + (ADJ ? 2 : 1) * kPkt);
+    const int l = threadIdx.x;
+    const int nq = wr >> 2;
+    for (int v = blockIdx.x; v < n_packets; v += gridDim.x) {
+        const int p = xcd_packet(v, n_packets);
+        const uint32_t *es = ent + (size_t)p * kPkt;
+        const u32x4 *rs = (const u32x4 *)(reg + (size_t)p * wr);
+        uint32_t x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = es[l + i * kWave];
+        u32x4 q[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) q[i] = rs[min(l + i * kWave, nq - 1)];
+        __syncthreads();  // the previous packet is out of LDS
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) ((u32x4 *)rg)[min(l + i * kWave, nq - 1)] = q[i];
+        __syncthreads();
+        const int64_t base = (int64_t)rg[kBHdr] | ((int64_t)rg[kBHdr + 1] << 32);
+        const int64_t dim = rg[kBHdr + 2];
+        const int k0 = (int)rg[kBHdr + 3], m = (int)rg[kBHdr + 4], slot = (int)rg[kBHdr + 5];
+        double *psi = arena + base, *lam = psi + dim;
+        {
+            const int t = min(l, max(2 * m - 1, 0));
+            const double c = cs[2 * k0 + t];
+            if (l < 2 * m) scs[l] = c;
+        }
+        double v0[4], v1[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t xi = x[i] == kNone ? 0u : x[i];
+            v0[i] = psi[xi];
+            if (ADJ) v1[i] = lam[xi];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            tp[l + i * kWave] = v0[i];
+            if (ADJ) tl[l + i * kWave] = v1[i];
+        }
+        __syncthreads();
+        const uint32_t *rp = rg + kPktHdr;
+        auto pair_at = [&](uint32_t t) { return (rp[t >> 1] >> ((t & 1u) << 4)) & 0xFFFFu; };
+        double acc[kPktMaxOps];
+#pragma unroll
+        for (int jj = 0; jj < kPktMaxOps; ++jj) {
+            acc[jj] = 0.0;
+            if (jj < m) {
+                const int j = ADJ ? m - 1 - jj : jj;
+                const uint32_t o0 = j ? rg[j] : 0u, o1 = rg[1 + j];
+                const double c = scs[2 * j], sn = scs[2 * j + 1];
+                for (uint32_t t = o0 + l; t < o1; t += kWave) {
+                    const uint32_t w = pair_at(t);
+                    const int xs = (int)(w & 0xFFu), xd = (int)(w >> 8);
+                    double va = tp[xs], vb = tp[xd];
+                    if (ADJ) {
+                        double la = tl[xs], lb = tl[xd];
+                        acc[jj] += lb * va - la * vb;
+                        rotp(va, vb, c, -sn);
+                        rotp(la, lb, c, -sn);
+                        tl[xs] = la;
+                        tl[xd] = lb;
+                    } else {
+                        rotp(va, vb, c, sn);
+                    }
+                    tp[xs] = va;
+                    tp[xd] = vb;
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (x[i] != kNone) {
+                psi[x[i]] = tp[l + i * kWave];
+                if (ADJ) lam[x[i]] = tl[l + i * kWave];
+            }
+        if (ADJ) {
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1)
+#pragma unroll
+                for (int jj = 0; jj < kPktMaxOps; ++jj) acc[jj] += __shfl_xor(acc[jj], off, kWave);
+#pragma unroll
+            for (int jj = 0; jj < kPktMaxOps; ++jj)
+                if (jj < m && l == 0) gpart[(size_t)(k0 + m - 1 - jj) * pstride + slot] = acc[jj];
+        }
+    }
+}
+
 // ---- host: union-find over the amplitudes touched by a run ----
 struct UnionFind {
     std::vector<int32_t> parent, size, comp;
@@ -282,9 +387,11 @@ int upload_words(const std::vector<uint32_t> &vec, FusedSched &S, uint32_t **dst
 
 int64_t packet_max_dim() { return (int64_t)1 << 22; }
 
-int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
-                  const FusedOpts &o, FusedSched &S) {
-    S.release();
+int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
+                 const FusedOpts &o, bool every_run, PacketPlan &S) {
+    S.groups.clear();
+    S.ent.clear();
+    S.reg.clear();
     const int K = (int)pops.size();
     S.count.assign(K, -1);
     const int64_t N = nsa * nsb;
@@ -300,7 +407,7 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
     const double bw = 4.0e12, bw_pk = 2.0e12, t_launch = 5.0e-6, t_chain = 6.0e-6;
     const double amp = (double)o.es * 2;  // psi and lam
     const int max_ops = std::min(o.max_ops, kPktMaxOps);
-    std::vector<uint32_t> ent, reg;
+    std::vector<uint32_t> &ent = S.ent, &reg = S.reg;
     std::vector<int32_t> csize, crow, order, pk_of, pfill, cnt, cur;
     std::vector<int32_t> slot(N, 0), rpar(nsa);
     auto single = [&](int k) {
@@ -329,7 +436,9 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
         bool fuse = m >= 2 && o.mode != 1 && !uf.touched.empty();
         double npairs = 0.0;
         for (int k = i; k < j; ++k) npairs += pairs_of(pops[k]);
-        if (fuse && o.mode == 0) {
+        if (every_run) {
+            fuse = true;  // every run becomes a packet run (one with no pairs has no packets)
+        } else if (fuse && o.mode == 0) {
             const double t_ops = m * t_launch + npairs * 4.0 * amp / bw;
             const double t_pk = t_chain + ((double)uf.touched.size() * (2.0 * amp + 4.0) + npairs * 4.0) / bw_pk;
             fuse = t_pk < t_ops;
@@ -442,8 +551,18 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
         uf.reset();
         i = j;
     }
-    int rc;
-    if ((rc = upload_words(ent, S, &S.d_aprog)) || (rc = upload_words(reg, S, &S.d_bprog))) {
+    return FSV_OK;
+}
+
+int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
+                  const FusedOpts &o, FusedSched &S) {
+    S.release();
+    PacketPlan pp;
+    int rc = plan_packets(nsa, nsb, pops, lists, o, false, pp);
+    if (rc) return rc;
+    S.groups = std::move(pp.groups);
+    S.count = std::move(pp.count);
+    if ((rc = upload_words(pp.ent, S, &S.d_aprog)) || (rc = upload_words(pp.reg, S, &S.d_bprog))) {
         S.release();
         return rc;
     }
@@ -467,6 +586,92 @@ hipError_t pkt_impl(void *psi, void *lam, const FusedSched &S, const FGroup &g, 
 }
 
 }  // namespace
+
+int build_batch_packets(const std::vector<BatchPacketInst> &insts, const std::vector<PairOp> &ops,
+                        const std::vector<uint32_t> &lists, BatchPackets &B) {
+    B = BatchPackets{};
+    std::vector<PacketPlan> plans(insts.size());
+    FusedOpts o;
+    o.es = 8;
+    int R = 0;
+    int64_t total_k = 0;
+    for (size_t i = 0; i < insts.size(); ++i) {
+        const BatchPacketInst &I = insts[i];
+        if (I.nsa * I.nsb > packet_max_dim()) return fail(FSV_EINVAL, "internal: instance too large for packets");
+        const std::vector<PairOp> pops(ops.begin() + I.off_ops, ops.begin() + I.off_ops + I.K);
+        const int rc = plan_packets(I.nsa, I.nsb, pops, lists, o, true, plans[i]);
+        if (rc) return rc;
+        R = std::max(R, (int)plans[i].groups.size());
+        total_k = std::max<int64_t>(total_k, I.off_k + I.K);
+    }
+    B.runs = R;
+    B.count.assign((size_t)total_k, 0);
+    for (size_t i = 0; i < insts.size(); ++i)
+        for (const FGroup &g : plans[i].groups) B.pstride = std::max(B.pstride, g.n_packets);
+    B.pstride = std::max(B.pstride, 1);
+    // launch r holds run r - (R - runs_i) of instance i (runs aligned at the end)
+    for (int r = 0; r < R; ++r) {
+        int wr = kPktHdr + 4;
+        int npk = 0;
+        for (size_t i = 0; i < insts.size(); ++i) {
+            const int ri = r - (R - (int)plans[i].groups.size());
+            if (ri < 0) continue;
+            wr = std::max(wr, plans[i].groups[ri].wr);
+            npk += plans[i].groups[ri].n_packets;
+        }
+        B.ent_off.push_back((int64_t)B.ent.size());
+        B.reg_off.push_back((int64_t)B.reg.size());
+        B.wr.push_back(wr);
+        B.npk.push_back(npk);
+        B.ent.resize(B.ent.size() + (size_t)npk * kPkt, kNone);
+        B.reg.resize(B.reg.size() + (size_t)npk * wr, 0u);
+        int64_t at = 0;
+        for (size_t i = 0; i < insts.size(); ++i) {
+            const int ri = r - (R - (int)plans[i].groups.size());
+            if (ri < 0) continue;
+            const BatchPacketInst &I = insts[i];
+            const FGroup &g = plans[i].groups[ri];
+            for (int k = g.k0; k < g.k0 + g.nops; ++k) B.count[(size_t)(I.off_k + k)] = g.n_packets;
+            for (int q = 0; q < g.n_packets; ++q, ++at) {
+                std::copy_n(plans[i].ent.begin() + g.ent_off + (int64_t)q * kPkt, kPkt,
+                            B.ent.begin() + B.ent_off.back() + at * kPkt);
+                uint32_t *h = &B.reg[(size_t)(B.reg_off.back() + at * wr)];
+                std::copy_n(plans[i].reg.begin() + g.reg_off + (int64_t)q * g.wr, g.wr, h);
+                const int64_t base = I.off_state;
+                h[kBHdr] = (uint32_t)(base & 0xFFFFFFFF);
+                h[kBHdr + 1] = (uint32_t)(base >> 32);
+                h[kBHdr + 2] = (uint32_t)(I.nsa * I.nsb);
+                h[kBHdr + 3] = (uint32_t)(I.off_k + g.k0);
+                h[kBHdr + 4] = (uint32_t)g.nops;
+                h[kBHdr + 5] = (uint32_t)q;
+            }
+        }
+    }
+    return FSV_OK;
+}
+
+size_t batch_packet_lds(int wr, bool adjoint) {
+    return sizeof(double) * kPktScalars + (size_t)kPkt * (adjoint ? 2 : 1) * sizeof(double) + (size_t)wr * 4;
+}
+
+hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent, const uint32_t *reg, int wr,
+                                int npk, const double *cs, double *gpart, int pstride, hipStream_t st) {
+    if (npk <= 0) return hipSuccess;
+    const dim3 grid((unsigned)std::min(npk, max_grid())), block(kWave);
+    const size_t shm = batch_packet_lds(wr, adjoint);
+    if (adjoint) {
+        if (wr <= 4 * kWave * 2)
+            hipLaunchKernelGGL((k_bpkt<true, 2>), grid, block, shm, st, arena, ent, reg, wr, npk, cs, gpart, pstride);
+        else
+            hipLaunchKernelGGL((k_bpkt<true, 4>), grid, block, shm, st, arena, ent, reg, wr, npk, cs, gpart, pstride);
+    } else {
+        if (wr <= 4 * kWave * 2)
+            hipLaunchKernelGGL((k_bpkt<false, 2>), grid, block, shm, st, arena, ent, reg, wr, npk, cs, gpart, pstride);
+        else
+            hipLaunchKernelGGL((k_bpkt<false, 4>), grid, block, shm, st, arena, ent, reg, wr, npk, cs, gpart, pstride);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_packets(int vtype, bool adjoint, void *psi, void *lam, const FusedSched &S, const FGroup &g,
                           const double *cs, double *gpart, int gstride, hipStream_t st) {

@@ -114,7 +114,7 @@ def test_pool_rejects_bad_input(fsv):
     assert ei.value.code == -4
 
 
-@pytest.mark.parametrize("mode", ["phased", "persistent"])
+@pytest.mark.parametrize("mode", ["phased", "persistent", "packets"])
 def test_batch_qeb_instances(fsv, monkeypatch, mode):
     monkeypatch.setenv("FSV_BATCH_MODE", mode)
     probs = []

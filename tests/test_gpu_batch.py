@@ -20,7 +20,7 @@ def fsv(gpu):
 
 
 @pytest.mark.parametrize("sigma", ["lds", "global"])
-@pytest.mark.parametrize("mode", ["phased", "persistent"])
+@pytest.mark.parametrize("mode", ["phased", "persistent", "packets"])
 def test_batch_mixed_small(fsv, mode, sigma, monkeypatch):
     # H C with rows staged in LDS, and from global memory only (the path taken
     # by rows too long for LDS)
@@ -48,7 +48,7 @@ def test_batch_mixed_small(fsv, mode, sigma, monkeypatch):
             assert np.abs(g[i] - g_ref).max() < 1e-9, i
 
 
-@pytest.mark.parametrize("mode", ["phased", "persistent"])
+@pytest.mark.parametrize("mode", ["phased", "persistent", "packets"])
 def test_batch_c4_full(fsv, mode, monkeypatch):
     monkeypatch.setenv("FSV_BATCH_MODE", mode)
     probs = batch_config()
