@@ -37,9 +37,10 @@ namespace {
 
 struct BInst {
     int32_t M, nsa, nsb, nexcA, nexcB, K, ref;
-    int32_t ec;   // alpha excitations staged per LDS pass (even); 0: global-memory sigma
+    int32_t ec;   // alpha excitations staged per LDS pass (even); 0: global-memory sigma;
+                  // -1: factorised alpha-beta term with the row's intermediate in LDS
     int32_t wB;   // width of the beta string Hamiltonian in ELL form
-    int32_t pad;
+    int32_t R;    // exact pivoted-Cholesky rank of (pq|rs) used by the factorised form (0: direct)
     int64_t dim;
     int64_t off_state;  // first double of psi in the arena; lam follows psi
     int64_t off_ops;    // first BOp
@@ -50,8 +51,12 @@ struct BInst {
     int64_t off_excA;   // alpha excitation lists, [Ia][e]
     int64_t off_excB;   // beta excitation lists transposed, [f][Ib]
     int64_t off_task;   // first sigma task (row) of this instance
+    int64_t off_lt;     // factor table [pq][l] (M^2 x kBLr, zero beyond R)
     double ecore;
 };
+
+constexpr int kBLr = 8;       // factor columns of the factorised form (ranks <= 8)
+constexpr int kBLrStride = 9;  // LDS row stride (doubles) of its staged factors and intermediate
 
 // Flat device tables of all instances.
 struct BTabs {
@@ -62,6 +67,7 @@ struct BTabs {
     const int32_t *ellc;
     const double *ellv;
     const uint32_t *excA, *excBT;
+    const double *lt;
 };
 
 using BOp = PairOp;
@@ -129,6 +135,54 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
             }
             S[(int64_t)Ia * nsb + ib] = a;
             eacc += x0 * a;
+        }
+        return eacc;
+    }
+    if (I.ec < 0) {
+        // factorised: (pq|rs) = sum_l L_l[pq] L_l[rs]; Y[Jb][l] = sum_e s_e L_l[pq_e]
+        // C[Ja_e][Jb] built in LDS, then S[Ib] += sum_f s_f sum_l L_l[rs_f] Y[Jb_f][l]
+        double *crow = lds, *acc = lds + nsb, *yr = lds + 2 * nsb, *lt = yr + (int64_t)nsb * kBLrStride;
+        const double *ltg = T.lt + I.off_lt;
+        __syncthreads();  // earlier readers of lds are done
+        for (int j = tid; j < nsb; j += bs) crow[j] = crowg[j];
+        for (int t = tid; t < M2 * kBLr; t += bs) lt[(t / kBLr) * kBLrStride + t % kBLr] = ltg[t];
+        __syncthreads();
+        for (int ib = tid; ib < nsb; ib += bs) {
+            double a = I.ecore * crow[ib];
+            for (int64_t q = q0; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
+            for (int q = 0; q < I.wB; ++q) a += elv[(int64_t)q * nsb + ib] * crow[elc[(int64_t)q * nsb + ib]];
+            acc[ib] = a;
+        }
+        for (int jb = tid; jb < nsb; jb += bs) {
+            double y[kBLr];
+#pragma unroll
+            for (int l = 0; l < kBLr; ++l) y[l] = 0.0;
+            for (int e = 0; e < I.nexcA; ++e) {
+                const uint32_t wa = exa[e];
+                const double x = C[(int64_t)(wa & 0xFFFFu) * nsb + jb];
+                const double xv = (wa >> 31) ? -x : x;
+                const double *w = lt + ((wa >> 16) & 0x1FFu) * kBLrStride;
+#pragma unroll
+                for (int l = 0; l < kBLr; ++l) y[l] += w[l] * xv;
+            }
+#pragma unroll
+            for (int l = 0; l < kBLr; ++l) yr[(int64_t)jb * kBLrStride + l] = y[l];
+        }
+        __syncthreads();
+        for (int ib = tid; ib < nsb; ib += bs) {
+            double s = 0.0;
+            for (int f = 0; f < I.nexcB; ++f) {
+                const uint32_t wb = exb[(int64_t)f * nsb + ib];
+                const double *w = lt + ((wb >> 16) & 0x1FFu) * kBLrStride;
+                const double *y = yr + (int64_t)(wb & 0xFFFFu) * kBLrStride;
+                double t = 0.0;
+#pragma unroll
+                for (int l = 0; l < kBLr; ++l) t += w[l] * y[l];
+                s += (wb >> 31) ? -t : t;
+            }
+            const double a = acc[ib] + s;
+            S[(int64_t)Ia * nsb + ib] = a;
+            eacc += crow[ib] * a;
         }
         return eacc;
     }
@@ -353,24 +407,36 @@ __global__ __launch_bounds__(64) void k_preduce(const BInst *__restrict__ inst, 
     }
 }
 
-// The same sums for packet runs: operator k's partials are its run's packets,
-// count[k] of them at gpart[k * pstride + slot].
-__global__ __launch_bounds__(64) void k_preduce_pk(const BInst *__restrict__ inst, const int32_t *__restrict__ count,
-                                                   int pstride, const double *__restrict__ epart,
-                                                   const double *__restrict__ gpart, double *__restrict__ grad,
-                                                   double *__restrict__ eout) {
-    const int y = blockIdx.x;
-    const BInst I = inst[y];
-    if (threadIdx.x == 0) {
+// The same sums for packet runs, one thread per operator (global index kk):
+// its partials are its run's packets, count[kk] of them at
+// gpart[kk * pstride + slot]; the energies, one thread per instance.
+__global__ __launch_bounds__(256) void k_preduce_pk(const BInst *__restrict__ inst, int count_inst,
+                                                    const int32_t *__restrict__ count, int64_t total_k, int pstride,
+                                                    const double *__restrict__ epart,
+                                                    const double *__restrict__ gpart, double *__restrict__ grad,
+                                                    double *__restrict__ eout) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < total_k) {
+        double s = 0.0;
+        for (int x = 0; x < count[t]; ++x) s += gpart[t * pstride + x];
+        grad[t] = 2.0 * s;
+    }
+    if (t < count_inst) {
+        const BInst I = inst[t];
         double e = 0.0;
         for (int r = 0; r < I.nsa; ++r) e += epart[I.off_task + r];
-        eout[y] = e;
+        eout[t] = e;
     }
-    for (int k = threadIdx.x; k < I.K; k += blockDim.x) {
-        const int64_t kk = I.off_k + k;
-        double s = 0.0;
-        for (int x = 0; x < count[kk]; ++x) s += gpart[kk * pstride + x];
-        grad[kk] = 2.0 * s;
+}
+
+// cos and sin of every angle (the first step of each captured evaluation).
+__global__ __launch_bounds__(256) void k_cossin(const double *__restrict__ theta, double *__restrict__ cs,
+                                                int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        double s, c;
+        sincos(theta[k], &s, &c);
+        cs[2 * k] = c;
+        cs[2 * k + 1] = s;
     }
 }
 
@@ -409,12 +475,12 @@ struct fsv_batch {
     int32_t *d_tinst = nullptr;
     BOp *d_ops = nullptr;
     uint32_t *d_lists = nullptr, *d_excA = nullptr, *d_excBT = nullptr;
-    double *d_cs = nullptr, *d_g = nullptr, *d_hval = nullptr, *d_ellv = nullptr;
+    double *d_cs = nullptr, *d_theta = nullptr, *d_g = nullptr, *d_hval = nullptr, *d_ellv = nullptr;
     double *d_grad = nullptr, *d_e = nullptr;
     int64_t *d_hptr = nullptr;
     int32_t *d_hcol = nullptr, *d_ellc = nullptr;
     double *d_arena = nullptr;
-    double *h_pin = nullptr;  // cs (2 total_k) | grad (total_k) | E (count)
+    double *h_pin = nullptr;  // theta (total_k) | spare (total_k) | grad (total_k) | E (count)
     int block = 256, per_cu = 2, cus = 256;
     int mode = 1;       // 0 persistent work-queue kernel, 1 phased launches, 2 packet runs
     int gx = 32;        // phased mode: workgroups per instance per rotation launch
@@ -433,7 +499,8 @@ struct fsv_batch {
     uint32_t *d_pent = nullptr, *d_preg = nullptr;
     int32_t *d_pcount = nullptr;
     double *d_pgpart = nullptr;
-    BTabs tabs() const { return BTabs{d_g, d_hptr, d_hcol, d_hval, d_ellc, d_ellv, d_excA, d_excBT}; }
+    double *d_lt = nullptr;
+    BTabs tabs() const { return BTabs{d_g, d_hptr, d_hcol, d_hval, d_ellc, d_ellv, d_excA, d_excBT, d_lt}; }
     ~fsv_batch() {
         if (work) (void)hipStreamSynchronize(work);
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -463,6 +530,14 @@ int set_lds_budget(fsv_batch &B, size_t budget) {
     size_t need = 0;
     for (BInst &I : B.inst) {
         const int64_t nsb = I.nsb, M2 = (int64_t)I.M * I.M;
+        if (I.R > 0 && !B.force_global) {  // factorised form when its row fits
+            const size_t nf = (size_t)8 * (2 * nsb + (nsb + M2) * kBLrStride);
+            if (nf <= budget) {
+                I.ec = -1;
+                need = std::max(need, nf);
+                continue;
+            }
+        }
         const int64_t room = (int64_t)(budget / 8) - 2 * nsb;
         int64_t ec = room > 0 ? (room / (nsb + M2)) & ~1LL : 0;
         ec = std::min<int64_t>(ec, (I.nexcA + 1) & ~1);
@@ -478,6 +553,11 @@ int set_lds_budget(fsv_batch &B, size_t budget) {
 
 int enqueue(fsv_batch &B) {
     const BTabs T = B.tabs();
+    if (B.total_k) {
+        hipLaunchKernelGGL(k_cossin, dim3(blocks_for(B.total_k, 256)), dim3(256), 0, B.work, B.d_theta, B.d_cs,
+                           B.total_k);
+        BHIP(hipGetLastError());
+    }
     if (B.mode == 2) {
         hipLaunchKernelGGL(k_pinit, dim3((unsigned)B.gx, (unsigned)B.count), dim3(256), 0, B.work, B.d_inst,
                            B.d_arena);
@@ -492,8 +572,9 @@ int enqueue(fsv_batch &B) {
         for (int r = P.runs - 1; r >= 0; --r)
             BHIP(launch_batch_packets(true, B.d_arena, B.d_pent + P.ent_off[r], B.d_preg + P.reg_off[r], P.wr[r],
                                       P.npk[r], B.d_cs, B.d_pgpart, P.pstride, B.work));
-        hipLaunchKernelGGL(k_preduce_pk, dim3((unsigned)B.count), dim3(64), 0, B.work, B.d_inst, B.d_pcount,
-                           P.pstride, B.d_epart, B.d_pgpart, B.d_grad, B.d_e);
+        const int64_t nt = std::max<int64_t>(B.total_k, B.count);
+        hipLaunchKernelGGL(k_preduce_pk, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, B.work, B.d_inst, B.count,
+                           B.d_pcount, B.total_k, P.pstride, B.d_epart, B.d_pgpart, B.d_grad, B.d_e);
         BHIP(hipGetLastError());
         return FSV_OK;
     }
@@ -552,16 +633,15 @@ int launch(fsv_batch &B) {
 }
 
 int run(fsv_batch &B, const double *theta, double *E_out, double *grad_out) {
-    double *cs = B.h_pin;
+    double *th = B.h_pin;
     for (int64_t k = 0; k < B.total_k; ++k) {
         if (!std::isfinite(theta[k])) return fail(FSV_ENONFINITE, "non-finite theta at %lld", (long long)k);
-        cs[2 * k] = std::cos(theta[k]);
-        cs[2 * k + 1] = std::sin(theta[k]);
+        th[k] = theta[k];
     }
     BHIP(hipEventRecord(B.ev_in, B.user));
     BHIP(hipStreamWaitEvent(B.work, B.ev_in, 0));
     if (B.total_k)
-        BHIP(hipMemcpyAsync(B.d_cs, cs, sizeof(double) * 2 * B.total_k, hipMemcpyHostToDevice, B.work));
+        BHIP(hipMemcpyAsync(B.d_theta, th, sizeof(double) * B.total_k, hipMemcpyHostToDevice, B.work));
     int rc = launch(B);
     if (rc) return rc;
     double *hg = B.h_pin + 2 * B.total_k, *he = hg + B.total_k;
@@ -600,11 +680,15 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     int env_mode = -1;
     if (const char *m = std::getenv("FSV_BATCH_MODE"))
         env_mode = std::strcmp(m, "persistent") == 0 ? 0 : (std::strcmp(m, "packets") == 0 ? 2 : 1);
-    if (const char *m = std::getenv("FSV_BATCH_SIGMA")) B->force_global = std::strcmp(m, "global") == 0;
+    bool lr_off = false;
+    if (const char *m = std::getenv("FSV_BATCH_SIGMA")) {
+        B->force_global = std::strcmp(m, "global") == 0;
+        lr_off = std::strcmp(m, "direct") == 0;
+    }
 
     std::vector<BOp> ops;
     std::vector<uint32_t> lists, excA, excBT;
-    std::vector<double> gall, hval, ellv;
+    std::vector<double> gall, hval, ellv, ltall;
     std::vector<int64_t> hptr;
     std::vector<int32_t> hcol, ellc;
     std::vector<double> cost(count);
@@ -668,6 +752,32 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         for (int r = 0; r < I.nsb; ++r)
             for (int f = 0; f < I.nexcB; ++f)
                 excBT[I.off_excB + (int64_t)f * I.nsb + r] = eb[(size_t)r * I.nexcB + f];
+        // exact low-rank factors of (pq|rs) for the factorised alpha-beta term,
+        // accepted as for a plan: rank <= 8, fewer multiply-adds, and g
+        // reproduced to 1e-12 relative
+        I.R = 0;
+        I.off_lt = (int64_t)ltall.size();
+        if (!lr_off && I.nexcA > 0 && I.nexcB > 0) {
+            const int M2 = M * M;
+            std::vector<double> L;
+            const int R = pivoted_cholesky(M2, p.g, 1e-14, L);
+            if (R > 0 && R <= kBLr && (int64_t)R * (I.nexcA + I.nexcB) < (int64_t)I.nexcA * I.nexcB) {
+                double gmax = 0.0, err = 0.0;
+                for (int a = 0; a < M2; ++a)
+                    for (int b = 0; b < M2; ++b) {
+                        double v = 0.0;
+                        for (int k = 0; k < R; ++k) v += L[(size_t)k * M2 + a] * L[(size_t)k * M2 + b];
+                        gmax = std::max(gmax, std::fabs(p.g[(size_t)a * M2 + b]));
+                        err = std::max(err, std::fabs(v - p.g[(size_t)a * M2 + b]));
+                    }
+                if (err <= 1e-12 * std::max(1.0, gmax)) {
+                    I.R = R;
+                    ltall.resize(ltall.size() + (size_t)M2 * kBLr, 0.0);
+                    for (int k = 0; k < R; ++k)
+                        for (int a = 0; a < M2; ++a) ltall[(size_t)I.off_lt + (size_t)a * kBLr + k] = L[(size_t)k * M2 + a];
+                }
+            }
+        }
         // operators in the alpha-first basis = the blocked JW ordering (qubit
         // excitations carry the signs of the instance's own qubit ordering)
         double pairs = 0.0;
@@ -677,7 +787,8 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
             pairs += (double)(o.nA >= 0 ? o.nA : I.nsa) * (double)(o.nB >= 0 ? o.nB : I.nsb);
             ops.push_back(o);
         }
-        cost[i] = (double)I.dim * (nnz_a + w + (double)I.nexcA * I.nexcB) + 3.0 * pairs;
+        cost[i] = (double)I.dim * (nnz_a + w + (I.R ? 2.0 * I.R * (I.nexcA + I.nexcB) : (double)I.nexcA * I.nexcB)) +
+                  3.0 * pairs;
         B->inst.push_back(I);
     }
     B->total_k = kk;
@@ -735,18 +846,19 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         (rc = dmalloc(o, &B->d_counter, 4)) || (rc = dmalloc(o, &B->d_tinst, tinst.size())) ||
         (rc = dmalloc(o, &B->d_ops, ops.size())) || (rc = dmalloc(o, &B->d_lists, lists.size())) ||
         (rc = dmalloc(o, &B->d_excA, excA.size())) || (rc = dmalloc(o, &B->d_excBT, excBT.size())) ||
-        (rc = dmalloc(o, &B->d_cs, 2 * (size_t)kk)) || (rc = dmalloc(o, &B->d_g, gall.size())) ||
+        (rc = dmalloc(o, &B->d_cs, 2 * (size_t)kk)) || (rc = dmalloc(o, &B->d_theta, std::max<size_t>(kk, 1))) ||
+        (rc = dmalloc(o, &B->d_g, gall.size())) ||
         (rc = dmalloc(o, &B->d_hval, hval.size())) || (rc = dmalloc(o, &B->d_hptr, hptr.size())) ||
         (rc = dmalloc(o, &B->d_hcol, hcol.size())) || (rc = dmalloc(o, &B->d_ellc, ellc.size())) ||
         (rc = dmalloc(o, &B->d_ellv, ellv.size())) || (rc = dmalloc(o, &B->d_grad, (size_t)kk)) ||
         (rc = dmalloc(o, &B->d_e, (size_t)count)) || (rc = dmalloc(o, &B->d_arena, (size_t)state)) ||
-        (rc = dmalloc(o, &B->d_epart, (size_t)B->ntasks)) ||
+        (rc = dmalloc(o, &B->d_epart, (size_t)B->ntasks)) || (rc = dmalloc(o, &B->d_lt, std::max<size_t>(ltall.size(), 1))) ||
         (rc = dmalloc(o, &B->d_gpart, (size_t)kk * B->part_cap)))
         return fin(rc);
     B->bytes = sizeof(BInst) * B->inst.size() + sizeof(int) * (count + 4) + 4 * tinst.size() +
                sizeof(BOp) * ops.size() + 4 * (lists.size() + excA.size() + excBT.size() + hcol.size() + ellc.size()) +
                8 * (2 * kk + gall.size() + hval.size() + hptr.size() + ellv.size() + kk + count) +
-               8 * ((size_t)B->ntasks + (size_t)kk * B->part_cap) + 8 * (size_t)state;
+               8 * ((size_t)B->ntasks + (size_t)kk * B->part_cap) + 8 * (size_t)state + 8 * ltall.size();
     struct Up { void *d; const void *h; size_t n; };
     const Up ups[] = {
         {B->d_order, B->order.data(), sizeof(int) * count},
@@ -761,6 +873,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         {B->d_hcol, hcol.data(), 4 * hcol.size()},
         {B->d_ellc, ellc.data(), 4 * ellc.size()},
         {B->d_ellv, ellv.data(), 8 * ellv.size()},
+        {B->d_lt, ltall.data(), 8 * ltall.size()},
     };
     for (const Up &u : ups)
         if (u.n && hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice) != hipSuccess)

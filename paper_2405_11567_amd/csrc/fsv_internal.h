@@ -63,6 +63,10 @@ void build_string_h(int M, const std::vector<uint32_t> &str, const std::vector<i
                     std::vector<int32_t> &col, std::vector<double> &val);
 void build_exc(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
                std::vector<uint32_t> &exc, int &nexc);
+// Pivoted Cholesky of a symmetric positive semidefinite n x n matrix:
+// G ~ sum_k L_k L_k^T with R rows of L (length n); returns R, or -1 when G is
+// not positive semidefinite within tol * max(diag).
+int pivoted_cholesky(int n, const double *G, double tol, std::vector<double> &L);
 // Pair lists of one operator for the sector-compressed state; appends to lists.
 PairOp build_pair_op(int M, const int32_t *op, const std::vector<uint32_t> &sa,
                      const std::vector<int32_t> &ra, const std::vector<uint32_t> &sb,

@@ -19,14 +19,15 @@ def fsv(gpu):
     return m
 
 
-@pytest.mark.parametrize("sigma", ["lds", "global"])
+@pytest.mark.parametrize("sigma", ["lds", "direct", "global"])
 @pytest.mark.parametrize("mode", ["phased", "persistent", "packets"])
 def test_batch_mixed_small(fsv, mode, sigma, monkeypatch):
-    # H C with rows staged in LDS, and from global memory only (the path taken
-    # by rows too long for LDS)
+    # H C with rows staged in LDS (the alpha-beta term through the factors of
+    # (pq|rs) where that is exact and cheaper, or directly), and from global
+    # memory only (the path taken by rows too long for LDS)
     monkeypatch.setenv("FSV_BATCH_MODE", mode)
-    if sigma == "global":
-        monkeypatch.setenv("FSV_BATCH_SIGMA", "global")
+    if sigma != "lds":
+        monkeypatch.setenv("FSV_BATCH_SIGMA", sigma)
     probs = []
     shapes = [(4, 2, 3), (6, 3, 10), (8, 4, 26), (8, 1, 5), (10, 7, 20), (12, 6, 40), (12, 4, 30),
               (10, 5, 0), (14, 7, 25), (6, 6, 0), (16, 9, 30)]
