@@ -407,25 +407,26 @@ __global__ __launch_bounds__(64) void k_preduce(const BInst *__restrict__ inst, 
     }
 }
 
-// The same sums for packet runs, one thread per operator (global index kk):
-// its partials are its run's packets, count[kk] of them at
-// gpart[kk * pstride + slot]; the energies, one thread per instance.
-__global__ __launch_bounds__(256) void k_preduce_pk(const BInst *__restrict__ inst, int count_inst,
-                                                    const int32_t *__restrict__ count, int64_t total_k, int pstride,
-                                                    const double *__restrict__ epart,
-                                                    const double *__restrict__ gpart, double *__restrict__ grad,
-                                                    double *__restrict__ eout) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// The same sums for packet runs, one wavefront per item: items below total_k
+// are operators (global index; its partials are its run's packets, count[kk]
+// of them at gpart[kk * pstride + slot]), the rest instances (energies).
+// Lanes take every 64th partial, then a butterfly: a fixed order.
+__global__ __launch_bounds__(64) void k_preduce_pk(const BInst *__restrict__ inst, const int32_t *__restrict__ count,
+                                                   int64_t total_k, int pstride, const double *__restrict__ epart,
+                                                   const double *__restrict__ gpart, double *__restrict__ grad,
+                                                   double *__restrict__ eout) {
+    const int64_t t = blockIdx.x;
+    const int l = threadIdx.x;
+    double s = 0.0;
     if (t < total_k) {
-        double s = 0.0;
-        for (int x = 0; x < count[t]; ++x) s += gpart[t * pstride + x];
-        grad[t] = 2.0 * s;
-    }
-    if (t < count_inst) {
-        const BInst I = inst[t];
-        double e = 0.0;
-        for (int r = 0; r < I.nsa; ++r) e += epart[I.off_task + r];
-        eout[t] = e;
+        for (int x = l; x < count[t]; x += kWave) s += gpart[t * pstride + x];
+        s = wave_sum(s);
+        if (l == 0) grad[t] = 2.0 * s;
+    } else {
+        const BInst I = inst[t - total_k];
+        for (int r = l; r < I.nsa; r += kWave) s += epart[I.off_task + r];
+        s = wave_sum(s);
+        if (l == 0) eout[t - total_k] = s;
     }
 }
 
@@ -572,8 +573,7 @@ int enqueue(fsv_batch &B) {
         for (int r = P.runs - 1; r >= 0; --r)
             BHIP(launch_batch_packets(true, B.d_arena, B.d_pent + P.ent_off[r], B.d_preg + P.reg_off[r], P.wr[r],
                                       P.npk[r], B.d_cs, B.d_pgpart, P.pstride, B.work));
-        const int64_t nt = std::max<int64_t>(B.total_k, B.count);
-        hipLaunchKernelGGL(k_preduce_pk, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, B.work, B.d_inst, B.count,
+        hipLaunchKernelGGL(k_preduce_pk, dim3((unsigned)(B.total_k + B.count)), dim3(kWave), 0, B.work, B.d_inst,
                            B.d_pcount, B.total_k, P.pstride, B.d_epart, B.d_pgpart, B.d_grad, B.d_e);
         BHIP(hipGetLastError());
         return FSV_OK;
