@@ -68,6 +68,17 @@ __device__ __forceinline__ int xcd_packet(int v, int n) {
     return x * per + min(x, rem) + i;
 }
 
+// psi and lam of one slot side by side in LDS (one 16- or 8-byte access)
+template <typename T> struct Slot2;
+template <> struct Slot2<double> {
+    using V = double2;
+    static __device__ __forceinline__ V make(double a, double b) { return make_double2(a, b); }
+};
+template <> struct Slot2<float> {
+    using V = float2;
+    static __device__ __forceinline__ V make(float a, float b) { return make_float2(a, b); }
+};
+
 template <typename T>
 __device__ __forceinline__ void rotp(T &a, T &b, T c, T s) {
     const T t = a;
@@ -82,8 +93,9 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
                                                double *__restrict__ gpart) {
     extern __shared__ double lds[];
     double *scs = lds;  // cos, sin of the run's operators
-    T *tp = (T *)(lds + kPktScalars);
-    T *tl = tp + kPkt;
+    using V2 = typename Slot2<T>::V;
+    T *tp = (T *)(lds + kPktScalars);  // forward: psi by slot
+    V2 *tv = (V2 *)tp;                 // adjoint: (psi, lam) by slot
     uint32_t *rg = (uint32_t *)(tp + (ADJ ? 2 : 1) * kPkt);
     const int l = threadIdx.x;
     {
@@ -120,8 +132,10 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
         for (int i = 0; i < NQ; ++i) ((u32x4 *)rg)[min(l + i * kWave, nq - 1)] = q[i];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            tp[l + i * kWave] = v0[i];
-            if (ADJ) tl[l + i * kWave] = v1[i];
+            if (ADJ)
+                tv[l + i * kWave] = Slot2<T>::make(v0[i], v1[i]);
+            else
+                tp[l + i * kWave] = v0[i];
         }
         __syncthreads();
         // Operator jj of the sweep order (adjoint: last to first).  Its pair
@@ -150,19 +164,20 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
                 for (uint32_t t = ob[jj] + l; t < oe[jj]; t += kWave) {
                     if (t != ob[jj] + l) w = pair_at(t);
                     const int xs = (int)(w & 0xFFu), xd = (int)(w >> 8);
-                    T va = tp[xs], vb = tp[xd];
                     if (ADJ) {
-                        T la = tl[xs], lb = tl[xd];
+                        const V2 A = tv[xs], B = tv[xd];
+                        T va = A.x, la = A.y, vb = B.x, lb = B.y;
                         acc[jj] += (double)lb * (double)va - (double)la * (double)vb;
                         rotp(va, vb, c, -s);  // U^+ = U(-theta)
                         rotp(la, lb, c, -s);
-                        tl[xs] = la;
-                        tl[xd] = lb;
+                        tv[xs] = Slot2<T>::make(va, la);
+                        tv[xd] = Slot2<T>::make(vb, lb);
                     } else {
+                        T va = tp[xs], vb = tp[xd];
                         rotp(va, vb, c, s);
+                        tp[xs] = va;
+                        tp[xd] = vb;
                     }
-                    tp[xs] = va;
-                    tp[xd] = vb;
                 }
                 __syncthreads();
             }
@@ -170,8 +185,13 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (x[i] != kNone) {
-                psi[x[i]] = tp[l + i * kWave];
-                if (ADJ) lam[x[i]] = tl[l + i * kWave];
+                if (ADJ) {
+                    const V2 A = tv[l + i * kWave];
+                    psi[x[i]] = A.x;
+                    lam[x[i]] = A.y;
+                } else {
+                    psi[x[i]] = tp[l + i * kWave];
+                }
             }
     }
     if (ADJ) {
@@ -202,8 +222,8 @@ __global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, cons
                                                 int pstride) {
     extern __shared__ double lds[];
     double *scs = lds;
-    double *tp = lds + kPktScalars;
-    double *tl = tp + kPkt;
+    double *tp = lds + kPktScalars;  // forward: psi by slot
+    double2 *tv = (double2 *)tp;     // adjoint: (psi, lam) by slot
     uint32_t *rg = (uint32_t *)(tp + (ADJ ? 2 : 1) * kPkt);
     const int l = threadIdx.x;
     const int nq = wr >> 2;
@@ -239,8 +259,10 @@ __global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, cons
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            tp[l + i * kWave] = v0[i];
-            if (ADJ) tl[l + i * kWave] = v1[i];
+            if (ADJ)
+                tv[l + i * kWave] = make_double2(v0[i], v1[i]);
+            else
+                tp[l + i * kWave] = v0[i];
         }
         __syncthreads();
         const uint32_t *rp = rg + kPktHdr;
@@ -256,19 +278,20 @@ __global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, cons
                 for (uint32_t t = o0 + l; t < o1; t += kWave) {
                     const uint32_t w = pair_at(t);
                     const int xs = (int)(w & 0xFFu), xd = (int)(w >> 8);
-                    double va = tp[xs], vb = tp[xd];
                     if (ADJ) {
-                        double la = tl[xs], lb = tl[xd];
+                        const double2 A = tv[xs], B = tv[xd];
+                        double va = A.x, la = A.y, vb = B.x, lb = B.y;
                         acc[jj] += lb * va - la * vb;
                         rotp(va, vb, c, -sn);
                         rotp(la, lb, c, -sn);
-                        tl[xs] = la;
-                        tl[xd] = lb;
+                        tv[xs] = make_double2(va, la);
+                        tv[xd] = make_double2(vb, lb);
                     } else {
+                        double va = tp[xs], vb = tp[xd];
                         rotp(va, vb, c, sn);
+                        tp[xs] = va;
+                        tp[xd] = vb;
                     }
-                    tp[xs] = va;
-                    tp[xd] = vb;
                 }
                 __syncthreads();
             }
@@ -276,8 +299,13 @@ __global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, cons
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (x[i] != kNone) {
-                psi[x[i]] = tp[l + i * kWave];
-                if (ADJ) lam[x[i]] = tl[l + i * kWave];
+                if (ADJ) {
+                    const double2 A = tv[l + i * kWave];
+                    psi[x[i]] = A.x;
+                    lam[x[i]] = A.y;
+                } else {
+                    psi[x[i]] = tp[l + i * kWave];
+                }
             }
         if (ADJ) {
 #pragma unroll
