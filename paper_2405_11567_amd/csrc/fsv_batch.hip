@@ -147,39 +147,78 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
         for (int j = tid; j < nsb; j += bs) crow[j] = crowg[j];
         for (int t = tid; t < M2 * kBLr; t += bs) lt[(t / kBLr) * kBLrStride + t % kBLr] = ltg[t];
         __syncthreads();
+        // Each loop below takes its list words kB at a time, loads first, so
+        // the dependent gathers of a batch are in flight together (the sums
+        // keep their order).
+        constexpr int kB = 4;
         for (int ib = tid; ib < nsb; ib += bs) {
             double a = I.ecore * crow[ib];
-            for (int64_t q = q0; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
-            for (int q = 0; q < I.wB; ++q) a += elv[(int64_t)q * nsb + ib] * crow[elc[(int64_t)q * nsb + ib]];
+            int64_t q = q0;
+            for (; q + kB <= q1; q += kB) {
+                double x[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) x[u] = C[(int64_t)T.hcol[q + u] * nsb + ib];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) a += T.hval[q + u] * x[u];
+            }
+            for (; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
+            int qb = 0;
+            for (; qb + kB <= I.wB; qb += kB) {
+                int32_t cidx[kB];
+                double wv[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    cidx[u] = elc[(int64_t)(qb + u) * nsb + ib];
+                    wv[u] = elv[(int64_t)(qb + u) * nsb + ib];
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u) a += wv[u] * crow[cidx[u]];
+            }
+            for (; qb < I.wB; ++qb) a += elv[(int64_t)qb * nsb + ib] * crow[elc[(int64_t)qb * nsb + ib]];
             acc[ib] = a;
         }
         for (int jb = tid; jb < nsb; jb += bs) {
             double y[kBLr];
 #pragma unroll
             for (int l = 0; l < kBLr; ++l) y[l] = 0.0;
-            for (int e = 0; e < I.nexcA; ++e) {
-                const uint32_t wa = exa[e];
-                const double x = C[(int64_t)(wa & 0xFFFFu) * nsb + jb];
+            auto step = [&](uint32_t wa, double x) {
                 const double xv = (wa >> 31) ? -x : x;
                 const double *w = lt + ((wa >> 16) & 0x1FFu) * kBLrStride;
 #pragma unroll
                 for (int l = 0; l < kBLr; ++l) y[l] += w[l] * xv;
+            };
+            int e = 0;
+            for (; e + kB <= I.nexcA; e += kB) {
+                double x[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) x[u] = C[(int64_t)(exa[e + u] & 0xFFFFu) * nsb + jb];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) step(exa[e + u], x[u]);
             }
+            for (; e < I.nexcA; ++e) step(exa[e], C[(int64_t)(exa[e] & 0xFFFFu) * nsb + jb]);
 #pragma unroll
             for (int l = 0; l < kBLr; ++l) yr[(int64_t)jb * kBLrStride + l] = y[l];
         }
         __syncthreads();
         for (int ib = tid; ib < nsb; ib += bs) {
             double s = 0.0;
-            for (int f = 0; f < I.nexcB; ++f) {
-                const uint32_t wb = exb[(int64_t)f * nsb + ib];
+            auto step = [&](uint32_t wb) {
                 const double *w = lt + ((wb >> 16) & 0x1FFu) * kBLrStride;
                 const double *y = yr + (int64_t)(wb & 0xFFFFu) * kBLrStride;
                 double t = 0.0;
 #pragma unroll
                 for (int l = 0; l < kBLr; ++l) t += w[l] * y[l];
                 s += (wb >> 31) ? -t : t;
+            };
+            int f = 0;
+            for (; f + kB <= I.nexcB; f += kB) {
+                uint32_t wb[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) wb[u] = exb[(int64_t)(f + u) * nsb + ib];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) step(wb[u]);
             }
+            for (; f < I.nexcB; ++f) step(exb[(int64_t)f * nsb + ib]);
             const double a = acc[ib] + s;
             S[(int64_t)Ia * nsb + ib] = a;
             eacc += crow[ib] * a;

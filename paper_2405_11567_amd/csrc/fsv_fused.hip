@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused(T *__restrict__ psi, T *_
     int32_t *sg0 = (int32_t *)(pb + a.bstride);
     const int tile = blockIdx.x;
     const int o = tile / a.n_blocks, b = tile - o * a.n_blocks;
-    // round 1: programs, angles, operator signs.  Indices are clamped rather
+    // first loads: programs, angles, operator signs.  Indices are clamped rather
     // than branched on so that each thread's loads are all in flight before
     // the first LDS write.
     {
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused(T *__restrict__ psi, T *_
     const int64_t c0 = pb[0];
     const uint32_t *rows = pa + 1;
     const int n = nr * L;
-    // round 2: the tile, kBatch loads per thread in flight
+    // second loads: the tile, kBatch loads per thread in flight
     for (int base = 0; base < n; base += kBatch * kFusedBlock) {
         T v[kBatch], w[kBatch];
 #pragma unroll
