@@ -300,6 +300,30 @@ def test_packet_runs_many_packets(fsv):
     assert e2 == e and np.array_equal(g2, g)
 
 
+@pytest.mark.parametrize("mode", ["packets", "tiles"])
+def test_time_runs_matches_sweeps(fsv, monkeypatch, mode):
+    # the per-run timing entry point launches the same sweeps eagerly: its
+    # forward sweep, H psi and adjoint sweep give the captured pass's energy
+    # and gradient, and it reports one positive time per run
+    monkeypatch.setenv("FSV_FUSE", mode)
+    p = config("C2")
+    plan = fsv.Plan(p)
+    psi, lam = plan.new_state(), plan.new_state()
+    e, g = plan.energy_grad(p.theta, psi, lam)
+    plan.set_theta(p.theta)
+    ms_f = plan.time_runs(psi)
+    assert len(ms_f) == len(np.unique(plan.runs()[0])) and (ms_f > 0).all()
+    plan.sigma_async(psi, lam)
+    ms_r = plan.time_runs(psi, lam, adjoint=True)
+    assert len(ms_r) == len(np.unique(plan.runs(adjoint=True)[0])) and (ms_r > 0).all()
+    e2, g2 = plan.finish()
+    assert abs(e2 - e) < 1e-12 and np.abs(g2 - g).max() < 1e-12
+    dplan = fsv.Plan(p, engine="dense")
+    with pytest.raises(fsv.FsvError) as ei:
+        dplan.time_runs(dplan.new_state())
+    assert ei.value.code == -4
+
+
 def test_sector_autotune(fsv):
     # every candidate LDS budget is run and timed; the chosen schedule keeps parity
     p = config("C2")
