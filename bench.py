@@ -367,6 +367,49 @@ def bench_multidet(fsv, torch, p, psi, lam, n_det=10000, reps=10):
             "onebody_property_ms": prop_ms, "onebody_property": val.real}
 
 
+def bench_strategy2(fsv, torch, p, psi, lam, outer=10, reps=5):
+    """The 24-qubit workload's self-consistent loop (Strategy 2): per outer
+    iteration set the one-body potential, one energy + adjoint-gradient step
+    on the angles, then the ansatz state, its energy and its 1-RDM, from which
+    the next potential is built (10 outer iterations).  Also each call of the
+    loop timed on its own."""
+    from paper_2405_11567_amd.scloop import self_consistent_loop
+    from workloads import potential_v0
+    plan = fsv.Plan(p, device=psi.device)
+    v0 = potential_v0(p.n_orb)
+    self_consistent_loop(plan, p.theta, v0, p.n_alpha, p.n_beta, kappa=0.5, outer=1, inner=1, lr=0.1,
+                         psi=psi, lam=lam)
+    quiet_gc()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = self_consistent_loop(plan, p.theta, v0, p.n_alpha, p.n_beta, kappa=0.5, outer=outer, inner=1,
+                               lr=0.1, psi=psi, lam=lam)
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / reps
+
+    plan.ansatz_apply(p.theta, psi)
+    out = {"outer_iterations": outer, "inner_steps": 1, "loop_ms": loop_ms, "ms_per_outer_iteration": loop_ms / outer,
+           "rdm1_ms": timed(lambda: plan.rdm1(psi)),
+           "set_onebody_potential_ms": timed(lambda: plan.set_onebody_potential(v0)),
+           "ansatz_apply_ms": timed(lambda: plan.ansatz_apply(p.theta, psi)),
+           "energy_ms": timed(lambda: plan.energy(psi)),
+           "first_converged_iteration": res.first_converged,
+           "last_energy": res.records[-1].energy, "last_e2": res.records[-1].e2}
+    plan.set_onebody_potential(None)
+    print(f"[bench] strategy-2 loop: {outer} outer iterations in {loop_ms:.2f} ms; 1-RDM {out['rdm1_ms']:.3f} ms",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def bench_batch(args):
     """C4: 256 independent instances (10..20 qubits), energy + adjoint gradient
     of every instance per step, in one persistent graph launch; compared with
@@ -435,6 +478,7 @@ def main():
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--no-pool", action="store_true", help="skip the ADAPT pool-screening measurement")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-amplitude variant")
+    ap.add_argument("--no-scf", action="store_true", help="skip the Strategy-2 self-consistent loop")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (the known-size "
@@ -543,6 +587,10 @@ def main():
     if args.engine == "sector" and args.precision == 0 and not args.no_pool:
         multidet = bench_multidet(fsv, torch, p, psi, lam)
 
+    strategy2 = None
+    if args.engine == "sector" and args.precision == 0 and not args.no_scf:
+        strategy2 = bench_strategy2(fsv, torch, p, psi, lam)
+
     cpu = None if args.no_cpu else cpu_baseline(p)
     out = {
         "metric": "energy+gradient evals/s and achieved HBM GB/s at 24 qubits vs plain FD method",
@@ -574,6 +622,7 @@ def main():
         "fp32_variant": fp32,
         "adapt_pool_screening": pool,
         "multideterminant_start": multidet,
+        "strategy2_loop": strategy2,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

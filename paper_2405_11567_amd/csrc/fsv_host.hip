@@ -110,6 +110,10 @@ struct fsv_plan {
     int64_t *d_ha_ptr = nullptr, *d_hb_ptr = nullptr;
     int32_t *d_ha_col = nullptr, *d_hb_col = nullptr;
     double *d_ha_val = nullptr, *d_hb_val = nullptr;
+    // device-side refresh of those values when the one-body potential changes
+    double *d_ha_v2 = nullptr, *d_hb_v2 = nullptr, *d_htilde = nullptr;  // two-body parts, h + v
+    int32_t *d_ha_desc = nullptr, *d_hb_desc = nullptr;                   // one-body descriptors
+    uint32_t *d_str_a = nullptr, *d_str_b = nullptr;                      // string masks
     int32_t *d_binA_off = nullptr, *d_binA_idx = nullptr, *d_binB_off = nullptr, *d_binB_idx = nullptr;
     double2 *d_C = nullptr, *d_S = nullptr, *d_CT = nullptr, *d_ST = nullptr, *d_O = nullptr;
     double2 *d_gamma = nullptr;
@@ -392,6 +396,32 @@ void build_string_h(int M, const std::vector<uint32_t> &str, const std::vector<i
     }
 }
 
+// One-body part of each entry of build_string_h's rows, in the same order:
+// the diagonal entry of row I is sum_{i in I} h_ii (desc = -2 - I), a single
+// excitation p <- q is sign * h_pq (desc = p*M+q, bit 30 for a negative sign),
+// a double has none (desc = -1).  The rest of each value is two-body only.
+void build_string_h_onebody(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
+                            std::vector<int32_t> &desc) {
+    desc.clear();
+    std::vector<int> occ, vir;
+    for (size_t I = 0; I < str.size(); ++I) {
+        const uint32_t s = str[I];
+        occ.clear();
+        vir.clear();
+        for (int p = 0; p < M; ++p) (s >> p & 1u ? occ : vir).push_back(p);
+        desc.push_back(-2 - (int32_t)I);
+        for (int p : occ)
+            for (int q : vir) {
+                const uint32_t J = (s & ~(1u << p)) | (1u << q);
+                desc.push_back((int32_t)(p * M + q) | (sign_epq(J, p, q) < 0 ? (1 << 30) : 0));
+            }
+        const size_t nd = occ.size() * (occ.size() - (occ.empty() ? 0 : 1)) / 2 * vir.size() *
+                          (vir.size() - (vir.empty() ? 0 : 1)) / 2;
+        desc.insert(desc.end(), nd, -1);
+    }
+    (void)rank;
+}
+
 // Gather-form single excitation lists: row I lists (J, p*M+q, sign) with
 // E_pq |J> = sign |I>, p in I and q either p or an empty orbital of I.
 void build_exc(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
@@ -634,18 +664,27 @@ bool want_dense_same_spin(const fsv_plan &P) {
     return nnz_a * 16.0 > (double)P.nsa && nnz_b * 16.0 > (double)P.nsb;
 }
 
+// New one-body potential: h + v goes up (M^2 doubles) and the string
+// Hamiltonian values (and their dense copies) are rebuilt on the device from
+// the fixed two-body parts and the one-body descriptors.
 int upload_hamiltonian_values(fsv_plan &P) {
     std::vector<double> ht(P.h);
     for (size_t i = 0; i < ht.size(); ++i) ht[i] += P.v[i];
-    std::vector<int32_t> ra(1u << P.M, -1), rb(1u << P.M, -1);
-    for (size_t i = 0; i < P.sa.size(); ++i) ra[P.sa[i]] = (int32_t)i;
-    for (size_t i = 0; i < P.sb.size(); ++i) rb[P.sb[i]] = (int32_t)i;
-    build_string_h(P.M, P.sa, ra, ht.data(), P.g.data(), P.ha_ptr, P.ha_col, P.ha_val);
-    build_string_h(P.M, P.sb, rb, ht.data(), P.g.data(), P.hb_ptr, P.hb_col, P.hb_val);
+    // earlier work on the stream (a previous refresh reading h + v, or
+    // products using the old values) completes before h + v is overwritten
+    HIPCHECK(hipStreamSynchronize(P.work));
     int rc;
-    if ((rc = upload(P, P.d_ha_val, P.ha_val.data(), P.ha_val.size()))) return rc;
-    if ((rc = upload(P, P.d_hb_val, P.hb_val.data(), P.hb_val.size()))) return rc;
-    return refresh_dense_same_spin(P);
+    if ((rc = upload(P, P.d_htilde, ht.data(), ht.size()))) return rc;
+    HIPCHECK(launch_string_h_values(P.d_ha_val, P.d_ha_v2, P.d_ha_desc, P.d_str_a, P.d_htilde, P.M,
+                                    (int64_t)P.ha_col.size(), P.work));
+    HIPCHECK(launch_string_h_values(P.d_hb_val, P.d_hb_v2, P.d_hb_desc, P.d_str_b, P.d_htilde, P.M,
+                                    (int64_t)P.hb_col.size(), P.work));
+    if (P.d_ha_dense) {
+        HIPCHECK(launch_csr_dense(P.d_ha_ptr, P.d_ha_col, P.d_ha_val, P.d_ha_dense, P.nsa, P.work));
+        HIPCHECK(launch_csr_dense(P.d_hb_ptr, P.d_hb_col, P.d_hb_val, P.d_hb_dense, P.nsb, P.work));
+        HIPCHECK(launch_ctranspose(false, P.d_hb_dense, P.d_hb_dense_t, P.nsb, P.nsb, P.work));
+    }
+    return FSV_OK;
 }
 
 // Byte model of one pair kernel (read + write of the touched 128-byte lines).
@@ -1158,6 +1197,29 @@ int build_device(fsv_plan &P) {
     if ((rc = upload(P, P.d_hb_ptr, P.hb_ptr.data(), P.hb_ptr.size()))) return rc;
     if ((rc = upload(P, P.d_hb_col, P.hb_col.data(), P.hb_col.size()))) return rc;
     if ((rc = upload(P, P.d_hb_val, P.hb_val.data(), P.hb_val.size()))) return rc;
+    {
+        std::vector<double> zero((size_t)M * M, 0.0), v2;
+        std::vector<int64_t> ptr2;
+        std::vector<int32_t> col2, desc;
+        auto part = [&](const std::vector<uint32_t> &str, const std::vector<int32_t> &rk, size_t nent,
+                        double **d_v2, int32_t **d_desc, uint32_t **d_str) -> int {
+            int r;
+            build_string_h(M, str, rk, zero.data(), P.g.data(), ptr2, col2, v2);
+            build_string_h_onebody(M, str, rk, desc);
+            if (v2.size() != nent || desc.size() != nent)
+                return fail(FSV_EINVAL, "internal: string Hamiltonian parts disagree");
+            if ((r = dalloc(P, d_v2, nent)) || (r = dalloc(P, d_desc, nent)) || (r = dalloc(P, d_str, str.size())))
+                return r;
+            if ((r = upload(P, *d_v2, v2.data(), nent)) || (r = upload(P, *d_desc, desc.data(), nent)) ||
+                (r = upload(P, *d_str, str.data(), str.size())))
+                return r;
+            return FSV_OK;
+        };
+        if ((rc = part(P.sa, ra, P.ha_val.size(), &P.d_ha_v2, &P.d_ha_desc, &P.d_str_a)) ||
+            (rc = part(P.sb, rb, P.hb_val.size(), &P.d_hb_v2, &P.d_hb_desc, &P.d_str_b)) ||
+            (rc = dalloc(P, &P.d_htilde, (size_t)M * M)))
+            return rc;
+    }
     int R = 0;
     std::vector<double> Lt;
     choose_sigma(P, R, Lt);

@@ -165,6 +165,12 @@ hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, v
 // partial[t * gx + x] = workgroup x's share of Re<lam|T_t|psi> for pool op t.
 hipError_t launch_pool(int vtype, const void *psi, const void *lam, const PairOp *ops, const uint32_t *lists,
                        int n_ops, int gx, int64_t nsa, int64_t nsb, double *partial, hipStream_t st);
+// String Hamiltonian values val[e] = v2[e] + one-body part of descriptor
+// desc[e] with h~ = ht (M x M): -1 none, -2 - I the diagonal of row I (sum of
+// h~_ii over the occupied orbitals of string str[I]), otherwise h~[desc &
+// 0x3FFFFFFF], negated when bit 30 is set.
+hipError_t launch_string_h_values(double *val, const double *v2, const int32_t *desc, const uint32_t *str,
+                                  const double *ht, int M, int64_t n, hipStream_t st);
 // Dense row-major copy (n x n) of an n-row CSR matrix.
 hipError_t launch_csr_dense(const int64_t *rowptr, const int32_t *col, const double *val, double *out, int64_t n,
                             hipStream_t st);

@@ -624,6 +624,27 @@ __global__ void k_combine(A *__restrict__ S, const A *__restrict__ ST, const A *
     if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.x] = acc;
 }
 
+// String Hamiltonian values from their two-body parts and the one-body
+// descriptors (see launch_string_h_values).
+__global__ __launch_bounds__(256) void k_string_h_values(double *__restrict__ val, const double *__restrict__ v2,
+                                                         const int32_t *__restrict__ desc,
+                                                         const uint32_t *__restrict__ str,
+                                                         const double *__restrict__ ht, int M, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = desc[e];
+        double o = 0.0;
+        if (d <= -2) {
+            const uint32_t s = str[-2 - d];
+            for (int i = 0; i < M; ++i)
+                if (s >> i & 1u) o += ht[i * M + i];
+        } else if (d >= 0) {
+            o = ht[d & 0x3FFFFFFF];
+            if (d & (1 << 30)) o = -o;
+        }
+        val[e] = o + v2[e];
+    }
+}
+
 // S += ecore C and this workgroup's share of <C|S> (real states whose beta
 // part went straight into S).
 __global__ __launch_bounds__(256) void k_ecore_dot(double *__restrict__ S, const double *__restrict__ C, double ecore,
@@ -881,6 +902,13 @@ hipError_t launch_pool(int vtype, const void *psi, const void *lam, const PairOp
                            nsa, nsb, partial);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_string_h_values(double *val, const double *v2, const int32_t *desc, const uint32_t *str,
+                                  const double *ht, int M, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_string_h_values, dim3(blocks_for(n, 256)), dim3(256), 0, st, val, v2, desc, str, ht, M, n);
     return hipGetLastError();
 }
 
