@@ -174,8 +174,14 @@ int rdm1(fsv_plan *plan, const void *psi_dev, double *gamma_out);
 
 /* Replace the one-body potential: the Hamiltonian becomes H with h -> h + v
  * (the basis-set correction potential operator of Strategy 2, spin-independent).
- * v: host, n_orb*n_orb real symmetric; NULL clears it.  Later energy,
- * energy_grad and batch calls use the new Hamiltonian. */
+ * v: host, n_orb*n_orb real symmetric (row-major, copied; the caller keeps
+ * ownership); NULL clears it.  The string Hamiltonian tables are refreshed on
+ * the device from their fixed two-body parts; the call waits for the plan's
+ * earlier work first.  Captured graphs read the tables, so later energy,
+ * energy_grad, stage-level and pool calls on this plan use the new
+ * Hamiltonian without re-capture (batches hold their own Hamiltonians).
+ * Errors: FSV_EINVAL (NULL plan, v not symmetric to 1e-12 of its largest
+ * entry), FSV_ENONFINITE (NaN or Inf in v); the old potential stays then. */
 int set_onebody_potential(fsv_plan *plan, const double *v);
 
 /* ---- stage-level asynchronous entry points (device outputs, no host sync) ----
