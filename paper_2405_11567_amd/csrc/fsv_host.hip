@@ -115,6 +115,7 @@ struct fsv_plan {
     int32_t *d_ha_desc = nullptr, *d_hb_desc = nullptr;                   // one-body descriptors
     uint32_t *d_str_a = nullptr, *d_str_b = nullptr;                      // string masks
     int32_t *d_binA_off = nullptr, *d_binA_idx = nullptr, *d_binB_off = nullptr, *d_binB_idx = nullptr;
+    // d_C also holds the interleaved (psi, lam) pairs of a packet adjoint sweep
     double2 *d_C = nullptr, *d_S = nullptr, *d_CT = nullptr, *d_ST = nullptr, *d_O = nullptr;
     double2 *d_gamma = nullptr;
     double *h_pin = nullptr;  // pinned: cs (2K) then out (K + 1) then gamma (4 M^2)
@@ -814,9 +815,21 @@ int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g) {
     return FSV_OK;
 }
 
-// One group of the adjoint sweep (operators last to first).
+// One group of the adjoint sweep (operators last to first).  Packet
+// schedules run on the interleaved pairs z (c and lam_c are unused then).
 int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g) {
     const int G = max_grid();
+    if (P.frev.packets) {
+        void *z = P.d_C;
+        if (g.fused) {
+            HIPCHECK(launch_packets(P.svt, true, z, P.frev, g, P.d_cs, P.d_gpart, G, P.work));
+            return FSV_OK;
+        }
+        for (int k = g.k0 + g.nops - 1; k >= g.k0; --k)
+            HIPCHECK(launch_cadj_zip(P.svt, z, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
+                                     P.d_gpart + (size_t)k * G, P.work));
+        return FSV_OK;
+    }
     if (g.fused) {
         HIPCHECK(launch_fused(P.svt, true, c, lam_c, P.frev, g, P.d_pops, P.d_cs, P.nsb, P.d_gpart, G, P.work));
         return FSV_OK;
@@ -855,8 +868,12 @@ int enq_sigma_sector(fsv_plan &P, const void *c, void *lam_c) {
     return FSV_OK;
 }
 
+// Packet schedules: the sweep first interleaves psi and lam into d_C (2 dim
+// values of the state's type, within its dim double2), so that each gather
+// of the packet kernels moves both; psi and lam are then left as they were.
 int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
     const int G = max_grid();
+    if (P.frev.packets) HIPCHECK(launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work));
     for (auto it = P.frev.groups.rbegin(); it != P.frev.groups.rend(); ++it) {
         const int rc = enq_group_rev(P, c, lam_c, *it);
         if (rc) return rc;
@@ -884,6 +901,8 @@ int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms)
         else if (!P.n_init && hipSuccess != launch_set_amp(c, P.svt, 0, P.ref_phase, P.work))
             rc = fail(FSV_EDEVICE, "initial-state launch failed");
     }
+    if (!rc && adjoint && P.frev.packets && hipSuccess != launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work))
+        rc = fail(FSV_EDEVICE, "interleave launch failed");
     if (!rc && hipEventRecord(ev[0], P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
     for (int t = 0; t < n && !rc; ++t) {
         const int i = adjoint ? n - 1 - t : t;

@@ -28,7 +28,9 @@
 // each load instruction covers 64 consecutive sorted indices), applies the run there (forward:
 // rotations in order; adjoint: for the last operator back to the first, the
 // gradient contribution, then psi and lam un-rotated) and scatters them back.
-// Untouched amplitudes are never read.  Consecutive workgroup ids go to
+// The adjoint sweep keeps psi and lam of each amplitude side by side in
+// memory, so a gather or scatter moves both in one access.  Untouched
+// amplitudes are never read.  Consecutive workgroup ids go to
 // different XCDs, so packet numbers are remapped to give each XCD a contiguous
 // range of packets: with packets laid out by row group, the packets that
 // share a cache line then share that XCD's L2.
@@ -86,8 +88,10 @@ __device__ __forceinline__ void rotp(T &a, T &b, T c, T s) {
     b = c * b + s * t;
 }
 
+// Forward: psi is the state.  Adjoint: z holds (psi, lam) of each amplitude
+// side by side, so one 16-byte (FP32: 8-byte) access moves both.
 template <typename T, bool ADJ, int NQ>
-__global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restrict__ lam,
+__global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slot2<T>::V *__restrict__ z,
                                                const uint32_t *__restrict__ ent,
                                                const uint32_t *__restrict__ reg, PArgs a,
                                                double *__restrict__ gpart) {
@@ -122,8 +126,13 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t xi = x[i] == kNone ? 0u : x[i];
-            v0[i] = psi[xi];
-            if (ADJ) v1[i] = lam[xi];
+            if (ADJ) {
+                const V2 zi = z[xi];
+                v0[i] = zi.x;
+                v1[i] = zi.y;
+            } else {
+                v0[i] = psi[xi];
+            }
         }
         __syncthreads();  // the previous packet is out of LDS
         // Unconditional LDS writes: a clamped lane writes the value its
@@ -185,13 +194,10 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, T *__restric
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (x[i] != kNone) {
-                if (ADJ) {
-                    const V2 A = tv[l + i * kWave];
-                    psi[x[i]] = A.x;
-                    lam[x[i]] = A.y;
-                } else {
+                if (ADJ)
+                    z[x[i]] = tv[l + i * kWave];
+                else
                     psi[x[i]] = tp[l + i * kWave];
-                }
             }
     }
     if (ADJ) {
@@ -594,22 +600,26 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
         S.release();
         return rc;
     }
+    S.packets = true;
     return FSV_OK;
 }
 
 namespace {
 
 template <typename T, bool ADJ>
-hipError_t pkt_impl(void *psi, void *lam, const FusedSched &S, const FGroup &g, const double *cs, double *gpart,
+hipError_t pkt_impl(void *state, const FusedSched &S, const FGroup &g, const double *cs, double *gpart,
                     int gstride, hipStream_t st) {
+    using V2 = typename Slot2<T>::V;
     PArgs a{g.k0, g.nops, g.wr, g.n_packets, gstride, cs};
     const uint32_t *ent = S.d_aprog + g.ent_off, *reg = S.d_bprog + g.reg_off;
     const size_t shm = sizeof(double) * kPktScalars + (size_t)kPkt * (ADJ ? 2 : 1) * sizeof(T) + (size_t)g.wr * 4;
     const dim3 grid((unsigned)std::min(g.n_packets, max_grid())), block(kWave);
+    T *psi = ADJ ? nullptr : (T *)state;
+    V2 *z = ADJ ? (V2 *)state : nullptr;
     if (g.wr <= 4 * kWave * 2)
-        hipLaunchKernelGGL((k_pkt<T, ADJ, 2>), grid, block, shm, st, (T *)psi, (T *)lam, ent, reg, a, gpart);
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 2>), grid, block, shm, st, psi, z, ent, reg, a, gpart);
     else  // wr <= kPktMaxWords
-        hipLaunchKernelGGL((k_pkt<T, ADJ, 4>), grid, block, shm, st, (T *)psi, (T *)lam, ent, reg, a, gpart);
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 4>), grid, block, shm, st, psi, z, ent, reg, a, gpart);
     return hipGetLastError();
 }
 
@@ -701,13 +711,13 @@ hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent
     return hipGetLastError();
 }
 
-hipError_t launch_packets(int vtype, bool adjoint, void *psi, void *lam, const FusedSched &S, const FGroup &g,
+hipError_t launch_packets(int vtype, bool adjoint, void *state, const FusedSched &S, const FGroup &g,
                           const double *cs, double *gpart, int gstride, hipStream_t st) {
     if (vtype == V_F64)
-        return adjoint ? pkt_impl<double, true>(psi, lam, S, g, cs, gpart, gstride, st)
-                       : pkt_impl<double, false>(psi, lam, S, g, cs, gpart, gstride, st);
-    return adjoint ? pkt_impl<float, true>(psi, lam, S, g, cs, gpart, gstride, st)
-                   : pkt_impl<float, false>(psi, lam, S, g, cs, gpart, gstride, st);
+        return adjoint ? pkt_impl<double, true>(state, S, g, cs, gpart, gstride, st)
+                       : pkt_impl<double, false>(state, S, g, cs, gpart, gstride, st);
+    return adjoint ? pkt_impl<float, true>(state, S, g, cs, gpart, gstride, st)
+                   : pkt_impl<float, false>(state, S, g, cs, gpart, gstride, st);
 }
 
 }  // namespace fsv
