@@ -233,9 +233,9 @@ def run_touched(p, k0, k1):
 def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps=5):
     """Roofline of the adjoint packet-run kernel: the adjoint sweep is launched
     eagerly with HIP events around every run (fsv_time_runs); achieved =
-    algorithmic bytes of the packet runs (their touched amplitudes, psi and
-    lam, read and written) over their measured time.  None when the plan has
-    no packet runs."""
+    algorithmic bytes of the packet runs (per touched amplitude: psi read from
+    the forward sweep's record, lam read and written) over their measured
+    time.  None when the plan has no packet runs."""
     start, tiles = plan.runs(adjoint=True)
     k = len(start)
     firsts = [t for t in range(k) if t == 0 or start[t] != start[t - 1]]
@@ -253,7 +253,7 @@ def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps
     med = np.median(np.array(times[1:]), axis=0)
     es = 8 if precision == 0 else 4
     amps = [run_touched(p, *groups[n]) for n in fused]
-    byts = [4.0 * es * a for a in amps]  # psi and lam, read and written
+    byts = [3.0 * es * a for a in amps]  # psi read; lam read and written
     ms = [float(med[n]) for n in fused]
     achieved = sum(byts) / (sum(ms) * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

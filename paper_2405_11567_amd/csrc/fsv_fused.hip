@@ -280,6 +280,7 @@ void FusedSched::release() {
     count.clear();
     d_aprog = d_bprog = nullptr;
     packets = false;
+    d_ckpt = nullptr;
 }
 
 int build_fused(int M, const std::vector<uint32_t> &sa, const std::vector<uint32_t> &sb,
@@ -526,8 +527,7 @@ size_t fused_lds_limit() {
 hipError_t launch_fused(int vtype, bool adjoint, void *psi, void *lam, const FusedSched &S, const FGroup &g,
                         const PairOp *d_pops, const double *cs, int64_t nsb, double *gpart, int gstride,
                         hipStream_t st) {
-    if (g.fused == 2)
-        return adjoint ? hipErrorInvalidValue : launch_packets(vtype, false, psi, S, g, cs, gpart, gstride, st);
+    if (g.fused == 2) return hipErrorInvalidValue;
     FArgs a;
     a.k0 = g.k0;
     a.nops = g.nops;

@@ -115,7 +115,6 @@ struct fsv_plan {
     int32_t *d_ha_desc = nullptr, *d_hb_desc = nullptr;                   // one-body descriptors
     uint32_t *d_str_a = nullptr, *d_str_b = nullptr;                      // string masks
     int32_t *d_binA_off = nullptr, *d_binA_idx = nullptr, *d_binB_off = nullptr, *d_binB_idx = nullptr;
-    // d_C also holds the interleaved (psi, lam) pairs of a packet adjoint sweep
     double2 *d_C = nullptr, *d_S = nullptr, *d_CT = nullptr, *d_ST = nullptr, *d_O = nullptr;
     double2 *d_gamma = nullptr;
     double *h_pin = nullptr;  // pinned: cs (2K) then out (K + 1) then gamma (4 M^2)
@@ -154,6 +153,9 @@ struct fsv_plan {
     // graphs
     uint64_t gen = 0;  // bumped whenever captured launches may have changed
     bool use_graph = true;
+    // packet runs: the records hold the forward sweep of the current angles,
+    // initial state and schedule (a recording forward sweep was enqueued last)
+    bool records_ok = false;
     hipGraphExec_t g_eg = nullptr;
     const void *g_eg_psi = nullptr, *g_eg_lam = nullptr;
     hipGraphExec_t g_e = nullptr;
@@ -734,6 +736,7 @@ int upload_counts(fsv_plan &P) {
 
 void drop_graphs(fsv_plan &P) {
     ++P.gen;  // graphs of pools built on this plan are stale too
+    P.records_ok = false;
     if (P.g_eg) (void)hipGraphExecDestroy(P.g_eg);
     if (P.g_e) (void)hipGraphExecDestroy(P.g_e);
     P.g_eg = nullptr;
@@ -804,8 +807,12 @@ int enq_reverse_dense(fsv_plan &P, void *psi, void *lam) {
 }
 
 // One group of the forward sweep: a fused run in one launch, or its single
-// operator.
-int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g) {
+// operator.  record: packet runs also write their records for the adjoint.
+int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g, bool record) {
+    if (g.fused == 2) {
+        HIPCHECK(launch_packets(P.svt, false, c, record, P.ffwd, g, P.d_cs, nullptr, 0, P.work));
+        return FSV_OK;
+    }
     if (g.fused) {
         HIPCHECK(launch_fused(P.svt, false, c, nullptr, P.ffwd, g, P.d_pops, P.d_cs, P.nsb, nullptr, 0, P.work));
         return FSV_OK;
@@ -815,19 +822,12 @@ int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g) {
     return FSV_OK;
 }
 
-// One group of the adjoint sweep (operators last to first).  Packet
-// schedules run on the interleaved pairs z (c and lam_c are unused then).
+// One group of the adjoint sweep (operators last to first).  A packet run
+// takes psi from the forward sweep's records and updates lam_c only.
 int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g) {
     const int G = max_grid();
-    if (P.frev.packets) {
-        void *z = P.d_C;
-        if (g.fused) {
-            HIPCHECK(launch_packets(P.svt, true, z, P.frev, g, P.d_cs, P.d_gpart, G, P.work));
-            return FSV_OK;
-        }
-        for (int k = g.k0 + g.nops - 1; k >= g.k0; --k)
-            HIPCHECK(launch_cadj_zip(P.svt, z, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
-                                     P.d_gpart + (size_t)k * G, P.work));
+    if (g.fused == 2) {
+        HIPCHECK(launch_packets(P.svt, true, lam_c, false, P.frev, g, P.d_cs, P.d_gpart, G, P.work));
         return FSV_OK;
     }
     if (g.fused) {
@@ -843,7 +843,7 @@ int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g) {
 // ---- sector-compressed engine: the state is C[Ia][Ib] in the first
 // nsa*nsb amplitudes of the caller's buffer.  With real angles and real
 // integrals every amplitude stays real, so it is stored real (FP64 or FP32). ----
-int enq_forward_sector(fsv_plan &P, void *c) {
+int enq_forward_sector(fsv_plan &P, void *c, bool record) {
     HIPCHECK(launch_fill_zero(c, (size_t)P.dim * vtype_bytes(P.svt), P.work));
     // The reference is string 0 x string 0.  Its alpha-first amplitude carries
     // the ordering sign so that the dense image starts at exactly +1 |ref>.
@@ -852,7 +852,7 @@ int enq_forward_sector(fsv_plan &P, void *c) {
     else
         HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
     for (const FGroup &g : P.ffwd.groups) {
-        const int rc = enq_group_fwd(P, c, g);
+        const int rc = enq_group_fwd(P, c, g, record);
         if (rc) return rc;
     }
     return FSV_OK;
@@ -868,12 +868,10 @@ int enq_sigma_sector(fsv_plan &P, const void *c, void *lam_c) {
     return FSV_OK;
 }
 
-// Packet schedules: the sweep first interleaves psi and lam into d_C (2 dim
-// values of the state's type, within its dim double2), so that each gather
-// of the packet kernels moves both; psi and lam are then left as they were.
+// Packet schedules read psi from the records of the last recording forward
+// sweep (c is not touched); other schedules un-rotate c in place.
 int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
     const int G = max_grid();
-    if (P.frev.packets) HIPCHECK(launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work));
     for (auto it = P.frev.groups.rbegin(); it != P.frev.groups.rend(); ++it) {
         const int rc = enq_group_rev(P, c, lam_c, *it);
         if (rc) return rc;
@@ -901,12 +899,10 @@ int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms)
         else if (!P.n_init && hipSuccess != launch_set_amp(c, P.svt, 0, P.ref_phase, P.work))
             rc = fail(FSV_EDEVICE, "initial-state launch failed");
     }
-    if (!rc && adjoint && P.frev.packets && hipSuccess != launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work))
-        rc = fail(FSV_EDEVICE, "interleave launch failed");
     if (!rc && hipEventRecord(ev[0], P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
     for (int t = 0; t < n && !rc; ++t) {
         const int i = adjoint ? n - 1 - t : t;
-        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i]) : enq_group_fwd(P, c, S.groups[i]);
+        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i]) : enq_group_fwd(P, c, S.groups[i], true);
         if (!rc && hipEventRecord(ev[t + 1], P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
     }
     if (!rc && adjoint &&
@@ -923,8 +919,10 @@ int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms)
     return rc;
 }
 
-int enq_forward(fsv_plan &P, void *psi) {
-    return P.engine == 0 ? enq_forward_sector(P, psi) : enq_forward_dense(P, psi);
+// record: the forward sweep of an energy + gradient pass (packet runs keep
+// their results for the adjoint sweep).
+int enq_forward(fsv_plan &P, void *psi, bool record) {
+    return P.engine == 0 ? enq_forward_sector(P, psi, record) : enq_forward_dense(P, psi);
 }
 
 int enq_sigma(fsv_plan &P, const void *psi, void *lam) {
@@ -939,7 +937,7 @@ int enq_reverse(fsv_plan &P, void *psi, void *lam) {
 // expanded (zero elsewhere) into the caller's 2^n buffer.
 int enq_ansatz_dense_out(fsv_plan &P, void *psi) {
     if (P.engine != 0) return enq_forward_dense(P, psi);
-    int rc = enq_forward_sector(P, P.d_S);
+    int rc = enq_forward_sector(P, P.d_S, false);
     if (rc) return rc;
     const double *S = (const double *)P.d_S;
     if (P.svt == V_F32) {
@@ -954,6 +952,7 @@ int enq_ansatz_dense_out(fsv_plan &P, void *psi) {
 int upload_theta(fsv_plan &P, const double *theta) {
     if (P.K > 0 && !theta) return fail(FSV_EINVAL, "theta is NULL");
     if (!finite_all(theta, (size_t)P.K)) return fail(FSV_ENONFINITE, "non-finite theta");
+    P.records_ok = false;
     double *h = P.h_pin;
     for (int k = 0; k < P.K; ++k) {
         h[2 * k] = std::cos(theta[k]);
@@ -978,7 +977,7 @@ typedef int (*enq_fn)(fsv_plan &, void *, void *);
 
 int run_energy_grad_body(fsv_plan &P, void *psi, void *lam) {
     int rc;
-    if ((rc = enq_forward(P, psi))) return rc;
+    if ((rc = enq_forward(P, psi, true))) return rc;
     if ((rc = enq_sigma(P, psi, lam))) return rc;
     if ((rc = enq_reverse(P, psi, lam))) return rc;
     return FSV_OK;
@@ -986,7 +985,7 @@ int run_energy_grad_body(fsv_plan &P, void *psi, void *lam) {
 
 int run_energy_body(fsv_plan &P, void *psi) {
     int rc;
-    if ((rc = enq_forward(P, psi))) return rc;
+    if ((rc = enq_forward(P, psi, false))) return rc;
     if ((rc = enq_sigma(P, psi, nullptr))) return rc;
     return FSV_OK;
 }
@@ -1451,13 +1450,25 @@ int fsv_plan_runs(const fsv_plan *P, int adjoint, int32_t *run_start, int32_t *f
     return (int)S.groups.size();
 }
 
+namespace {
+// The adjoint sweep of packet runs reads the forward sweep's records: they
+// must come from the current angles, initial state and schedule.
+int rc_records(const fsv_plan &P) {
+    if (P.engine != 0 || !P.frev.packets || P.frev.groups.empty() || P.records_ok) return FSV_OK;
+    return fail(FSV_ESTATE, "the adjoint sweep needs the forward sweep of the current angles first "
+                            "(fsv_forward_async)");
+}
+}  // namespace
+
 int fsv_time_runs(fsv_plan *P, int adjoint, void *psi, void *lam, float *ms) {
     if (!P || !psi || !ms || (adjoint && !lam)) return fail(FSV_EINVAL, "plan, psi, lam or ms is NULL");
     if (adjoint != 0 && adjoint != 1) return fail(FSV_EINVAL, "adjoint must be 0 or 1");
     if (P->engine != 0) return fail(FSV_ESTATE, "per-run timing is available on the sector engine only");
+    if (adjoint && (rc_records(*P))) return FSV_ESTATE;
     int rc;
     if ((rc = fence_in(*P))) return rc;
     if ((rc = time_sweep_sector(*P, adjoint, psi, lam, ms))) return rc;
+    if (!adjoint) P->records_ok = true;
     if ((rc = fence_out(*P))) return rc;
     return (int)(adjoint ? P->frev : P->ffwd).groups.size();
 }
@@ -1474,7 +1485,8 @@ int fsv_forward_async(fsv_plan *P, void *psi) {
     if (!P || !psi) return fail(FSV_EINVAL, "plan or psi is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
-    if ((rc = enq_forward(*P, psi))) return rc;
+    if ((rc = enq_forward(*P, psi, true))) return rc;
+    P->records_ok = true;
     return fence_out(*P);
 }
 
@@ -1488,6 +1500,7 @@ int fsv_sigma_async(fsv_plan *P, const void *psi, void *lam) {
 
 int fsv_reverse_async(fsv_plan *P, void *psi, void *lam) {
     if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
+    if (rc_records(*P)) return FSV_ESTATE;
     int rc;
     if ((rc = fence_in(*P))) return rc;
     if ((rc = enq_reverse(*P, psi, lam))) return rc;
@@ -1530,6 +1543,7 @@ int energy_grad(fsv_plan *P, const double *theta, void *psi, void *lam, double *
     if ((rc = fence_in(*P))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
     if ((rc = launch_energy_grad(*P, psi, lam))) return rc;
+    P->records_ok = P->engine == 0;
     if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
     return fence_out(*P);
 }
@@ -1865,7 +1879,7 @@ int fsv_pool_gradients(fsv_pool *Q, const double *theta, void *psi, void *lam, d
     if ((rc = upload_theta(P, theta))) return rc;
     auto body = [&]() -> int {
         int r;
-        if ((r = enq_forward(P, psi))) return r;
+        if ((r = enq_forward(P, psi, false))) return r;
         if ((r = enq_sigma(P, psi, lam))) return r;
         HIPCHECK(launch_pool(P.svt, psi, lam, Q->d_ops, Q->d_lists, Q->n, Q->gx, P.nsa, P.nsb, Q->d_part, P.work));
         HIPCHECK(launch_reduce_rows(Q->d_part, Q->d_counts, Q->gx, Q->n, 2.0, Q->d_out, P.work));

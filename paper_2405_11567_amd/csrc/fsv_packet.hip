@@ -28,9 +28,9 @@
 // each load instruction covers 64 consecutive sorted indices), applies the run there (forward:
 // rotations in order; adjoint: for the last operator back to the first, the
 // gradient contribution, then psi and lam un-rotated) and scatters them back.
-// The adjoint sweep keeps psi and lam of each amplitude side by side in
-// memory, so a gather or scatter moves both in one access.  Untouched
-// amplitudes are never read.  Consecutive workgroup ids go to
+// The forward sweep also writes each packet's results to a contiguous
+// record; the adjoint sweep reads psi from those records and gathers and
+// scatters only lam.  Untouched amplitudes are never read.  Consecutive workgroup ids go to
 // different XCDs, so packet numbers are remapped to give each XCD a contiguous
 // range of packets: with packets laid out by row group, the packets that
 // share a cache line then share that XCD's L2.
@@ -81,6 +81,29 @@ template <> struct Slot2<float> {
     static __device__ __forceinline__ V make(float a, float b) { return make_float2(a, b); }
 };
 
+// One DPP lane move of a double (two 32-bit moves); lanes of rows outside RM
+// receive 0.
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RM, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RM, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, complete in lane 63: sums within rows of 16 lanes
+// (quad swaps, half-row and row mirrors), then the last lane of row 0 is
+// broadcast into row 1 and of row 2 into row 3, then of row 1 into row 3.
+// Only vector ALU moves: no LDS traffic.
+__device__ __forceinline__ double wave_sum_to_last(double v) {
+    v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_move<0x140, 0xF>(v);  // row_mirror
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ void rotp(T &a, T &b, T c, T s) {
     const T t = a;
@@ -88,10 +111,13 @@ __device__ __forceinline__ void rotp(T &a, T &b, T c, T s) {
     b = c * b + s * t;
 }
 
-// Forward: psi is the state.  Adjoint: z holds (psi, lam) of each amplitude
-// side by side, so one 16-byte (FP32: 8-byte) access moves both.
-template <typename T, bool ADJ, int NQ>
-__global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slot2<T>::V *__restrict__ z,
+// Forward: st is psi; with CK the state after the run is also written, slot
+// by slot, to the packet's record ck[p * 256 + slot] (contiguous).  Adjoint:
+// st is lam; psi after the run comes from the forward sweep's records
+// (contiguous loads, no gather), so only lam is gathered and scattered, and
+// psi is un-rotated in LDS only.
+template <typename T, bool ADJ, int NQ, bool CK>
+__global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ st, T *__restrict__ ck,
                                                const uint32_t *__restrict__ ent,
                                                const uint32_t *__restrict__ reg, PArgs a,
                                                double *__restrict__ gpart) {
@@ -113,7 +139,8 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slo
     const int nq = a.wr >> 2;
     for (int v = blockIdx.x; v < a.n_packets; v += gridDim.x) {
         const int p = xcd_packet(v, a.n_packets);
-        // one round: indices and region (clamped, so every load is in flight at once)
+        // one round: indices, region and (adjoint) the record (clamped, so
+        // every load is in flight at once)
         const uint32_t *es = ent + (size_t)p * kPkt;
         const u32x4 *rs = (const u32x4 *)(reg + (size_t)p * a.wr);
         uint32_t x[4];
@@ -123,16 +150,17 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slo
 #pragma unroll
         for (int i = 0; i < NQ; ++i) q[i] = rs[min(l + i * kWave, nq - 1)];
         T v0[4], v1[4];
+        if (ADJ) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v0[i] = ck[(size_t)p * kPkt + l + i * kWave];
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t xi = x[i] == kNone ? 0u : x[i];
-            if (ADJ) {
-                const V2 zi = z[xi];
-                v0[i] = zi.x;
-                v1[i] = zi.y;
-            } else {
-                v0[i] = psi[xi];
-            }
+            if (ADJ)
+                v1[i] = st[xi];
+            else
+                v0[i] = st[xi];
         }
         __syncthreads();  // the previous packet is out of LDS
         // Unconditional LDS writes: a clamped lane writes the value its
@@ -192,23 +220,23 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slo
             }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (x[i] != kNone) {
-                if (ADJ)
-                    z[x[i]] = tv[l + i * kWave];
-                else
-                    psi[x[i]] = tp[l + i * kWave];
+        for (int i = 0; i < 4; ++i) {
+            if (ADJ) {
+                if (x[i] != kNone) st[x[i]] = tv[l + i * kWave].y;
+            } else {
+                const T r = tp[l + i * kWave];
+                if (x[i] != kNone) st[x[i]] = r;
+                if (CK) ck[(size_t)p * kPkt + l + i * kWave] = r;
             }
+        }
     }
     if (ADJ) {
-        // one butterfly for all operators: independent shuffles per step
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1)
-#pragma unroll
-            for (int jj = 0; jj < kPktMaxOps; ++jj) acc[jj] += __shfl_xor(acc[jj], off, kWave);
 #pragma unroll
         for (int jj = 0; jj < kPktMaxOps; ++jj)
-            if (jj < a.m && l == 0) gpart[(size_t)(a.k0 + a.m - 1 - jj) * a.gstride + blockIdx.x] = acc[jj];
+            if (jj < a.m) {
+                const double t = wave_sum_to_last(acc[jj]);
+                if (l == kWave - 1) gpart[(size_t)(a.k0 + a.m - 1 - jj) * a.gstride + blockIdx.x] = t;
+            }
     }
 }
 
@@ -249,7 +277,10 @@ __global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, cons
         __syncthreads();
         const int64_t base = (int64_t)rg[kBHdr] | ((int64_t)rg[kBHdr + 1] << 32);
         const int64_t dim = rg[kBHdr + 2];
-        const int k0 = (int)rg[kBHdr + 3], m = (int)rg[kBHdr + 4], slot = (int)rg[kBHdr + 5];
+        // the same for every lane: keep them scalar
+        const int k0 = __builtin_amdgcn_readfirstlane((int)rg[kBHdr + 3]);
+        const int m = __builtin_amdgcn_readfirstlane((int)rg[kBHdr + 4]);
+        const int slot = __builtin_amdgcn_readfirstlane((int)rg[kBHdr + 5]);
         double *psi = arena + base, *lam = psi + dim;
         {
             const int t = min(l, max(2 * m - 1, 0));
@@ -315,12 +346,11 @@ __global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, cons
             }
         if (ADJ) {
 #pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1)
-#pragma unroll
-                for (int jj = 0; jj < kPktMaxOps; ++jj) acc[jj] += __shfl_xor(acc[jj], off, kWave);
-#pragma unroll
             for (int jj = 0; jj < kPktMaxOps; ++jj)
-                if (jj < m && l == 0) gpart[(size_t)(k0 + m - 1 - jj) * pstride + slot] = acc[jj];
+                if (jj < m) {
+                    const double t = wave_sum_to_last(acc[jj]);
+                    if (l == kWave - 1) gpart[(size_t)(k0 + m - 1 - jj) * pstride + slot] = t;
+                }
         }
     }
 }
@@ -592,7 +622,7 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
                   const FusedOpts &o, FusedSched &S) {
     S.release();
     PacketPlan pp;
-    int rc = plan_packets(nsa, nsb, pops, lists, o, false, pp);
+    int rc = plan_packets(nsa, nsb, pops, lists, o, true, pp);
     if (rc) return rc;
     S.groups = std::move(pp.groups);
     S.count = std::move(pp.count);
@@ -600,27 +630,43 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
         S.release();
         return rc;
     }
+    // records of the forward sweep: one value per slot of every packet
+    const size_t bytes = std::max<size_t>(pp.ent.size(), 1) * (size_t)o.es;
+    void *ck = nullptr;
+    if (hipMalloc(&ck, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        S.release();
+        return fail(FSV_ENOMEM, "hipMalloc of %zu bytes for packet records failed", bytes);
+    }
+    S.mem.emplace_back(ck, [](void *q) { (void)hipFree(q); });
+    S.d_ckpt = ck;
     S.packets = true;
     return FSV_OK;
 }
 
 namespace {
 
-template <typename T, bool ADJ>
-hipError_t pkt_impl(void *state, const FusedSched &S, const FGroup &g, const double *cs, double *gpart,
-                    int gstride, hipStream_t st) {
-    using V2 = typename Slot2<T>::V;
+template <typename T, bool ADJ, bool CK>
+hipError_t pkt_impl(T *st, T *ck, const FusedSched &S, const FGroup &g, const double *cs, double *gpart, int gstride,
+                    hipStream_t stream) {
     PArgs a{g.k0, g.nops, g.wr, g.n_packets, gstride, cs};
     const uint32_t *ent = S.d_aprog + g.ent_off, *reg = S.d_bprog + g.reg_off;
     const size_t shm = sizeof(double) * kPktScalars + (size_t)kPkt * (ADJ ? 2 : 1) * sizeof(T) + (size_t)g.wr * 4;
     const dim3 grid((unsigned)std::min(g.n_packets, max_grid())), block(kWave);
-    T *psi = ADJ ? nullptr : (T *)state;
-    V2 *z = ADJ ? (V2 *)state : nullptr;
     if (g.wr <= 4 * kWave * 2)
-        hipLaunchKernelGGL((k_pkt<T, ADJ, 2>), grid, block, shm, st, psi, z, ent, reg, a, gpart);
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 2, CK>), grid, block, shm, stream, st, ck, ent, reg, a, gpart);
     else  // wr <= kPktMaxWords
-        hipLaunchKernelGGL((k_pkt<T, ADJ, 4>), grid, block, shm, st, psi, z, ent, reg, a, gpart);
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 4, CK>), grid, block, shm, stream, st, ck, ent, reg, a, gpart);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pkt_dispatch(bool adjoint, void *state, bool record, const FusedSched &S, const FGroup &g,
+                        const double *cs, double *gpart, int gstride, hipStream_t stream) {
+    T *st = (T *)state, *ck = (T *)S.d_ckpt + g.ent_off;
+    if (adjoint) return pkt_impl<T, true, true>(st, ck, S, g, cs, gpart, gstride, stream);
+    if (record) return pkt_impl<T, false, true>(st, ck, S, g, cs, gpart, gstride, stream);
+    return pkt_impl<T, false, false>(st, nullptr, S, g, cs, gpart, gstride, stream);
 }
 
 }  // namespace
@@ -711,13 +757,11 @@ hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent
     return hipGetLastError();
 }
 
-hipError_t launch_packets(int vtype, bool adjoint, void *state, const FusedSched &S, const FGroup &g,
+hipError_t launch_packets(int vtype, bool adjoint, void *state, bool record, const FusedSched &S, const FGroup &g,
                           const double *cs, double *gpart, int gstride, hipStream_t st) {
-    if (vtype == V_F64)
-        return adjoint ? pkt_impl<double, true>(state, S, g, cs, gpart, gstride, st)
-                       : pkt_impl<double, false>(state, S, g, cs, gpart, gstride, st);
-    return adjoint ? pkt_impl<float, true>(state, S, g, cs, gpart, gstride, st)
-                   : pkt_impl<float, false>(state, S, g, cs, gpart, gstride, st);
+    if (g.n_packets <= 0) return hipSuccess;  // a run whose operators have no pairs here
+    if (vtype == V_F64) return pkt_dispatch<double>(adjoint, state, record, S, g, cs, gpart, gstride, st);
+    return pkt_dispatch<float>(adjoint, state, record, S, g, cs, gpart, gstride, st);
 }
 
 }  // namespace fsv

@@ -184,8 +184,9 @@ def test_fp32_variant_c2(fsv, engine):
 
 @pytest.mark.parametrize("engine", ENGINES)
 def test_edge_cases(fsv, engine):
-    # K = 0, a spin with no electrons, a full shell, the smallest system
-    for (n, ne, k) in [(8, 4, 0), (10, 1, 5), (8, 8, 0), (2, 1, 0), (4, 2, 3)]:
+    # K = 0, a spin with no electrons, a full shell, the smallest system, and a
+    # full alpha shell (alpha-only operators have no pairs in the sector)
+    for (n, ne, k) in [(8, 4, 0), (10, 1, 5), (8, 8, 0), (2, 1, 0), (4, 2, 3), (8, 7, 6)]:
         p = random_problem(n, ne, k if k else None, seed=500 + n + ne, theta_std=0.3,
                            replace=True)
         if k == 0:
@@ -197,6 +198,38 @@ def test_edge_cases(fsv, engine):
         e_ref, g_ref = oracle_energy_grad(p)
         assert abs(e - e_ref) < 1e-10
         assert g.shape == (len(p.ops),) and (len(g) == 0 or np.abs(g - g_ref).max() < 1e-9)
+
+
+def test_reverse_stage_needs_recorded_forward(fsv):
+    # the adjoint sweep of packet runs reads psi from the records of the last
+    # forward sweep: it is refused until a recording forward sweep of the
+    # current angles has run, and new angles or an energy-only pass that
+    # uploads angles invalidate them again
+    p = config("C2")
+    plan = fsv.Plan(p)
+    psi, lam = plan.new_state(), plan.new_state()
+    assert (plan.runs(adjoint=True)[1] > 0).all()  # every operator in a packet run
+    e_ref, g_ref = oracle_energy_grad(p)
+    plan.set_theta(p.theta)
+    with pytest.raises(fsv.FsvError) as ei:
+        plan.reverse_async(psi, lam)
+    assert ei.value.code == -4
+    for _ in range(2):
+        plan.set_theta(p.theta)
+        plan.forward_async(psi)
+        plan.sigma_async(psi, lam)
+        plan.reverse_async(psi, lam)
+        e, g = plan.finish()
+        assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+    plan.energy_grad(p.theta, psi, lam)
+    plan.sigma_async(psi, lam)
+    plan.reverse_async(psi, lam)  # energy_grad's forward sweep recorded
+    e, g = plan.finish()
+    assert np.abs(g - g_ref).max() < 1e-9
+    plan.energy_grad_fd(p.theta[:], 1e-4, psi)
+    with pytest.raises(fsv.FsvError) as ei:
+        plan.reverse_async(psi, lam)
+    assert ei.value.code == -4
 
 
 def test_autograd_energyfn(fsv):
