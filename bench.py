@@ -232,7 +232,8 @@ def run_touched(p, k0, k1):
 
 def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps=5):
     """Roofline of the adjoint packet-run kernel: the adjoint sweep is launched
-    eagerly with HIP events around every run (fsv_time_runs); achieved =
+    eagerly and each packet kernel's own start and end go to HIP events
+    (fsv_time_runs); achieved =
     algorithmic bytes of the packet runs (per touched amplitude: psi read from
     the forward sweep's record, lam read and written) over their measured
     time.  None when the plan has no packet runs."""
@@ -240,8 +241,8 @@ def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps
     k = len(start)
     firsts = [t for t in range(k) if t == 0 or start[t] != start[t - 1]]
     groups = [(k0, (firsts[n + 1] if n + 1 < len(firsts) else k)) for n, k0 in enumerate(firsts)]
-    fused = [n for n, (k0, k1) in enumerate(groups) if tiles[k0] > 0 and k1 - k0 >= 2]
-    if not fused:
+    fused = [n for n, (k0, k1) in enumerate(groups) if tiles[k0] > 0]
+    if not fused or all(groups[n][1] - groups[n][0] < 2 for n in fused):
         return None
     times = []
     for _ in range(reps + 1):
@@ -261,8 +262,10 @@ def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps
             "kernel": "k_pkt<%s, true> (adjoint packet run)" % ("double" if precision == 0 else "float"),
             "avg_launch_us": float(np.mean(ms)) * 1e3,
             "algorithmic_bytes_per_launch": float(np.mean(byts)),
-            "launches_per_eval": len(fused), "operators_fused": int(sum(groups[n][1] - groups[n][0] for n in fused)),
+            "launches_per_eval": len(fused),
+            "operators_fused": int(sum(groups[n][1] - groups[n][0] for n in fused if groups[n][1] - groups[n][0] >= 2)),
             "mean_touched_amplitudes": float(np.mean(amps)),
+            "mean_packets": float(np.mean([tiles[groups[n][0]] for n in fused])),
             "adjoint_sweep_ms": float(med.sum())}
 
 

@@ -138,8 +138,9 @@ int fsv_plan_runs(const fsv_plan *plan, int adjoint, int32_t *run_start, int32_t
  * hold the final state and H psi, as after fsv_forward_async and
  * fsv_sigma_async, with the same requirement as fsv_reverse_async; the runs
  * are applied last to first and the gradient is reduced into the plan's
- * output, readable with fsv_finish) launched without a graph, with HIP events
- * around every run.  ms (host, one float per run of
+ * output, readable with fsv_finish) launched without a graph.  A packet run's
+ * time is its kernel's own duration (events given the kernel's start and end);
+ * any other run's is the time between events recorded around its launches.  ms (host, one float per run of
  * fsv_plan_runs, operator order) receives each run's time in milliseconds.
  * Synchronises the plan's stream.  Returns the number of runs (>= 0), or -1
  * for NULL arguments, -4 on the dense engine, -3 on a HIP error. */

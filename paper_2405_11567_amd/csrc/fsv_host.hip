@@ -434,18 +434,35 @@ void build_exc(int M, const std::vector<uint32_t> &str, const std::vector<int32_
     for (size_t I = 0; I < str.size(); ++I) {
         const uint32_t s = str[I];
         int cnt = 0;
+        // p -> q with q empty first; then the diagonal entries p -> p of the
+        // occupied p, the last popcount(s) entries of the list
         for (int p = 0; p < M; ++p) {
             if (!(s >> p & 1u)) continue;
             for (int q = 0; q < M; ++q) {
-                if (q != p && (s >> q & 1u)) continue;
+                if (s >> q & 1u) continue;
                 const uint32_t J = (s & ~(1u << p)) | (1u << q);
-                const int sg = (q == p) ? 1 : sign_epq(J, p, q);
-                exc.push_back(pack_exc((uint32_t)rank[J], (uint32_t)(p * M + q), sg < 0));
+                exc.push_back(pack_exc((uint32_t)rank[J], (uint32_t)(p * M + q), sign_epq(J, p, q) < 0));
                 ++cnt;
             }
         }
+        for (int p = 0; p < M; ++p)
+            if (s >> p & 1u) {
+                exc.push_back(pack_exc((uint32_t)rank[s], (uint32_t)(p * M + p), false));
+                ++cnt;
+            }
         nexc = cnt;
     }
+}
+
+// Per string I: sum over its occupied p of the factor row Lt[pp][0..rp), the
+// diagonal entries of I's excitation list folded into one (nstr x rp).
+std::vector<double> diag_factor_sums(int M, const std::vector<uint32_t> &str, const std::vector<double> &Lt, int rp) {
+    std::vector<double> d(str.size() * (size_t)rp, 0.0);
+    for (size_t I = 0; I < str.size(); ++I)
+        for (int p = 0; p < M; ++p)
+            if (str[I] >> p & 1u)
+                for (int l = 0; l < rp; ++l) d[I * rp + l] += Lt[(size_t)(p * M + p) * rp + l];
+    return d;
 }
 
 void build_bins(int M, const std::vector<uint32_t> &exc, int nexc, std::vector<int32_t> &off,
@@ -808,35 +825,43 @@ int enq_reverse_dense(fsv_plan &P, void *psi, void *lam) {
 
 // One group of the forward sweep: a fused run in one launch, or its single
 // operator.  record: packet runs also write their records for the adjoint.
-int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g, bool record) {
+// t0, t1 (optional, profiling): a packet run's kernel start and end times, or
+// events recorded before and after the group's launches.
+int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g, bool record, hipEvent_t t0 = nullptr,
+                  hipEvent_t t1 = nullptr) {
     if (g.fused == 2) {
-        HIPCHECK(launch_packets(P.svt, false, c, record, P.ffwd, g, P.d_cs, nullptr, 0, P.work));
+        HIPCHECK(launch_packets(P.svt, false, c, record, P.ffwd, g, P.d_cs, nullptr, 0, P.work, t0, t1));
         return FSV_OK;
     }
+    if (t0) HIPCHECK(hipEventRecord(t0, P.work));
     if (g.fused) {
         HIPCHECK(launch_fused(P.svt, false, c, nullptr, P.ffwd, g, P.d_pops, P.d_cs, P.nsb, nullptr, 0, P.work));
-        return FSV_OK;
+    } else {
+        for (int k = g.k0; k < g.k0 + g.nops; ++k)
+            HIPCHECK(launch_crot(P.svt, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
     }
-    for (int k = g.k0; k < g.k0 + g.nops; ++k)
-        HIPCHECK(launch_crot(P.svt, c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb, P.work));
+    if (t1) HIPCHECK(hipEventRecord(t1, P.work));
     return FSV_OK;
 }
 
 // One group of the adjoint sweep (operators last to first).  A packet run
 // takes psi from the forward sweep's records and updates lam_c only.
-int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g) {
+int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g, hipEvent_t t0 = nullptr,
+                  hipEvent_t t1 = nullptr) {
     const int G = max_grid();
     if (g.fused == 2) {
-        HIPCHECK(launch_packets(P.svt, true, lam_c, false, P.frev, g, P.d_cs, P.d_gpart, G, P.work));
+        HIPCHECK(launch_packets(P.svt, true, lam_c, false, P.frev, g, P.d_cs, P.d_gpart, G, P.work, t0, t1));
         return FSV_OK;
     }
+    if (t0) HIPCHECK(hipEventRecord(t0, P.work));
     if (g.fused) {
         HIPCHECK(launch_fused(P.svt, true, c, lam_c, P.frev, g, P.d_pops, P.d_cs, P.nsb, P.d_gpart, G, P.work));
-        return FSV_OK;
+    } else {
+        for (int k = g.k0 + g.nops - 1; k >= g.k0; --k)
+            HIPCHECK(launch_cadj(P.svt, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
+                                 P.d_gpart + (size_t)k * G, P.work));
     }
-    for (int k = g.k0 + g.nops - 1; k >= g.k0; --k)
-        HIPCHECK(launch_cadj(P.svt, c, lam_c, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
-                             P.d_gpart + (size_t)k * G, P.work));
+    if (t1) HIPCHECK(hipEventRecord(t1, P.work));
     return FSV_OK;
 }
 
@@ -882,12 +907,13 @@ int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
 
 // The forward (adjoint = 0: initial state, then the groups) or adjoint sweep
 // (adjoint = 1: groups last to first on psi, lam, then the gradient reduction)
-// launched eagerly with HIP events around every group; ms[i] = time of group i
-// (operator order).  Synchronises the work stream.
+// launched eagerly; ms[i] = time of group i (operator order): a packet run's
+// kernel time (events that take its start and end), the time between events
+// around the launches of any other group.  Synchronises the work stream.
 int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms) {
     const FusedSched &S = adjoint ? P.frev : P.ffwd;
     const int n = (int)S.groups.size();
-    std::vector<hipEvent_t> ev(n + 1, nullptr);
+    std::vector<hipEvent_t> ev(2 * (size_t)n, nullptr);  // group i: ev[2 i], ev[2 i + 1]
     int rc = FSV_OK;
     for (auto &e : ev)
         if (!rc && hipEventCreate(&e) != hipSuccess) rc = fail(FSV_EDEVICE, "hipEventCreate failed");
@@ -899,20 +925,21 @@ int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms)
         else if (!P.n_init && hipSuccess != launch_set_amp(c, P.svt, 0, P.ref_phase, P.work))
             rc = fail(FSV_EDEVICE, "initial-state launch failed");
     }
-    if (!rc && hipEventRecord(ev[0], P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
     for (int t = 0; t < n && !rc; ++t) {
         const int i = adjoint ? n - 1 - t : t;
-        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i]) : enq_group_fwd(P, c, S.groups[i], true);
-        if (!rc && hipEventRecord(ev[t + 1], P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "event record failed");
+        hipEvent_t t0 = ev[2 * (size_t)i], t1 = ev[2 * (size_t)i + 1];
+        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i], t0, t1)
+                     : enq_group_fwd(P, c, S.groups[i], true, t0, t1);
     }
     if (!rc && adjoint &&
         hipSuccess != launch_reduce_rows(P.d_gpart, P.d_ccount, max_grid(), P.K, 2.0, P.d_out + 1, P.work))
         rc = fail(FSV_EDEVICE, "reduction launch failed");
     if (!rc && hipStreamSynchronize(P.work) != hipSuccess) rc = fail(FSV_EDEVICE, "stream synchronize failed");
-    for (int t = 0; t < n && !rc; ++t) {
+    for (int i = 0; i < n && !rc; ++i) {
         float v = 0.f;
-        if (hipEventElapsedTime(&v, ev[t], ev[t + 1]) != hipSuccess) rc = fail(FSV_EDEVICE, "event timing failed");
-        ms[adjoint ? n - 1 - t : t] = v;
+        if (hipEventElapsedTime(&v, ev[2 * (size_t)i], ev[2 * (size_t)i + 1]) != hipSuccess)
+            rc = fail(FSV_EDEVICE, "event timing failed");
+        ms[i] = v;
     }
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
@@ -1241,12 +1268,16 @@ int build_device(fsv_plan &P) {
     int R = 0;
     std::vector<double> Lt;
     choose_sigma(P, R, Lt);
-    double *d_Lt = nullptr;
+    double *d_Lt = nullptr, *d_lda = nullptr, *d_ldb = nullptr;
     double2 *d_YT = nullptr;
     if (R > 0) {
+        const int rp = lr_pad(R);
+        const std::vector<double> da = diag_factor_sums(M, P.sa, Lt, rp), db = diag_factor_sums(M, P.sb, Lt, rp);
         if ((rc = dalloc(P, &d_Lt, Lt.size()))) return rc;
         if ((rc = upload(P, d_Lt, Lt.data(), Lt.size()))) return rc;
-        if ((rc = dalloc(P, &d_YT, (size_t)lr_pad(R) * P.dim))) return rc;  // complex-sized
+        if ((rc = dalloc(P, &d_lda, da.size())) || (rc = upload(P, d_lda, da.data(), da.size()))) return rc;
+        if ((rc = dalloc(P, &d_ldb, db.size())) || (rc = upload(P, d_ldb, db.data(), db.size()))) return rc;
+        if ((rc = dalloc(P, &d_YT, (size_t)rp * P.dim))) return rc;  // complex-sized
     }
     P.lr_R = R;
     if (want_dense_same_spin(P)) {
@@ -1263,7 +1294,8 @@ int build_device(fsv_plan &P) {
     }
     P.tabs = SectorTabs{P.nsa, P.nsb, M, P.nexcA, P.nexcB, P.d_ha_ptr, P.d_hb_ptr, P.d_ha_col,
                         P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_excBT, P.d_g, P.ecore,
-                        R, d_Lt, d_YT, P.d_ha_dense, P.d_hb_dense, (void *)P.blas, P.d_hb_dense_t};
+                        R, d_Lt, d_YT, P.d_ha_dense, P.d_hb_dense, (void *)P.blas, P.d_hb_dense_t,
+                        d_lda, d_ldb, P.na, P.nb};
     if (P.blas) {
         // one eager product per amplitude type, outside any graph capture, so
         // that the library has loaded its kernels and sized its workspace

@@ -146,6 +146,11 @@ struct SectorTabs {
     // hb_dense transposed (its column-major form): real states add the beta
     // product into S with one untransposed GEMM on it
     const double *hb_dense_t;
+    // With the factorisation: per alpha (beta) string, the factor rows of its
+    // diagonal excitations summed (nsa x RP, nsb x RP).  Each string's list in
+    // excA / excB ends with its ndA (ndB) diagonal entries p -> p.
+    const double *lr_da, *lr_db;
+    int ndA, ndB;
 };
 
 int cadj_blocks(const PairOp &op, int64_t nsa, int64_t nsb);  // partials written by launch_cadj
@@ -285,8 +290,10 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
 // One packet run.  Forward: state = psi; record: also write the run's
 // results to S.d_ckpt.  Adjoint: state = lam, psi from the records of the
 // last recording forward sweep; gradient partials gpart[k * gstride + workgroup].
+// t0, t1 (optional): events given the kernel's own start and end times.
 hipError_t launch_packets(int vtype, bool adjoint, void *state, bool record, const FusedSched &S, const FGroup &g,
-                          const double *cs, double *gpart, int gstride, hipStream_t st);
+                          const double *cs, double *gpart, int gstride, hipStream_t st, hipEvent_t t0 = nullptr,
+                          hipEvent_t t1 = nullptr);
 void init_fused_kernels();
 size_t fused_lds_limit();
 // Forward (psi) or adjoint (psi, lam, gradient partials gpart[k * gstride + tile]).

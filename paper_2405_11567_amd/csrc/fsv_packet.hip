@@ -34,6 +34,7 @@
 // different XCDs, so packet numbers are remapped to give each XCD a contiguous
 // range of packets: with packets laid out by row group, the packets that
 // share a cache line then share that XCD's L2.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -646,27 +647,39 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
 
 namespace {
 
+// t0 / t1 (optional): events that take the kernel's own start and end times.
 template <typename T, bool ADJ, bool CK>
 hipError_t pkt_impl(T *st, T *ck, const FusedSched &S, const FGroup &g, const double *cs, double *gpart, int gstride,
-                    hipStream_t stream) {
+                    hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
     PArgs a{g.k0, g.nops, g.wr, g.n_packets, gstride, cs};
     const uint32_t *ent = S.d_aprog + g.ent_off, *reg = S.d_bprog + g.reg_off;
-    const size_t shm = sizeof(double) * kPktScalars + (size_t)kPkt * (ADJ ? 2 : 1) * sizeof(T) + (size_t)g.wr * 4;
+    const uint32_t shm =
+        (uint32_t)(sizeof(double) * kPktScalars + (size_t)kPkt * (ADJ ? 2 : 1) * sizeof(T) + (size_t)g.wr * 4);
     const dim3 grid((unsigned)std::min(g.n_packets, max_grid())), block(kWave);
-    if (g.wr <= 4 * kWave * 2)
+    const bool narrow = g.wr <= 4 * kWave * 2;  // else wr <= kPktMaxWords
+    if (t0 || t1) {
+        if (narrow)
+            hipExtLaunchKernelGGL(k_pkt<T, ADJ, 2, CK>, grid, block, shm, stream, t0, t1, 0u, st, ck, ent, reg, a,
+                                  gpart);
+        else
+            hipExtLaunchKernelGGL(k_pkt<T, ADJ, 4, CK>, grid, block, shm, stream, t0, t1, 0u, st, ck, ent, reg, a,
+                                  gpart);
+    } else if (narrow) {
         hipLaunchKernelGGL((k_pkt<T, ADJ, 2, CK>), grid, block, shm, stream, st, ck, ent, reg, a, gpart);
-    else  // wr <= kPktMaxWords
+    } else {
         hipLaunchKernelGGL((k_pkt<T, ADJ, 4, CK>), grid, block, shm, stream, st, ck, ent, reg, a, gpart);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t pkt_dispatch(bool adjoint, void *state, bool record, const FusedSched &S, const FGroup &g,
-                        const double *cs, double *gpart, int gstride, hipStream_t stream) {
+                        const double *cs, double *gpart, int gstride, hipStream_t stream, hipEvent_t t0,
+                        hipEvent_t t1) {
     T *st = (T *)state, *ck = (T *)S.d_ckpt + g.ent_off;
-    if (adjoint) return pkt_impl<T, true, true>(st, ck, S, g, cs, gpart, gstride, stream);
-    if (record) return pkt_impl<T, false, true>(st, ck, S, g, cs, gpart, gstride, stream);
-    return pkt_impl<T, false, false>(st, nullptr, S, g, cs, gpart, gstride, stream);
+    if (adjoint) return pkt_impl<T, true, true>(st, ck, S, g, cs, gpart, gstride, stream, t0, t1);
+    if (record) return pkt_impl<T, false, true>(st, ck, S, g, cs, gpart, gstride, stream, t0, t1);
+    return pkt_impl<T, false, false>(st, nullptr, S, g, cs, gpart, gstride, stream, t0, t1);
 }
 
 }  // namespace
@@ -758,10 +771,16 @@ hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent
 }
 
 hipError_t launch_packets(int vtype, bool adjoint, void *state, bool record, const FusedSched &S, const FGroup &g,
-                          const double *cs, double *gpart, int gstride, hipStream_t st) {
-    if (g.n_packets <= 0) return hipSuccess;  // a run whose operators have no pairs here
-    if (vtype == V_F64) return pkt_dispatch<double>(adjoint, state, record, S, g, cs, gpart, gstride, st);
-    return pkt_dispatch<float>(adjoint, state, record, S, g, cs, gpart, gstride, st);
+                          const double *cs, double *gpart, int gstride, hipStream_t st, hipEvent_t t0,
+                          hipEvent_t t1) {
+    if (g.n_packets <= 0) {  // a run whose operators have no pairs here: no launch
+        hipError_t e = hipSuccess;
+        if (t0) e = hipEventRecord(t0, st);
+        if (t1 && e == hipSuccess) e = hipEventRecord(t1, st);
+        return e;
+    }
+    if (vtype == V_F64) return pkt_dispatch<double>(adjoint, state, record, S, g, cs, gpart, gstride, st, t0, t1);
+    return pkt_dispatch<float>(adjoint, state, record, S, g, cs, gpart, gstride, st, t0, t1);
 }
 
 }  // namespace fsv

@@ -456,12 +456,17 @@ __global__ __launch_bounds__(1024) void k_lr_b(const A *__restrict__ Y, A *__res
 // then step 2 runs on it as in k_lr_b.  Y never goes to memory.  Rows are
 // kLrStride = 9 doubles apart (72 bytes: lanes' 8-byte reads start in 32
 // different bank pairs), which keeps two workgroups per CU at 24 qubits.
+// A string's diagonal excitations (the last ndA / ndB entries of its list)
+// all map it to itself, so each step takes them as one term with the
+// string's summed factor row (da / db).
 constexpr int kLrStride = 9;
 
 __global__ __launch_bounds__(1024) void k_lr_ab(const double *__restrict__ C, double *__restrict__ S,
                                                 const uint32_t *__restrict__ excA, int nexcA,
                                                 const uint32_t *__restrict__ excBT, int nexcB,
-                                                const double *__restrict__ Lt, int M2, int64_t nsb) {
+                                                const double *__restrict__ Lt, int M2, int64_t nsb,
+                                                const double *__restrict__ da, const double *__restrict__ db,
+                                                int ndA, int ndB) {
     constexpr int RP = 8;
     extern __shared__ double smem_d[];
     double *lt = smem_d;                // M2 x kLrStride
@@ -469,12 +474,17 @@ __global__ __launch_bounds__(1024) void k_lr_ab(const double *__restrict__ C, do
     const int64_t Ia = blockIdx.x;
     for (int i = threadIdx.x; i < M2 * RP; i += blockDim.x) lt[(i / RP) * kLrStride + i % RP] = Lt[i];
     const uint32_t *ex = excA + Ia * nexcA;
+    const int noffA = nexcA - ndA, noffB = nexcB - ndB;
+    const double *dar = da + Ia * RP;
     for (int64_t Jb = threadIdx.x; Jb < nsb; Jb += blockDim.x) {
         double acc[RP];
+        {
+            const double xv = C[Ia * nsb + Jb];
 #pragma unroll
-        for (int l = 0; l < RP; ++l) acc[l] = 0.0;
+            for (int l = 0; l < RP; ++l) acc[l] = dar[l] * xv;
+        }
         int e = 0;
-        for (; e + 4 <= nexcA; e += 4) {
+        for (; e + 4 <= noffA; e += 4) {
             double x[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) x[u] = C[(int64_t)(ex[e + u] & 0xFFFFu) * nsb + Jb];
@@ -487,7 +497,7 @@ __global__ __launch_bounds__(1024) void k_lr_ab(const double *__restrict__ C, do
                 for (int l = 0; l < RP; ++l) axpy(acc[l], lr[l], xv);
             }
         }
-        for (; e < nexcA; ++e) {
+        for (; e < noffA; ++e) {
             const uint32_t ea = ex[e];
             const double *lr = Lt + ((ea >> 16) & 0x1FFu) * RP;
             const double xv = neg_if((ea >> 31) != 0, C[(int64_t)(ea & 0xFFFFu) * nsb + Jb]);
@@ -501,6 +511,12 @@ __global__ __launch_bounds__(1024) void k_lr_ab(const double *__restrict__ C, do
     double *srow = S + Ia * nsb;
     for (int64_t Ib = threadIdx.x; Ib < nsb; Ib += blockDim.x) {
         double acc = 0.0;
+        {
+            const double *dbr = db + Ib * RP;
+            const double *y = yr + Ib * kLrStride;
+#pragma unroll
+            for (int l = 0; l < RP; ++l) axpy(acc, dbr[l], y[l]);
+        }
         auto step = [&](uint32_t eb) {
             const double *w = lt + ((eb >> 16) & 0x1FFu) * kLrStride;
             const double *y = yr + (int64_t)(eb & 0xFFFFu) * kLrStride;
@@ -510,14 +526,14 @@ __global__ __launch_bounds__(1024) void k_lr_ab(const double *__restrict__ C, do
             acc += neg_if((eb >> 31) != 0, t);
         };
         int f = 0;
-        for (; f + kExcBatchAB <= nexcB; f += kExcBatchAB) {
+        for (; f + kExcBatchAB <= noffB; f += kExcBatchAB) {
             uint32_t eb[kExcBatchAB];
 #pragma unroll
             for (int u = 0; u < kExcBatchAB; ++u) eb[u] = excBT[(int64_t)(f + u) * nsb + Ib];
 #pragma unroll
             for (int u = 0; u < kExcBatchAB; ++u) step(eb[u]);
         }
-        for (; f < nexcB; ++f) step(excBT[(int64_t)f * nsb + Ib]);
+        for (; f < noffB; ++f) step(excBT[(int64_t)f * nsb + Ib]);
         srow[Ib] += acc;
     }
 }
@@ -719,7 +735,8 @@ hipError_t lr_launch(const SectorTabs &T, const A *C, A *S, hipStream_t st) {
     if (lr_fused_ok<A, RP>(T)) {
         const size_t shm = (size_t)(T.M * T.M + T.nsb) * kLrStride * sizeof(double);
         hipLaunchKernelGGL(k_lr_ab, dim3((unsigned)T.nsa), dim3(1024), shm, st, (const double *)C, (double *)S,
-                           T.excA, T.nexcA, T.excBT, T.nexcB, T.Lt, T.M * T.M, T.nsb);
+                           T.excA, T.nexcA, T.excBT, T.nexcB, T.Lt, T.M * T.M, T.nsb, T.lr_da, T.lr_db, T.ndA,
+                           T.ndB);
         return hipGetLastError();
     }
     A *Y = (A *)T.YT;
