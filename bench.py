@@ -233,16 +233,15 @@ def run_touched(p, k0, k1):
 def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps=5):
     """Roofline of the adjoint packet-run kernel: the adjoint sweep is launched
     eagerly and each packet kernel's own start and end go to HIP events
-    (fsv_time_runs); achieved =
-    algorithmic bytes of the packet runs (per touched amplitude: psi read from
-    the forward sweep's record, lam read and written) over their measured
+    (fsv_time_runs); achieved = algorithmic bytes of the packet runs (their
+    touched amplitudes, psi and lam, read and written) over their measured
     time.  None when the plan has no packet runs."""
     start, tiles = plan.runs(adjoint=True)
     k = len(start)
     firsts = [t for t in range(k) if t == 0 or start[t] != start[t - 1]]
     groups = [(k0, (firsts[n + 1] if n + 1 < len(firsts) else k)) for n, k0 in enumerate(firsts)]
     fused = [n for n, (k0, k1) in enumerate(groups) if tiles[k0] > 0]
-    if not fused or all(groups[n][1] - groups[n][0] < 2 for n in fused):
+    if not fused:
         return None
     times = []
     for _ in range(reps + 1):
@@ -254,7 +253,7 @@ def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps
     med = np.median(np.array(times[1:]), axis=0)
     es = 8 if precision == 0 else 4
     amps = [run_touched(p, *groups[n]) for n in fused]
-    byts = [3.0 * es * a for a in amps]  # psi read; lam read and written
+    byts = [4.0 * es * a for a in amps]  # psi and lam, read and written
     ms = [float(med[n]) for n in fused]
     achieved = sum(byts) / (sum(ms) * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -263,7 +262,7 @@ def packet_roofline(fsv, torch, plan, p, precision, psi, lam, traffic=None, reps
             "avg_launch_us": float(np.mean(ms)) * 1e3,
             "algorithmic_bytes_per_launch": float(np.mean(byts)),
             "launches_per_eval": len(fused),
-            "operators_fused": int(sum(groups[n][1] - groups[n][0] for n in fused if groups[n][1] - groups[n][0] >= 2)),
+            "operators_fused": int(sum(groups[n][1] - groups[n][0] for n in fused)),
             "mean_touched_amplitudes": float(np.mean(amps)),
             "mean_packets": float(np.mean([tiles[groups[n][0]] for n in fused])),
             "adjoint_sweep_ms": float(med.sum())}

@@ -36,8 +36,7 @@
  *    O(2^n) memory.  The plan owns only O(K + n_orb^4 + sector) tables and a
  *    sector-sized workspace (the (n_alpha, n_beta) sector is the only part of
  *    the state that the operators above ever make nonzero), plus, with packet
- *    runs (fsv_plan_runs), their programs and one recorded value per packet
- *    slot (about the number of runs times the sector size).
+ *    runs (fsv_plan_runs), their programs (indices and pairs of each packet).
  *  - Every function returns FSV_OK (0) or a negative status, never throws and
  *    never exits.  fsv_last_error() returns a thread-local message for the last
  *    failure on the calling thread.
@@ -136,12 +135,12 @@ int fsv_plan_runs(const fsv_plan *plan, int adjoint, int32_t *run_start, int32_t
 /* Profiling: the sector engine's forward sweep (adjoint = 0: psi is
  * initialised, then every run) or adjoint sweep (adjoint = 1: psi and lam must
  * hold the final state and H psi, as after fsv_forward_async and
- * fsv_sigma_async, with the same requirement as fsv_reverse_async; the runs
- * are applied last to first and the gradient is reduced into the plan's
- * output, readable with fsv_finish) launched without a graph.  A packet run's
- * time is its kernel's own duration (events given the kernel's start and end);
- * any other run's is the time between events recorded around its launches.  ms (host, one float per run of
- * fsv_plan_runs, operator order) receives each run's time in milliseconds.
+ * fsv_sigma_async; the runs are applied last to first and the gradient is
+ * reduced into the plan's output, readable with fsv_finish) launched without a
+ * graph.  A packet run's time is its kernel's own duration (events given the
+ * kernel's start and end); any other run's is the time between events recorded
+ * around its launches.  ms (host, one float per run of fsv_plan_runs, operator
+ * order) receives each run's time in milliseconds.
  * Synchronises the plan's stream.  Returns the number of runs (>= 0), or -1
  * for NULL arguments, -4 on the dense engine, -3 on a HIP error. */
 int fsv_time_runs(fsv_plan *plan, int adjoint, void *psi_dev, void *lam_dev, float *ms);
@@ -159,9 +158,7 @@ int energy(fsv_plan *plan, const void *psi_dev, double *E_out);
 /* Energy of psi(theta) and its gradient dE/dtheta_k by the adjoint method:
  * after the forward sweep lam = H psi, then for k = K..1
  * grad_k = 2 Re <lam| (tau_k - tau_k^+) |psi>, psi <- U_k^+ psi,
- * lam <- U_k^+ lam (no per-operator state is stored: with packet runs the
- * forward sweep records psi after each run on the amplitudes the run touches,
- * and the adjoint sweep un-rotates it within the run).  psi_dev and
+ * lam <- U_k^+ lam (the states are recomputed, never stored).  psi_dev and
  * lam_dev are caller-owned work buffers of fsv_state_bytes each; their
  * contents on return are unspecified.  grad_out: host, K doubles. */
 int energy_grad(fsv_plan *plan, const double *theta, void *psi_dev, void *lam_dev,
@@ -200,13 +197,9 @@ int fsv_set_theta(fsv_plan *plan, const double *theta);
 int fsv_forward_async(fsv_plan *plan, void *psi_dev);
 /* lam <- H psi (zero outside the sector); E on the device. */
 int fsv_sigma_async(fsv_plan *plan, const void *psi_dev, void *lam_dev);
-/* Reverse adjoint sweep over all K operators; per-operator partial sums on the
- * device.  psi must be the forward sweep's result and lam = H psi.  Packet runs
- * take psi from the records that the forward sweep wrote (psi_dev is then not
- * read), so the plan's last forward sweep must be a recording one with the
- * current angles, initial state and schedule (fsv_forward_async, energy_grad,
- * or fsv_time_runs with adjoint = 0): FSV_ESTATE otherwise.  lam_dev (and,
- * without packet runs, psi_dev) are overwritten. */
+/* Reverse adjoint sweep over all K operators (psi = the forward sweep's
+ * result, lam = H psi); per-operator partial sums on the device.  The contents
+ * of psi_dev and lam_dev on return are unspecified. */
 int fsv_reverse_async(fsv_plan *plan, void *psi_dev, void *lam_dev);
 /* Reduce the partial sums, copy E and grad to the host and wait. */
 int fsv_finish(fsv_plan *plan, double *E_out, double *grad_out);

@@ -280,7 +280,6 @@ void FusedSched::release() {
     count.clear();
     d_aprog = d_bprog = nullptr;
     packets = false;
-    d_ckpt = nullptr;
 }
 
 int build_fused(int M, const std::vector<uint32_t> &sa, const std::vector<uint32_t> &sb,

@@ -115,6 +115,7 @@ struct fsv_plan {
     int32_t *d_ha_desc = nullptr, *d_hb_desc = nullptr;                   // one-body descriptors
     uint32_t *d_str_a = nullptr, *d_str_b = nullptr;                      // string masks
     int32_t *d_binA_off = nullptr, *d_binA_idx = nullptr, *d_binB_off = nullptr, *d_binB_idx = nullptr;
+    // d_C also holds the interleaved (psi, lam) pairs of a packet adjoint sweep
     double2 *d_C = nullptr, *d_S = nullptr, *d_CT = nullptr, *d_ST = nullptr, *d_O = nullptr;
     double2 *d_gamma = nullptr;
     double *h_pin = nullptr;  // pinned: cs (2K) then out (K + 1) then gamma (4 M^2)
@@ -153,9 +154,6 @@ struct fsv_plan {
     // graphs
     uint64_t gen = 0;  // bumped whenever captured launches may have changed
     bool use_graph = true;
-    // packet runs: the records hold the forward sweep of the current angles,
-    // initial state and schedule (a recording forward sweep was enqueued last)
-    bool records_ok = false;
     hipGraphExec_t g_eg = nullptr;
     const void *g_eg_psi = nullptr, *g_eg_lam = nullptr;
     hipGraphExec_t g_e = nullptr;
@@ -753,7 +751,6 @@ int upload_counts(fsv_plan &P) {
 
 void drop_graphs(fsv_plan &P) {
     ++P.gen;  // graphs of pools built on this plan are stale too
-    P.records_ok = false;
     if (P.g_eg) (void)hipGraphExecDestroy(P.g_eg);
     if (P.g_e) (void)hipGraphExecDestroy(P.g_e);
     P.g_eg = nullptr;
@@ -824,13 +821,11 @@ int enq_reverse_dense(fsv_plan &P, void *psi, void *lam) {
 }
 
 // One group of the forward sweep: a fused run in one launch, or its single
-// operator.  record: packet runs also write their records for the adjoint.
-// t0, t1 (optional, profiling): a packet run's kernel start and end times, or
-// events recorded before and after the group's launches.
-int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g, bool record, hipEvent_t t0 = nullptr,
-                  hipEvent_t t1 = nullptr) {
+// operator.  t0, t1 (optional, profiling): a packet run's kernel start and end
+// times, or events recorded before and after the group's launches.
+int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
     if (g.fused == 2) {
-        HIPCHECK(launch_packets(P.svt, false, c, record, P.ffwd, g, P.d_cs, nullptr, 0, P.work, t0, t1));
+        HIPCHECK(launch_packets(P.svt, false, c, P.ffwd, g, P.d_cs, nullptr, 0, P.work, t0, t1));
         return FSV_OK;
     }
     if (t0) HIPCHECK(hipEventRecord(t0, P.work));
@@ -844,13 +839,22 @@ int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g, bool record, hipEvent_t
     return FSV_OK;
 }
 
-// One group of the adjoint sweep (operators last to first).  A packet run
-// takes psi from the forward sweep's records and updates lam_c only.
+// One group of the adjoint sweep (operators last to first).  Packet
+// schedules run on the interleaved pairs z in d_C (c and lam_c are unused).
 int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g, hipEvent_t t0 = nullptr,
                   hipEvent_t t1 = nullptr) {
     const int G = max_grid();
-    if (g.fused == 2) {
-        HIPCHECK(launch_packets(P.svt, true, lam_c, false, P.frev, g, P.d_cs, P.d_gpart, G, P.work, t0, t1));
+    if (P.frev.packets) {
+        void *z = P.d_C;
+        if (g.fused) {
+            HIPCHECK(launch_packets(P.svt, true, z, P.frev, g, P.d_cs, P.d_gpart, G, P.work, t0, t1));
+            return FSV_OK;
+        }
+        if (t0) HIPCHECK(hipEventRecord(t0, P.work));
+        for (int k = g.k0 + g.nops - 1; k >= g.k0; --k)
+            HIPCHECK(launch_cadj_zip(P.svt, z, P.pops[k], P.d_plists, P.d_cs, k, P.nsa, P.nsb,
+                                     P.d_gpart + (size_t)k * G, P.work));
+        if (t1) HIPCHECK(hipEventRecord(t1, P.work));
         return FSV_OK;
     }
     if (t0) HIPCHECK(hipEventRecord(t0, P.work));
@@ -868,7 +872,7 @@ int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g, hipEvent_t
 // ---- sector-compressed engine: the state is C[Ia][Ib] in the first
 // nsa*nsb amplitudes of the caller's buffer.  With real angles and real
 // integrals every amplitude stays real, so it is stored real (FP64 or FP32). ----
-int enq_forward_sector(fsv_plan &P, void *c, bool record) {
+int enq_forward_sector(fsv_plan &P, void *c) {
     HIPCHECK(launch_fill_zero(c, (size_t)P.dim * vtype_bytes(P.svt), P.work));
     // The reference is string 0 x string 0.  Its alpha-first amplitude carries
     // the ordering sign so that the dense image starts at exactly +1 |ref>.
@@ -877,7 +881,7 @@ int enq_forward_sector(fsv_plan &P, void *c, bool record) {
     else
         HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
     for (const FGroup &g : P.ffwd.groups) {
-        const int rc = enq_group_fwd(P, c, g, record);
+        const int rc = enq_group_fwd(P, c, g);
         if (rc) return rc;
     }
     return FSV_OK;
@@ -893,10 +897,13 @@ int enq_sigma_sector(fsv_plan &P, const void *c, void *lam_c) {
     return FSV_OK;
 }
 
-// Packet schedules read psi from the records of the last recording forward
-// sweep (c is not touched); other schedules un-rotate c in place.
+// Packet schedules first interleave psi and lam into d_C (2 dim values of
+// the state's type, within its dim double2), so that each gather of the packet
+// kernels moves both; psi and lam are then left as they were.  Other
+// schedules un-rotate c and lam_c in place.
 int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
     const int G = max_grid();
+    if (P.frev.packets) HIPCHECK(launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work));
     for (auto it = P.frev.groups.rbegin(); it != P.frev.groups.rend(); ++it) {
         const int rc = enq_group_rev(P, c, lam_c, *it);
         if (rc) return rc;
@@ -925,11 +932,12 @@ int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms)
         else if (!P.n_init && hipSuccess != launch_set_amp(c, P.svt, 0, P.ref_phase, P.work))
             rc = fail(FSV_EDEVICE, "initial-state launch failed");
     }
+    if (!rc && adjoint && P.frev.packets && hipSuccess != launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work))
+        rc = fail(FSV_EDEVICE, "interleave launch failed");
     for (int t = 0; t < n && !rc; ++t) {
         const int i = adjoint ? n - 1 - t : t;
         hipEvent_t t0 = ev[2 * (size_t)i], t1 = ev[2 * (size_t)i + 1];
-        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i], t0, t1)
-                     : enq_group_fwd(P, c, S.groups[i], true, t0, t1);
+        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i], t0, t1) : enq_group_fwd(P, c, S.groups[i], t0, t1);
     }
     if (!rc && adjoint &&
         hipSuccess != launch_reduce_rows(P.d_gpart, P.d_ccount, max_grid(), P.K, 2.0, P.d_out + 1, P.work))
@@ -946,10 +954,8 @@ int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms)
     return rc;
 }
 
-// record: the forward sweep of an energy + gradient pass (packet runs keep
-// their results for the adjoint sweep).
-int enq_forward(fsv_plan &P, void *psi, bool record) {
-    return P.engine == 0 ? enq_forward_sector(P, psi, record) : enq_forward_dense(P, psi);
+int enq_forward(fsv_plan &P, void *psi) {
+    return P.engine == 0 ? enq_forward_sector(P, psi) : enq_forward_dense(P, psi);
 }
 
 int enq_sigma(fsv_plan &P, const void *psi, void *lam) {
@@ -964,7 +970,7 @@ int enq_reverse(fsv_plan &P, void *psi, void *lam) {
 // expanded (zero elsewhere) into the caller's 2^n buffer.
 int enq_ansatz_dense_out(fsv_plan &P, void *psi) {
     if (P.engine != 0) return enq_forward_dense(P, psi);
-    int rc = enq_forward_sector(P, P.d_S, false);
+    int rc = enq_forward_sector(P, P.d_S);
     if (rc) return rc;
     const double *S = (const double *)P.d_S;
     if (P.svt == V_F32) {
@@ -979,7 +985,6 @@ int enq_ansatz_dense_out(fsv_plan &P, void *psi) {
 int upload_theta(fsv_plan &P, const double *theta) {
     if (P.K > 0 && !theta) return fail(FSV_EINVAL, "theta is NULL");
     if (!finite_all(theta, (size_t)P.K)) return fail(FSV_ENONFINITE, "non-finite theta");
-    P.records_ok = false;
     double *h = P.h_pin;
     for (int k = 0; k < P.K; ++k) {
         h[2 * k] = std::cos(theta[k]);
@@ -1004,7 +1009,7 @@ typedef int (*enq_fn)(fsv_plan &, void *, void *);
 
 int run_energy_grad_body(fsv_plan &P, void *psi, void *lam) {
     int rc;
-    if ((rc = enq_forward(P, psi, true))) return rc;
+    if ((rc = enq_forward(P, psi))) return rc;
     if ((rc = enq_sigma(P, psi, lam))) return rc;
     if ((rc = enq_reverse(P, psi, lam))) return rc;
     return FSV_OK;
@@ -1012,7 +1017,7 @@ int run_energy_grad_body(fsv_plan &P, void *psi, void *lam) {
 
 int run_energy_body(fsv_plan &P, void *psi) {
     int rc;
-    if ((rc = enq_forward(P, psi, false))) return rc;
+    if ((rc = enq_forward(P, psi))) return rc;
     if ((rc = enq_sigma(P, psi, nullptr))) return rc;
     return FSV_OK;
 }
@@ -1482,25 +1487,14 @@ int fsv_plan_runs(const fsv_plan *P, int adjoint, int32_t *run_start, int32_t *f
     return (int)S.groups.size();
 }
 
-namespace {
-// The adjoint sweep of packet runs reads the forward sweep's records: they
-// must come from the current angles, initial state and schedule.
-int rc_records(const fsv_plan &P) {
-    if (P.engine != 0 || !P.frev.packets || P.frev.groups.empty() || P.records_ok) return FSV_OK;
-    return fail(FSV_ESTATE, "the adjoint sweep needs the forward sweep of the current angles first "
-                            "(fsv_forward_async)");
-}
-}  // namespace
 
 int fsv_time_runs(fsv_plan *P, int adjoint, void *psi, void *lam, float *ms) {
     if (!P || !psi || !ms || (adjoint && !lam)) return fail(FSV_EINVAL, "plan, psi, lam or ms is NULL");
     if (adjoint != 0 && adjoint != 1) return fail(FSV_EINVAL, "adjoint must be 0 or 1");
     if (P->engine != 0) return fail(FSV_ESTATE, "per-run timing is available on the sector engine only");
-    if (adjoint && (rc_records(*P))) return FSV_ESTATE;
     int rc;
     if ((rc = fence_in(*P))) return rc;
     if ((rc = time_sweep_sector(*P, adjoint, psi, lam, ms))) return rc;
-    if (!adjoint) P->records_ok = true;
     if ((rc = fence_out(*P))) return rc;
     return (int)(adjoint ? P->frev : P->ffwd).groups.size();
 }
@@ -1517,8 +1511,7 @@ int fsv_forward_async(fsv_plan *P, void *psi) {
     if (!P || !psi) return fail(FSV_EINVAL, "plan or psi is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
-    if ((rc = enq_forward(*P, psi, true))) return rc;
-    P->records_ok = true;
+    if ((rc = enq_forward(*P, psi))) return rc;
     return fence_out(*P);
 }
 
@@ -1532,7 +1525,6 @@ int fsv_sigma_async(fsv_plan *P, const void *psi, void *lam) {
 
 int fsv_reverse_async(fsv_plan *P, void *psi, void *lam) {
     if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
-    if (rc_records(*P)) return FSV_ESTATE;
     int rc;
     if ((rc = fence_in(*P))) return rc;
     if ((rc = enq_reverse(*P, psi, lam))) return rc;
@@ -1575,7 +1567,6 @@ int energy_grad(fsv_plan *P, const double *theta, void *psi, void *lam, double *
     if ((rc = fence_in(*P))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
     if ((rc = launch_energy_grad(*P, psi, lam))) return rc;
-    P->records_ok = P->engine == 0;
     if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
     return fence_out(*P);
 }
@@ -1911,7 +1902,7 @@ int fsv_pool_gradients(fsv_pool *Q, const double *theta, void *psi, void *lam, d
     if ((rc = upload_theta(P, theta))) return rc;
     auto body = [&]() -> int {
         int r;
-        if ((r = enq_forward(P, psi, false))) return r;
+        if ((r = enq_forward(P, psi))) return r;
         if ((r = enq_sigma(P, psi, lam))) return r;
         HIPCHECK(launch_pool(P.svt, psi, lam, Q->d_ops, Q->d_lists, Q->n, Q->gx, P.nsa, P.nsb, Q->d_part, P.work));
         HIPCHECK(launch_reduce_rows(Q->d_part, Q->d_counts, Q->gx, Q->n, 2.0, Q->d_out, P.work));

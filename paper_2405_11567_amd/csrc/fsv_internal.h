@@ -159,6 +159,11 @@ hipError_t launch_crot(int vtype, void *psi, const PairOp &op, const uint32_t *l
 hipError_t launch_cadj(int vtype, void *psi, void *lam, const PairOp &op, const uint32_t *lists,
                        const double *cs, int k, int64_t nsa, int64_t nsb, double *partial,
                        hipStream_t st);
+// Real sector states (V_F64 / V_F32) only: z[i] = (psi[i], lam[i]) for i < n,
+// and launch_cadj on such interleaved pairs.
+hipError_t launch_zip(int vtype, const void *psi, const void *lam, void *z, int64_t n, hipStream_t st);
+hipError_t launch_cadj_zip(int vtype, void *z, const PairOp &op, const uint32_t *lists, const double *cs, int k,
+                           int64_t nsa, int64_t nsb, double *partial, hipStream_t st);
 // out (vtype_out) <- in (vtype_in), element-wise; complex <-> real keeps the real part.
 hipError_t launch_convert(int vt_in, const void *in, int vt_out, void *out, int64_t n, hipStream_t st);
 // S = H C on the sector; C, S, CT, ST hold nsa*nsb values of type complex
@@ -223,8 +228,7 @@ struct FusedSched {
     std::vector<FGroup> groups;  // in operator order
     std::vector<int> count;      // per operator: gradient partials of its fused run, -1 if not fused
     uint32_t *d_aprog = nullptr, *d_bprog = nullptr;  // packet runs: index lists, regions
-    bool packets = false;        // built by build_packets (every run is a packet run)
-    void *d_ckpt = nullptr;      // packet runs: the forward sweep's records (one value per ent slot)
+    bool packets = false;        // built by build_packets: the adjoint sweep runs on (psi, lam) pairs
     std::vector<std::shared_ptr<void>> mem;  // device buffers (shared by schedules that alias them)
     void release();
     void share(const FusedSched &o) {  // the same runs and device tables as o
@@ -234,7 +238,6 @@ struct FusedSched {
         d_aprog = o.d_aprog;
         d_bprog = o.d_bprog;
         packets = o.packets;
-        d_ckpt = o.d_ckpt;
         mem = o.mem;
     }
     FusedSched() = default;
@@ -287,11 +290,10 @@ hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent
 int64_t packet_max_dim();
 int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
                   const FusedOpts &o, FusedSched &S);
-// One packet run.  Forward: state = psi; record: also write the run's
-// results to S.d_ckpt.  Adjoint: state = lam, psi from the records of the
-// last recording forward sweep; gradient partials gpart[k * gstride + workgroup].
+// One packet run: forward (state = psi) or adjoint (state = the interleaved
+// (psi, lam) pairs of launch_zip; gradient partials gpart[k * gstride + workgroup]).
 // t0, t1 (optional): events given the kernel's own start and end times.
-hipError_t launch_packets(int vtype, bool adjoint, void *state, bool record, const FusedSched &S, const FGroup &g,
+hipError_t launch_packets(int vtype, bool adjoint, void *state, const FusedSched &S, const FGroup &g,
                           const double *cs, double *gpart, int gstride, hipStream_t st, hipEvent_t t0 = nullptr,
                           hipEvent_t t1 = nullptr);
 void init_fused_kernels();

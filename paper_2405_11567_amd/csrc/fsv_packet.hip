@@ -28,9 +28,9 @@
 // each load instruction covers 64 consecutive sorted indices), applies the run there (forward:
 // rotations in order; adjoint: for the last operator back to the first, the
 // gradient contribution, then psi and lam un-rotated) and scatters them back.
-// The forward sweep also writes each packet's results to a contiguous
-// record; the adjoint sweep reads psi from those records and gathers and
-// scatters only lam.  Untouched amplitudes are never read.  Consecutive workgroup ids go to
+// The adjoint sweep keeps psi and lam of each amplitude side by side in
+// memory, so a gather or scatter moves both in one access.  Untouched
+// amplitudes are never read.  Consecutive workgroup ids go to
 // different XCDs, so packet numbers are remapped to give each XCD a contiguous
 // range of packets: with packets laid out by row group, the packets that
 // share a cache line then share that XCD's L2.
@@ -112,13 +112,10 @@ __device__ __forceinline__ void rotp(T &a, T &b, T c, T s) {
     b = c * b + s * t;
 }
 
-// Forward: st is psi; with CK the state after the run is also written, slot
-// by slot, to the packet's record ck[p * 256 + slot] (contiguous).  Adjoint:
-// st is lam; psi after the run comes from the forward sweep's records
-// (contiguous loads, no gather), so only lam is gathered and scattered, and
-// psi is un-rotated in LDS only.
-template <typename T, bool ADJ, int NQ, bool CK>
-__global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ st, T *__restrict__ ck,
+// Forward: psi is the state.  Adjoint: z holds (psi, lam) of each amplitude
+// side by side, so one 16-byte (FP32: 8-byte) access moves both.
+template <typename T, bool ADJ, int NQ>
+__global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slot2<T>::V *__restrict__ z,
                                                const uint32_t *__restrict__ ent,
                                                const uint32_t *__restrict__ reg, PArgs a,
                                                double *__restrict__ gpart) {
@@ -140,8 +137,7 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ st, T *__restrict
     const int nq = a.wr >> 2;
     for (int v = blockIdx.x; v < a.n_packets; v += gridDim.x) {
         const int p = xcd_packet(v, a.n_packets);
-        // one round: indices, region and (adjoint) the record (clamped, so
-        // every load is in flight at once)
+        // one round: indices and region (clamped, so every load is in flight at once)
         const uint32_t *es = ent + (size_t)p * kPkt;
         const u32x4 *rs = (const u32x4 *)(reg + (size_t)p * a.wr);
         uint32_t x[4];
@@ -151,17 +147,16 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ st, T *__restrict
 #pragma unroll
         for (int i = 0; i < NQ; ++i) q[i] = rs[min(l + i * kWave, nq - 1)];
         T v0[4], v1[4];
-        if (ADJ) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v0[i] = ck[(size_t)p * kPkt + l + i * kWave];
-        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t xi = x[i] == kNone ? 0u : x[i];
-            if (ADJ)
-                v1[i] = st[xi];
-            else
-                v0[i] = st[xi];
+            if (ADJ) {
+                const V2 zi = z[xi];
+                v0[i] = zi.x;
+                v1[i] = zi.y;
+            } else {
+                v0[i] = psi[xi];
+            }
         }
         __syncthreads();  // the previous packet is out of LDS
         // Unconditional LDS writes: a clamped lane writes the value its
@@ -221,15 +216,13 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ st, T *__restrict
             }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (ADJ) {
-                if (x[i] != kNone) st[x[i]] = tv[l + i * kWave].y;
-            } else {
-                const T r = tp[l + i * kWave];
-                if (x[i] != kNone) st[x[i]] = r;
-                if (CK) ck[(size_t)p * kPkt + l + i * kWave] = r;
+        for (int i = 0; i < 4; ++i)
+            if (x[i] != kNone) {
+                if (ADJ)
+                    z[x[i]] = tv[l + i * kWave];
+                else
+                    psi[x[i]] = tp[l + i * kWave];
             }
-        }
     }
     if (ADJ) {
 #pragma unroll
@@ -623,7 +616,7 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
                   const FusedOpts &o, FusedSched &S) {
     S.release();
     PacketPlan pp;
-    int rc = plan_packets(nsa, nsb, pops, lists, o, true, pp);
+    int rc = plan_packets(nsa, nsb, pops, lists, o, false, pp);
     if (rc) return rc;
     S.groups = std::move(pp.groups);
     S.count = std::move(pp.count);
@@ -631,16 +624,6 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
         S.release();
         return rc;
     }
-    // records of the forward sweep: one value per slot of every packet
-    const size_t bytes = std::max<size_t>(pp.ent.size(), 1) * (size_t)o.es;
-    void *ck = nullptr;
-    if (hipMalloc(&ck, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        S.release();
-        return fail(FSV_ENOMEM, "hipMalloc of %zu bytes for packet records failed", bytes);
-    }
-    S.mem.emplace_back(ck, [](void *q) { (void)hipFree(q); });
-    S.d_ckpt = ck;
     S.packets = true;
     return FSV_OK;
 }
@@ -648,38 +631,29 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
 namespace {
 
 // t0 / t1 (optional): events that take the kernel's own start and end times.
-template <typename T, bool ADJ, bool CK>
-hipError_t pkt_impl(T *st, T *ck, const FusedSched &S, const FGroup &g, const double *cs, double *gpart, int gstride,
+template <typename T, bool ADJ>
+hipError_t pkt_impl(void *state, const FusedSched &S, const FGroup &g, const double *cs, double *gpart, int gstride,
                     hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
+    using V2 = typename Slot2<T>::V;
     PArgs a{g.k0, g.nops, g.wr, g.n_packets, gstride, cs};
     const uint32_t *ent = S.d_aprog + g.ent_off, *reg = S.d_bprog + g.reg_off;
     const uint32_t shm =
         (uint32_t)(sizeof(double) * kPktScalars + (size_t)kPkt * (ADJ ? 2 : 1) * sizeof(T) + (size_t)g.wr * 4);
     const dim3 grid((unsigned)std::min(g.n_packets, max_grid())), block(kWave);
+    T *psi = ADJ ? nullptr : (T *)state;
+    V2 *z = ADJ ? (V2 *)state : nullptr;
     const bool narrow = g.wr <= 4 * kWave * 2;  // else wr <= kPktMaxWords
     if (t0 || t1) {
         if (narrow)
-            hipExtLaunchKernelGGL(k_pkt<T, ADJ, 2, CK>, grid, block, shm, stream, t0, t1, 0u, st, ck, ent, reg, a,
-                                  gpart);
+            hipExtLaunchKernelGGL(k_pkt<T, ADJ, 2>, grid, block, shm, stream, t0, t1, 0u, psi, z, ent, reg, a, gpart);
         else
-            hipExtLaunchKernelGGL(k_pkt<T, ADJ, 4, CK>, grid, block, shm, stream, t0, t1, 0u, st, ck, ent, reg, a,
-                                  gpart);
+            hipExtLaunchKernelGGL(k_pkt<T, ADJ, 4>, grid, block, shm, stream, t0, t1, 0u, psi, z, ent, reg, a, gpart);
     } else if (narrow) {
-        hipLaunchKernelGGL((k_pkt<T, ADJ, 2, CK>), grid, block, shm, stream, st, ck, ent, reg, a, gpart);
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 2>), grid, block, shm, stream, psi, z, ent, reg, a, gpart);
     } else {
-        hipLaunchKernelGGL((k_pkt<T, ADJ, 4, CK>), grid, block, shm, stream, st, ck, ent, reg, a, gpart);
+        hipLaunchKernelGGL((k_pkt<T, ADJ, 4>), grid, block, shm, stream, psi, z, ent, reg, a, gpart);
     }
     return hipGetLastError();
-}
-
-template <typename T>
-hipError_t pkt_dispatch(bool adjoint, void *state, bool record, const FusedSched &S, const FGroup &g,
-                        const double *cs, double *gpart, int gstride, hipStream_t stream, hipEvent_t t0,
-                        hipEvent_t t1) {
-    T *st = (T *)state, *ck = (T *)S.d_ckpt + g.ent_off;
-    if (adjoint) return pkt_impl<T, true, true>(st, ck, S, g, cs, gpart, gstride, stream, t0, t1);
-    if (record) return pkt_impl<T, false, true>(st, ck, S, g, cs, gpart, gstride, stream, t0, t1);
-    return pkt_impl<T, false, false>(st, nullptr, S, g, cs, gpart, gstride, stream, t0, t1);
 }
 
 }  // namespace
@@ -770,7 +744,7 @@ hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent
     return hipGetLastError();
 }
 
-hipError_t launch_packets(int vtype, bool adjoint, void *state, bool record, const FusedSched &S, const FGroup &g,
+hipError_t launch_packets(int vtype, bool adjoint, void *state, const FusedSched &S, const FGroup &g,
                           const double *cs, double *gpart, int gstride, hipStream_t st, hipEvent_t t0,
                           hipEvent_t t1) {
     if (g.n_packets <= 0) {  // a run whose operators have no pairs here: no launch
@@ -779,8 +753,11 @@ hipError_t launch_packets(int vtype, bool adjoint, void *state, bool record, con
         if (t1 && e == hipSuccess) e = hipEventRecord(t1, st);
         return e;
     }
-    if (vtype == V_F64) return pkt_dispatch<double>(adjoint, state, record, S, g, cs, gpart, gstride, st, t0, t1);
-    return pkt_dispatch<float>(adjoint, state, record, S, g, cs, gpart, gstride, st, t0, t1);
+    if (vtype == V_F64)
+        return adjoint ? pkt_impl<double, true>(state, S, g, cs, gpart, gstride, st, t0, t1)
+                       : pkt_impl<double, false>(state, S, g, cs, gpart, gstride, st, t0, t1);
+    return adjoint ? pkt_impl<float, true>(state, S, g, cs, gpart, gstride, st, t0, t1)
+                   : pkt_impl<float, false>(state, S, g, cs, gpart, gstride, st, t0, t1);
 }
 
 }  // namespace fsv

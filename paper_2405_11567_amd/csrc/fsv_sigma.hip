@@ -188,6 +188,53 @@ __global__ __launch_bounds__(256) void k_cadj(V *__restrict__ psi, V *__restrict
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
+// The adjoint sweep of packet runs keeps psi and lam of each (real) sector
+// amplitude side by side: z[i] = (psi[i], lam[i]).
+template <typename R> struct Zip2;
+template <> struct Zip2<double> { using P = double2; };
+template <> struct Zip2<float> { using P = float2; };
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_zip(const R *__restrict__ psi, const R *__restrict__ lam,
+                                             typename Zip2<R>::P *__restrict__ z, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = {psi[i], lam[i]};
+}
+
+// k_cadj on the interleaved pairs.
+template <typename R>
+__global__ __launch_bounds__(256) void k_cadj_zip(typename Zip2<R>::P *__restrict__ z, PairOp op,
+                                                  const uint32_t *__restrict__ lists,
+                                                  const double *__restrict__ cs, int k, int64_t nsa,
+                                                  int64_t nsb, double *__restrict__ partial) {
+    const R c = (R)cs[2 * k], s = (R)cs[2 * k + 1];
+    const int64_t na = op.nA >= 0 ? op.nA : nsa, nb = op.nB >= 0 ? op.nB : nsb;
+    double acc = 0.0;
+    for (int64_t u = blockIdx.y; u < na; u += gridDim.y) {
+        int64_t ia, ia2;
+        bool nrow;
+        pair_row(op, lists, u, ia, ia2, nrow);
+        for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nb;
+             v += (int64_t)gridDim.x * blockDim.x) {
+            int64_t ib, ib2;
+            bool neg = nrow;
+            pair_col(op, lists, v, ib, ib2, neg);
+            const int64_t xs = ia * nsb + ib, xd = ia2 * nsb + ib2;
+            const auto A = z[xs], B = z[xd];
+            R a = A.x, la = A.y, b = B.x, lb = B.y;
+            const double o = (double)lb * (double)a - (double)la * (double)b;
+            acc += neg ? -o : o;
+            const R sg = neg ? s : -s;  // U^+ = U(-theta)
+            rot(a, b, c, sg);
+            rot(la, lb, c, sg);
+            z[xs] = {a, la};
+            z[xd] = {b, lb};
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
 // ---------------------------------------------------------------- sigma ----
 // out[I][:] = sum_k val[k] in[col[k]][:].  Blocks are dispatched row-fastest
 // over one column tile at a time (blockIdx.x = row, blockIdx.y = tile), so the
@@ -835,6 +882,22 @@ hipError_t cadj_impl(void *psi, void *lam, const PairOp &op, const uint32_t *lis
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t cadj_zip_impl(void *z, const PairOp &op, const uint32_t *lists, const double *cs, int k,
+                         int64_t nsa, int64_t nsb, double *partial, hipStream_t st) {
+    const CGrid g = cgrid_of(op, nsa, nsb);
+    hipLaunchKernelGGL(k_cadj_zip<R>, dim3(g.gx, g.gy), dim3(g.block), 0, st, (typename Zip2<R>::P *)z, op,
+                       lists, cs, k, nsa, nsb, partial);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t zip_impl(const void *psi, const void *lam, void *z, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zip<R>, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const R *)psi, (const R *)lam,
+                       (typename Zip2<R>::P *)z, n);
+    return hipGetLastError();
+}
+
 template <typename I, typename O>
 hipError_t convert_impl(const void *in, void *out, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL((k_convert<I, O>), dim3(blocks_for(n, 256)), dim3(256), 0, st, (const I *)in, (O *)out, n);
@@ -889,6 +952,19 @@ hipError_t launch_cadj(int vt, void *psi, void *lam, const PairOp &op, const uin
     case V_F64: return cadj_impl<double>(psi, lam, op, lists, cs, k, nsa, nsb, partial, st);
     default: return cadj_impl<float>(psi, lam, op, lists, cs, k, nsa, nsb, partial, st);
     }
+}
+
+hipError_t launch_cadj_zip(int vt, void *z, const PairOp &op, const uint32_t *lists, const double *cs, int k,
+                           int64_t nsa, int64_t nsb, double *partial, hipStream_t st) {
+    if (vt == V_F64) return cadj_zip_impl<double>(z, op, lists, cs, k, nsa, nsb, partial, st);
+    if (vt == V_F32) return cadj_zip_impl<float>(z, op, lists, cs, k, nsa, nsb, partial, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_zip(int vt, const void *psi, const void *lam, void *z, int64_t n, hipStream_t st) {
+    if (vt == V_F64) return zip_impl<double>(psi, lam, z, n, st);
+    if (vt == V_F32) return zip_impl<float>(psi, lam, z, n, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_convert(int vi, const void *in, int vo, void *out, int64_t n, hipStream_t st) {
