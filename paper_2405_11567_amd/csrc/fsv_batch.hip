@@ -52,6 +52,9 @@ struct BInst {
     int64_t off_excB;   // beta excitation lists transposed, [f][Ib]
     int64_t off_task;   // first sigma task (row) of this instance
     int64_t off_lt;     // factor table [pq][l] (M^2 x kBLr, zero beyond R)
+    int64_t off_da;     // per alpha string, then per beta string: the factor rows of its
+                        // diagonal excitations summed ((nsa + nsb) x kBLr)
+    int32_t ndA, ndB;   // diagonal entries at the end of each alpha / beta excitation list
     double ecore;
 };
 
@@ -68,6 +71,7 @@ struct BTabs {
     const double *ellv;
     const uint32_t *excA, *excBT;
     const double *lt;
+    const double *ldiag;
 };
 
 using BOp = PairOp;
@@ -143,23 +147,27 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
         // C[Ja_e][Jb] built in LDS, then S[Ib] += sum_f s_f sum_l L_l[rs_f] Y[Jb_f][l]
         double *crow = lds, *acc = lds + nsb, *yr = lds + 2 * nsb, *lt = yr + (int64_t)nsb * kBLrStride;
         const double *ltg = T.lt + I.off_lt;
+        const double *dag = T.ldiag + I.off_da, *dbg = dag + (int64_t)I.nsa * kBLr;
+        const int noffA = I.nexcA - I.ndA, noffB = I.nexcB - I.ndB;
+        double *dal = lt + kBLr;  // Ia's summed diagonal factors, in the unused last column of lt's rows
         __syncthreads();  // earlier readers of lds are done
         for (int j = tid; j < nsb; j += bs) crow[j] = crowg[j];
         for (int t = tid; t < M2 * kBLr; t += bs) lt[(t / kBLr) * kBLrStride + t % kBLr] = ltg[t];
+        if (tid < kBLr) dal[tid * kBLrStride] = dag[(int64_t)Ia * kBLr + tid];  // M2 >= kBLr rows (host)
         __syncthreads();
         // Each loop below takes its list words kB at a time, loads first, so
         // the dependent gathers of a batch are in flight together (the sums
         // keep their order).
-        constexpr int kB = 4;
+        constexpr int kB = 4, kBA = 8;  // alpha rows: coalesced row loads with uniform list words
         for (int ib = tid; ib < nsb; ib += bs) {
             double a = I.ecore * crow[ib];
             int64_t q = q0;
-            for (; q + kB <= q1; q += kB) {
-                double x[kB];
+            for (; q + kBA <= q1; q += kBA) {
+                double x[kBA];
 #pragma unroll
-                for (int u = 0; u < kB; ++u) x[u] = C[(int64_t)T.hcol[q + u] * nsb + ib];
+                for (int u = 0; u < kBA; ++u) x[u] = C[(int64_t)T.hcol[q + u] * nsb + ib];
 #pragma unroll
-                for (int u = 0; u < kB; ++u) a += T.hval[q + u] * x[u];
+                for (int u = 0; u < kBA; ++u) a += T.hval[q + u] * x[u];
             }
             for (; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
             int qb = 0;
@@ -177,10 +185,12 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
             for (; qb < I.wB; ++qb) a += elv[(int64_t)qb * nsb + ib] * crow[elc[(int64_t)qb * nsb + ib]];
             acc[ib] = a;
         }
+        // a string's diagonal excitations (the last of its list) all map it
+        // to itself: one term with its summed factor row
         for (int jb = tid; jb < nsb; jb += bs) {
             double y[kBLr];
 #pragma unroll
-            for (int l = 0; l < kBLr; ++l) y[l] = 0.0;
+            for (int l = 0; l < kBLr; ++l) y[l] = dal[l * kBLrStride] * crow[jb];
             auto step = [&](uint32_t wa, double x) {
                 const double xv = (wa >> 31) ? -x : x;
                 const double *w = lt + ((wa >> 16) & 0x1FFu) * kBLrStride;
@@ -188,16 +198,23 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
                 for (int l = 0; l < kBLr; ++l) y[l] += w[l] * xv;
             };
             int e = 0;
-            for (; e + kB <= I.nexcA; e += kB) {
+            for (; e + kB <= noffA; e += kB) {
                 double x[kB];
 #pragma unroll
                 for (int u = 0; u < kB; ++u) x[u] = C[(int64_t)(exa[e + u] & 0xFFFFu) * nsb + jb];
 #pragma unroll
                 for (int u = 0; u < kB; ++u) step(exa[e + u], x[u]);
             }
-            for (; e < I.nexcA; ++e) step(exa[e], C[(int64_t)(exa[e] & 0xFFFFu) * nsb + jb]);
+            for (; e < noffA; ++e) step(exa[e], C[(int64_t)(exa[e] & 0xFFFFu) * nsb + jb]);
+            // the beta diagonal term of element jb needs only Y[jb]: added here,
+            // by the thread that wrote acc[jb]
+            double dt = 0.0;
 #pragma unroll
-            for (int l = 0; l < kBLr; ++l) yr[(int64_t)jb * kBLrStride + l] = y[l];
+            for (int l = 0; l < kBLr; ++l) {
+                yr[(int64_t)jb * kBLrStride + l] = y[l];
+                dt += dbg[(int64_t)jb * kBLr + l] * y[l];
+            }
+            acc[jb] += dt;
         }
         __syncthreads();
         for (int ib = tid; ib < nsb; ib += bs) {
@@ -211,14 +228,14 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
                 s += (wb >> 31) ? -t : t;
             };
             int f = 0;
-            for (; f + kB <= I.nexcB; f += kB) {
+            for (; f + kB <= noffB; f += kB) {
                 uint32_t wb[kB];
 #pragma unroll
                 for (int u = 0; u < kB; ++u) wb[u] = exb[(int64_t)(f + u) * nsb + ib];
 #pragma unroll
                 for (int u = 0; u < kB; ++u) step(wb[u]);
             }
-            for (; f < I.nexcB; ++f) step(exb[(int64_t)f * nsb + ib]);
+            for (; f < noffB; ++f) step(exb[(int64_t)f * nsb + ib]);
             const double a = acc[ib] + s;
             S[(int64_t)Ia * nsb + ib] = a;
             eacc += crow[ib] * a;
@@ -539,8 +556,8 @@ struct fsv_batch {
     uint32_t *d_pent = nullptr, *d_preg = nullptr;
     int32_t *d_pcount = nullptr;
     double *d_pgpart = nullptr;
-    double *d_lt = nullptr;
-    BTabs tabs() const { return BTabs{d_g, d_hptr, d_hcol, d_hval, d_ellc, d_ellv, d_excA, d_excBT, d_lt}; }
+    double *d_lt = nullptr, *d_ldiag = nullptr;
+    BTabs tabs() const { return BTabs{d_g, d_hptr, d_hcol, d_hval, d_ellc, d_ellv, d_excA, d_excBT, d_lt, d_ldiag}; }
     ~fsv_batch() {
         if (work) (void)hipStreamSynchronize(work);
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -727,7 +744,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
 
     std::vector<BOp> ops;
     std::vector<uint32_t> lists, excA, excBT;
-    std::vector<double> gall, hval, ellv, ltall;
+    std::vector<double> gall, hval, ellv, ltall, ldiag;
     std::vector<int64_t> hptr;
     std::vector<int32_t> hcol, ellc;
     std::vector<double> cost(count);
@@ -796,7 +813,10 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         // reproduced to 1e-12 relative
         I.R = 0;
         I.off_lt = (int64_t)ltall.size();
-        if (!lr_off && I.nexcA > 0 && I.nexcB > 0) {
+        I.off_da = (int64_t)ldiag.size();
+        I.ndA = __builtin_popcount(sa[0]);
+        I.ndB = __builtin_popcount(sb[0]);
+        if (!lr_off && I.nexcA > 0 && I.nexcB > 0 && M * M >= kBLr) {  // (the kernel keeps 8 values in lt's rows)
             const int M2 = M * M;
             std::vector<double> L;
             const int R = pivoted_cholesky(M2, p.g, 1e-14, L);
@@ -814,6 +834,10 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
                     ltall.resize(ltall.size() + (size_t)M2 * kBLr, 0.0);
                     for (int k = 0; k < R; ++k)
                         for (int a = 0; a < M2; ++a) ltall[(size_t)I.off_lt + (size_t)a * kBLr + k] = L[(size_t)k * M2 + a];
+                    const std::vector<double> lt(ltall.begin() + I.off_lt, ltall.end());
+                    const std::vector<double> da = diag_factor_sums(M, sa, lt, kBLr), db = diag_factor_sums(M, sb, lt, kBLr);
+                    ldiag.insert(ldiag.end(), da.begin(), da.end());
+                    ldiag.insert(ldiag.end(), db.begin(), db.end());
                 }
             }
         }
@@ -892,12 +916,13 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         (rc = dmalloc(o, &B->d_ellv, ellv.size())) || (rc = dmalloc(o, &B->d_grad, (size_t)kk)) ||
         (rc = dmalloc(o, &B->d_e, (size_t)count)) || (rc = dmalloc(o, &B->d_arena, (size_t)state)) ||
         (rc = dmalloc(o, &B->d_epart, (size_t)B->ntasks)) || (rc = dmalloc(o, &B->d_lt, std::max<size_t>(ltall.size(), 1))) ||
+        (rc = dmalloc(o, &B->d_ldiag, std::max<size_t>(ldiag.size(), 1))) ||
         (rc = dmalloc(o, &B->d_gpart, (size_t)kk * B->part_cap)))
         return fin(rc);
     B->bytes = sizeof(BInst) * B->inst.size() + sizeof(int) * (count + 4) + 4 * tinst.size() +
                sizeof(BOp) * ops.size() + 4 * (lists.size() + excA.size() + excBT.size() + hcol.size() + ellc.size()) +
                8 * (2 * kk + gall.size() + hval.size() + hptr.size() + ellv.size() + kk + count) +
-               8 * ((size_t)B->ntasks + (size_t)kk * B->part_cap) + 8 * (size_t)state + 8 * ltall.size();
+               8 * ((size_t)B->ntasks + (size_t)kk * B->part_cap) + 8 * (size_t)state + 8 * (ltall.size() + ldiag.size());
     struct Up { void *d; const void *h; size_t n; };
     const Up ups[] = {
         {B->d_order, B->order.data(), sizeof(int) * count},
@@ -913,6 +938,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         {B->d_ellc, ellc.data(), 4 * ellc.size()},
         {B->d_ellv, ellv.data(), 8 * ellv.size()},
         {B->d_lt, ltall.data(), 8 * ltall.size()},
+        {B->d_ldiag, ldiag.data(), 8 * ldiag.size()},
     };
     for (const Up &u : ups)
         if (u.n && hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice) != hipSuccess)

@@ -61,8 +61,13 @@ std::vector<uint32_t> strings_of(int M, int N);  // popcount-N masks, ascending
 void build_string_h(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
                     const double *ht, const double *g, std::vector<int64_t> &ptr,
                     std::vector<int32_t> &col, std::vector<double> &val);
+// Per string (ascending rank): its excitations p -> q, q empty, then its
+// diagonal entries p -> p (the last popcount entries), as packed words.
 void build_exc(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
                std::vector<uint32_t> &exc, int &nexc);
+// Per string: the factor rows Lt[pp][0..rp) of its occupied p summed (its
+// diagonal excitations folded into one), nstr x rp.
+std::vector<double> diag_factor_sums(int M, const std::vector<uint32_t> &str, const std::vector<double> &Lt, int rp);
 // Pivoted Cholesky of a symmetric positive semidefinite n x n matrix:
 // G ~ sum_k L_k L_k^T with R rows of L (length n); returns R, or -1 when G is
 // not positive semidefinite within tol * max(diag).
