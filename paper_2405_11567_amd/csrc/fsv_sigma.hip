@@ -188,8 +188,10 @@ __global__ __launch_bounds__(256) void k_cadj(V *__restrict__ psi, V *__restrict
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
-// The adjoint sweep of packet runs keeps psi and lam of each (real) sector
-// amplitude side by side: z[i] = (psi[i], lam[i]).
+// ---------------------------------------------------------------- sigma ----
+// This section opens with two helpers of the adjoint sweep of packet runs,
+// which keeps psi and lam of each (real) sector amplitude side by side:
+// z[i] = (psi[i], lam[i]).
 template <typename R> struct Zip2;
 template <> struct Zip2<double> { using P = double2; };
 template <> struct Zip2<float> { using P = float2; };
@@ -235,7 +237,6 @@ __global__ __launch_bounds__(256) void k_cadj_zip(typename Zip2<R>::P *__restric
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
-// ---------------------------------------------------------------- sigma ----
 // out[I][:] = sum_k val[k] in[col[k]][:].  Blocks are dispatched row-fastest
 // over one column tile at a time (blockIdx.x = row, blockIdx.y = tile), so the
 // workgroups in flight share the input rows of the same tile in L2.
