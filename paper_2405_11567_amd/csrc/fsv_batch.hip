@@ -55,6 +55,9 @@ struct BInst {
     int64_t off_da;     // per alpha string, then per beta string: the factor rows of its
                         // diagonal excitations summed ((nsa + nsb) x kBLr)
     int32_t ndA, ndB;   // diagonal entries at the end of each alpha / beta excitation list
+    int32_t ssd;        // 1: k_pss computes the same-spin part of S (dense, matrix cores)
+    int64_t off_hd;     // dense alpha string Hamiltonian (nsa x nsa), then the beta one
+                        // transposed (nsb x nsb), both row-major
     double ecore;
 };
 
@@ -104,9 +107,12 @@ __device__ inline uint32_t pairs_of(const BInst &I, const BOp &op) {
 
 // Row Ia of S = H C; returns this thread's share of sum_Ib C[Ia][Ib] S[Ia][Ib].
 // Called by every thread of the workgroup (it synchronises); lds holds at
-// least 2 nsb + (nsb + M^2) ec doubles when ec > 0.
+// least 2 nsb + (nsb + M^2) ec doubles when ec > 0.  SS: k_pss has already
+// written the same-spin part of S (instances with ssd set).
+template <bool SS>
 __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C, double *__restrict__ S,
                             const BTabs &T, double *lds) {
+    constexpr bool ss = SS;
     const int nsb = I.nsb, bs = blockDim.x, tid = threadIdx.x;
     const int M2 = I.M * I.M;
     const double *crowg = C + (int64_t)Ia * nsb;
@@ -122,9 +128,13 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
         for (int ib = tid; ib < nsb; ib += bs) {
             const double x0 = crowg[ib];
             double a = I.ecore * x0;
-            for (int64_t q = q0; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
-            for (int q = 0; q < I.wB; ++q)
-                a += elv[(int64_t)q * nsb + ib] * crowg[elc[(int64_t)q * nsb + ib]];
+            if (ss) {
+                a += S[(int64_t)Ia * nsb + ib];
+            } else {
+                for (int64_t q = q0; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
+                for (int q = 0; q < I.wB; ++q)
+                    a += elv[(int64_t)q * nsb + ib] * crowg[elc[(int64_t)q * nsb + ib]];
+            }
             for (int e = 0; e < I.nexcA; ++e) {
                 const uint32_t wa = exa[e];
                 const double *crj = C + (int64_t)(wa & 0xFFFFu) * nsb;
@@ -161,6 +171,10 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
         constexpr int kB = 4, kBA = 8;  // alpha rows: coalesced row loads with uniform list words
         for (int ib = tid; ib < nsb; ib += bs) {
             double a = I.ecore * crow[ib];
+            if (ss) {
+                acc[ib] = a + S[(int64_t)Ia * nsb + ib];
+                continue;
+            }
             int64_t q = q0;
             for (; q + kBA <= q1; q += kBA) {
                 double x[kBA];
@@ -249,8 +263,12 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
     __syncthreads();
     for (int ib = tid; ib < nsb; ib += bs) {
         double a = I.ecore * crow[ib];
-        for (int64_t q = q0; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
-        for (int q = 0; q < I.wB; ++q) a += elv[(int64_t)q * nsb + ib] * crow[elc[(int64_t)q * nsb + ib]];
+        if (ss) {
+            a += S[(int64_t)Ia * nsb + ib];
+        } else {
+            for (int64_t q = q0; q < q1; ++q) a += T.hval[q] * C[(int64_t)T.hcol[q] * nsb + ib];
+            for (int q = 0; q < I.wB; ++q) a += elv[(int64_t)q * nsb + ib] * crow[elc[(int64_t)q * nsb + ib]];
+        }
         acc[ib] = a;
     }
     for (int e0 = 0; e0 < I.nexcA; e0 += ec) {
@@ -338,7 +356,7 @@ __global__ __launch_bounds__(1024) void k_batch(
         }
 
         double eacc = 0.0;  // lam = H psi, E = <psi|lam>
-        for (int Ia = 0; Ia < I.nsa; ++Ia) eacc += sigma_row(I, Ia, psi, lam, T, lds);
+        for (int Ia = 0; Ia < I.nsa; ++Ia) eacc += sigma_row<false>(I, Ia, psi, lam, T, lds);
         const double E = block_sum(eacc);  // also orders lam before the sweep
 
         for (int k = I.K - 1; k >= 0; --k) {  // reverse adjoint sweep
@@ -402,15 +420,89 @@ __global__ __launch_bounds__(256) void k_pfwd(const BInst *__restrict__ inst, co
     }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Same-spin part of S = H C for instances with ssd set, on the FP64 matrix
+// cores: S = Ha C + C Hb^T (Ha, Hb^T dense row-major, nsa x nsa and nsb x nsb;
+// C, S row-major nsa x nsb in the arena).  One wavefront per 32 x 32 tile
+// (task = instance, first row, first column), as 2 x 2 blocks of the 16 x 16
+// x 4 FP64 MFMA: lane l feeds A[l % 16][l / 16] and B[l / 16][l % 16] of each
+// step and holds D[4 r + l / 16][l % 16] in its result element r < 4 (checked
+// on the device lane by lane).  Operands
+// outside the matrices are read as zero (masked loads), and only the tile's
+// entries inside S are written.
+constexpr int kPssTile = 32;
+constexpr int kPssK = 4;  // k steps per round: all their loads in flight before the MFMAs
+
+__global__ __launch_bounds__(kWave) void k_pss(const BInst *__restrict__ inst, const int32_t *__restrict__ tasks,
+                                               const double *__restrict__ hd, double *__restrict__ arena) {
+    const int32_t *t = tasks + 3 * (int64_t)blockIdx.x;
+    const BInst &I = inst[t[0]];
+    const int m0 = t[1], n0 = t[2];
+    const int nsa = I.nsa, nsb = I.nsb;
+    const double *C = arena + I.off_state;
+    double *S = arena + I.off_state + I.dim;
+    const double *Ha = hd + I.off_hd, *Hbt = Ha + (int64_t)nsa * nsa;
+    const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // two products over their own inner dimension: (A, lda, B, ldb, K)
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        const double *A = part == 0 ? Ha : C;
+        const double *B = part == 0 ? C : Hbt;
+        const int K = part == 0 ? nsa : nsb, lda = K;
+        for (int k0 = 0; k0 < K; k0 += 4 * kPssK) {
+            double a[kPssK][2], b[kPssK][2];
+#pragma unroll
+            for (int u = 0; u < kPssK; ++u) {
+                const int kk = k0 + 4 * u + lk;
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi) {
+                    const int m = m0 + 16 * bi + li;
+                    a[u][bi] = (m < nsa && kk < K) ? A[(int64_t)m * lda + kk] : 0.0;
+                }
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    const int n = n0 + 16 * bj + li;
+                    b[u][bj] = (kk < K && n < nsb) ? B[(int64_t)kk * nsb + n] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kPssK; ++u)
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+                        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][bi], b[u][bj], acc[bi][bj], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + 16 * bi + 4 * r + lk, n = n0 + 16 * bj + li;
+                if (m < nsa && n < nsb) S[(int64_t)m * nsb + n] = acc[bi][bj][r];
+            }
+}
+
+// Row tasks task0 + blockIdx.x.  SS: the launch covers only instances with
+// ssd set, after k_pss (their same-spin part of S is in place).
+template <bool SS>
 __global__ __launch_bounds__(256) void k_psigma(const BInst *__restrict__ inst, const int32_t *__restrict__ tinst,
                                                 BTabs T, double *__restrict__ arena,
-                                                double *__restrict__ epart) {
+                                                double *__restrict__ epart, int64_t task0) {
     extern __shared__ double lds[];
-    const int task = blockIdx.x;
+    const int64_t task = task0 + blockIdx.x;
     const BInst I = inst[tinst[task]];
     const double *psi = arena + I.off_state;
     double *lam = arena + I.off_state + I.dim;
-    const double e = block_sum(sigma_row(I, task - (int)I.off_task, psi, lam, T, lds));
+    const double e = block_sum(sigma_row<SS>(I, (int)(task - I.off_task), psi, lam, T, lds));
     if (threadIdx.x == 0) epart[task] = e;
 }
 
@@ -521,6 +613,7 @@ struct fsv_batch {
     int count = 0;
     int64_t total_k = 0;
     int64_t ntasks = 0;  // sigma row tasks = sum of the alpha string counts
+    int64_t ntasks_ss = 0;  // the first ntasks_ss of them belong to instances with ssd set
     std::vector<BInst> inst;
     std::vector<int> order;
     std::vector<void *> owned;
@@ -548,6 +641,10 @@ struct fsv_batch {
     int kmax = 0;
     double *d_epart = nullptr, *d_gpart = nullptr;
     size_t part_cap = 0;  // workgroups per instance the gradient partials hold
+    // dense same-spin products (k_pss) of the instances with ssd set
+    double *d_hd = nullptr;
+    int32_t *d_pss = nullptr;  // tasks: instance, first row, first column
+    int64_t n_pss = 0;
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;
     // packet runs (mode 2): one launch per run index, the runs of all instances
@@ -608,6 +705,22 @@ int set_lds_budget(fsv_batch &B, size_t budget) {
     return FSV_OK;
 }
 
+// H C of every instance: the dense same-spin products of the instances with
+// ssd set, their rows, then the rows of the others.
+hipError_t launch_sigma(fsv_batch &B, const BTabs &T) {
+    if (B.n_pss > 0) {
+        hipLaunchKernelGGL(k_pss, dim3((unsigned)B.n_pss), dim3(kWave), 0, B.work, B.d_inst, B.d_pss, B.d_hd,
+                           B.d_arena);
+        hipLaunchKernelGGL(k_psigma<true>, dim3((unsigned)B.ntasks_ss), dim3(256), B.lds_bytes, B.work, B.d_inst,
+                           B.d_tinst, T, B.d_arena, B.d_epart, (int64_t)0);
+    }
+    const int64_t rest = B.ntasks - (B.n_pss > 0 ? B.ntasks_ss : 0);
+    if (rest > 0)
+        hipLaunchKernelGGL(k_psigma<false>, dim3((unsigned)rest), dim3(256), B.lds_bytes, B.work, B.d_inst,
+                           B.d_tinst, T, B.d_arena, B.d_epart, B.ntasks - rest);
+    return hipGetLastError();
+}
+
 int enqueue(fsv_batch &B) {
     const BTabs T = B.tabs();
     if (B.total_k) {
@@ -623,9 +736,7 @@ int enqueue(fsv_batch &B) {
         for (int r = 0; r < P.runs; ++r)
             BHIP(launch_batch_packets(false, B.d_arena, B.d_pent + P.ent_off[r], B.d_preg + P.reg_off[r], P.wr[r],
                                       P.npk[r], B.d_cs, nullptr, P.pstride, B.work));
-        hipLaunchKernelGGL(k_psigma, dim3((unsigned)B.ntasks), dim3(256), B.lds_bytes, B.work, B.d_inst,
-                           B.d_tinst, T, B.d_arena, B.d_epart);
-        BHIP(hipGetLastError());
+        BHIP(launch_sigma(B, T));
         for (int r = P.runs - 1; r >= 0; --r)
             BHIP(launch_batch_packets(true, B.d_arena, B.d_pent + P.ent_off[r], B.d_preg + P.reg_off[r], P.wr[r],
                                       P.npk[r], B.d_cs, B.d_pgpart, P.pstride, B.work));
@@ -643,9 +754,7 @@ int enqueue(fsv_batch &B) {
                                B.d_arena, k);
             BHIP(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_psigma, dim3((unsigned)B.ntasks), dim3(256), B.lds_bytes, B.work, B.d_inst,
-                           B.d_tinst, T, B.d_arena, B.d_epart);
-        BHIP(hipGetLastError());
+        BHIP(launch_sigma(B, T));
         for (int k = B.kmax - 1; k >= 0; --k) {
             hipLaunchKernelGGL(k_prev, grid, dim3(256), 0, B.work, B.d_inst, B.d_ops, B.d_lists, B.d_cs,
                                B.d_arena, k, B.d_gpart);
@@ -737,6 +846,10 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     if (const char *m = std::getenv("FSV_BATCH_MODE"))
         env_mode = std::strcmp(m, "persistent") == 0 ? 0 : (std::strcmp(m, "packets") == 0 ? 2 : 1);
     bool lr_off = false;
+    // same-spin products: dense on the matrix cores (default) or sparse rows
+    // (FSV_BATCH_SAME_SPIN=sparse)
+    const char *ssm = std::getenv("FSV_BATCH_SAME_SPIN");
+    const bool ss_sparse = ssm && std::strcmp(ssm, "sparse") == 0;
     if (const char *m = std::getenv("FSV_BATCH_SIGMA")) {
         B->force_global = std::strcmp(m, "global") == 0;
         lr_off = std::strcmp(m, "direct") == 0;
@@ -744,7 +857,8 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
 
     std::vector<BOp> ops;
     std::vector<uint32_t> lists, excA, excBT;
-    std::vector<double> gall, hval, ellv, ltall, ldiag;
+    std::vector<double> gall, hval, ellv, ltall, ldiag, hdense;
+    std::vector<int32_t> pss;
     std::vector<int64_t> hptr;
     std::vector<int32_t> hcol, ellc;
     std::vector<double> cost(count);
@@ -782,9 +896,25 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         hcol.insert(hcol.end(), col.begin(), col.end());
         hval.insert(hval.end(), val.begin(), val.end());
         const double nnz_a = (double)col.size() / std::max(1, I.nsa);
+        // dense copies for the matrix-core same-spin product, on instances
+        // with at least one full 16 x 16 block each way
+        I.ssd = !ss_sparse && I.nsa >= 16 && I.nsb >= 16;
+        I.off_hd = (int64_t)hdense.size();
+        if (I.ssd) {
+            hdense.resize(hdense.size() + (size_t)I.nsa * I.nsa + (size_t)I.nsb * I.nsb, 0.0);
+            for (int r = 0; r < I.nsa; ++r)
+                for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) hdense[(size_t)(I.off_hd + (int64_t)r * I.nsa + col[q])] = val[q];
+        }
         // beta string Hamiltonian as transposed ELL: slot q of row Ib at [q][Ib],
         // padded with zero weights on the diagonal
         build_string_h(M, sb, rb, p.h, p.g, ptr, col, val);
+        if (I.ssd) {  // Hb transposed: Hbt[Jb][Ib] = Hb[Ib][Jb]
+            const int64_t o = I.off_hd + (int64_t)I.nsa * I.nsa;
+            for (int r = 0; r < I.nsb; ++r)
+                for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) hdense[(size_t)(o + (int64_t)col[q] * I.nsb + r)] = val[q];
+            for (int m0 = 0; m0 < I.nsa; m0 += kPssTile)
+                for (int n0 = 0; n0 < I.nsb; n0 += kPssTile) pss.insert(pss.end(), {i, m0, n0});
+        }
         int w = 0;
         for (int r = 0; r < I.nsb; ++r) w = std::max<int>(w, (int)(ptr[r + 1] - ptr[r]));
         I.wB = w;
@@ -860,12 +990,17 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     B->order.resize(count);
     std::iota(B->order.begin(), B->order.end(), 0);
     std::stable_sort(B->order.begin(), B->order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    // sigma row tasks, most expensive instances first; each instance's rows
-    // are contiguous so its energy partials sum in a fixed order
+    // sigma row tasks: the instances whose same-spin part comes from k_pss
+    // first, then the others, most expensive first within each group; each
+    // instance's rows are contiguous so its energy partials sum in a fixed order
     std::vector<int32_t> tinst;
-    for (int i : B->order) {
-        B->inst[i].off_task = (int64_t)tinst.size();
-        tinst.insert(tinst.end(), (size_t)B->inst[i].nsa, i);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i : B->order) {
+            if ((B->inst[i].ssd != 0) != (pass == 0)) continue;
+            B->inst[i].off_task = (int64_t)tinst.size();
+            tinst.insert(tinst.end(), (size_t)B->inst[i].nsa, i);
+        }
+        if (pass == 0) B->ntasks_ss = (int64_t)tinst.size();
     }
     B->ntasks = (int64_t)tinst.size();
 
@@ -894,7 +1029,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     // dynamic LDS limit of the sigma kernels: a CU's 160 KiB less their static
     // LDS, or the default 64 KiB if the attribute cannot be raised
     B->lds_max = 163840;
-    for (const void *f : {(const void *)k_psigma, (const void *)k_batch}) {
+    for (const void *f : {(const void *)k_psigma<true>, (const void *)k_psigma<false>, (const void *)k_batch}) {
         hipFuncAttributes fa;
         size_t lim = 163840;
         if (hipFuncGetAttributes(&fa, f) == hipSuccess) lim -= fa.sharedSizeBytes;
@@ -917,12 +1052,14 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         (rc = dmalloc(o, &B->d_e, (size_t)count)) || (rc = dmalloc(o, &B->d_arena, (size_t)state)) ||
         (rc = dmalloc(o, &B->d_epart, (size_t)B->ntasks)) || (rc = dmalloc(o, &B->d_lt, std::max<size_t>(ltall.size(), 1))) ||
         (rc = dmalloc(o, &B->d_ldiag, std::max<size_t>(ldiag.size(), 1))) ||
+        (rc = dmalloc(o, &B->d_hd, std::max<size_t>(hdense.size(), 1))) ||
+        (rc = dmalloc(o, &B->d_pss, std::max<size_t>(pss.size(), 1))) ||
         (rc = dmalloc(o, &B->d_gpart, (size_t)kk * B->part_cap)))
         return fin(rc);
     B->bytes = sizeof(BInst) * B->inst.size() + sizeof(int) * (count + 4) + 4 * tinst.size() +
                sizeof(BOp) * ops.size() + 4 * (lists.size() + excA.size() + excBT.size() + hcol.size() + ellc.size()) +
                8 * (2 * kk + gall.size() + hval.size() + hptr.size() + ellv.size() + kk + count) +
-               8 * ((size_t)B->ntasks + (size_t)kk * B->part_cap) + 8 * (size_t)state + 8 * (ltall.size() + ldiag.size());
+               8 * ((size_t)B->ntasks + (size_t)kk * B->part_cap) + 8 * (size_t)state + 8 * (ltall.size() + ldiag.size() + hdense.size()) + 4 * pss.size();
     struct Up { void *d; const void *h; size_t n; };
     const Up ups[] = {
         {B->d_order, B->order.data(), sizeof(int) * count},
@@ -939,7 +1076,10 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         {B->d_ellv, ellv.data(), 8 * ellv.size()},
         {B->d_lt, ltall.data(), 8 * ltall.size()},
         {B->d_ldiag, ldiag.data(), 8 * ldiag.size()},
+        {B->d_hd, hdense.data(), 8 * hdense.size()},
+        {B->d_pss, pss.data(), 4 * pss.size()},
     };
+    B->n_pss = (int64_t)pss.size() / 3;
     for (const Up &u : ups)
         if (u.n && hipMemcpy(u.d, u.h, u.n, hipMemcpyHostToDevice) != hipSuccess)
             return fin(fail(FSV_EDEVICE, "upload failed"));

@@ -19,15 +19,20 @@ def fsv(gpu):
     return m
 
 
+@pytest.mark.parametrize("same_spin", ["dense", "sparse"])
 @pytest.mark.parametrize("sigma", ["lds", "direct", "global"])
 @pytest.mark.parametrize("mode", ["phased", "persistent", "packets"])
-def test_batch_mixed_small(fsv, mode, sigma, monkeypatch):
+def test_batch_mixed_small(fsv, mode, sigma, same_spin, monkeypatch):
     # H C with rows staged in LDS (the alpha-beta term through the factors of
     # (pq|rs) where that is exact and cheaper, or directly), and from global
-    # memory only (the path taken by rows too long for LDS)
+    # memory only (the path taken by rows too long for LDS); same-spin parts on
+    # the matrix cores (instances of at least 16 x 16 strings: 20 x 20, 35 x 35,
+    # 56 x 70 here, so partial tiles and inner dimensions) or as sparse rows
     monkeypatch.setenv("FSV_BATCH_MODE", mode)
     if sigma != "lds":
         monkeypatch.setenv("FSV_BATCH_SIGMA", sigma)
+    if same_spin == "sparse":
+        monkeypatch.setenv("FSV_BATCH_SAME_SPIN", "sparse")
     probs = []
     shapes = [(4, 2, 3), (6, 3, 10), (8, 4, 26), (8, 1, 5), (10, 7, 20), (12, 6, 40), (12, 4, 30),
               (10, 5, 0), (14, 7, 25), (6, 6, 0), (16, 9, 30)]
@@ -39,7 +44,7 @@ def test_batch_mixed_small(fsv, mode, sigma, monkeypatch):
             p.theta = np.zeros(0)
         p.e_core = 0.1 * i
         probs.append(p)
-    say("batch mixed", len(probs), mode, sigma)
+    say("batch mixed", len(probs), mode, sigma, same_spin)
     b = fsv.Batch(probs)
     e, g = b.energy_grad([p.theta for p in probs])
     for i, p in enumerate(probs):
