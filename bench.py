@@ -424,7 +424,9 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     b = fsv.Batch(probs, device=dev)
-    thetas = [p.theta for p in probs]
+    # all angles as one flat array (the batch's own layout), so that a step
+    # times the library call and not per-instance array marshalling
+    thetas = np.concatenate([p.theta for p in probs])
     tune = b.autotune() if args.tune else ""
     if tune:
         print(tune, file=sys.stderr, flush=True)

@@ -313,20 +313,34 @@ class Batch:
         self._lib = lib
         self.count = len(problems)
         self.bytes = int(lib.fsv_batch_bytes(handle))
+        self._total = int(sum(self.n_ops))
+        self._offsets = [0] + np.cumsum(self.n_ops).tolist()
 
     def energy_grad(self, thetas):
-        th = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64).reshape(-1)
-                                                  for t in thetas]))
-        if th.size != sum(self.n_ops):
+        """Energies and gradients of every instance.  thetas: one angle array
+        per instance (the gradients come back the same way), or one flat
+        float64 array of all angles in instance order (the gradients come back
+        as one flat array)."""
+        flat = isinstance(thetas, np.ndarray) and thetas.ndim == 1
+        if flat:
+            th = np.ascontiguousarray(thetas, dtype=np.float64)
+        else:
+            try:  # one C-level concatenation when every entry is already 1-D
+                th = np.concatenate(thetas).astype(np.float64, copy=False)
+            except ValueError:
+                th = None
+            if th is None or th.ndim != 1:
+                th = np.concatenate([np.asarray(t, dtype=np.float64).reshape(-1) for t in thetas]) \
+                    if len(thetas) else np.zeros(0)
+        if th.size != self._total:
             raise ValueError("theta sizes do not match the batch")
-        e = np.zeros(self.count)
-        g = np.zeros(th.size)
+        e = np.empty(self.count)
+        g = np.empty(th.size)
         check(self._lib.fsv_batch_energy_grad(self._h, _dptr(th), _dptr(e), _dptr(g)))
-        out, off = [], 0
-        for k in self.n_ops:
-            out.append(g[off:off + k])
-            off += k
-        return e, out
+        if flat:
+            return e, g
+        o = self._offsets
+        return e, [g[o[i]:o[i + 1]] for i in range(self.count)]
 
     def autotune(self) -> str:
         rep = ctypes.c_char_p()

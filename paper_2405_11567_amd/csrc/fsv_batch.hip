@@ -432,7 +432,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // outside the matrices are read as zero (masked loads), and only the tile's
 // entries inside S are written.
 constexpr int kPssTile = 32;
-constexpr int kPssK = 4;  // k steps per round: all their loads in flight before the MFMAs
+constexpr int kPssK = 8;  // k steps per round: all their loads in flight before the MFMAs
 
 __global__ __launch_bounds__(kWave) void k_pss(const BInst *__restrict__ inst, const int32_t *__restrict__ tasks,
                                                const double *__restrict__ hd, double *__restrict__ arena) {

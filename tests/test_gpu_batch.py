@@ -72,6 +72,8 @@ def test_batch_c4_full(fsv, mode, monkeypatch):
     assert worst_e < 1e-10 and worst_g < 1e-9
     e2, g2 = b.energy_grad(thetas)
     assert np.array_equal(e, e2) and all(np.array_equal(a, c) for a, c in zip(g, g2))
+    ef, gf = b.energy_grad(np.concatenate(thetas))  # flat angles in, flat gradients out
+    assert np.array_equal(ef, e) and np.array_equal(gf, np.concatenate(g))
     rep = b.autotune()
     say(rep)
     e3, g3 = b.energy_grad(thetas)
