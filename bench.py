@@ -173,11 +173,10 @@ def rotation_source_hash():
 
 
 def packet_source_hash():
-    """sha256 (16 hex digits) of the packet kernel's device code (the file up
-    to its host-side union-find)."""
+    """sha256 (16 hex digits) of the packet source file: its kernels and the
+    host code that forms runs and packs components (both set the traffic)."""
     import hashlib
-    text = open(PACKET_SOURCE).read()
-    return hashlib.sha256(text[: text.index("// ---- host: union-find")].encode()).hexdigest()[:16]
+    return hashlib.sha256(open(PACKET_SOURCE, "rb").read()).hexdigest()[:16]
 
 
 def traffic_from_profile(workload, path=TRAFFIC_PROFILE, source_hash=rotation_source_hash):

@@ -441,6 +441,108 @@ int upload_words(const std::vector<uint32_t> &vec, FusedSched &S, uint32_t **dst
     return FSV_OK;
 }
 
+// Packing of whole components into packets of at most kPkt amplitudes.  A
+// packet is started with the first unpacked component in `order` (row group
+// by row group), then grown greedily with the component that shares the most
+// 128-byte lines of the 8-byte state (16 amplitudes) with what the packet
+// already holds (ties: earlier in `order`), or, when no such component fits,
+// with the earliest unpacked one in `order` that fits (a queue per size).
+// Every component touching a line lies in the line's row group, so packets
+// still follow the group order.  pk_of[c] = packet of component c; returns
+// the packet count.
+struct PackScratch {
+    std::vector<int32_t> cstart, cmem, lstart, lcomp, pos, score, cand, plines, cnt;
+    std::vector<uint8_t> done, lin;
+    std::vector<std::vector<int32_t>> bysize;  // unpacked components of each size, in order
+    std::vector<size_t> head;
+};
+
+int pack_by_lines(const std::vector<int32_t> &tv, UnionFind &uf, const std::vector<int32_t> &csize,
+                  const std::vector<int32_t> &order, std::vector<int32_t> &pk_of, PackScratch &w) {
+    const int nc = (int)csize.size();
+    constexpr int kLineShift = 4;
+    pk_of.assign(nc, -1);
+    if (nc == 0) return 0;
+    // lines of each component (ascending, distinct): tv is sorted, so a
+    // component's members arrive in ascending order
+    w.cstart.assign(nc + 1, 0);
+    for (int32_t x : tv) ++w.cstart[uf.comp[uf.find(x)] + 1];
+    for (int c = 0; c < nc; ++c) w.cstart[c + 1] += w.cstart[c];
+    w.cmem.assign(tv.size(), 0);
+    w.cnt.assign(w.cstart.begin(), w.cstart.end() - 1);
+    for (int32_t x : tv) {
+        const int c = uf.comp[uf.find(x)];
+        const int32_t ln = x >> kLineShift;
+        const int at = w.cnt[c];
+        if (at == w.cstart[c] || w.cmem[at - 1] != ln) w.cmem[w.cnt[c]++] = ln;
+    }
+    // line -> components (CSR over the lines that occur)
+    const int32_t nl = (tv.back() >> kLineShift) + 1;
+    w.lstart.assign((size_t)nl + 1, 0);
+    for (int c = 0; c < nc; ++c)
+        for (int t = w.cstart[c]; t < w.cnt[c]; ++t) ++w.lstart[w.cmem[t] + 1];
+    for (int32_t l = 0; l < nl; ++l) w.lstart[l + 1] += w.lstart[l];
+    w.lcomp.assign(w.lstart[nl], 0);
+    std::vector<int32_t> &lfill = w.plines;  // reused as a cursor per line
+    lfill.assign(w.lstart.begin(), w.lstart.end() - 1);
+    for (int c = 0; c < nc; ++c)
+        for (int t = w.cstart[c]; t < w.cnt[c]; ++t) w.lcomp[lfill[w.cmem[t]]++] = c;
+    w.pos.assign(nc, 0);
+    for (int t = 0; t < nc; ++t) w.pos[order[t]] = t;
+    w.done.assign(nc, 0);
+    w.score.assign(nc, 0);
+    w.lin.assign((size_t)nl, 0);
+    w.plines.clear();
+    w.bysize.assign(kPkt + 1, {});
+    w.head.assign(kPkt + 1, 0);
+    for (int t = 0; t < nc; ++t) w.bysize[csize[order[t]]].push_back(order[t]);
+    int npk = 0;
+    size_t si = 0;
+    while (true) {
+        while (si < (size_t)nc && w.done[order[si]]) ++si;
+        if (si == (size_t)nc) break;
+        const int p = npk++;
+        int fill = 0;
+        w.cand.clear();
+        auto add = [&](int c) {
+            w.done[c] = 1;
+            pk_of[c] = p;
+            fill += csize[c];
+            for (int t = w.cstart[c]; t < w.cnt[c]; ++t) {
+                const int32_t ln = w.cmem[t];
+                if (w.lin[ln]) continue;
+                w.lin[ln] = 1;
+                w.plines.push_back(ln);
+                for (int32_t u = w.lstart[ln]; u < w.lstart[ln + 1]; ++u) {
+                    const int d = w.lcomp[u];
+                    if (!w.done[d] && w.score[d]++ == 0) w.cand.push_back(d);
+                }
+            }
+        };
+        add(order[si]);
+        while (fill < kPkt) {
+            int best = -1;
+            for (int d : w.cand)
+                if (!w.done[d] && fill + csize[d] <= kPkt &&
+                    (best < 0 || w.score[d] > w.score[best] || (w.score[d] == w.score[best] && w.pos[d] < w.pos[best])))
+                    best = d;
+            if (best < 0)  // the earliest unpacked component (in order) that fits
+                for (int sz = 1; sz <= kPkt - fill; ++sz) {
+                    std::vector<int32_t> &q = w.bysize[sz];
+                    size_t &h = w.head[sz];
+                    while (h < q.size() && w.done[q[h]]) ++h;
+                    if (h < q.size() && (best < 0 || w.pos[q[h]] < w.pos[best])) best = q[h];
+                }
+            if (best < 0) break;
+            add(best);
+        }
+        for (int d : w.cand) w.score[d] = 0;
+        for (int32_t ln : w.plines) w.lin[ln] = 0;
+        w.plines.clear();
+    }
+    return npk;
+}
+
 }  // namespace
 
 int64_t packet_max_dim() { return (int64_t)1 << 22; }
@@ -467,6 +569,7 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
     const int max_ops = std::min(o.max_ops, kPktMaxOps);
     std::vector<uint32_t> &ent = S.ent, &reg = S.reg;
     std::vector<int32_t> csize, crow, order, pk_of, pfill, cnt, cur;
+    PackScratch pk;
     std::vector<int32_t> slot(N, 0), rpar(nsa);
     auto single = [&](int k) {
         FGroup s{};
@@ -539,16 +642,7 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
         for (size_t c = 0; c < order.size(); ++c) order[c] = (int32_t)c;
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t u, int32_t v) { return rfind(crow[u]) < rfind(crow[v]); });
-        pk_of.assign(csize.size(), 0);
-        int npk = 0, fill = kPkt;
-        for (int32_t c : order) {
-            if (fill + csize[c] > kPkt) {
-                ++npk;
-                fill = 0;
-            }
-            pk_of[c] = npk - 1;
-            fill += csize[c];
-        }
+        const int npk = pack_by_lines(tv, uf, csize, order, pk_of, pk);
         const size_t e0 = ent.size();
         ent.resize(e0 + (size_t)npk * kPkt, kNone);
         pfill.assign(npk, 0);
