@@ -257,15 +257,22 @@ int fsv_pool_gradients(fsv_pool *pool, const double *theta, void *psi_dev, void 
  * operators; at most 24 qubits: larger systems belong in a plan); all must use
  * precision 0.  Real angles and integrals keep every amplitude real, so the
  * batch stores each instance's sector state as real FP64 in a device arena
- * that it owns.  H C runs as one workgroup per (instance, alpha string) with
- * the row and the alpha-excitation source rows staged in LDS (rows too long
+ * that it owns.  H C: for instances of at least 16 x 16 strings the
+ * same-spin part runs as dense FP64 products on the matrix cores (all such
+ * instances in one launch; FSV_BATCH_SAME_SPIN=sparse keeps them on sparse
+ * rows), then one workgroup per (instance, alpha string) adds the rest with
+ * the row staged in LDS (the alpha-beta term through exact low-rank factors of
+ * (pq|rs) where they exist, FSV_BATCH_SIGMA=direct avoids them; rows too long
  * for the LDS budget, or FSV_BATCH_SIGMA=global, read global memory only).
- * Two launch schemes, chosen by fsv_batch_autotune (or FSV_BATCH_MODE =
- * persistent | phased at creation): a persistent kernel whose workgroups take
- * whole instances from a device work queue, largest first; or phased launches
- * (one per operator index and phase, every instance in each) captured into
- * one graph.  Results are identical to rounding.  Errors: FSV_EINVAL for an
- * invalid instance (the message names it), FSV_ENOMEM, FSV_EDEVICE. */
+ * Three launch schemes, chosen by fsv_batch_autotune (or FSV_BATCH_MODE =
+ * packets | phased | persistent at creation): component-packet runs (the
+ * default when every instance has at most 2^22 sector amplitudes; launch r
+ * carries run r of every instance, runs aligned at their ends); phased
+ * launches (one per operator index and phase, every instance in each), both
+ * captured into one graph; or a persistent kernel whose workgroups take whole
+ * instances from a device work queue, largest first.  Results are identical
+ * to rounding.  Errors: FSV_EINVAL for an invalid instance (the message names
+ * it), FSV_ENOMEM, FSV_EDEVICE. */
 int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count, void *hip_stream);
 int fsv_batch_destroy(fsv_batch *batch);
 /* theta_concat: host, sum_i K_i doubles in instance order.  E_out: host,
