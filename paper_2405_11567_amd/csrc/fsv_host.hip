@@ -872,6 +872,24 @@ int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g, hipEvent_t
 // ---- sector-compressed engine: the state is C[Ia][Ib] in the first
 // nsa*nsb amplitudes of the caller's buffer.  With real angles and real
 // integrals every amplitude stays real, so it is stored real (FP64 or FP32). ----
+// The first forward run acts on the reference state, which is zero except
+// at sector amplitude 0: every other packet maps zeros to zeros, so only the
+// packet holding amplitude 0 is launched (none when the run leaves it alone).
+// Not for a multi-determinant start.  Returns the group to launch (n_packets
+// 0: nothing to launch).
+FGroup first_run_on_reference(const fsv_plan &P, const FGroup &g) {
+    FGroup h = g;
+    if (P.n_init || g.fused != 2 || g.k0 != 0) return h;
+    if (g.ref_pk < 0) {
+        h.n_packets = 0;
+        return h;
+    }
+    h.ent_off += (int64_t)g.ref_pk * kPacketAmps;
+    h.reg_off += (int64_t)g.ref_pk * g.wr;
+    h.n_packets = 1;
+    return h;
+}
+
 int enq_forward_sector(fsv_plan &P, void *c) {
     HIPCHECK(launch_fill_zero(c, (size_t)P.dim * vtype_bytes(P.svt), P.work));
     // The reference is string 0 x string 0.  Its alpha-first amplitude carries
@@ -881,7 +899,7 @@ int enq_forward_sector(fsv_plan &P, void *c) {
     else
         HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
     for (const FGroup &g : P.ffwd.groups) {
-        const int rc = enq_group_fwd(P, c, g);
+        const int rc = enq_group_fwd(P, c, first_run_on_reference(P, g));
         if (rc) return rc;
     }
     return FSV_OK;
@@ -937,7 +955,8 @@ int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms)
     for (int t = 0; t < n && !rc; ++t) {
         const int i = adjoint ? n - 1 - t : t;
         hipEvent_t t0 = ev[2 * (size_t)i], t1 = ev[2 * (size_t)i + 1];
-        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i], t0, t1) : enq_group_fwd(P, c, S.groups[i], t0, t1);
+        rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i], t0, t1)
+                     : enq_group_fwd(P, c, first_run_on_reference(P, S.groups[i]), t0, t1);
     }
     if (!rc && adjoint &&
         hipSuccess != launch_reduce_rows(P.d_gpart, P.d_ccount, max_grid(), P.K, 2.0, P.d_out + 1, P.work))

@@ -199,6 +199,7 @@ hipError_t launch_scatter_real(int precision, void *lam, const double *S, const 
 void init_sigma_kernels();
 
 // ---- fused operator runs on the sector state (fsv_fused.hip, fsv_packet.hip) ----
+constexpr int kPacketAmps = 256;  // amplitudes (index slots) of one packet
 // A run of consecutive operators applied tile by tile in LDS (fused = 1), by
 // connected-component packets (fused = 2), or a single operator left to the
 // per-operator kernels (fused = 0, nops = 1).  A tile run keeps, per alpha
@@ -215,6 +216,7 @@ struct FGroup {
     size_t lds;                  // dynamic LDS bytes of one tile / packet workgroup
     int32_t n_packets, wr;
     int64_t ent_off, reg_off;
+    int32_t ref_pk = -1;         // packet run: the packet holding sector amplitude 0 (-1: none)
 };
 
 struct FusedOpts {

@@ -49,7 +49,7 @@ namespace fsv {
 
 namespace {
 
-constexpr int kPkt = 256;            // amplitudes per packet (4 per lane)
+constexpr int kPkt = kPacketAmps;    // amplitudes per packet (4 per lane)
 constexpr int kPktHdr = 32;          // header words of a region
 constexpr int kPktMaxOps = 15;       // operators per run: 15 x 128 16-bit pairs + header <= kPktMaxWords
 constexpr int kPktMaxWords = 1024;   // region words (header + pairs)
@@ -696,6 +696,7 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
         g.wr = wr;
         g.ent_off = (int64_t)e0;
         g.reg_off = (int64_t)r0;
+        g.ref_pk = tv.front() == 0 ? pk_of[uf.comp[uf.find(0)]] : -1;  // tv is sorted
         g.lds = sizeof(double) * kPktScalars + (size_t)kPkt * 2 * o.es + (size_t)wr * 4;
         const int grid = std::min(npk, max_grid());
         for (int k = i; k < j; ++k) S.count[k] = grid;
