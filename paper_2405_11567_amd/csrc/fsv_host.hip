@@ -872,21 +872,17 @@ int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g, hipEvent_t
 // ---- sector-compressed engine: the state is C[Ia][Ib] in the first
 // nsa*nsb amplitudes of the caller's buffer.  With real angles and real
 // integrals every amplitude stays real, so it is stored real (FP64 or FP32). ----
-// The first forward run acts on the reference state, which is zero except
-// at sector amplitude 0: every other packet maps zeros to zeros, so only the
-// packet holding amplitude 0 is launched (none when the run leaves it alone).
-// Not for a multi-determinant start.  Returns the group to launch (n_packets
-// 0: nothing to launch).
-FGroup first_run_on_reference(const fsv_plan &P, const FGroup &g) {
+// From the reference state the forward sweep's first runs act on a state
+// that is zero outside a few components: every other packet maps zeros to
+// zeros, so only the packets the plan recorded as holding nonzero amplitudes
+// are launched (FGroup::sub_n; none when the run leaves the support alone).
+// Not for a multi-determinant start.
+FGroup forward_run(const fsv_plan &P, const FGroup &g) {
     FGroup h = g;
-    if (P.n_init || g.fused != 2 || g.k0 != 0) return h;
-    if (g.ref_pk < 0) {
-        h.n_packets = 0;
-        return h;
-    }
-    h.ent_off += (int64_t)g.ref_pk * kPacketAmps;
-    h.reg_off += (int64_t)g.ref_pk * g.wr;
-    h.n_packets = 1;
+    if (P.n_init || g.fused != 2 || g.sub_n < 0) return h;
+    h.ent_off = g.sub_ent_off;
+    h.reg_off = g.sub_reg_off;
+    h.n_packets = g.sub_n;
     return h;
 }
 
@@ -899,7 +895,7 @@ int enq_forward_sector(fsv_plan &P, void *c) {
     else
         HIPCHECK(launch_set_amp(c, P.svt, 0, P.ref_phase, P.work));
     for (const FGroup &g : P.ffwd.groups) {
-        const int rc = enq_group_fwd(P, c, first_run_on_reference(P, g));
+        const int rc = enq_group_fwd(P, c, forward_run(P, g));
         if (rc) return rc;
     }
     return FSV_OK;
@@ -956,7 +952,7 @@ int time_sweep_sector(fsv_plan &P, int adjoint, void *c, void *lam_c, float *ms)
         const int i = adjoint ? n - 1 - t : t;
         hipEvent_t t0 = ev[2 * (size_t)i], t1 = ev[2 * (size_t)i + 1];
         rc = adjoint ? enq_group_rev(P, c, lam_c, S.groups[i], t0, t1)
-                     : enq_group_fwd(P, c, first_run_on_reference(P, S.groups[i]), t0, t1);
+                     : enq_group_fwd(P, c, forward_run(P, S.groups[i]), t0, t1);
     }
     if (!rc && adjoint &&
         hipSuccess != launch_reduce_rows(P.d_gpart, P.d_ccount, max_grid(), P.K, 2.0, P.d_out + 1, P.work))

@@ -216,7 +216,12 @@ struct FGroup {
     size_t lds;                  // dynamic LDS bytes of one tile / packet workgroup
     int32_t n_packets, wr;
     int64_t ent_off, reg_off;
-    int32_t ref_pk = -1;         // packet run: the packet holding sector amplitude 0 (-1: none)
+    // Forward sweep from the reference state: while the state is zero outside
+    // a few components, only the packets that hold nonzero amplitudes need to
+    // run.  sub_n >= 0: those packets' programs, copied contiguously at
+    // sub_ent_off / sub_reg_off; -1: launch every packet.
+    int32_t sub_n = -1;
+    int64_t sub_ent_off = 0, sub_reg_off = 0;
 };
 
 struct FusedOpts {

@@ -571,11 +571,17 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
     std::vector<int32_t> csize, crow, order, pk_of, pfill, cnt, cur;
     PackScratch pk;
     std::vector<int32_t> slot(N, 0), rpar(nsa);
+    // support of the forward state from the reference (sector amplitude 0),
+    // followed through the first runs while their nonzero packets are few
+    bool track = !every_run;
+    std::vector<uint8_t> nz, pmark, cmark;
+    if (track) nz.assign(N, 0), nz[0] = 1;
     auto single = [&](int k) {
         FGroup s{};
         s.k0 = k;
         s.nops = 1;
         S.groups.push_back(s);
+        track = false;  // one launch over all its pairs: the support is not followed further
     };
     int i = 0;
     while (i < K) {
@@ -696,7 +702,38 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
         g.wr = wr;
         g.ent_off = (int64_t)e0;
         g.reg_off = (int64_t)r0;
-        g.ref_pk = tv.front() == 0 ? pk_of[uf.comp[uf.find(0)]] : -1;  // tv is sorted
+        if (track) {
+            // packets holding a nonzero amplitude, and the components that
+            // become nonzero (untouched amplitudes keep their values)
+            pmark.assign(npk, 0);
+            cmark.assign(csize.size(), 0);
+            for (int32_t x : tv)
+                if (nz[x]) {
+                    const int c = uf.comp[uf.find(x)];
+                    cmark[c] = 1;
+                    pmark[pk_of[c]] = 1;
+                }
+            int nsel = 0;
+            for (int q = 0; q < npk; ++q) nsel += pmark[q];
+            if (2 * nsel > npk) {
+                track = false;
+            } else {
+                for (int32_t x : tv)
+                    if (cmark[uf.comp[uf.find(x)]]) nz[x] = 1;
+                g.sub_n = nsel;
+                g.sub_ent_off = (int64_t)ent.size();
+                g.sub_reg_off = (int64_t)reg.size();
+                ent.resize(ent.size() + (size_t)nsel * kPkt);
+                reg.resize(reg.size() + (size_t)nsel * wr);
+                for (int q = 0, t = 0; q < npk; ++q)
+                    if (pmark[q]) {
+                        std::copy_n(ent.begin() + e0 + (size_t)q * kPkt, kPkt,
+                                    ent.begin() + g.sub_ent_off + (size_t)t * kPkt);
+                        std::copy_n(reg.begin() + r0 + (size_t)q * wr, wr, reg.begin() + g.sub_reg_off + (size_t)t * wr);
+                        ++t;
+                    }
+            }
+        }
         g.lds = sizeof(double) * kPktScalars + (size_t)kPkt * 2 * o.es + (size_t)wr * 4;
         const int grid = std::min(npk, max_grid());
         for (int k = i; k < j; ++k) S.count[k] = grid;
