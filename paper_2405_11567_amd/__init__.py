@@ -8,6 +8,7 @@ PyTorch provides the device buffers and the stream.
 from __future__ import annotations
 
 import ctypes
+import weakref
 
 import numpy as np
 
@@ -69,6 +70,10 @@ class Plan:
                                       ctypes.c_void_p(self.stream.cuda_stream)))
         self._h = handle
         self._lib = lib
+        # pools compiled for this plan: closed before it (a pool reads the
+        # plan when it is destroyed, and a garbage cycle may finalise the
+        # plan first)
+        self._pools = weakref.WeakSet()
         self.state_bytes = int(lib.fsv_state_bytes(handle))
         nsa, nsb, ref = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
         check(lib.fsv_plan_info(handle, ctypes.byref(nsa), ctypes.byref(nsb), ctypes.byref(ref)))
@@ -234,6 +239,8 @@ class Plan:
         return rep.value.decode() if rep.value else ""
 
     def close(self):
+        for q in list(getattr(self, "_pools", ())):
+            q.close()
         if getattr(self, "_h", None):
             check(self._lib.fsv_plan_destroy(self._h))
             self._h = None
@@ -261,6 +268,7 @@ class Pool:
                                             self.excitation))
         self._h = handle
         self._lib = plan._lib
+        plan._pools.add(self)
 
     def gradients(self, theta, psi=None, lam=None):
         """(E(theta), screening values) with psi / lam work buffers of the

@@ -114,6 +114,20 @@ def test_pool_rejects_bad_input(fsv):
     assert ei.value.code == -4
 
 
+def test_plan_close_closes_its_pools(fsv):
+    # a pool reads its plan when destroyed: closing the plan (or a garbage
+    # cycle finalising it first) closes its pools before the plan
+    p = config("C1")
+    plan = fsv.Plan(p)
+    q1, q2 = plan.pool(p.ops), plan.pool(p.ops[:5])
+    e, g = q1.gradients(p.theta)
+    assert np.isfinite(e) and g.shape == (p.n_ops,)
+    plan.close()
+    assert q1._h is None and q2._h is None and plan._h is None
+    q1.close()
+    plan.close()
+
+
 @pytest.mark.parametrize("mode", ["phased", "persistent", "packets"])
 def test_batch_qeb_instances(fsv, monkeypatch, mode):
     monkeypatch.setenv("FSV_BATCH_MODE", mode)
