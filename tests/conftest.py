@@ -27,3 +27,15 @@ def gpu():
         pytest.skip("no GPU visible")
     import torch
     return torch.device("cuda:0")
+
+
+@pytest.fixture(autouse=True)
+def _collect_plans(request):
+    # Plans, pools and batches held by reference cycles (pytest.raises keeps
+    # the test frame alive through the exception's traceback) are destroyed
+    # when the test ends, not at whatever later allocation triggers the
+    # garbage collector.
+    yield
+    if request.node.get_closest_marker("gpu") is not None:
+        import gc
+        gc.collect()
