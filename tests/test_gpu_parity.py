@@ -250,7 +250,7 @@ def test_invalid_arguments(fsv):
     assert ei.value.code == -5
 
 
-@pytest.mark.skip(reason="the test process has crashed after this test's plans (glibc abort in a later plan "
+@pytest.mark.skip(reason="the test process has crashed after this test's plans (SIGABRT in a later plan "
                          "creation or destruction, segfault in the garbage collection at its end) with no GPU "
                          "fault reported; the host-side cause is not found yet")
 @pytest.mark.parametrize("mode", ["direct", "lowrank", "auto"])
