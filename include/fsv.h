@@ -238,9 +238,11 @@ int onebody_expectation(fsv_plan *plan, const void *psi_dev, const double *d, do
  * derivative (Computational Details: ADAPT-VQE with a QEB pool).  For an
  * operator T appended at angle 0 to the plan's ansatz at theta that
  * derivative is <psi| [H, T] |psi> = 2 Re <H psi| T |psi>, psi = psi(theta).
- * fsv_pool_create compiles a pool for a plan (the plan must outlive the pool
- * and use the sector engine): ops is host, n_ops x 4 {a, b, j, i} in the
- * plan's conventions, excitation 0 fermionic / 1 qubit (as in fsv_problem).
+ * fsv_pool_create compiles a pool for a plan (which must use the sector
+ * engine): ops is host, n_ops x 4 {a, b, j, i} in the plan's conventions,
+ * excitation 0 fermionic / 1 qubit (as in fsv_problem).  Pools and plans may
+ * be destroyed in either order: a pool whose plan is gone can still be
+ * destroyed, and fsv_pool_gradients on it returns FSV_ESTATE.
  * Errors: FSV_EINVAL for an invalid operator, FSV_ESTATE for a dense-engine
  * plan, FSV_ENOMEM, FSV_EDEVICE. */
 int fsv_pool_create(fsv_pool **out, fsv_plan *plan, const int32_t *ops, int32_t n_ops, int32_t excitation);

@@ -982,6 +982,42 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         }
         cost[i] = (double)I.dim * (nnz_a + w + (I.R ? 2.0 * I.R * (I.nexcA + I.nexcB) : (double)I.nexcA * I.nexcB)) +
                   3.0 * pairs;
+        // bounds of this instance's tables as the batch kernels read them
+        {
+            bool good = I.nsa <= 32768 && I.nsb <= 32768 && M * M <= 511;
+            for (int k = 0; good && k < p.n_ops; ++k) {
+                const BOp &o = ops[(size_t)I.off_ops + k];
+                for (int side = 0; side < 2 && good; ++side) {
+                    const int32_t n = side ? o.nB : o.nA;
+                    const int64_t off = side ? o.offB : o.offA, ns = side ? I.nsb : I.nsa;
+                    if (n < -1 || (n >= 0 && off + n > (int64_t)lists.size())) good = false;
+                    for (int32_t u = 0; good && u < n; ++u) {
+                        const uint32_t e = lists[off + u];
+                        good = (int64_t)(e & 0x7FFFu) < ns && (int64_t)((e >> 15) & 0x7FFFu) < ns;
+                    }
+                }
+            }
+            auto exc_ok = [&](const std::vector<uint32_t> &ex, int nexc, int ns, int nd) {
+                if ((int64_t)ex.size() != (int64_t)ns * nexc || nd > nexc) return false;
+                for (int r = 0; r < ns; ++r)
+                    for (int e = 0; e < nexc; ++e) {
+                        const uint32_t x = ex[(size_t)r * nexc + e];
+                        if ((int)(x & 0xFFFFu) >= ns || (int)((x >> 16) & 0x1FFu) >= M * M) return false;
+                        if (e >= nexc - nd && (x & 0xFFFFu) != (uint32_t)r) return false;
+                    }
+                return true;
+            };
+            good = good && exc_ok(ea, I.nexcA, I.nsa, I.ndA) && exc_ok(eb, I.nexcB, I.nsb, I.ndB);
+            for (int64_t r = 0; good && r < I.nsa; ++r)
+                for (int64_t q = hptr[I.off_ha + r] - base; good && q < hptr[I.off_ha + r + 1] - base; ++q)
+                    good = hcol[base + q] >= 0 && hcol[base + q] < I.nsa;
+            for (size_t q = 0; good && q < (size_t)w * I.nsb; ++q)
+                good = ellc[I.off_hb + q] >= 0 && ellc[I.off_hb + q] < I.nsb;
+            if (!good) {
+                delete B;
+                return fail(FSV_EINVAL, "internal: instance %d tables out of range", i);
+            }
+        }
         B->inst.push_back(I);
     }
     B->total_k = kk;

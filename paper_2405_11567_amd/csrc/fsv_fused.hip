@@ -461,6 +461,45 @@ int build_fused(int M, const std::vector<uint32_t> &sa, const std::vector<uint32
         S.groups.push_back(g);
         i = j;
     }
+    // bounds of every tile program as k_fused reads it: rows of an orbit are
+    // alpha ranks, a block is a column range of C, local pairs stay inside the
+    // tile and each operator's list lies inside the program
+    for (const FGroup &g : S.groups) {
+        if (!g.fused) continue;
+        if ((int64_t)g.n_orbits * g.n_blocks > o.max_tiles || g.rmax > kMaxTileRows || g.lmax > kMaxTileCols ||
+            g.lds > o.lds_limit)
+            return fail(FSV_EINVAL, "internal: tile run at operator %d exceeds its limits", g.k0);
+        for (int32_t ob = 0; ob < g.n_orbits; ++ob) {
+            const uint32_t *w = &aprog[(size_t)g.aprog_off + (size_t)ob * g.astride];
+            const uint32_t nr = w[0];
+            if (nr < 1 || nr > (uint32_t)g.rmax) return fail(FSV_EINVAL, "internal: tile orbit size");
+            for (uint32_t t = 0; t < nr; ++t)
+                if ((int64_t)w[1 + t] >= nsa) return fail(FSV_EINVAL, "internal: tile row rank");
+            for (int jj = 0; jj < g.nops; ++jj) {
+                const uint32_t off = w[1 + g.rmax + 2 * jj], cnt = w[2 + g.rmax + 2 * jj];
+                if (cnt == kAll) continue;
+                if ((size_t)off + cnt > (size_t)g.astride) return fail(FSV_EINVAL, "internal: tile alpha list");
+                for (uint32_t u = 0; u < cnt; ++u) {
+                    const uint32_t e = w[off + u];
+                    if ((e & 0xFFu) >= nr || ((e >> 8) & 0xFFu) >= nr) return fail(FSV_EINVAL, "internal: tile alpha pair");
+                }
+            }
+        }
+        for (int32_t bk = 0; bk < g.n_blocks; ++bk) {
+            const uint32_t *w = &bprog[(size_t)g.bprog_off + (size_t)bk * g.bstride];
+            const uint32_t c0 = w[0], L = w[1];
+            if (L < 1 || L > (uint32_t)g.lmax || (int64_t)c0 + L > nsb) return fail(FSV_EINVAL, "internal: tile block");
+            for (int jj = 0; jj < g.nops; ++jj) {
+                const uint32_t off = w[2 + 2 * jj], cnt = w[3 + 2 * jj];
+                if (cnt == kAll) continue;
+                if ((size_t)off + cnt > (size_t)g.bstride) return fail(FSV_EINVAL, "internal: tile beta list");
+                for (uint32_t v = 0; v < cnt; ++v) {
+                    const uint32_t e = w[off + v];
+                    if ((e & 0x7FFFu) >= L || ((e >> 15) & 0x7FFFu) >= L) return fail(FSV_EINVAL, "internal: tile beta pair");
+                }
+            }
+        }
+    }
     auto up = [&](const std::vector<uint32_t> &vec, uint32_t **dst) -> int {
         void *p = nullptr;
         const size_t bytes = std::max<size_t>(vec.size(), 1) * 4;

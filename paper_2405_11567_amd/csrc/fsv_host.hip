@@ -100,6 +100,10 @@ struct fsv_plan {
     // device
     hipStream_t user = nullptr, work = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // recorded after each angle upload from h_pin: the next upload waits for
+    // it before rewriting the pinned angles (fsv_set_theta returns at once)
+    hipEvent_t ev_cs = nullptr;
+    bool cs_pending = false;
     std::vector<DevBuf> bufs;
     RotOp *d_rot = nullptr;
     double *d_cs = nullptr, *d_gpart = nullptr, *d_epart = nullptr, *d_out = nullptr;
@@ -159,10 +163,15 @@ struct fsv_plan {
     hipGraphExec_t g_e = nullptr;
     const void *g_e_psi = nullptr;
 
+    // pools compiled for this plan and still alive: a plan destroyed first
+    // detaches them (they then refuse to run), so a pool never reads a freed plan
+    std::vector<fsv_pool *> pools;
+
     ~fsv_plan();
 };
 
-// An operator pool compiled for one plan's sector (ADAPT screening).
+// An operator pool compiled for one plan's sector (ADAPT screening).  plan is
+// nullptr once that plan has been destroyed.
 struct fsv_pool {
     fsv_plan *plan = nullptr;
     int n = 0, gx = 1;
@@ -624,7 +633,7 @@ namespace {
 // Choose the factorised alpha-beta product when (pq|rs) has a small exact
 // pivoted-Cholesky rank: per sector element it costs R (e_a + e_b) instead of
 // e_a e_b multiply-adds.  The factorisation must reproduce g to 1e-12 relative.
-int lr_pad(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : 32); }
+int lr_pad(int) { return 8; }  // factor columns of the factorised kernels (ranks <= 8)
 
 void choose_sigma(fsv_plan &P, int &R_out, std::vector<double> &Lt_out) {
     R_out = 0;
@@ -634,7 +643,9 @@ void choose_sigma(fsv_plan &P, int &R_out, std::vector<double> &Lt_out) {
     if (P.nexcA <= 0 || P.nexcB <= 0 || M2 > 511) return;
     std::vector<double> L;
     const int R = pivoted_cholesky(M2, P.g.data(), 1e-14, L);
-    if (R <= 0 || R > 32) return;
+    // ranks above 8 take the direct product: the 16- and 32-column factorised
+    // kernels are kept out of use (no parity test of theirs has passed)
+    if (R <= 0 || R > 8) return;
     double gmax = 0.0, err = 0.0;
     for (int i = 0; i < M2; ++i)
         for (int j = 0; j < M2; ++j) {
@@ -1001,12 +1012,19 @@ int upload_theta(fsv_plan &P, const double *theta) {
     if (P.K > 0 && !theta) return fail(FSV_EINVAL, "theta is NULL");
     if (!finite_all(theta, (size_t)P.K)) return fail(FSV_ENONFINITE, "non-finite theta");
     double *h = P.h_pin;
+    if (P.cs_pending) {  // the previous upload may still be reading h
+        HIPCHECK(hipEventSynchronize(P.ev_cs));
+        P.cs_pending = false;
+    }
     for (int k = 0; k < P.K; ++k) {
         h[2 * k] = std::cos(theta[k]);
         h[2 * k + 1] = std::sin(theta[k]);
     }
-    if (P.K > 0)
+    if (P.K > 0) {
         HIPCHECK(hipMemcpyAsync(P.d_cs, h, sizeof(double) * 2 * P.K, hipMemcpyHostToDevice, P.work));
+        HIPCHECK(hipEventRecord(P.ev_cs, P.work));
+        P.cs_pending = true;
+    }
     return FSV_OK;
 }
 
@@ -1127,12 +1145,83 @@ int rebuild_fused(fsv_plan &P) {
     return upload(P, P.d_ccount, ccount.data(), (size_t)P.K);
 }
 
+// Bounds of the host tables before they go to the device, as the kernels read
+// them: pair-list entries (15-bit string ranks) name strings of their spin,
+// excitation words (16-bit rank, 9-bit orbital pair) name strings and orbital
+// pairs, each string's list ends with its diagonal excitations, the bins and
+// the CSR string Hamiltonians index inside their arrays, and every gradient
+// partial count fits the partial rows.
+int check_tables(const fsv_plan &P, const std::vector<uint32_t> &excA, const std::vector<uint32_t> &excB,
+                 const std::vector<int32_t> &boA, const std::vector<int32_t> &biA, const std::vector<int32_t> &boB,
+                 const std::vector<int32_t> &biB) {
+    const int M = P.M, M2 = M * M;
+    if (P.nsa > 32768 || P.nsb > 32768 || M2 > 511) return fail(FSV_EINVAL, "internal: sector too large for the tables");
+    for (int k = 0; k < P.K; ++k) {
+        const PairOp &o = P.pops[k];
+        auto side = [&](int32_t n, int64_t off, int64_t ns) {
+            if (n < -1 || (n >= 0 && off + n > (int64_t)P.h_plists.size())) return false;
+            for (int32_t u = 0; u < n; ++u) {
+                const uint32_t e = P.h_plists[off + u];
+                if ((int64_t)(e & 0x7FFFu) >= ns || (int64_t)((e >> 15) & 0x7FFFu) >= ns) return false;
+            }
+            return true;
+        };
+        if (!side(o.nA, o.offA, P.nsa) || !side(o.nB, o.offB, P.nsb))
+            return fail(FSV_EINVAL, "internal: pair list of operator %d out of range", k);
+    }
+    auto exc_ok = [&](const std::vector<uint32_t> &exc, int nexc, int64_t ns, int nd) {
+        if ((int64_t)exc.size() != ns * nexc || nd > nexc) return false;
+        for (int64_t I = 0; I < ns; ++I)
+            for (int e = 0; e < nexc; ++e) {
+                const uint32_t w = exc[(size_t)I * nexc + e];
+                const uint32_t pq = (w >> 16) & 0x1FFu;
+                if ((int64_t)(w & 0xFFFFu) >= ns || (int)pq >= M2) return false;
+                if (e >= nexc - nd && ((w & 0xFFFFu) != (uint32_t)I || pq % (M + 1) != 0)) return false;
+            }
+        return true;
+    };
+    if (!exc_ok(excA, P.nexcA, P.nsa, P.na) || !exc_ok(excB, P.nexcB, P.nsb, P.nb))
+        return fail(FSV_EINVAL, "internal: excitation lists out of range");
+    auto bins_ok = [&](const std::vector<int32_t> &off, const std::vector<int32_t> &idx, size_t n) {
+        if ((int)off.size() != M2 + 1 || off[0] != 0 || (size_t)off[M2] != idx.size() || idx.size() != n) return false;
+        for (int b = 0; b < M2; ++b)
+            if (off[b + 1] < off[b]) return false;
+        for (int32_t i : idx)
+            if (i < 0 || (size_t)i >= n) return false;
+        return true;
+    };
+    if (!bins_ok(boA, biA, excA.size()) || !bins_ok(boB, biB, excB.size()))
+        return fail(FSV_EINVAL, "internal: density-matrix bins out of range");
+    for (int k = 0; k < P.K; ++k)
+        if (P.frev.count[k] > max_grid()) return fail(FSV_EINVAL, "internal: gradient partials of operator %d", k);
+    if (P.pin_doubles < 3 * (size_t)P.K + 1 + 4 * (size_t)M2) return fail(FSV_EINVAL, "internal: pinned buffer");
+    return FSV_OK;
+}
+
+int check_csr(const std::vector<int64_t> &ptr, const std::vector<int32_t> &col, size_t nval,
+              const std::vector<int32_t> *desc, int64_t ns, int M2) {
+    if ((int64_t)ptr.size() != ns + 1 || ptr[0] != 0 || (size_t)ptr[ns] != col.size() || col.size() != nval)
+        return fail(FSV_EINVAL, "internal: string Hamiltonian rows");
+    for (int64_t I = 0; I < ns; ++I)
+        if (ptr[I + 1] < ptr[I]) return fail(FSV_EINVAL, "internal: string Hamiltonian rows");
+    for (int32_t c : col)
+        if (c < 0 || c >= ns) return fail(FSV_EINVAL, "internal: string Hamiltonian column");
+    if (desc) {
+        if (desc->size() != nval) return fail(FSV_EINVAL, "internal: one-body descriptors");
+        for (int32_t d : *desc)
+            if ((d <= -2 && -2 - (int64_t)d >= ns) || (d >= 0 && (d & 0x3FFFFFFF) >= M2))
+                return fail(FSV_EINVAL, "internal: one-body descriptor out of range");
+    }
+    return FSV_OK;
+}
+
 int build_device(fsv_plan &P) {
     int rc;
     init_kernels();
     HIPCHECK(hipStreamCreateWithFlags(&P.work, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&P.ev_in, hipEventDisableTiming));
     HIPCHECK(hipEventCreateWithFlags(&P.ev_out, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&P.ev_cs, hipEventDisableTiming));
     const int M = P.M, G = max_grid();
     const size_t M2 = (size_t)M * M;
     P.pin_doubles = 2 * (size_t)P.K + (size_t)P.K + 1 + 4 * M2 + 8;
@@ -1197,6 +1286,7 @@ int build_device(fsv_plan &P) {
     if (const char *e = std::getenv("FSV_NO_FUSE")) P.fuse_mode = e[0] ? 1 : P.fuse_mode;
     if (std::getenv("FSV_FORCE_FUSE")) P.fuse_mode = 2;
     if ((rc = rebuild_fused(P))) return rc;
+    if ((rc = check_tables(P, excA, excB, boA, biA, boB, biB))) return rc;
 
     if ((rc = dalloc(P, &P.d_rot, P.K))) return rc;
     if ((rc = dalloc(P, &P.d_cs, 2 * (size_t)P.K))) return rc;
@@ -1250,6 +1340,9 @@ int build_device(fsv_plan &P) {
     std::vector<double> ht(P.h);
     build_string_h(M, P.sa, ra, ht.data(), P.g.data(), P.ha_ptr, P.ha_col, P.ha_val);
     build_string_h(M, P.sb, rb, ht.data(), P.g.data(), P.hb_ptr, P.hb_col, P.hb_val);
+    if ((rc = check_csr(P.ha_ptr, P.ha_col, P.ha_val.size(), nullptr, P.nsa, (int)M2)) ||
+        (rc = check_csr(P.hb_ptr, P.hb_col, P.hb_val.size(), nullptr, P.nsb, (int)M2)))
+        return rc;
     if ((rc = dalloc(P, &P.d_ha_ptr, P.ha_ptr.size()))) return rc;
     if ((rc = dalloc(P, &P.d_ha_col, P.ha_col.size()))) return rc;
     if ((rc = dalloc(P, &P.d_ha_val, P.ha_val.size()))) return rc;
@@ -1273,6 +1366,7 @@ int build_device(fsv_plan &P) {
             build_string_h_onebody(M, str, rk, desc);
             if (v2.size() != nent || desc.size() != nent)
                 return fail(FSV_EINVAL, "internal: string Hamiltonian parts disagree");
+            if ((r = check_csr(ptr2, col2, v2.size(), &desc, (int64_t)str.size(), (int)M2))) return r;
             if ((r = dalloc(P, d_v2, nent)) || (r = dalloc(P, d_desc, nent)) || (r = dalloc(P, d_str, str.size())))
                 return r;
             if ((r = upload(P, *d_v2, v2.data(), nent)) || (r = upload(P, *d_desc, desc.data(), nent)) ||
@@ -1331,6 +1425,7 @@ int build_device(fsv_plan &P) {
 }  // namespace
 
 fsv_plan::~fsv_plan() {
+    for (fsv_pool *q : pools) q->plan = nullptr;
     drop_graphs(*this);
     for (void *p : init_mem) (void)hipFree(p);
     if (blas) (void)rocblas_destroy_handle(blas);
@@ -1338,6 +1433,7 @@ fsv_plan::~fsv_plan() {
     if (h_pin) (void)hipHostFree(h_pin);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ev_cs) (void)hipEventDestroy(ev_cs);
     if (work) (void)hipStreamDestroy(work);
 }
 
@@ -1868,6 +1964,18 @@ int fsv_pool_create(fsv_pool **out, fsv_plan *P, const int32_t *ops, int32_t n_o
         maxpairs = std::max(maxpairs, (double)(po.nA >= 0 ? po.nA : P->nsa) * (double)(po.nB >= 0 ? po.nB : P->nsb));
         pops.push_back(po);
     }
+    for (int t = 0; t < n_ops; ++t)  // pair-list bounds, as for the plan's own operators
+        for (int side = 0; side < 2; ++side) {
+            const int32_t n = side ? pops[t].nB : pops[t].nA;
+            const int64_t off = side ? pops[t].offB : pops[t].offA, ns = side ? P->nsb : P->nsa;
+            bool good = n >= -1 && (n < 0 || off + n <= (int64_t)lists.size());
+            for (int32_t u = 0; good && u < n; ++u)
+                good = (int64_t)(lists[off + u] & 0x7FFFu) < ns && (int64_t)((lists[off + u] >> 15) & 0x7FFFu) < ns;
+            if (!good) {
+                delete Q;
+                return fail(FSV_EINVAL, "internal: pair list of pool operator %d out of range", t);
+            }
+        }
     // workgroups per operator: ~16 pairs per thread for the largest, at most 64
     Q->gx = (int)std::min(64.0, std::max(1.0, std::ceil(maxpairs / (256.0 * 16.0))));
     auto dal = [&](void **p, size_t bytes) -> int {
@@ -1895,6 +2003,7 @@ int fsv_pool_create(fsv_pool **out, fsv_plan *P, const int32_t *ops, int32_t n_o
         delete Q;
         return fail(FSV_EDEVICE, "pool upload failed");
     }
+    P->pools.push_back(Q);
     *out = Q;
     clear_error();
     return FSV_OK;
@@ -1902,7 +2011,10 @@ int fsv_pool_create(fsv_pool **out, fsv_plan *P, const int32_t *ops, int32_t n_o
 
 int fsv_pool_destroy(fsv_pool *Q) {
     if (!Q) return FSV_OK;
-    if (Q->plan && Q->plan->work) (void)hipStreamSynchronize(Q->plan->work);
+    if (fsv_plan *P = Q->plan) {
+        if (P->work) (void)hipStreamSynchronize(P->work);
+        P->pools.erase(std::remove(P->pools.begin(), P->pools.end(), Q), P->pools.end());
+    }
     delete Q;
     return FSV_OK;
 }
@@ -1910,6 +2022,7 @@ int fsv_pool_destroy(fsv_pool *Q) {
 int fsv_pool_gradients(fsv_pool *Q, const double *theta, void *psi, void *lam, double *E_out, double *grad_out) {
     if (!Q || !psi || !lam || !grad_out) return fail(FSV_EINVAL, "pool, psi, lam or grad_out is NULL");
     if (psi == lam) return fail(FSV_EINVAL, "psi and lam must be distinct buffers");
+    if (!Q->plan) return fail(FSV_ESTATE, "the plan of this pool has been destroyed");
     fsv_plan &P = *Q->plan;
     if (P.engine != 0) return fail(FSV_ESTATE, "pool screening runs on the sector engine");
     int rc;

@@ -138,8 +138,9 @@ struct SectorTabs {
     double ecore;
     // Optional exact factorisation (pq|rs) = sum_l L[l][pq] L[l][rs] of rank R
     // (pivoted Cholesky of the pair supermatrix): Lt holds L transposed and
-    // padded to RP = 8, 16 or 32 columns (M^2 x RP, zero beyond R) and YT is an
-    // RP * nsa * nsb work array (complex-sized).  R = 0: direct product.
+    // padded to RP = 8 columns (M^2 x RP, zero beyond R) and YT is an
+    // RP * nsa * nsb work array (complex-sized).  R = 0 (also for every rank
+    // above 8): direct product.
     int R;
     const double *Lt;
     void *YT;

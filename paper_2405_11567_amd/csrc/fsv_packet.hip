@@ -744,12 +744,78 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
     return FSV_OK;
 }
 
+// Bounds of one packet program (index list at ent[e0], region at reg[r0] of
+// wr words) of a run of m operators, as the packet kernels read them: the
+// index list holds h[0] ascending amplitude indices below dim, then padding;
+// the cumulative pair counts h[1..m] never decrease and fit the region; every
+// pair names two distinct filled slots, and no slot appears in two pairs of
+// one operator (the lanes of a wavefront apply an operator's pairs at once).
+int check_packet(const std::vector<uint32_t> &ent, size_t e0, const std::vector<uint32_t> &reg, size_t r0, int wr,
+                 int m, int64_t dim, const char *what) {
+    if (e0 + kPkt > ent.size() || r0 + (size_t)wr > reg.size())
+        return fail(FSV_EINVAL, "internal: %s program outside its table", what);
+    const uint32_t *h = &reg[r0];
+    const uint32_t fill = h[0];
+    if (fill < 1 || fill > (uint32_t)kPkt) return fail(FSV_EINVAL, "internal: %s holds %u amplitudes", what, fill);
+    for (uint32_t t = 0; t < (uint32_t)kPkt; ++t) {
+        const uint32_t x = ent[e0 + t];
+        if (t < fill) {
+            if ((int64_t)x >= dim || (t > 0 && x <= ent[e0 + t - 1]))
+                return fail(FSV_EINVAL, "internal: %s index %u out of order or range", what, t);
+        } else if (x != kNone) {
+            return fail(FSV_EINVAL, "internal: %s padding slot %u is not empty", what, t);
+        }
+    }
+    uint32_t prev = 0;
+    std::vector<uint8_t> used(kPkt);
+    for (int j = 0; j < m; ++j) {
+        const uint32_t end = h[1 + j];
+        if (end < prev || end > 2u * (uint32_t)(wr - kPktHdr))
+            return fail(FSV_EINVAL, "internal: %s pair range of operator %d", what, j);
+        std::fill(used.begin(), used.end(), 0);
+        for (uint32_t t = prev; t < end; ++t) {
+            const uint32_t w = (reg[r0 + kPktHdr + (t >> 1)] >> ((t & 1u) << 4)) & 0xFFFFu;
+            const uint32_t a = w & 0xFFu, b = w >> 8;
+            if (a >= fill || b >= fill || a == b || used[a] || used[b])
+                return fail(FSV_EINVAL, "internal: %s pair %u of operator %d", what, t, j);
+            used[a] = used[b] = 1;
+        }
+        prev = end;
+    }
+    return FSV_OK;
+}
+
+// Every program of every packet run (and of its forward-support copy).
+int check_packet_plan(const PacketPlan &P, int64_t dim, int K) {
+    for (const FGroup &g : P.groups) {
+        if (g.k0 < 0 || g.nops < 1 || g.k0 + g.nops > K) return fail(FSV_EINVAL, "internal: run bounds");
+        if (g.fused != 2) continue;
+        if (g.nops > kPktMaxOps || g.wr < kPktHdr + 4 || g.wr > kPktMaxWords || (g.wr & 3) || g.n_packets < 0)
+            return fail(FSV_EINVAL, "internal: packet run at operator %d has region %d", g.k0, g.wr);
+        int rc;
+        for (int q = 0; q < g.n_packets; ++q)
+            if ((rc = check_packet(P.ent, (size_t)g.ent_off + (size_t)q * kPkt, P.reg, (size_t)g.reg_off + (size_t)q * g.wr,
+                                   g.wr, g.nops, dim, "packet")))
+                return rc;
+        for (int q = 0; q < g.sub_n; ++q)
+            if ((rc = check_packet(P.ent, (size_t)g.sub_ent_off + (size_t)q * kPkt, P.reg,
+                                   (size_t)g.sub_reg_off + (size_t)q * g.wr, g.wr, g.nops, dim, "support packet")))
+                return rc;
+        if (g.sub_n > g.n_packets) return fail(FSV_EINVAL, "internal: support copy larger than its run");
+        for (int k = g.k0; k < g.k0 + g.nops; ++k)
+            if (P.count[k] != std::min(g.n_packets, max_grid()))
+                return fail(FSV_EINVAL, "internal: gradient partial count of operator %d", k);
+    }
+    return FSV_OK;
+}
+
 int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
                   const FusedOpts &o, FusedSched &S) {
     S.release();
     PacketPlan pp;
     int rc = plan_packets(nsa, nsb, pops, lists, o, false, pp);
     if (rc) return rc;
+    if ((rc = check_packet_plan(pp, nsa * nsb, (int)pops.size()))) return rc;
     S.groups = std::move(pp.groups);
     S.count = std::move(pp.count);
     if ((rc = upload_words(pp.ent, S, &S.d_aprog)) || (rc = upload_words(pp.reg, S, &S.d_bprog))) {
@@ -802,7 +868,8 @@ int build_batch_packets(const std::vector<BatchPacketInst> &insts, const std::ve
         const BatchPacketInst &I = insts[i];
         if (I.nsa * I.nsb > packet_max_dim()) return fail(FSV_EINVAL, "internal: instance too large for packets");
         const std::vector<PairOp> pops(ops.begin() + I.off_ops, ops.begin() + I.off_ops + I.K);
-        const int rc = plan_packets(I.nsa, I.nsb, pops, lists, o, true, plans[i]);
+        int rc = plan_packets(I.nsa, I.nsb, pops, lists, o, true, plans[i]);
+        if (!rc) rc = check_packet_plan(plans[i], I.nsa * I.nsb, I.K);
         if (rc) return rc;
         R = std::max(R, (int)plans[i].groups.size());
         total_k = std::max<int64_t>(total_k, I.off_k + I.K);

@@ -397,7 +397,8 @@ __global__ __launch_bounds__(BLOCK) void k_sigma_ab_reg(const uint32_t *__restri
 }
 
 // Factorised alpha-beta term, (pq|rs) = sum_l L_l[pq] L_l[rs] (l < R, padded
-// to RP = 8, 16 or 32 with zero columns of Lt, which is M^2 x RP):
+// to RP = 8 with zero columns of Lt, which is M^2 x RP; wider ranks take the
+// direct product):
 //   S[Ia][Ib] += sum_l (A_l C B_l^T)[Ia][Ib],  A_l = sum_pq L_l[pq] E^alpha_pq,
 //   B_l = sum_rs L_l[rs] E^beta_rs,
 // in two steps through Y[Ia][Jb][l] = (A_l C)[Ia][Jb] (l fastest).
@@ -837,8 +838,8 @@ hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, doubl
                                T.excB, T.nexcB, T.g, T.M, C, S, nsb);
     }
     if (T.nexcA > 0 && T.nexcB > 0 && T.R > 0) {
-        hipError_t e = T.R <= 8 ? lr_launch<A, 8>(T, C, S, st)
-                                : (T.R <= 16 ? lr_launch<A, 16>(T, C, S, st) : lr_launch<A, 32>(T, C, S, st));
+        if (T.R > 8) return hipErrorInvalidValue;  // wider factorisations take the direct product
+        const hipError_t e = lr_launch<A, 8>(T, C, S, st);
         if (e != hipSuccess) return e;
     }
     if (T.hb_dense_t && sizeof(A) == sizeof(double)) {

@@ -1,0 +1,92 @@
+"""pytest plugin: run the GPU test files on the CPU against the host-check
+build of the library (tests/cpu_runtime/build.py), so that their exact
+sequence of plan / pool / batch lifetimes, calls, oracle calls and garbage
+collections runs with the library's host code under AddressSanitizer.
+
+Kernels do not run in that build, so results are meaningless: use it with
+`python -O -m pytest --assert=plain -p tests.cpu_runtime.stub_plugin ...`,
+which strips the tests' assertions.  States are CPU tensors standing in for
+device buffers (the library never reads them on the host).
+"""
+
+from __future__ import annotations
+
+import contextlib
+import ctypes
+import os
+import types
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BUILD = os.path.join(HERE, "_build")
+
+
+def pytest_configure(config):
+    import torch
+
+    import paper_2405_11567_amd as fsv
+    from paper_2405_11567_amd import _lib
+
+    ctypes.CDLL(os.path.join(BUILD, "libhipstub.so"), mode=ctypes.RTLD_GLOBAL)
+    _lib.LIB_PATH = os.path.join(BUILD, "libfsv_hostcheck.so")
+    _lib._lib = None
+
+    cuda = types.SimpleNamespace(
+        is_available=lambda: True,
+        device=lambda *_: contextlib.nullcontext(),
+        current_stream=lambda *_: types.SimpleNamespace(cuda_stream=0),
+        synchronize=lambda *_: None,
+    )
+
+    class TorchShim:
+        def __getattr__(self, name):
+            if name == "cuda":
+                return cuda
+            if name == "device":
+                return lambda *a, **k: torch.device("cpu")
+            return getattr(torch, name)
+
+    shim = TorchShim()
+    fsv._torch = lambda: shim
+
+    # states come from the stand-in's device allocator, so that its copy and
+    # GEMM checks cover them; the tensor frees its buffer when it dies
+    import weakref
+    stub = ctypes.CDLL(os.path.join(BUILD, "libhipstub.so"))
+    stub.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    stub.hipFree.argtypes = [ctypes.c_void_p]
+
+    def new_state(self):
+        nbytes = (1 << self.n_qubits) * (16 if self.precision == 0 else 8)
+        p = ctypes.c_void_p()
+        if stub.hipMalloc(ctypes.byref(p), nbytes) != 0:
+            raise MemoryError("stand-in hipMalloc failed")
+        buf = (ctypes.c_char * nbytes).from_address(p.value)
+        t = torch.frombuffer(buf, dtype=self.dtype)
+        weakref.finalize(t, stub.hipFree, p.value)
+        return t
+
+    fsv.Plan.new_state = new_state
+
+    # the oracle: its AddressSanitizer build when one is present
+    asan_oracle = os.environ.get("FSV_ORACLE_LIB")
+    if asan_oracle:
+        from oracle import sector
+        sector._LIB = asan_oracle
+        sector.build = lambda force=False: asan_oracle
+
+
+
+def pytest_sessionstart(session):
+    import sys
+    for mod in list(sys.modules.values()):
+        if getattr(mod, "gpu_available", None) is not None and mod.__name__.endswith("conftest"):
+            mod.gpu_available = lambda: True
+
+
+def pytest_collection_modifyitems(config, items):
+    # FSV_STUB_RUN_SKIPPED=1: also replay tests that are skipped on the GPU
+    if os.environ.get("FSV_STUB_RUN_SKIPPED"):
+        for it in items:
+            it.own_markers = [m for m in it.own_markers if m.name != "skip"]

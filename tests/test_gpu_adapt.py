@@ -144,8 +144,19 @@ def test_batch_qeb_instances(fsv, monkeypatch, mode):
         assert abs(e[i] - e_ref) < 1e-10 and np.abs(g[i] - g_ref).max() < 1e-9
 
 
+def oracle_pick(g):
+    # ADAPT's choice, written here independently of the product: the largest
+    # screening magnitude, ties (equal after rounding to 1e-10) to the first index
+    mag = np.round(np.abs(g), 10)
+    best = 0
+    for t in range(1, len(mag)):
+        if mag[t] > mag[best]:
+            best = t
+    return best
+
+
 def oracle_adapt(p, pool_ops, excitation, max_ops, grad_tol, inner, lr):
-    from paper_2405_11567_amd.adapt import pick
+    pick = oracle_pick
     m, na, nb, o = p.n_orb, p.n_alpha, p.n_beta, p.ordering
     ops = np.zeros((0, 4), dtype=np.int32)
     theta = np.zeros(0)

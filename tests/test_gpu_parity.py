@@ -278,6 +278,64 @@ def test_sigma_paths(fsv, monkeypatch, mode, nfac):
         assert abs(plan.energy(psi) - e_ref) < 1e-10
 
 
+def _general_g(m, nfac, seed):
+    # (pq|rs) = sum over nfac random symmetric factors: rank min(nfac, m(m+1)/2),
+    # like integrals read from an FCIDUMP file (no low-rank structure assumed)
+    rng = np.random.default_rng(seed)
+    g = np.zeros((m, m, m, m))
+    for _ in range(nfac):
+        l = rng.normal(0, 0.05, (m, m))
+        l = l + l.T
+        g += np.einsum("pq,rs->pqrs", l, l)
+    return g
+
+
+@pytest.mark.parametrize("n,ne,nfac", [(12, 5, 30), (16, 8, 12), (16, 7, 40)])
+@pytest.mark.parametrize("engine", ENGINES)
+def test_alpha_beta_general_integrals(fsv, n, ne, nfac, engine):
+    # the alpha-beta product on integrals of full pair rank (or rank 12): every
+    # rank above 8 takes the direct product; energy, adjoint gradient, the
+    # ansatz state's energy and 1-RDM against the oracle
+    p = random_problem(n, ne, 60, seed=1300 + n + ne, theta_std=0.3, replace=True, ordering=n % 3 % 2)
+    p.g = _general_g(p.n_orb, nfac, seed=nfac)
+    say("general integrals", n, ne, nfac, engine)
+    plan = fsv.Plan(p, engine=engine)
+    e, gr = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p)
+    assert abs(e - e_ref) < 1e-10 and np.abs(gr - g_ref).max() < 1e-9
+    psi = plan.ansatz_apply(p.theta)
+    assert abs(plan.energy(psi) - e_ref) < 1e-10
+    gam = plan.rdm1(psi)
+    ref = sector.rdm1(oracle_state(p), p.n_orb, p.n_alpha, p.n_beta, p.ordering)
+    assert np.abs(gam - ref).max() < 1e-12
+
+
+def test_set_theta_does_not_change_a_queued_sweep(fsv):
+    # set_theta returns before its angle copy has run; a second set_theta must
+    # not rewrite the angles a queued sweep is still to read: the first sweep's
+    # result is the oracle's at theta1, the next one's at theta2
+    p = config("C2")
+    plan = fsv.Plan(p)
+    psi, lam = plan.new_state(), plan.new_state()
+    th1 = p.theta
+    th2 = p.theta[::-1].copy()
+    e1_ref, g1_ref = oracle_energy_grad(p, theta=th1)
+    e2_ref, g2_ref = oracle_energy_grad(p, theta=th2)
+    for _ in range(3):
+        plan.set_theta(th1)
+        plan.forward_async(psi)
+        plan.sigma_async(psi, lam)
+        plan.reverse_async(psi, lam)
+        plan.set_theta(th2)
+        e, g = plan.finish()
+        assert abs(e - e1_ref) < 1e-10 and np.abs(g - g1_ref).max() < 1e-9
+        plan.forward_async(psi)
+        plan.sigma_async(psi, lam)
+        plan.reverse_async(psi, lam)
+        e, g = plan.finish()
+        assert abs(e - e2_ref) < 1e-10 and np.abs(g - g2_ref).max() < 1e-9
+
+
 @pytest.mark.parametrize("mode", ["auto", "none", "force", "tiles", "packets"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_fused_runs_sector(fsv, monkeypatch, mode, precision):
