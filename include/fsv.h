@@ -33,10 +33,24 @@
  *  - Amplitude buffers are device pointers to 2^n complex values: interleaved
  *    (re, im) float64 for precision 0, float32 for precision 1.  The caller
  *    owns and allocates them (fsv_state_bytes); the library never allocates
- *    O(2^n) memory.  The plan owns only O(K + n_orb^4 + sector) tables and a
- *    sector-sized workspace (the (n_alpha, n_beta) sector is the only part of
- *    the state that the operators above ever make nonzero), plus, with packet
- *    runs (fsv_plan_runs), their programs (indices and pairs of each packet).
+ *    O(2^n) memory.
+ *  - Device memory of a plan (all of it sized by the (n_alpha, n_beta)
+ *    sector, the only part of the state the operators above ever make
+ *    nonzero, of dimension D = C(n_orb, n_alpha) C(n_orb, n_beta)):
+ *      - its tables, owned by the plan and allocated at creation: operator pair
+ *        lists, string tables and same-spin string Hamiltonians (sparse rows,
+ *        and dense copies of D_alpha^2 + 2 D_beta^2 doubles where the dense
+ *        products are chosen), integrals, and the programs of the fused
+ *        operator runs (fsv_plan_runs); fsv_plan_device_bytes reports them;
+ *      - its workspace of fsv_plan_workspace_bytes: four complex sector
+ *        vectors (16 D bytes each), the factorised alpha-beta intermediate
+ *        (8 x 16 D bytes, when that product is used), density-matrix overlaps
+ *        and the per-operator gradient partials (K x 8192 doubles).  The caller
+ *        may provide it (fsv_plan_set_workspace; the Python binding allocates
+ *        it through PyTorch, so that running out of memory shows up there);
+ *        otherwise the plan allocates it on the first call that needs it.
+ *    The FP64 GEMM library used for dense same-spin products keeps its own
+ *    small per-handle workspace besides.
  *  - Every function returns FSV_OK (0) or a negative status, never throws and
  *    never exits.  fsv_last_error() returns a thread-local message for the last
  *    failure on the calling thread.
@@ -96,6 +110,22 @@ int fsv_plan_destroy(fsv_plan *plan);
 
 /* Bytes of one amplitude buffer: 2^n_qubits * (16 or 8). 0 for NULL. */
 size_t fsv_state_bytes(const fsv_plan *plan);
+
+/* Bytes of the plan's workspace (see the conventions above).  0 for NULL. */
+size_t fsv_plan_workspace_bytes(const fsv_plan *plan);
+
+/* Device bytes the plan owns now: its tables, plus its workspace when the
+ * plan allocated that itself.  0 for NULL. */
+size_t fsv_plan_device_bytes(const fsv_plan *plan);
+
+/* Give the plan a caller-owned workspace: ws_dev (device, 256-byte aligned)
+ * of at least fsv_plan_workspace_bytes bytes, which the caller keeps alive
+ * and unused by other work until the plan is destroyed or another workspace
+ * is set.  A workspace the plan allocated itself is freed.  ws_dev = NULL
+ * goes back to a plan-owned workspace (allocated on the next call).  Waits
+ * for the plan's earlier work.  Its contents between calls are unspecified.
+ * Errors: FSV_EINVAL (NULL plan, too small or misaligned), FSV_EDEVICE. */
+int fsv_plan_set_workspace(fsv_plan *plan, void *ws_dev, size_t bytes);
 
 /* Sector dimensions: number of alpha strings, beta strings, and the dense
  * index of the reference determinant.  Any pointer may be NULL. */
@@ -257,9 +287,10 @@ int fsv_pool_gradients(fsv_pool *pool, const double *theta, void *psi_dev, void 
 /* ---- batches: many independent instances in one graph launch ----
  * Each instance has its own problem (qubit count, electrons, integrals,
  * operators; at most 24 qubits: larger systems belong in a plan); all must use
- * precision 0.  Real angles and integrals keep every amplitude real, so the
- * batch stores each instance's sector state as real FP64 in a device arena
- * that it owns.  H C: for instances of at least 16 x 16 strings the
+ * precision 0.  Real angles and integrals keep every amplitude real, so each
+ * instance's sector state psi and its H psi are stored as real FP64 in a
+ * device arena of fsv_batch_arena_bytes that the caller owns and passes to
+ * every evaluation (the batch owns only its tables, fsv_batch_bytes).  H C: for instances of at least 16 x 16 strings the
  * same-spin part runs as dense FP64 products on the matrix cores (all such
  * instances in one launch; FSV_BATCH_SAME_SPIN=sparse keeps them on sparse
  * rows), then one workgroup per (instance, alpha string) adds the rest with
@@ -267,28 +298,39 @@ int fsv_pool_gradients(fsv_pool *pool, const double *theta, void *psi_dev, void 
  * (pq|rs) where they exist, FSV_BATCH_SIGMA=direct avoids them; rows too long
  * for the LDS budget, or FSV_BATCH_SIGMA=global, read global memory only).
  * Three launch schemes, chosen by fsv_batch_autotune (or FSV_BATCH_MODE =
- * packets | phased | persistent at creation): component-packet runs (the
- * default when every instance has at most 2^22 sector amplitudes; launch r
- * carries run r of every instance, runs aligned at their ends); phased
- * launches (one per operator index and phase, every instance in each), both
- * captured into one graph; or a persistent kernel whose workgroups take whole
- * instances from a device work queue, largest first.  Results are identical
- * to rounding.  Errors: FSV_EINVAL for an invalid instance (the message names
- * it), FSV_ENOMEM, FSV_EDEVICE. */
+ * packets | phased | persistent at creation), each captured into one graph
+ * that a call launches once: component-packet runs (the default when every
+ * instance has at most 2^22 sector amplitudes; launch r carries run r of
+ * every instance, runs aligned at their ends, so the graph holds two
+ * launches per run index plus the H psi and reduction launches, about 33 for
+ * 256 instances of 50..150 operators); phased launches (one per operator
+ * index and phase, every instance in each); or a single persistent kernel
+ * whose workgroups take whole instances from a device work queue, largest
+ * first (measured slower than packet runs on that workload, so not the
+ * default).  Results are identical to rounding.  Errors: FSV_EINVAL for an
+ * invalid instance (the message names it), FSV_ENOMEM, FSV_EDEVICE. */
 int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count, void *hip_stream);
 int fsv_batch_destroy(fsv_batch *batch);
-/* theta_concat: host, sum_i K_i doubles in instance order.  E_out: host,
- * count doubles.  grad_concat: host, sum_i K_i doubles. */
-int fsv_batch_energy_grad(fsv_batch *batch, const double *theta_concat, double *E_out,
+/* Bytes of the state arena an evaluation needs: 2 x 8 x sum_i D_i (psi and
+ * H psi of every instance, real FP64).  0 for NULL. */
+size_t fsv_batch_arena_bytes(const fsv_batch *batch);
+/* theta_concat: host, sum_i K_i doubles in instance order.  arena_dev:
+ * device, 256-byte aligned, at least fsv_batch_arena_bytes bytes, owned by
+ * the caller; its contents on return are unspecified (a different arena than
+ * the previous call's makes the batch capture its graph again).  E_out: host,
+ * count doubles.  grad_concat: host, sum_i K_i doubles.  Errors: FSV_EINVAL
+ * (NULL or misaligned arguments), FSV_ENONFINITE, FSV_EDEVICE. */
+int fsv_batch_energy_grad(fsv_batch *batch, const double *theta_concat, void *arena_dev, double *E_out,
                           double *grad_concat);
-/* Device bytes the batch owns (arena + tables). */
+/* Device bytes the batch owns (its tables; the arena is the caller's). */
 size_t fsv_batch_bytes(const fsv_batch *batch);
 /* Autotuner: times every candidate on this batch through its own captured
  * graph and keeps the fastest: launch scheme, persistent workgroup size and
  * workgroups per CU, phased workgroups per instance, and the LDS budget of an
  * H C workgroup (which sets how many alpha excitations it stages per pass).
- * *report (may be NULL) receives a static summary string. */
-int fsv_batch_autotune(fsv_batch *batch, const char **report);
+ * arena_dev as for fsv_batch_energy_grad.  *report (may be NULL) receives a
+ * static summary string. */
+int fsv_batch_autotune(fsv_batch *batch, void *arena_dev, const char **report);
 
 #ifdef __cplusplus
 }

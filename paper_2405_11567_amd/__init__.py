@@ -30,6 +30,12 @@ def _torch():
     return torch
 
 
+def _device_buffer(device, nbytes: int):
+    """An uninitialised device buffer of nbytes from PyTorch's allocator."""
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
 def _cproblem(n_qubits, n_alpha, n_beta, h, g, ops, e_core, ordering, precision, keep, excitation=0):
     h = np.ascontiguousarray(h, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
@@ -75,12 +81,22 @@ class Plan:
         # plan first)
         self._pools = weakref.WeakSet()
         self.state_bytes = int(lib.fsv_state_bytes(handle))
+        # the plan's sector workspace comes from PyTorch's allocator, so that
+        # running out of device memory shows up there
+        self.workspace_bytes = int(lib.fsv_plan_workspace_bytes(handle))
+        self._ws = _device_buffer(self.device, self.workspace_bytes)
+        check(lib.fsv_plan_set_workspace(handle, ctypes.c_void_p(self._ws.data_ptr()), self.workspace_bytes))
         nsa, nsb, ref = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
         check(lib.fsv_plan_info(handle, ctypes.byref(nsa), ctypes.byref(nsb), ctypes.byref(ref)))
         self.n_alpha_strings, self.n_beta_strings = nsa.value, nsb.value
         self.reference_index = ref.value
         if engine is not None:
             self.set_engine(engine)
+
+    @property
+    def device_bytes(self) -> int:
+        """Device bytes the library holds for this plan (its tables)."""
+        return int(self._lib.fsv_plan_device_bytes(self._h))
 
     def set_engine(self, engine: str):
         """'sector' (default): energy_grad keeps only the (n_alpha, n_beta)
@@ -321,6 +337,9 @@ class Batch:
         self._lib = lib
         self.count = len(problems)
         self.bytes = int(lib.fsv_batch_bytes(handle))
+        # the state arena (psi and H psi of every instance) is the caller's
+        self.arena_bytes = int(lib.fsv_batch_arena_bytes(handle))
+        self.arena = _device_buffer(self.device, self.arena_bytes)
         self._total = int(sum(self.n_ops))
         self._offsets = [0] + np.cumsum(self.n_ops).tolist()
 
@@ -344,7 +363,8 @@ class Batch:
             raise ValueError("theta sizes do not match the batch")
         e = np.empty(self.count)
         g = np.empty(th.size)
-        check(self._lib.fsv_batch_energy_grad(self._h, _dptr(th), _dptr(e), _dptr(g)))
+        check(self._lib.fsv_batch_energy_grad(self._h, _dptr(th), ctypes.c_void_p(self.arena.data_ptr()),
+                                              _dptr(e), _dptr(g)))
         if flat:
             return e, g
         o = self._offsets
@@ -352,7 +372,7 @@ class Batch:
 
     def autotune(self) -> str:
         rep = ctypes.c_char_p()
-        check(self._lib.fsv_batch_autotune(self._h, ctypes.byref(rep)))
+        check(self._lib.fsv_batch_autotune(self._h, ctypes.c_void_p(self.arena.data_ptr()), ctypes.byref(rep)))
         return rep.value.decode() if rep.value else ""
 
     def close(self):

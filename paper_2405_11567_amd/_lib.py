@@ -43,6 +43,7 @@ class Problem(ctypes.Structure):
 
 EXPORTS = [
     "fsv_last_error", "fsv_plan_create", "fsv_plan_destroy", "fsv_state_bytes", "fsv_plan_info",
+    "fsv_plan_workspace_bytes", "fsv_plan_device_bytes", "fsv_plan_set_workspace", "fsv_batch_arena_bytes",
     "fsv_plan_set_engine", "fsv_plan_runs", "fsv_time_runs",
     "ansatz_apply", "energy", "energy_grad", "energy_grad_fd", "rdm1", "set_onebody_potential",
     "fsv_set_theta", "fsv_forward_async", "fsv_sigma_async", "fsv_reverse_async", "fsv_finish",
@@ -71,6 +72,10 @@ def load():
     lib.fsv_state_bytes.argtypes = [vp]
     lib.fsv_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_uint64)]
+    for name in ("fsv_plan_workspace_bytes", "fsv_plan_device_bytes", "fsv_batch_arena_bytes"):
+        getattr(lib, name).restype = ctypes.c_size_t
+        getattr(lib, name).argtypes = [vp]
+    lib.fsv_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
     lib.fsv_plan_set_engine.argtypes = [vp, c_int]
     lib.fsv_plan_runs.argtypes = [vp, c_int, i32, i32]
     lib.fsv_time_runs.argtypes = [vp, c_int, vp, vp, ctypes.POINTER(ctypes.c_float)]
@@ -88,17 +93,18 @@ def load():
     lib.fsv_autotune.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_char_p)]
     lib.fsv_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Problem), ctypes.c_int32, vp]
     lib.fsv_batch_destroy.argtypes = [vp]
-    lib.fsv_batch_energy_grad.argtypes = [vp, d, d, d]
+    lib.fsv_batch_energy_grad.argtypes = [vp, d, vp, d, d]
     lib.fsv_batch_bytes.restype = ctypes.c_size_t
     lib.fsv_batch_bytes.argtypes = [vp]
-    lib.fsv_batch_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p)]
+    lib.fsv_batch_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_char_p)]
     lib.fsv_pool_create.argtypes = [ctypes.POINTER(vp), vp, i32, ctypes.c_int32, ctypes.c_int32]
     lib.fsv_pool_destroy.argtypes = [vp]
     lib.fsv_pool_gradients.argtypes = [vp, d, vp, vp, d, d]
     lib.fsv_set_initial_state.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), d]
     lib.onebody_expectation.argtypes = [vp, vp, d, d]
     for name in EXPORTS:
-        if name not in ("fsv_last_error", "fsv_state_bytes", "fsv_batch_bytes"):
+        if name not in ("fsv_last_error", "fsv_state_bytes", "fsv_batch_bytes", "fsv_plan_workspace_bytes",
+                        "fsv_plan_device_bytes", "fsv_batch_arena_bytes"):
             getattr(lib, name).restype = c_int
     _lib = lib
     return lib

@@ -594,7 +594,7 @@ __global__ void k_zero_int(int *p) {
 }
 
 template <typename T>
-int dmalloc(std::vector<void *> &owned, T **out, size_t count) {
+int dmalloc(std::vector<void *> &owned, size_t &total, T **out, size_t count) {
     void *p = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
     hipError_t e = hipMalloc(&p, bytes);
@@ -603,6 +603,7 @@ int dmalloc(std::vector<void *> &owned, T **out, size_t count) {
         return fail(FSV_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     }
     owned.push_back(p);
+    total += bytes;
     *out = (T *)p;
     return FSV_OK;
 }
@@ -629,7 +630,8 @@ struct fsv_batch {
     double *d_grad = nullptr, *d_e = nullptr;
     int64_t *d_hptr = nullptr;
     int32_t *d_hcol = nullptr, *d_ellc = nullptr;
-    double *d_arena = nullptr;
+    double *d_arena = nullptr;  // the caller's arena of the current call (arena_bytes)
+    size_t arena_bytes = 0;
     double *h_pin = nullptr;  // theta (total_k) | spare (total_k) | grad (total_k) | E (count)
     int block = 256, per_cu = 2, cus = 256;
     int mode = 1;       // 0 persistent work-queue kernel, 1 phased launches, 2 packet runs
@@ -1076,26 +1078,23 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         B->lds_max = std::min(B->lds_max, lim);
     }
     auto& o = B->owned;
-    if ((rc = dmalloc(o, &B->d_inst, B->inst.size())) || (rc = dmalloc(o, &B->d_order, count)) ||
-        (rc = dmalloc(o, &B->d_counter, 4)) || (rc = dmalloc(o, &B->d_tinst, tinst.size())) ||
-        (rc = dmalloc(o, &B->d_ops, ops.size())) || (rc = dmalloc(o, &B->d_lists, lists.size())) ||
-        (rc = dmalloc(o, &B->d_excA, excA.size())) || (rc = dmalloc(o, &B->d_excBT, excBT.size())) ||
-        (rc = dmalloc(o, &B->d_cs, 2 * (size_t)kk)) || (rc = dmalloc(o, &B->d_theta, std::max<size_t>(kk, 1))) ||
-        (rc = dmalloc(o, &B->d_g, gall.size())) ||
-        (rc = dmalloc(o, &B->d_hval, hval.size())) || (rc = dmalloc(o, &B->d_hptr, hptr.size())) ||
-        (rc = dmalloc(o, &B->d_hcol, hcol.size())) || (rc = dmalloc(o, &B->d_ellc, ellc.size())) ||
-        (rc = dmalloc(o, &B->d_ellv, ellv.size())) || (rc = dmalloc(o, &B->d_grad, (size_t)kk)) ||
-        (rc = dmalloc(o, &B->d_e, (size_t)count)) || (rc = dmalloc(o, &B->d_arena, (size_t)state)) ||
-        (rc = dmalloc(o, &B->d_epart, (size_t)B->ntasks)) || (rc = dmalloc(o, &B->d_lt, std::max<size_t>(ltall.size(), 1))) ||
-        (rc = dmalloc(o, &B->d_ldiag, std::max<size_t>(ldiag.size(), 1))) ||
-        (rc = dmalloc(o, &B->d_hd, std::max<size_t>(hdense.size(), 1))) ||
-        (rc = dmalloc(o, &B->d_pss, std::max<size_t>(pss.size(), 1))) ||
-        (rc = dmalloc(o, &B->d_gpart, (size_t)kk * B->part_cap)))
+    if ((rc = dmalloc(o, B->bytes, &B->d_inst, B->inst.size())) || (rc = dmalloc(o, B->bytes, &B->d_order, count)) ||
+        (rc = dmalloc(o, B->bytes, &B->d_counter, 4)) || (rc = dmalloc(o, B->bytes, &B->d_tinst, tinst.size())) ||
+        (rc = dmalloc(o, B->bytes, &B->d_ops, ops.size())) || (rc = dmalloc(o, B->bytes, &B->d_lists, lists.size())) ||
+        (rc = dmalloc(o, B->bytes, &B->d_excA, excA.size())) || (rc = dmalloc(o, B->bytes, &B->d_excBT, excBT.size())) ||
+        (rc = dmalloc(o, B->bytes, &B->d_cs, 2 * (size_t)kk)) || (rc = dmalloc(o, B->bytes, &B->d_theta, std::max<size_t>(kk, 1))) ||
+        (rc = dmalloc(o, B->bytes, &B->d_g, gall.size())) ||
+        (rc = dmalloc(o, B->bytes, &B->d_hval, hval.size())) || (rc = dmalloc(o, B->bytes, &B->d_hptr, hptr.size())) ||
+        (rc = dmalloc(o, B->bytes, &B->d_hcol, hcol.size())) || (rc = dmalloc(o, B->bytes, &B->d_ellc, ellc.size())) ||
+        (rc = dmalloc(o, B->bytes, &B->d_ellv, ellv.size())) || (rc = dmalloc(o, B->bytes, &B->d_grad, (size_t)kk)) ||
+        (rc = dmalloc(o, B->bytes, &B->d_e, (size_t)count)) ||
+        (rc = dmalloc(o, B->bytes, &B->d_epart, (size_t)B->ntasks)) || (rc = dmalloc(o, B->bytes, &B->d_lt, std::max<size_t>(ltall.size(), 1))) ||
+        (rc = dmalloc(o, B->bytes, &B->d_ldiag, std::max<size_t>(ldiag.size(), 1))) ||
+        (rc = dmalloc(o, B->bytes, &B->d_hd, std::max<size_t>(hdense.size(), 1))) ||
+        (rc = dmalloc(o, B->bytes, &B->d_pss, std::max<size_t>(pss.size(), 1))) ||
+        (rc = dmalloc(o, B->bytes, &B->d_gpart, (size_t)kk * B->part_cap)))
         return fin(rc);
-    B->bytes = sizeof(BInst) * B->inst.size() + sizeof(int) * (count + 4) + 4 * tinst.size() +
-               sizeof(BOp) * ops.size() + 4 * (lists.size() + excA.size() + excBT.size() + hcol.size() + ellc.size()) +
-               8 * (2 * kk + gall.size() + hval.size() + hptr.size() + ellv.size() + kk + count) +
-               8 * ((size_t)B->ntasks + (size_t)kk * B->part_cap) + 8 * (size_t)state + 8 * (ltall.size() + ldiag.size() + hdense.size()) + 4 * pss.size();
+    B->arena_bytes = 8 * (size_t)std::max<int64_t>(state, 1);
     struct Up { void *d; const void *h; size_t n; };
     const Up ups[] = {
         {B->d_order, B->order.data(), sizeof(int) * count},
@@ -1128,15 +1127,14 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
         for (const BInst &I : B->inst) pi.push_back({I.nsa, I.nsb, I.off_state, I.off_ops, I.off_k, I.K});
         if ((rc = build_batch_packets(pi, ops, lists, B->pk))) return fin(rc);
         const BatchPackets &P = B->pk;
-        if ((rc = dmalloc(o, &B->d_pent, std::max<size_t>(P.ent.size(), 1))) ||
-            (rc = dmalloc(o, &B->d_preg, std::max<size_t>(P.reg.size(), 1))) ||
-            (rc = dmalloc(o, &B->d_pcount, (size_t)kk)) || (rc = dmalloc(o, &B->d_pgpart, (size_t)kk * P.pstride)))
+        if ((rc = dmalloc(o, B->bytes, &B->d_pent, std::max<size_t>(P.ent.size(), 1))) ||
+            (rc = dmalloc(o, B->bytes, &B->d_preg, std::max<size_t>(P.reg.size(), 1))) ||
+            (rc = dmalloc(o, B->bytes, &B->d_pcount, (size_t)kk)) || (rc = dmalloc(o, B->bytes, &B->d_pgpart, (size_t)kk * P.pstride)))
             return fin(rc);
         if ((!P.ent.empty() && hipMemcpy(B->d_pent, P.ent.data(), 4 * P.ent.size(), hipMemcpyHostToDevice) != hipSuccess) ||
             (!P.reg.empty() && hipMemcpy(B->d_preg, P.reg.data(), 4 * P.reg.size(), hipMemcpyHostToDevice) != hipSuccess) ||
             hipMemcpy(B->d_pcount, P.count.data(), 4 * (size_t)kk, hipMemcpyHostToDevice) != hipSuccess)
             return fin(fail(FSV_EDEVICE, "upload of packet runs failed"));
-        B->bytes += 4 * (P.ent.size() + P.reg.size() + (size_t)kk) + 8 * (size_t)kk * P.pstride;
         B->pk_ok = true;
         B->mode = 2;
     }
@@ -1153,16 +1151,41 @@ int fsv_batch_destroy(fsv_batch *B) {
 
 size_t fsv_batch_bytes(const fsv_batch *B) { return B ? B->bytes : 0; }
 
-int fsv_batch_energy_grad(fsv_batch *B, const double *theta, double *E_out, double *grad_out) {
+size_t fsv_batch_arena_bytes(const fsv_batch *B) { return B ? B->arena_bytes : 0; }
+
+}  // extern "C"
+
+namespace {
+// The caller's arena for this call: a different block than the captured
+// graph's drops that graph.
+int bind_arena(fsv_batch &B, void *arena) {
+    if (!arena) return fail(FSV_EINVAL, "arena_dev is NULL");
+    if ((uintptr_t)arena & 255) return fail(FSV_EINVAL, "the arena must be 256-byte aligned");
+    if ((double *)arena != B.d_arena) {
+        if (B.work) BHIP(hipStreamSynchronize(B.work));
+        if (B.graph) (void)hipGraphExecDestroy(B.graph);
+        B.graph = nullptr;
+        B.d_arena = (double *)arena;
+    }
+    return FSV_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fsv_batch_energy_grad(fsv_batch *B, const double *theta, void *arena_dev, double *E_out, double *grad_out) {
     if (!B) return fail(FSV_EINVAL, "batch is NULL");
     if (B->total_k > 0 && (!theta || !grad_out)) return fail(FSV_EINVAL, "theta and grad_out are required");
     if (!E_out) return fail(FSV_EINVAL, "E_out is NULL");
+    int rc = bind_arena(*B, arena_dev);
+    if (rc) return rc;
     return run(*B, theta, E_out, grad_out);
 }
 
-int fsv_batch_autotune(fsv_batch *B, const char **report) {
+int fsv_batch_autotune(fsv_batch *B, void *arena_dev, const char **report) {
     static thread_local std::string rep;
     if (!B) return fail(FSV_EINVAL, "batch is NULL");
+    if (int rc = bind_arena(*B, arena_dev)) return rc;
     std::vector<double> th(B->total_k, 0.1), e(B->count), g(B->total_k);
     {
         int rc = run(*B, th.data(), e.data(), g.data());  // also leaves valid angles on the device

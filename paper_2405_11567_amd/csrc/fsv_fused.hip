@@ -276,6 +276,7 @@ uint32_t spin_mask(const int32_t *op, int spin) {
 
 void FusedSched::release() {
     mem.clear();
+    bytes = 0;
     groups.clear();
     count.clear();
     d_aprog = d_bprog = nullptr;
@@ -508,6 +509,7 @@ int build_fused(int M, const std::vector<uint32_t> &sa, const std::vector<uint32
             return fail(FSV_ENOMEM, "hipMalloc of %zu bytes for fused programs failed", bytes);
         }
         S.mem.emplace_back(p, [](void *q) { (void)hipFree(q); });
+        S.bytes += bytes;
         if (!vec.empty() && hipMemcpy(p, vec.data(), vec.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
             return fail(FSV_EDEVICE, "upload of fused programs failed");
         *dst = (uint32_t *)p;

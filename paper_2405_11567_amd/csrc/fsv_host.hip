@@ -119,9 +119,15 @@ struct fsv_plan {
     int32_t *d_ha_desc = nullptr, *d_hb_desc = nullptr;                   // one-body descriptors
     uint32_t *d_str_a = nullptr, *d_str_b = nullptr;                      // string masks
     int32_t *d_binA_off = nullptr, *d_binA_idx = nullptr, *d_binB_off = nullptr, *d_binB_idx = nullptr;
-    // d_C also holds the interleaved (psi, lam) pairs of a packet adjoint sweep
+    // Sector workspace: one block, caller-provided (fsv_plan_set_workspace) or
+    // allocated by the plan on first use, holding d_C .. d_epart below.
+    // d_C also holds the interleaved (psi, lam) pairs of a packet adjoint sweep.
     double2 *d_C = nullptr, *d_S = nullptr, *d_CT = nullptr, *d_ST = nullptr, *d_O = nullptr;
-    double2 *d_gamma = nullptr;
+    double2 *d_gamma = nullptr, *d_YT = nullptr;
+    void *ws = nullptr;
+    bool ws_owned = false, ws_warm = false;
+    size_t ws_bytes = 0;
+    size_t ws_off[10] = {};  // byte offsets of C, S, CT, ST, O, gamma, YT, gpart, epart; [9] = end
     double *h_pin = nullptr;  // pinned: cs (2K) then out (K + 1) then gamma (4 M^2)
     size_t pin_doubles = 0;
 
@@ -1290,9 +1296,7 @@ int build_device(fsv_plan &P) {
 
     if ((rc = dalloc(P, &P.d_rot, P.K))) return rc;
     if ((rc = dalloc(P, &P.d_cs, 2 * (size_t)P.K))) return rc;
-    if ((rc = dalloc(P, &P.d_gpart, (size_t)std::max(P.K, 1) * G))) return rc;
     if ((rc = dalloc(P, &P.d_gcount, (size_t)P.K))) return rc;
-    if ((rc = dalloc(P, &P.d_epart, 1024))) return rc;
     if ((rc = dalloc(P, &P.d_ecount, 1))) return rc;
     if ((rc = dalloc(P, &P.d_out, (size_t)P.K + 1))) return rc;
     if ((rc = dalloc(P, &P.d_Xa, P.nsa))) return rc;
@@ -1307,12 +1311,6 @@ int build_device(fsv_plan &P) {
     if ((rc = dalloc(P, &P.d_binA_idx, biA.size()))) return rc;
     if ((rc = dalloc(P, &P.d_binB_off, boB.size()))) return rc;
     if ((rc = dalloc(P, &P.d_binB_idx, biB.size()))) return rc;
-    if ((rc = dalloc(P, &P.d_C, P.dim))) return rc;
-    if ((rc = dalloc(P, &P.d_S, P.dim))) return rc;
-    if ((rc = dalloc(P, &P.d_CT, P.dim))) return rc;
-    if ((rc = dalloc(P, &P.d_ST, P.dim))) return rc;
-    if ((rc = dalloc(P, &P.d_O, std::max(P.nsa * P.nexcA, P.nsb * P.nexcB)))) return rc;
-    if ((rc = dalloc(P, &P.d_gamma, 2 * M2))) return rc;
 
     if ((rc = upload(P, P.d_rot, P.rot.data(), P.rot.size()))) return rc;
     if ((rc = upload(P, P.d_Xa, Xa.data(), Xa.size()))) return rc;
@@ -1383,7 +1381,6 @@ int build_device(fsv_plan &P) {
     std::vector<double> Lt;
     choose_sigma(P, R, Lt);
     double *d_Lt = nullptr, *d_lda = nullptr, *d_ldb = nullptr;
-    double2 *d_YT = nullptr;
     if (R > 0) {
         const int rp = lr_pad(R);
         const std::vector<double> da = diag_factor_sums(M, P.sa, Lt, rp), db = diag_factor_sums(M, P.sb, Lt, rp);
@@ -1391,9 +1388,21 @@ int build_device(fsv_plan &P) {
         if ((rc = upload(P, d_Lt, Lt.data(), Lt.size()))) return rc;
         if ((rc = dalloc(P, &d_lda, da.size())) || (rc = upload(P, d_lda, da.data(), da.size()))) return rc;
         if ((rc = dalloc(P, &d_ldb, db.size())) || (rc = upload(P, d_ldb, db.data(), db.size()))) return rc;
-        if ((rc = dalloc(P, &d_YT, (size_t)rp * P.dim))) return rc;  // complex-sized
     }
     P.lr_R = R;
+    {  // workspace layout (256-byte aligned parts)
+        const size_t parts[9] = {16 * (size_t)P.dim, 16 * (size_t)P.dim, 16 * (size_t)P.dim, 16 * (size_t)P.dim,
+                                 16 * (size_t)std::max<int64_t>(std::max(P.nsa * P.nexcA, P.nsb * P.nexcB), 1),
+                                 16 * 2 * M2, R > 0 ? 16 * (size_t)lr_pad(R) * P.dim : 0,
+                                 8 * (size_t)std::max(P.K, 1) * G, 8 * 1024};
+        size_t at = 0;
+        for (int i = 0; i < 9; ++i) {
+            P.ws_off[i] = at;
+            at += (parts[i] + 255) & ~(size_t)255;
+        }
+        P.ws_off[9] = at;
+        P.ws_bytes = at;
+    }
     if (want_dense_same_spin(P)) {
         if (rocblas_create_handle(&P.blas) != rocblas_status_success) {
             P.blas = nullptr;
@@ -1408,18 +1417,61 @@ int build_device(fsv_plan &P) {
     }
     P.tabs = SectorTabs{P.nsa, P.nsb, M, P.nexcA, P.nexcB, P.d_ha_ptr, P.d_hb_ptr, P.d_ha_col,
                         P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_excBT, P.d_g, P.ecore,
-                        R, d_Lt, d_YT, P.d_ha_dense, P.d_hb_dense, (void *)P.blas, P.d_hb_dense_t,
+                        R, d_Lt, nullptr, P.d_ha_dense, P.d_hb_dense, (void *)P.blas, P.d_hb_dense_t,
                         d_lda, d_ldb, P.na, P.nb};
-    if (P.blas) {
+    return FSV_OK;
+}
+
+// Point the workspace parts into the block at base (device, ws_bytes).
+// Captured graphs name the old parts, so they are dropped.
+int bind_workspace(fsv_plan &P, void *base) {
+    char *b = (char *)base;
+    P.ws = base;
+    P.d_C = (double2 *)(b + P.ws_off[0]);
+    P.d_S = (double2 *)(b + P.ws_off[1]);
+    P.d_CT = (double2 *)(b + P.ws_off[2]);
+    P.d_ST = (double2 *)(b + P.ws_off[3]);
+    P.d_O = (double2 *)(b + P.ws_off[4]);
+    P.d_gamma = (double2 *)(b + P.ws_off[5]);
+    P.d_YT = P.lr_R > 0 ? (double2 *)(b + P.ws_off[6]) : nullptr;
+    P.d_gpart = (double *)(b + P.ws_off[7]);
+    P.d_epart = (double *)(b + P.ws_off[8]);
+    P.tabs.YT = P.d_YT;
+    drop_graphs(P);
+    if (P.blas && !P.ws_warm) {
         // one eager product per amplitude type, outside any graph capture, so
-        // that the library has loaded its kernels and sized its workspace
-        // before the first capture (the work buffers hold no state yet)
+        // that the GEMM library has loaded its kernels and sized its own
+        // workspace before the first capture (the work buffers hold no state)
         HIPCHECK(launch_fill_zero(P.d_C, (size_t)P.dim * sizeof(double2), P.work));
         HIPCHECK(launch_sector_sigma(false, P.tabs, P.d_C, P.d_S, P.d_CT, P.d_ST, P.d_epart, P.work));
         HIPCHECK(launch_sector_sigma(true, P.tabs, P.d_C, P.d_S, P.d_CT, P.d_ST, P.d_epart, P.work));
         HIPCHECK(hipStreamSynchronize(P.work));
+        P.ws_warm = true;
     }
     return FSV_OK;
+}
+
+void release_workspace(fsv_plan &P) {
+    if (P.ws_owned && P.ws) (void)hipFree(P.ws);
+    P.ws = nullptr;
+    P.ws_owned = false;
+}
+
+// The workspace of a call: the caller's block, or the plan's own, allocated
+// on the first call that needs one.
+int need_workspace(fsv_plan &P) {
+    if (P.ws) return FSV_OK;
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, P.ws_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FSV_ENOMEM, "hipMalloc of the %zu-byte plan workspace failed: %s", P.ws_bytes,
+                    hipGetErrorString(e));
+    }
+    P.ws_owned = true;
+    const int rc = bind_workspace(P, p);
+    if (rc) release_workspace(P);
+    return rc;
 }
 
 }  // namespace
@@ -1427,6 +1479,7 @@ int build_device(fsv_plan &P) {
 fsv_plan::~fsv_plan() {
     for (fsv_pool *q : pools) q->plan = nullptr;
     drop_graphs(*this);
+    release_workspace(*this);
     for (void *p : init_mem) (void)hipFree(p);
     if (blas) (void)rocblas_destroy_handle(blas);
     for (auto &b : bufs) (void)hipFree(b.p);
@@ -1566,6 +1619,35 @@ size_t fsv_state_bytes(const fsv_plan *P) {
     return ((size_t)1 << P->n) * (size_t)P->amp_bytes;
 }
 
+size_t fsv_plan_workspace_bytes(const fsv_plan *P) { return P ? P->ws_bytes : 0; }
+
+size_t fsv_plan_device_bytes(const fsv_plan *P) {
+    if (!P) return 0;
+    size_t t = 0;
+    for (const DevBuf &b : P->bufs) t += b.bytes;
+    t += P->frev.bytes;                  // the forward schedule shares these or
+    if (P->ffwd.mem != P->frev.mem) t += P->ffwd.bytes;  // holds its own
+    t += 32 * (size_t)P->n_init;         // initial-state lists (4 x 8 bytes per determinant)
+    if (P->ws_owned) t += P->ws_bytes;
+    return t;
+}
+
+int fsv_plan_set_workspace(fsv_plan *P, void *ws_dev, size_t bytes) {
+    if (!P) return fail(FSV_EINVAL, "plan is NULL");
+    if (ws_dev && bytes < P->ws_bytes)
+        return fail(FSV_EINVAL, "workspace of %zu bytes; the plan needs %zu", bytes, P->ws_bytes);
+    if (ws_dev && ((uintptr_t)ws_dev & 255))
+        return fail(FSV_EINVAL, "the workspace must be 256-byte aligned");
+    if (ws_dev == P->ws) return FSV_OK;
+    if (P->work) HIPCHECK(hipStreamSynchronize(P->work));
+    release_workspace(*P);
+    drop_graphs(*P);
+    if (!ws_dev) return FSV_OK;  // the plan allocates its own on the next call
+    const int rc = bind_workspace(*P, ws_dev);
+    if (rc) P->ws = nullptr;
+    return rc;
+}
+
 int fsv_plan_info(const fsv_plan *P, int64_t *nsa, int64_t *nsb, uint64_t *ref) {
     if (!P) return fail(FSV_EINVAL, "plan is NULL");
     if (nsa) *nsa = P->nsa;
@@ -1605,6 +1687,7 @@ int fsv_time_runs(fsv_plan *P, int adjoint, void *psi, void *lam, float *ms) {
     if (P->engine != 0) return fail(FSV_ESTATE, "per-run timing is available on the sector engine only");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     if ((rc = time_sweep_sector(*P, adjoint, psi, lam, ms))) return rc;
     if ((rc = fence_out(*P))) return rc;
     return (int)(adjoint ? P->frev : P->ffwd).groups.size();
@@ -1622,6 +1705,7 @@ int fsv_forward_async(fsv_plan *P, void *psi) {
     if (!P || !psi) return fail(FSV_EINVAL, "plan or psi is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     if ((rc = enq_forward(*P, psi))) return rc;
     return fence_out(*P);
 }
@@ -1630,6 +1714,7 @@ int fsv_sigma_async(fsv_plan *P, const void *psi, void *lam) {
     if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     if ((rc = enq_sigma(*P, psi, lam))) return rc;
     return fence_out(*P);
 }
@@ -1638,6 +1723,7 @@ int fsv_reverse_async(fsv_plan *P, void *psi, void *lam) {
     if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     if ((rc = enq_reverse(*P, psi, lam))) return rc;
     return fence_out(*P);
 }
@@ -1654,6 +1740,7 @@ int ansatz_apply(fsv_plan *P, const double *theta, void *psi) {
     if (!P || !psi) return fail(FSV_EINVAL, "plan or psi is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
     if ((rc = enq_ansatz_dense_out(*P, psi))) return rc;
     HIPCHECK(hipStreamSynchronize(P->work));
@@ -1664,6 +1751,7 @@ int energy(fsv_plan *P, const void *psi, double *E_out) {
     if (!P || !psi || !E_out) return fail(FSV_EINVAL, "plan, psi or E_out is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     if ((rc = enq_sigma_dense(*P, psi, nullptr))) return rc;
     if ((rc = download_out(*P, E_out, nullptr, false))) return rc;
     return fence_out(*P);
@@ -1676,6 +1764,7 @@ int energy_grad(fsv_plan *P, const double *theta, void *psi, void *lam, double *
     if (P->K > 0 && !grad_out) return fail(FSV_EINVAL, "grad_out is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
     if ((rc = launch_energy_grad(*P, psi, lam))) return rc;
     if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
@@ -1689,6 +1778,7 @@ int energy_grad_fd(fsv_plan *P, const double *theta, double step, void *psi, dou
     if (P->K > 0 && !grad_out) return fail(FSV_EINVAL, "grad_out is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     std::vector<double> th(theta, theta + P->K);
     double e0 = 0.0;
     if ((rc = upload_theta(*P, th.data()))) return rc;
@@ -1715,6 +1805,7 @@ int rdm1(fsv_plan *P, const void *psi, double *gamma_out) {
     if (!P || !psi || !gamma_out) return fail(FSV_EINVAL, "plan, psi or gamma_out is NULL");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     hipStream_t st = P->work;
     const int M2 = P->M * P->M;
     HIPCHECK(launch_gather(P->precision, psi, P->d_Xa, P->d_Xb, P->d_sa, P->d_PPb, P->nsa, P->nsb, P->d_C, st));
@@ -1765,6 +1856,7 @@ int fsv_autotune(fsv_plan *P, void *psi, void *lam, const char **report) {
     if (psi == lam) return fail(FSV_EINVAL, "psi and lam must be distinct buffers");
     int rc;
     if ((rc = fence_in(*P))) return rc;
+    if ((rc = need_workspace(*P))) return rc;
     if (P->engine == 0) {
         if ((rc = autotune_sector(*P, psi, lam, rep))) return rc;
         if (report) *report = rep.c_str();
@@ -2027,6 +2119,7 @@ int fsv_pool_gradients(fsv_pool *Q, const double *theta, void *psi, void *lam, d
     if (P.engine != 0) return fail(FSV_ESTATE, "pool screening runs on the sector engine");
     int rc;
     if ((rc = fence_in(P))) return rc;
+    if ((rc = need_workspace(P))) return rc;
     if ((rc = upload_theta(P, theta))) return rc;
     auto body = [&]() -> int {
         int r;

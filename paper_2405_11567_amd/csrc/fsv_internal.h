@@ -243,6 +243,7 @@ struct FusedSched {
     uint32_t *d_aprog = nullptr, *d_bprog = nullptr;  // packet runs: index lists, regions
     bool packets = false;        // built by build_packets: the adjoint sweep runs on (psi, lam) pairs
     std::vector<std::shared_ptr<void>> mem;  // device buffers (shared by schedules that alias them)
+    size_t bytes = 0;                        // their size
     void release();
     void share(const FusedSched &o) {  // the same runs and device tables as o
         release();
@@ -252,6 +253,7 @@ struct FusedSched {
         d_bprog = o.d_bprog;
         packets = o.packets;
         mem = o.mem;
+        bytes = o.bytes;
     }
     FusedSched() = default;
     FusedSched(const FusedSched &) = delete;

@@ -435,6 +435,7 @@ int upload_words(const std::vector<uint32_t> &vec, FusedSched &S, uint32_t **dst
         return fail(FSV_ENOMEM, "hipMalloc of %zu bytes for packet programs failed", bytes);
     }
     S.mem.emplace_back(p, [](void *q) { (void)hipFree(q); });
+    S.bytes += bytes;
     if (!vec.empty() && hipMemcpy(p, vec.data(), vec.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
         return fail(FSV_EDEVICE, "upload of packet programs failed");
     *dst = (uint32_t *)p;

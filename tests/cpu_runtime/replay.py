@@ -55,13 +55,17 @@ for name, args in {
     "fsv_set_initial_state": [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), D],
     "onebody_expectation": [vp, vp, D, D],
     "fsv_batch_create": [ctypes.POINTER(vp), ctypes.POINTER(CProblem), ctypes.c_int32, vp],
-    "fsv_batch_destroy": [vp], "fsv_batch_energy_grad": [vp, D, D, D],
-    "fsv_batch_autotune": [vp, ctypes.POINTER(ctypes.c_char_p)],
+    "fsv_batch_destroy": [vp], "fsv_batch_energy_grad": [vp, D, vp, D, D],
+    "fsv_batch_autotune": [vp, vp, ctypes.POINTER(ctypes.c_char_p)],
 }.items():
     getattr(lib, name).argtypes = args
     getattr(lib, name).restype = ctypes.c_int
-lib.fsv_state_bytes.restype = ctypes.c_size_t
-lib.fsv_state_bytes.argtypes = [vp]
+for name in ("fsv_state_bytes", "fsv_plan_workspace_bytes", "fsv_plan_device_bytes", "fsv_batch_arena_bytes",
+             "fsv_batch_bytes"):
+    getattr(lib, name).restype = ctypes.c_size_t
+    getattr(lib, name).argtypes = [vp]
+lib.fsv_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+lib.fsv_plan_set_workspace.restype = ctypes.c_int
 
 
 def dp(a):
@@ -107,9 +111,25 @@ def make_plan(p, precision=0, engine=0):
     return h
 
 
-def exercise_plan(p, precision=0, engine=0, fd=False, stages=True, extras=True):
-    """The calls a GPU parity test makes on one plan."""
+def exercise_plan(p, precision=0, engine=0, fd=False, stages=True, extras=True, caller_ws=None):
+    """The calls a GPU parity test makes on one plan.  The device memory the
+    plan reports owning must be exactly what it allocated: its tables after
+    creation, plus its own workspace once a call needed one, or the tables
+    alone with a caller workspace (every other case a caller workspace)."""
+    live0 = stub.hip_stub_live_device_bytes()
     plan = make_plan(p, precision, engine)
+    tables = lib.fsv_plan_device_bytes(plan)
+    if stub.hip_stub_live_device_bytes() - live0 != tables:
+        raise RuntimeError("fsv_plan_device_bytes does not match the plan's allocations")
+    global _ws_turn
+    _ws_turn = (_ws_turn + 1) % 2
+    wsb = lib.fsv_plan_workspace_bytes(plan)
+    ws = None
+    if caller_ws if caller_ws is not None else _ws_turn:
+        ws = Dev(wsb)
+        ok(lib.fsv_plan_set_workspace(plan, ws.p, wsb), "set_workspace")
+        if lib.fsv_plan_set_workspace(plan, ws.p, wsb - 8) != -1:
+            raise RuntimeError("a too-small workspace must be rejected")
     k = p.n_ops
     sb = lib.fsv_state_bytes(plan)
     psi, lam = Dev(sb), Dev(sb)
@@ -120,6 +140,9 @@ def exercise_plan(p, precision=0, engine=0, fd=False, stages=True, extras=True):
         ok(lib.energy_grad(plan, dp(th), psi.p, lam.p, ctypes.byref(e), dp(grad)), "energy_grad")
     psi2, lam2 = Dev(sb), Dev(sb)  # new buffers: the graph is captured again
     ok(lib.energy_grad(plan, dp(th), psi2.p, lam2.p, ctypes.byref(e), dp(grad)), "energy_grad")
+    own = lib.fsv_plan_device_bytes(plan) - tables
+    if own != (0 if ws else wsb):
+        raise RuntimeError(f"plan-owned workspace {own} bytes, expected {0 if ws else wsb}")
     ok(lib.ansatz_apply(plan, dp(th), psi.p), "ansatz_apply")
     ok(lib.energy(plan, psi.p, ctypes.byref(e)), "energy")
     if extras:
@@ -145,6 +168,13 @@ def exercise_plan(p, precision=0, engine=0, fd=False, stages=True, extras=True):
     for b in (psi, lam, psi2, lam2):
         b.free()
     ok(lib.fsv_plan_destroy(plan), "destroy")
+    if ws:
+        ws.free()
+    if stub.hip_stub_live_device_bytes() != live0:
+        raise RuntimeError("the plan left device memory behind")
+
+
+_ws_turn = 0
 
 
 def with_env(env, fn):
@@ -319,17 +349,26 @@ def run_batch(probs, tune=False):
     for i, p in enumerate(probs):
         arr[i] = cproblem(p, 0, keep)
     b = vp()
+    live0 = stub.hip_stub_live_device_bytes()
     ok(lib.fsv_batch_create(ctypes.byref(b), arr, len(probs), None), "batch create")
+    if stub.hip_stub_live_device_bytes() - live0 != lib.fsv_batch_bytes(b):
+        raise RuntimeError("fsv_batch_bytes does not match the batch's allocations")
+    arena = Dev(lib.fsv_batch_arena_bytes(b))
+    arena2 = Dev(lib.fsv_batch_arena_bytes(b))
     th = np.ascontiguousarray(np.concatenate([p.theta for p in probs]) if probs else np.zeros(0))
     e = np.zeros(len(probs))
     g = np.zeros(max(th.size, 1))
-    for _ in range(2):
-        ok(lib.fsv_batch_energy_grad(b, dp(th), dp(e), dp(g)), "batch eval")
+    for a in (arena, arena, arena2):
+        ok(lib.fsv_batch_energy_grad(b, dp(th), a.p, dp(e), dp(g)), "batch eval")
     if tune:
         rep = ctypes.c_char_p()
-        ok(lib.fsv_batch_autotune(b, ctypes.byref(rep)), "batch autotune")
-        ok(lib.fsv_batch_energy_grad(b, dp(th), dp(e), dp(g)), "batch eval")
+        ok(lib.fsv_batch_autotune(b, arena.p, ctypes.byref(rep)), "batch autotune")
+        ok(lib.fsv_batch_energy_grad(b, dp(th), arena.p, dp(e), dp(g)), "batch eval")
     ok(lib.fsv_batch_destroy(b), "batch destroy")
+    arena.free()
+    arena2.free()
+    if stub.hip_stub_live_device_bytes() != live0:
+        raise RuntimeError("the batch left device memory behind")
 
 
 def suite_c3():

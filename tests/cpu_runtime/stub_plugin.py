@@ -57,17 +57,20 @@ def pytest_configure(config):
     stub.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
     stub.hipFree.argtypes = [ctypes.c_void_p]
 
-    def new_state(self):
-        nbytes = (1 << self.n_qubits) * (16 if self.precision == 0 else 8)
+    def stub_tensor(nbytes, dtype):
         p = ctypes.c_void_p()
-        if stub.hipMalloc(ctypes.byref(p), nbytes) != 0:
+        if stub.hipMalloc(ctypes.byref(p), max(nbytes, 1)) != 0:
             raise MemoryError("stand-in hipMalloc failed")
-        buf = (ctypes.c_char * nbytes).from_address(p.value)
-        t = torch.frombuffer(buf, dtype=self.dtype)
+        buf = (ctypes.c_char * max(nbytes, 1)).from_address(p.value)
+        t = torch.frombuffer(buf, dtype=dtype)
         weakref.finalize(t, stub.hipFree, p.value)
         return t
 
+    def new_state(self):
+        return stub_tensor((1 << self.n_qubits) * (16 if self.precision == 0 else 8), self.dtype)
+
     fsv.Plan.new_state = new_state
+    fsv._device_buffer = lambda device, nbytes: stub_tensor(int(nbytes), torch.uint8)
 
     # the oracle: its AddressSanitizer build when one is present
     asan_oracle = os.environ.get("FSV_ORACLE_LIB")

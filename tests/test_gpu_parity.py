@@ -310,6 +310,34 @@ def test_alpha_beta_general_integrals(fsv, n, ne, nfac, engine):
     assert np.abs(gam - ref).max() < 1e-12
 
 
+def test_workspace_ownership(fsv):
+    # the binding hands the plan a PyTorch workspace, so the plan owns only its
+    # tables; given none, the plan allocates exactly fsv_plan_workspace_bytes
+    # itself on the first call; results are the same either way, and a
+    # too-small or misaligned workspace is refused
+    import ctypes
+    p = config("C2")
+    e_ref, g_ref = oracle_energy_grad(p)
+    plan = fsv.Plan(p)
+    lib = plan._lib
+    tables = plan.device_bytes
+    assert plan.workspace_bytes > 16 * plan.n_alpha_strings * plan.n_beta_strings
+    e, g = plan.energy_grad(p.theta)
+    assert plan.device_bytes == tables
+    assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+    assert lib.fsv_plan_set_workspace(plan._h, None, 0) == 0
+    e2, g2 = plan.energy_grad(p.theta)
+    assert plan.device_bytes == tables + plan.workspace_bytes
+    assert e2 == e and np.array_equal(g2, g)
+    ws = plan._ws
+    assert lib.fsv_plan_set_workspace(plan._h, ctypes.c_void_p(ws.data_ptr()), plan.workspace_bytes - 8) == -1
+    assert lib.fsv_plan_set_workspace(plan._h, ctypes.c_void_p(ws.data_ptr() + 8), plan.workspace_bytes) == -1
+    assert lib.fsv_plan_set_workspace(plan._h, ctypes.c_void_p(ws.data_ptr()), plan.workspace_bytes) == 0
+    assert plan.device_bytes == tables
+    e3, g3 = plan.energy_grad(p.theta)
+    assert e3 == e and np.array_equal(g3, g)
+
+
 def test_set_theta_does_not_change_a_queued_sweep(fsv):
     # set_theta returns before its angle copy has run; a second set_theta must
     # not rewrite the angles a queued sweep is still to read: the first sweep's
