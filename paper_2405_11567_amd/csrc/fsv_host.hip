@@ -1221,6 +1221,8 @@ int check_csr(const std::vector<int64_t> &ptr, const std::vector<int32_t> &col, 
     return FSV_OK;
 }
 
+int bind_workspace(fsv_plan &P, void *base);
+
 int build_device(fsv_plan &P) {
     int rc;
     init_kernels();
@@ -1419,6 +1421,21 @@ int build_device(fsv_plan &P) {
                         P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_excBT, P.d_g, P.ecore,
                         R, d_Lt, nullptr, P.d_ha_dense, P.d_hb_dense, (void *)P.blas, P.d_hb_dense_t,
                         d_lda, d_ldb, P.na, P.nb};
+    if (P.blas) {
+        // one eager product per amplitude type on a temporary workspace, outside
+        // any capture, so that the GEMM library has loaded its kernels and sized
+        // its own workspace before any call of the plan (captured or not)
+        void *tmp = nullptr;
+        const hipError_t e = hipMalloc(&tmp, P.ws_bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FSV_ENOMEM, "hipMalloc of %zu bytes failed: %s", P.ws_bytes, hipGetErrorString(e));
+        }
+        rc = bind_workspace(P, tmp);
+        P.ws = nullptr;
+        (void)hipFree(tmp);
+        if (rc) return rc;
+    }
     return FSV_OK;
 }
 

@@ -56,6 +56,7 @@ constexpr int kPktMaxWords = 1024;   // region words (header + pairs)
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // padding of the index list
 // an operator's pairs in one packet are disjoint: at most kPkt / 2 of them
 static_assert(kPktHdr + kPktMaxOps * (kPkt / 2) / 2 <= kPktMaxWords, "packet region bound");
+static_assert(kPktMaxOps <= 16, "gradient sums take 16 values per lane");
 constexpr int kPktScalars = 2 * 16;  // LDS doubles: angles of <= 16 operators
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -91,18 +92,42 @@ __device__ __forceinline__ double dpp_move(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes, complete in lane 63: sums within rows of 16 lanes
-// (quad swaps, half-row and row mirrors), then the last lane of row 0 is
-// broadcast into row 1 and of row 2 into row 3, then of row 1 into row 3.
-// Only vector ALU moves: no LDS traffic.
-__device__ __forceinline__ double wave_sum_to_last(double v) {
-    v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
-    v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
-    v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
-    v += dpp_move<0x140, 0xF>(v);  // row_mirror
-    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
+// Sums over the 64 lanes of 16 values at once (a transposing butterfly):
+// at each exchange a lane keeps half of its values and sends the other half
+// to its partner, which keeps the opposite half, so 8 + 4 + 2 + 1 exchanges
+// (then two of one value) replace 16 separate six-step sums.  Lanes differing
+// in bit 0 and bit 1 exchange through DPP quad permutations, the others
+// through lane shuffles.  On return lane l holds the total of value
+// 8 b0 + 4 b1 + 2 b2 + b3 (b = the low bits of l); every row of 16 lanes holds
+// all 16 totals.
+__device__ __forceinline__ double wave_sum16(const double (&v)[16]) {
+    const int l = threadIdx.x & (kWave - 1);
+    const bool b0 = l & 1, b1 = l & 2, b2 = l & 4, b3 = l & 8;
+    double w8[8], w4[4], w2[2];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const double keep = b0 ? v[r + 8] : v[r], send = b0 ? v[r] : v[r + 8];
+        w8[r] = keep + dpp_move<0xB1, 0xF>(send);  // quad_perm [1, 0, 3, 2]: lane ^ 1
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double keep = b1 ? w8[r + 4] : w8[r], send = b1 ? w8[r] : w8[r + 4];
+        w4[r] = keep + dpp_move<0x4E, 0xF>(send);  // quad_perm [2, 3, 0, 1]: lane ^ 2
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const double keep = b2 ? w4[r + 2] : w4[r], send = b2 ? w4[r] : w4[r + 2];
+        w2[r] = keep + __shfl_xor(send, 4, kWave);
+    }
+    double w = (b3 ? w2[1] : w2[0]) + __shfl_xor(b3 ? w2[0] : w2[1], 8, kWave);
+    w += __shfl_xor(w, 16, kWave);
+    w += __shfl_xor(w, 32, kWave);
+    return w;
+}
+
+// The value whose total lane l holds after wave_sum16.
+__device__ __forceinline__ int wave_sum16_index(int l) {
+    return ((l & 1) << 3) | ((l & 2) << 1) | ((l & 4) >> 1) | ((l & 8) >> 3);
 }
 
 template <typename T>
@@ -131,9 +156,9 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slo
         const double v = a.cs[2 * a.k0 + t];
         if (l < 2 * a.m) scs[l] = v;
     }
-    double acc[kPktMaxOps];  // this lane's share of each operator's gradient term (sweep order)
+    double acc[16];  // this lane's share of each operator's gradient term (sweep order; 16th unused)
 #pragma unroll
-    for (int jj = 0; jj < kPktMaxOps; ++jj) acc[jj] = 0.0;
+    for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
     const int nq = a.wr >> 2;
     for (int v = blockIdx.x; v < a.n_packets; v += gridDim.x) {
         const int p = xcd_packet(v, a.n_packets);
@@ -225,12 +250,9 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slo
             }
     }
     if (ADJ) {
-#pragma unroll
-        for (int jj = 0; jj < kPktMaxOps; ++jj)
-            if (jj < a.m) {
-                const double t = wave_sum_to_last(acc[jj]);
-                if (l == kWave - 1) gpart[(size_t)(a.k0 + a.m - 1 - jj) * a.gstride + blockIdx.x] = t;
-            }
+        const double t = wave_sum16(acc);
+        const int jj = wave_sum16_index(l);
+        if (l < 16 && jj < a.m) gpart[(size_t)(a.k0 + a.m - 1 - jj) * a.gstride + blockIdx.x] = t;
     }
 }
 
@@ -298,7 +320,8 @@ __global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, cons
         __syncthreads();
         const uint32_t *rp = rg + kPktHdr;
         auto pair_at = [&](uint32_t t) { return (rp[t >> 1] >> ((t & 1u) << 4)) & 0xFFFFu; };
-        double acc[kPktMaxOps];
+        double acc[16];
+        acc[15] = 0.0;
 #pragma unroll
         for (int jj = 0; jj < kPktMaxOps; ++jj) {
             acc[jj] = 0.0;
@@ -339,12 +362,9 @@ __global__ __launch_bounds__(kWave) void k_bpkt(double *__restrict__ arena, cons
                 }
             }
         if (ADJ) {
-#pragma unroll
-            for (int jj = 0; jj < kPktMaxOps; ++jj)
-                if (jj < m) {
-                    const double t = wave_sum_to_last(acc[jj]);
-                    if (l == kWave - 1) gpart[(size_t)(k0 + m - 1 - jj) * pstride + slot] = t;
-                }
+            const double t = wave_sum16(acc);
+            const int jj = wave_sum16_index(l);
+            if (l < 16 && jj < m) gpart[(size_t)(k0 + m - 1 - jj) * pstride + slot] = t;
         }
     }
 }
