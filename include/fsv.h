@@ -194,6 +194,24 @@ int energy(fsv_plan *plan, const void *psi_dev, double *E_out);
 int energy_grad(fsv_plan *plan, const double *theta, void *psi_dev, void *lam_dev,
                 double *E_out, double *grad_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * energy and adjoint gradient as energy_grad (same kernels, same results to
+ * rounding), with no allocation in the call.  Its per-call scratch (the
+ * interleaved (psi, lam) pairs of the adjoint sweep, the transposes and the
+ * factorised intermediate of H psi, the energy and gradient partials) lives in
+ * one static device block of 64 MiB per GPU that the library holds until the
+ * process ends, not in the plan's workspace.  A plan whose scratch exceeds the
+ * block (sector states above roughly 1.3 M amplitudes at K = 200) gets
+ * FSV_EINVAL, the needed size in the message; the dense engine gets
+ * FSV_ESTATE.  Kernels are launched one by one (no graph is captured or
+ * instantiated).  Every call on one GPU shares its block: calls that overlap
+ * on one GPU (plans on different streams, or threads) race and must be
+ * serialised by the caller.  Nothing in the block needs to start at zero; its
+ * contents between calls are unspecified.  Arguments as for energy_grad. */
+int energy_grad_noalloc(fsv_plan *plan, const double *theta, void *psi_dev, void *lam_dev, double *E_out,
+                        double *grad_out);
+
 /* Same energy and gradient by central finite differences of the energy,
  * 2K + 1 energy evaluations with step `step` (the plain per-parameter method
  * the adjoint is compared against).  psi_dev is a work buffer. */

@@ -167,6 +167,16 @@ class Plan:
                                     ctypes.byref(e), _dptr(grad)))
         return e.value, grad
 
+    def energy_grad_noalloc(self, theta, psi, lam):
+        """energy_grad without any device allocation in the call (its scratch is
+        the library's static per-GPU block); psi and lam are required."""
+        th = self._theta(theta)
+        grad = np.zeros(self.n_ops)
+        e = ctypes.c_double()
+        check(self._lib.energy_grad_noalloc(self._h, _dptr(th), self._check_state(psi), self._check_state(lam),
+                                            ctypes.byref(e), _dptr(grad)))
+        return e.value, grad
+
     def energy_grad_fd(self, theta, step: float = 1e-5, psi=None):
         psi = self.new_state() if psi is None else psi
         th = self._theta(theta)

@@ -45,7 +45,8 @@ EXPORTS = [
     "fsv_last_error", "fsv_plan_create", "fsv_plan_destroy", "fsv_state_bytes", "fsv_plan_info",
     "fsv_plan_workspace_bytes", "fsv_plan_device_bytes", "fsv_plan_set_workspace", "fsv_batch_arena_bytes",
     "fsv_plan_set_engine", "fsv_plan_runs", "fsv_time_runs",
-    "ansatz_apply", "energy", "energy_grad", "energy_grad_fd", "rdm1", "set_onebody_potential",
+    "ansatz_apply", "energy", "energy_grad", "energy_grad_noalloc", "energy_grad_fd", "rdm1",
+    "set_onebody_potential",
     "fsv_set_theta", "fsv_forward_async", "fsv_sigma_async", "fsv_reverse_async", "fsv_finish",
     "fsv_autotune", "fsv_batch_create", "fsv_batch_destroy", "fsv_batch_energy_grad",
     "fsv_batch_bytes", "fsv_batch_autotune", "fsv_pool_create", "fsv_pool_destroy", "fsv_pool_gradients",
@@ -82,6 +83,7 @@ def load():
     lib.ansatz_apply.argtypes = [vp, d, vp]
     lib.energy.argtypes = [vp, vp, d]
     lib.energy_grad.argtypes = [vp, d, vp, vp, d, d]
+    lib.energy_grad_noalloc.argtypes = [vp, d, vp, vp, d, d]
     lib.energy_grad_fd.argtypes = [vp, d, ctypes.c_double, vp, d, d]
     lib.rdm1.argtypes = [vp, vp, d]
     lib.set_onebody_potential.argtypes = [vp, d]

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -67,6 +68,41 @@ struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
 };
+
+}  // namespace
+
+// ------------------------------------------------------- no-alloc scratch --
+// Scratch of energy_grad_noalloc: one block per GPU, part of the library's
+// device image, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: it is a host-side stand-in there.  The
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address (looked up on its first use).
+int scratch_address(void **out) {
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FSV_EDEVICE, "device %d outside the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(FSV_EDEVICE, "hipGetSymbolAddress of the scratch block failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FSV_OK;
+}
 
 }  // namespace
 
@@ -128,6 +164,9 @@ struct fsv_plan {
     bool ws_owned = false, ws_warm = false;
     size_t ws_bytes = 0;
     size_t ws_off[10] = {};  // byte offsets of C, S, CT, ST, O, gamma, YT, gpart, epart; [9] = end
+    // the parts energy_grad_noalloc takes from the scratch block (sector
+    // engine): C, S, CT, ST, YT, gpart, epart offsets; [7] = end
+    size_t na_off[8] = {};
     double *h_pin = nullptr;  // pinned: cs (2K) then out (K + 1) then gamma (4 M^2)
     size_t pin_doubles = 0;
 
@@ -1421,6 +1460,20 @@ int build_device(fsv_plan &P) {
                         P.d_hb_col, P.d_ha_val, P.d_hb_val, P.d_excA, P.d_excB, P.d_excBT, P.d_g, P.ecore,
                         R, d_Lt, nullptr, P.d_ha_dense, P.d_hb_dense, (void *)P.blas, P.d_hb_dense_t,
                         d_lda, d_ldb, P.na, P.nb};
+    {  // the scratch parts of energy_grad_noalloc (sector engine, real states)
+        const bool f32 = P.svt == V_F32;
+        const size_t parts[7] = {16 * (size_t)P.dim,                           // C: (psi, lam) pairs; FP32: widened psi
+                                 f32 ? 8 * (size_t)P.dim : 0,                  // S: FP32 only, H psi in FP64
+                                 8 * (size_t)P.dim, 8 * (size_t)P.dim,         // CT, ST: real transposes
+                                 lr_uses_intermediate(P.tabs, false) ? 8 * (size_t)lr_pad(R) * P.dim : 0,
+                                 8 * (size_t)std::max(P.K, 1) * G, 8 * 1024};
+        size_t at = 0;
+        for (int i = 0; i < 7; ++i) {
+            P.na_off[i] = at;
+            at += (parts[i] + 255) & ~(size_t)255;
+        }
+        P.na_off[7] = at;
+    }
     if (P.blas) {
         // one eager product per amplitude type on a temporary workspace, outside
         // any capture, so that the GEMM library has loaded its kernels and sized
@@ -1784,6 +1837,48 @@ int energy_grad(fsv_plan *P, const double *theta, void *psi, void *lam, double *
     if ((rc = need_workspace(*P))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
     if ((rc = launch_energy_grad(*P, psi, lam))) return rc;
+    if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
+    return fence_out(*P);
+}
+
+int energy_grad_noalloc(fsv_plan *P, const double *theta, void *psi, void *lam, double *E_out,
+                        double *grad_out) {
+    if (!P || !psi || !lam) return fail(FSV_EINVAL, "plan, psi or lam is NULL");
+    if (psi == lam) return fail(FSV_EINVAL, "psi and lam must be distinct buffers");
+    if (P->K > 0 && !grad_out) return fail(FSV_EINVAL, "grad_out is NULL");
+    if (P->engine != 0) return fail(FSV_ESTATE, "energy_grad_noalloc runs on the sector engine");
+    if (P->na_off[7] > kScratchBytes)
+        return fail(FSV_EINVAL, "this plan needs %zu bytes of scratch; energy_grad_noalloc has %zu", P->na_off[7],
+                    kScratchBytes);
+    void *base = nullptr;
+    int rc;
+    if ((rc = scratch_address(&base))) return rc;
+    if ((rc = fence_in(*P))) return rc;
+    if ((rc = upload_theta(*P, theta))) return rc;
+    // the pass takes its parts from the scratch block: the plan's workspace
+    // fields point there for the duration of the (eager) launches
+    char *b = (char *)base;
+    double2 *sv[5] = {P->d_C, P->d_S, P->d_CT, P->d_ST, P->d_YT};
+    double *sg = P->d_gpart, *se = P->d_epart;
+    void *syt = P->tabs.YT;
+    P->d_C = (double2 *)(b + P->na_off[0]);
+    P->d_S = (double2 *)(b + P->na_off[1]);
+    P->d_CT = (double2 *)(b + P->na_off[2]);
+    P->d_ST = (double2 *)(b + P->na_off[3]);
+    P->d_YT = (double2 *)(b + P->na_off[4]);
+    P->tabs.YT = P->d_YT;
+    P->d_gpart = (double *)(b + P->na_off[5]);
+    P->d_epart = (double *)(b + P->na_off[6]);
+    rc = run_energy_grad_body(*P, psi, lam);
+    P->d_C = sv[0];
+    P->d_S = sv[1];
+    P->d_CT = sv[2];
+    P->d_ST = sv[3];
+    P->d_YT = sv[4];
+    P->tabs.YT = syt;
+    P->d_gpart = sg;
+    P->d_epart = se;
+    if (rc) return rc;
     if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
     return fence_out(*P);
 }

@@ -175,6 +175,9 @@ hipError_t launch_convert(int vt_in, const void *in, int vt_out, void *out, int6
 // S = H C on the sector; C, S, CT, ST hold nsa*nsb values of type complex
 // (cplex) or real double.  Writes combine_grid(nsa*nsb) partials of Re<C|S>.
 unsigned combine_grid(int64_t dim);
+// Whether the product on a real (cplex = false) or complex sector state writes
+// the factorised intermediate YT (the two-kernel form of the alpha-beta term).
+bool lr_uses_intermediate(const SectorTabs &T, bool cplex);
 hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, void *S, void *CT,
                                void *ST, double *epart, hipStream_t st);
 // ADAPT pool screening on a real sector state (V_F64 / V_F32): grid (gx, n_ops),

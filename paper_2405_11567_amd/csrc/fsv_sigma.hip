@@ -802,6 +802,15 @@ hipError_t lr_launch(const SectorTabs &T, const A *C, A *S, hipStream_t st) {
     return hipGetLastError();
 }
 
+}  // namespace
+
+bool lr_uses_intermediate(const SectorTabs &T, bool cplex) {
+    if (T.R <= 0 || T.nexcA <= 0 || T.nexcB <= 0) return false;
+    return cplex ? true : !lr_fused_ok<double, 8>(T);
+}
+
+namespace {
+
 template <typename A>
 hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, double *epart, hipStream_t st) {
     const int64_t nsa = T.nsa, nsb = T.nsb;

@@ -46,6 +46,7 @@ for name, args in {
     "fsv_plan_runs": [vp, ctypes.c_int, I32, I32],
     "fsv_time_runs": [vp, ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_float)],
     "ansatz_apply": [vp, D, vp], "energy": [vp, vp, D], "energy_grad": [vp, D, vp, vp, D, D],
+    "energy_grad_noalloc": [vp, D, vp, vp, D, D],
     "energy_grad_fd": [vp, D, ctypes.c_double, vp, D, D], "rdm1": [vp, vp, D],
     "set_onebody_potential": [vp, D], "fsv_set_theta": [vp, D], "fsv_forward_async": [vp, vp],
     "fsv_sigma_async": [vp, vp, vp], "fsv_reverse_async": [vp, vp, vp], "fsv_finish": [vp, D, D],
@@ -140,6 +141,9 @@ def exercise_plan(p, precision=0, engine=0, fd=False, stages=True, extras=True, 
         ok(lib.energy_grad(plan, dp(th), psi.p, lam.p, ctypes.byref(e), dp(grad)), "energy_grad")
     psi2, lam2 = Dev(sb), Dev(sb)  # new buffers: the graph is captured again
     ok(lib.energy_grad(plan, dp(th), psi2.p, lam2.p, ctypes.byref(e), dp(grad)), "energy_grad")
+    rc = lib.energy_grad_noalloc(plan, dp(th), psi.p, lam.p, ctypes.byref(e), dp(grad))
+    if rc not in ((0, -1) if engine == 0 else (-4,)):
+        raise RuntimeError(f"energy_grad_noalloc: {rc} {lib.fsv_last_error().decode()}")
     own = lib.fsv_plan_device_bytes(plan) - tables
     if own != (0 if ws else wsb):
         raise RuntimeError(f"plan-owned workspace {own} bytes, expected {0 if ws else wsb}")
