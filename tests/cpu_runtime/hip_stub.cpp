@@ -1,13 +1,21 @@
 // A host-only stand-in for the parts of the HIP runtime (and rocBLAS) that
-// libfsv calls, for checking the library's host side on a machine without a
-// GPU.  Test infrastructure: it never computes anything.
+// libfsv calls, for checking the library on a machine without a GPU.  Test
+// infrastructure.  Two builds use it:
+//
+//  - the host-check build (library compiled by hipcc): kernels do not run;
+//  - the kernel-executing build (library compiled as plain C++ against
+//    kexec/hip/hip_runtime.h): each launch runs the kernel on the host, one
+//    fiber per work-item, one workgroup after another, with workgroup
+//    barriers, wavefront exchanges and a dynamic LDS block of exactly the
+//    launch's size (so AddressSanitizer checks LDS accesses too); the GEMM is
+//    computed.
 //
 //  - "Device" memory is host memory from malloc, so AddressSanitizer sees every
 //    allocation; each copy is checked against the allocation it names (device
 //    side) or the pinned buffer it touches (host side) and then performed.
 //  - Kernel launches are checked (a registered kernel, a launch shape the
 //    hardware accepts, dynamic LDS within the limit set for that kernel) and
-//    logged; kernels do not run.
+//    logged.
 //  - Streams, events, graphs and BLAS handles live in registries: use or
 //    destruction of an unknown or already destroyed handle aborts with a
 //    message, as does freeing memory that is not allocated.
@@ -20,15 +28,31 @@
 #include <cxxabi.h>
 #include <stdint.h>
 
+#include <sanitizer/common_interface_defs.h>
+#include <sys/mman.h>
+#include <ucontext.h>
+
+#include <array>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <string>
+#include <thread>
 #include <vector>
+
+// work-item coordinates of the kernel-executing build (kexec/hip/hip_runtime.h)
+struct fsv_cpu_idx {
+    uint32_t x, y, z;
+};
+thread_local fsv_cpu_idx threadIdx, blockIdx;
+thread_local dim3 blockDim, gridDim;
 
 namespace {
 
@@ -51,7 +75,7 @@ struct Kernel {
 };
 
 struct Node {
-    int kind = 0;  // 0 launch, 1 copy
+    int kind = 0;  // 0 launch, 1 copy, 2 GEMM (kernel-executing build)
     const void *fn = nullptr;
     dim3 grid, block;
     size_t shm = 0;
@@ -59,6 +83,8 @@ struct Node {
     const void *src = nullptr;
     size_t bytes = 0;
     hipMemcpyKind ck = hipMemcpyDefault;
+    std::shared_ptr<void> ctx;  // kernel-executing build: the launch's bound arguments
+    void (*run)(void *) = nullptr;
 };
 
 struct Stream {
@@ -77,6 +103,7 @@ std::map<hipGraphExec_t, std::vector<Node> *> &execs() { static std::map<hipGrap
 std::set<void *> &blas_handles() { static std::set<void *> s; return s; }
 
 unsigned long g_launches = 0, g_replays = 0;
+bool g_exec = false;  // kernel-executing build loaded
 
 std::string demangle(const char *s) {
     int st = 0;
@@ -141,9 +168,22 @@ void do_copy(void *dst, const void *src, size_t n, hipMemcpyKind k, const char *
     if (n) std::memmove(dst, src, n);
 }
 
-void check_launch(const void *fn, dim3 g, dim3 b, size_t shm, const char *what) {
+// The kernel-executing build has no registration: kernels are known by
+// their host address.
+std::map<const void *, Kernel>::iterator find_kernel(const void *fn, const char *what) {
     auto it = kernels().find(fn);
-    if (it == kernels().end()) die("%s: launch of an unregistered kernel %p", what, fn);
+    if (it == kernels().end()) {
+        if (!g_exec) die("%s: unregistered kernel %p", what, fn);
+        it = kernels().emplace(fn, Kernel{}).first;
+        char buf[32];
+        std::snprintf(buf, sizeof buf, "kernel@%p", fn);
+        it->second.name = buf;
+    }
+    return it;
+}
+
+void check_launch(const void *fn, dim3 g, dim3 b, size_t shm, const char *what) {
+    auto it = find_kernel(fn, what);
     const Kernel &K = it->second;
     const char *nm = K.name.c_str();
     if (g.x == 0 || g.y == 0 || g.z == 0) die("%s: %s launched with an empty grid (%u, %u, %u)", what, nm, g.x, g.y, g.z);
@@ -172,6 +212,203 @@ void launch_or_record(const void *fn, dim3 g, dim3 b, size_t shm, hipStream_t st
     ++g_launches;
 }
 
+// ---- kernel execution (kernel-executing build) ----
+// One workgroup at a time, each work-item a fiber (ucontext) on the calling
+// thread, run in lane order until it returns or waits.  A workgroup barrier
+// releases when every work-item that has not returned waits at it (the
+// hardware counts the waves still running); a wavefront exchange releases
+// when every live lane of the wavefront waits at it.  Any other standstill
+// is reported as a hang.  Deterministic: the same launch always runs the
+// work-items in the same order.
+enum FiberState { F_RUN, F_BARRIER, F_WAVE, F_DONE };
+
+struct Fiber {
+    ucontext_t ctx;
+    void *stack = nullptr;
+    void *fake = nullptr;  // AddressSanitizer's fake-stack handle while suspended
+    int state = F_DONE;
+};
+
+constexpr size_t kFiberStack = 256 << 10;
+
+struct Exec {
+    std::vector<Fiber> fibers;
+    ucontext_t sched;
+    void *sched_fake = nullptr;
+    const void *sched_bottom = nullptr;
+    size_t sched_size = 0;
+    int cur = -1, n = 0;
+    void (*fn)(void *) = nullptr;
+    void *arg = nullptr;
+    dim3 bdim, gdim;
+    fsv_cpu_idx bidx{0, 0, 0};
+    void *dyn = nullptr;
+    const char *name = "";
+    std::vector<std::array<unsigned char, 64>> slot;  // one exchange slot per work-item
+};
+
+Exec g_x;
+bool g_in_kernel = false;
+
+void set_coords(int i) {
+    blockDim = g_x.bdim;
+    gridDim = g_x.gdim;
+    blockIdx = g_x.bidx;
+    threadIdx = fsv_cpu_idx{i % g_x.bdim.x, (i / g_x.bdim.x) % g_x.bdim.y, i / (g_x.bdim.x * g_x.bdim.y)};
+}
+
+// From a work-item back to the scheduler (state already set).
+void yield_fiber(bool dying) {
+    Fiber &f = g_x.fibers[g_x.cur];
+    __sanitizer_start_switch_fiber(dying ? nullptr : &f.fake, g_x.sched_bottom, g_x.sched_size);
+    swapcontext(&f.ctx, &g_x.sched);
+    __sanitizer_finish_switch_fiber(f.fake, &g_x.sched_bottom, &g_x.sched_size);
+    set_coords(g_x.cur);
+}
+
+void fiber_main() {
+    __sanitizer_finish_switch_fiber(nullptr, &g_x.sched_bottom, &g_x.sched_size);
+    set_coords(g_x.cur);
+    g_x.fn(g_x.arg);
+    g_x.fibers[g_x.cur].state = F_DONE;
+    yield_fiber(true);
+}
+
+void resume(int i) {
+    g_x.cur = i;
+    Fiber &f = g_x.fibers[i];
+    __sanitizer_start_switch_fiber(&g_x.sched_fake, f.stack, kFiberStack);
+    swapcontext(&g_x.sched, &f.ctx);
+    __sanitizer_finish_switch_fiber(g_x.sched_fake, nullptr, nullptr);
+}
+
+void run_block(const char *name) {
+    const int n = g_x.n;
+    while ((int)g_x.fibers.size() < n) {
+        Fiber f;
+        f.stack = mmap(nullptr, kFiberStack, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+        if (f.stack == MAP_FAILED) die("mmap of a work-item stack failed");
+        g_x.fibers.push_back(f);
+    }
+    for (int i = 0; i < n; ++i) {
+        Fiber &f = g_x.fibers[i];
+        getcontext(&f.ctx);
+        f.ctx.uc_stack.ss_sp = f.stack;
+        f.ctx.uc_stack.ss_size = kFiberStack;
+        f.ctx.uc_link = nullptr;
+        makecontext(&f.ctx, fiber_main, 0);
+        f.state = F_RUN;
+        f.fake = nullptr;
+    }
+    g_x.slot.assign((size_t)((n + 63) / 64) * 64, std::array<unsigned char, 64>{});
+    for (;;) {
+        for (int i = 0; i < n; ++i)
+            if (g_x.fibers[i].state == F_RUN) resume(i);
+        bool all_done = true, released = false;
+        for (int w = 0; w * 64 < n; ++w) {
+            const int lo = w * 64, hi = std::min(n, lo + 64);
+            bool any_wave = false, all_wave = true;
+            for (int i = lo; i < hi; ++i) {
+                const int st = g_x.fibers[i].state;
+                if (st == F_DONE) continue;
+                all_done = false;
+                if (st == F_WAVE) any_wave = true;
+                else all_wave = false;
+            }
+            if (any_wave && all_wave) {
+                for (int i = lo; i < hi; ++i)
+                    if (g_x.fibers[i].state == F_WAVE) g_x.fibers[i].state = F_RUN;
+                released = true;
+            }
+        }
+        if (all_done) break;
+        if (released) continue;
+        bool all_barrier = true;
+        for (int i = 0; i < n; ++i) {
+            const int st = g_x.fibers[i].state;
+            if (st != F_DONE && st != F_BARRIER) all_barrier = false;
+        }
+        if (!all_barrier) {
+            int nb = 0, nw = 0;
+            for (int i = 0; i < n; ++i) {
+                nb += g_x.fibers[i].state == F_BARRIER;
+                nw += g_x.fibers[i].state == F_WAVE;
+            }
+            die("kernel %s hangs: block (%u, %u, %u), %d work-items at a workgroup barrier, %d at a wavefront "
+                "exchange whose wavefront has lanes elsewhere", name, g_x.bidx.x, g_x.bidx.y, g_x.bidx.z, nb, nw);
+        }
+        for (int i = 0; i < n; ++i)
+            if (g_x.fibers[i].state == F_BARRIER) g_x.fibers[i].state = F_RUN;
+    }
+}
+
+struct ExecProfile {
+    std::map<std::string, std::pair<double, long>> t;
+    ~ExecProfile() {
+        if (!std::getenv("FSV_STUB_PROFILE")) return;
+        for (auto &kv : t)
+            std::fprintf(stderr, "hip_stub: %9.3f s %6ld launches  %s\n", kv.second.first, kv.second.second,
+                         kv.first.c_str());
+    }
+};
+ExecProfile g_prof;
+
+void exec_grid(void (*f)(void *), void *c, dim3 g, dim3 b, size_t shm, const char *name) {
+    if (g_in_kernel) die("kernel launch from inside kernel %s", g_x.name);
+    const auto t0 = std::chrono::steady_clock::now();
+    g_in_kernel = true;
+    g_x.fn = f;
+    g_x.arg = c;
+    g_x.gdim = g;
+    g_x.bdim = b;
+    g_x.n = (int)(b.x * b.y * b.z);
+    g_x.name = name;
+    for (uint32_t z = 0; z < g.z; ++z)
+        for (uint32_t y = 0; y < g.y; ++y)
+            for (uint32_t x = 0; x < g.x; ++x) {
+                g_x.bidx = fsv_cpu_idx{x, y, z};
+                g_x.dyn = std::malloc(shm ? shm : 1);
+                std::memset(g_x.dyn, 0xFF, shm ? shm : 1);  // LDS starts undefined: NaN pattern
+                run_block(name);
+                std::free(g_x.dyn);
+                g_x.dyn = nullptr;
+            }
+    g_in_kernel = false;
+    auto &e = g_prof.t[name];
+    e.first += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    e.second += 1;
+}
+
+std::map<void *, hipStream_t> &blas_stream() { static std::map<void *, hipStream_t> m; return m; }
+
+struct Gemm {
+    int m, n, k;
+    double alpha;
+    const double *A;
+    int lda;
+    const double *B;
+    int ldb;
+    double beta;
+    double *C;
+    int ldc;
+};
+
+void run_gemm(void *p) {
+    const Gemm &g = *(const Gemm *)p;
+    std::vector<double> col((size_t)g.m);
+    for (int j = 0; j < g.n; ++j) {
+        for (int i = 0; i < g.m; ++i) col[i] = 0.0;
+        for (int q = 0; q < g.k; ++q) {
+            const double bv = g.B[(size_t)j * g.ldb + q];
+            for (int i = 0; i < g.m; ++i) col[i] += g.A[(size_t)q * g.lda + i] * bv;
+        }
+        for (int i = 0; i < g.m; ++i) {
+            double &cv = g.C[(size_t)j * g.ldc + i];
+            cv = g.alpha * col[i] + (g.beta == 0.0 ? 0.0 : g.beta * cv);
+        }
+    }
+}
+
 struct CallCfg {
     dim3 g, b;
     size_t shm;
@@ -180,6 +417,92 @@ struct CallCfg {
 thread_local std::vector<CallCfg> g_cfg;
 
 }  // namespace
+
+// ---- entry points of the kernel-executing build (C++ linkage) ----
+void fsv_cpu_enable() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_exec = true;
+}
+
+void *fsv_cpu_dyn_lds() { return g_x.dyn; }
+
+void fsv_cpu_syncthreads() {
+    g_x.fibers[g_x.cur].state = F_BARRIER;
+    yield_fiber(false);
+}
+
+static void wave_wait() {
+    g_x.fibers[g_x.cur].state = F_WAVE;
+    yield_fiber(false);
+}
+
+void fsv_cpu_wave_exchange(const void *mine, void *out, size_t n, int src) {
+    const int me = g_x.cur, base = me & ~63;
+    if (n > 64 || src < 0 || src > 63) die("wavefront exchange of %zu bytes from lane %d", n, src);
+    std::memcpy(g_x.slot[me].data(), mine, n);
+    wave_wait();
+    std::memcpy(out, g_x.slot[base + src].data(), n);
+    wave_wait();
+}
+
+void fsv_cpu_mfma_f64_16x16x4(double a, double b, const double *c, double *d) {
+    const int me = g_x.cur, base = me & ~63, l = me & 63;
+    const double mine[2] = {a, b};
+    std::memcpy(g_x.slot[me].data(), mine, sizeof mine);
+    wave_wait();
+    auto op = [&](int lane, int which) {
+        double v[2];
+        std::memcpy(v, g_x.slot[base + lane].data(), sizeof v);
+        return v[which];
+    };
+    for (int r = 0; r < 4; ++r) {
+        const int row = 4 * r + l / 16, col = l % 16;
+        double acc = c[r];
+        for (int k = 0; k < 4; ++k) acc += op(row + 16 * k, 0) * op(col + 16 * k, 1);
+        d[r] = acc;
+    }
+    wave_wait();
+}
+
+const void *fsv_cpu_symbol(const void *p, size_t n) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    symbols()[p] = "symbol";
+    dev_allocs()[(uintptr_t)p] = n;
+    return p;
+}
+
+hipError_t fsv_cpu_launch(const void *fn, const char *name, dim3 g, dim3 b, size_t shm, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1, void (*run)(void *), void *ctx, void (*del)(void *),
+                          void *(*)(void *)) {
+    std::shared_ptr<void> c(ctx, del);
+    std::string nm;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_exec = true;
+        if (e0) check_event(e0, "kernel launch start event");
+        if (e1) check_event(e1, "kernel launch stop event");
+        auto it = find_kernel(fn, name);
+        if (it->second.name.rfind("kernel@", 0) == 0) it->second.name = name;
+        nm = it->second.name;
+        check_launch(fn, g, b, shm, name);
+        Stream *s = stream_of(st, name);
+        if (s && s->capturing) {
+            Node n;
+            n.kind = 0;
+            n.fn = fn;
+            n.grid = g;
+            n.block = b;
+            n.shm = shm;
+            n.ctx = c;
+            n.run = run;
+            s->rec.push_back(n);
+            return hipSuccess;
+        }
+        ++g_launches;
+    }
+    exec_grid(run, c.get(), g, b, shm, nm.c_str());
+    return hipSuccess;
+}
 
 extern "C" {
 
@@ -235,8 +558,7 @@ hipError_t hipExtLaunchKernel(const void *fn, dim3 g, dim3 b, void **, size_t sh
 
 hipError_t hipFuncSetAttribute(const void *fn, hipFuncAttribute attr, int value) {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = kernels().find(fn);
-    if (it == kernels().end()) die("hipFuncSetAttribute on an unregistered kernel");
+    auto it = find_kernel(fn, "hipFuncSetAttribute");
     if (attr == hipFuncAttributeMaxDynamicSharedMemorySize) {
         if (value < 0 || value > 163840) return hipErrorInvalidValue;
         it->second.max_dyn = value;
@@ -245,8 +567,7 @@ hipError_t hipFuncSetAttribute(const void *fn, hipFuncAttribute attr, int value)
 }
 hipError_t hipFuncGetAttributes(hipFuncAttributes *a, const void *fn) {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = kernels().find(fn);
-    if (it == kernels().end()) die("hipFuncGetAttributes on an unregistered kernel");
+    auto it = find_kernel(fn, "hipFuncGetAttributes");
     std::memset(a, 0, sizeof *a);
     a->maxDynamicSharedSizeBytes = it->second.max_dyn;
     a->maxThreadsPerBlock = 1024;
@@ -278,8 +599,8 @@ const char *hipGetErrorString(hipError_t) { return "hip_stub error"; }
 // ---- memory ----
 hipError_t hipMalloc(void **p, size_t n) {
     std::lock_guard<std::mutex> lk(g_mu);
-    void *q = std::malloc(n ? n : 1);
-    if (!q) return hipErrorOutOfMemory;
+    void *q = nullptr;  // device allocations are at least 256-byte aligned
+    if (posix_memalign(&q, 256, n ? n : 1) != 0) return hipErrorOutOfMemory;
     dev_allocs()[(uintptr_t)q] = n ? n : 1;
     *p = q;
     return hipSuccess;
@@ -465,6 +786,9 @@ hipError_t hipGraphLaunch(hipGraphExec_t ex, hipStream_t s) {
         if (n.kind == 0) {
             check_launch(n.fn, n.grid, n.block, n.shm, "graph replay");
             ++g_launches;
+            if (n.run) exec_grid(n.run, n.ctx.get(), n.grid, n.block, n.shm, kernels()[n.fn].name.c_str());
+        } else if (n.kind == 2) {
+            run_gemm(n.ctx.get());
         } else {
             do_copy(n.dst, n.src, n.bytes, n.ck, "graph replay copy");
         }
@@ -495,11 +819,13 @@ int rocblas_create_handle(rocblas_handle_t *h) {
     std::lock_guard<std::mutex> lk(g_mu);
     *h = std::malloc(8);
     blas_handles().insert(*h);
+    blas_stream()[*h] = nullptr;
     return 0;
 }
 int rocblas_destroy_handle(rocblas_handle_t h) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!blas_handles().erase(h)) die("rocblas_destroy_handle of an unknown handle");
+    blas_stream().erase(h);
     std::free(h);
     return 0;
 }
@@ -507,6 +833,7 @@ int rocblas_set_stream(rocblas_handle_t h, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!blas_handles().count(h)) die("rocblas_set_stream on an unknown handle");
     stream_of(s, "rocblas_set_stream");
+    blas_stream()[h] = s;
     return 0;
 }
 int rocblas_set_atomics_mode(rocblas_handle_t h, int) {
@@ -515,9 +842,10 @@ int rocblas_set_atomics_mode(rocblas_handle_t h, int) {
     return 0;
 }
 // Column-major C (m x n, ldc) = alpha op(A) op(B) + beta C; only untransposed
-// operands are used by the library.
-int rocblas_dgemm(rocblas_handle_t h, int ta, int tb, int m, int n, int k, const double *, const double *A, int lda,
-                  const double *B, int ldb, const double *, double *C, int ldc) {
+// operands are used by the library.  The kernel-executing build computes it
+// (recorded into a graph when the handle's stream is capturing).
+int rocblas_dgemm(rocblas_handle_t h, int ta, int tb, int m, int n, int k, const double *alpha, const double *A,
+                  int lda, const double *B, int ldb, const double *beta, double *C, int ldc) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!blas_handles().count(h)) die("rocblas_dgemm on an unknown handle");
     if (ta != 111 || tb != 111) die("rocblas_dgemm: transposed operands are not used by the library");
@@ -528,6 +856,19 @@ int rocblas_dgemm(rocblas_handle_t h, int ta, int tb, int m, int n, int k, const
         in_alloc(dev_allocs(), B, 8 * ((size_t)ldb * (n - 1) + k), "rocblas_dgemm B");
     }
     if (m && n) in_alloc(dev_allocs(), C, 8 * ((size_t)ldc * (n - 1) + m), "rocblas_dgemm C");
+    if (!g_exec || !m || !n) return 0;
+    auto *g = new Gemm{m, n, k, *alpha, A, lda, B, ldb, *beta, C, ldc};
+    std::shared_ptr<void> ctx(g, [](void *p) { delete (Gemm *)p; });
+    Stream *s = stream_of(blas_stream()[h], "rocblas_dgemm");
+    if (s && s->capturing) {
+        Node nd;
+        nd.kind = 2;
+        nd.ctx = ctx;
+        nd.run = &run_gemm;
+        s->rec.push_back(nd);
+        return 0;
+    }
+    run_gemm(g);
     return 0;
 }
 

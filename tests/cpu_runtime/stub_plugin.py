@@ -1,12 +1,16 @@
-"""pytest plugin: run the GPU test files on the CPU against the host-check
-build of the library (tests/cpu_runtime/build.py), so that their exact
-sequence of plan / pool / batch lifetimes, calls, oracle calls and garbage
-collections runs with the library's host code under AddressSanitizer.
+"""pytest plugin: run the GPU test files on the CPU against a checking build
+of the library (tests/cpu_runtime/build.py), so that their exact sequence of
+plan / pool / batch lifetimes, calls, oracle calls and garbage collections
+runs under AddressSanitizer.
 
-Kernels do not run in that build, so results are meaningless: use it with
-`python -O -m pytest --assert=plain -p tests.cpu_runtime.stub_plugin ...`,
-which strips the tests' assertions.  States are CPU tensors standing in for
-device buffers (the library never reads them on the host).
+* Default: the host-check build.  Kernels do not run, so results are
+  meaningless: use it with
+  `python -O -m pytest --assert=plain -p tests.cpu_runtime.stub_plugin ...`,
+  which strips the tests' assertions.
+* FSV_STUB_LIB=kexec: the kernel-executing build.  Kernels run on the host,
+  so results are real and the tests' assertions stay on.
+
+States are CPU tensors over buffers of the stand-in's device allocator.
 """
 
 from __future__ import annotations
@@ -29,7 +33,8 @@ def pytest_configure(config):
     from paper_2405_11567_amd import _lib
 
     ctypes.CDLL(os.path.join(BUILD, "libhipstub.so"), mode=ctypes.RTLD_GLOBAL)
-    _lib.LIB_PATH = os.path.join(BUILD, "libfsv_hostcheck.so")
+    kexec = os.environ.get("FSV_STUB_LIB") == "kexec"
+    _lib.LIB_PATH = os.path.join(BUILD, "libfsv_kexec.so" if kexec else "libfsv_hostcheck.so")
     _lib._lib = None
 
     cuda = types.SimpleNamespace(

@@ -9,6 +9,12 @@ library's own table checks run at plan, pool and batch creation.
 Regression pinned here: destroying a pool after its plan used to read the
 freed plan (heap-use-after-free found by this replay); the pool is now
 detached and refuses to run.
+
+The kernel-executing build (tests/cpu_runtime/kexec) goes further: the
+kernels themselves run on the host, one fiber per work-item, so GPU test
+cases run end to end on the CPU with every kernel access to device memory
+and to its dynamic LDS checked by AddressSanitizer, and their results are
+compared with the oracle by the test's own assertions.
 """
 
 import os
@@ -59,3 +65,38 @@ def test_replay_pools_and_lifetimes(hostcheck):
 
 def test_replay_batches(hostcheck):
     _replay(hostcheck, "batch")
+
+
+@pytest.fixture(scope="module")
+def kexec(hostcheck):
+    import build as rt_build  # tests/cpu_runtime/build.py
+    rt_build.build_kexec()
+    return hostcheck
+
+
+def _gpu_tests_on_cpu(asan, *selection, timeout=1200):
+    env = dict(os.environ)
+    env.update(LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1", FSV_STUB_LIB="kexec", FSV_STUB_RUN_SKIPPED="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "tests.cpu_runtime.stub_plugin",
+                        "-p", "no:cacheprovider", *selection], env=env, cwd=ROOT, capture_output=True, text=True,
+                       timeout=timeout)
+    tail = (r.stdout + r.stderr)[-6000:]
+    assert r.returncode == 0, tail
+    assert "AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, tail
+    return r.stdout
+
+
+def test_kernels_on_cpu_sigma_paths(kexec):
+    # the alpha-beta product directly, through the rank-8 factors (forced) and
+    # by the automatic choice, on both engines: the case after which the GPU
+    # test process aborted, with its kernels run under AddressSanitizer
+    out = _gpu_tests_on_cpu(kexec, "tests/test_gpu_parity.py::test_sigma_paths", "-k", "8-")
+    assert "3 passed" in out
+
+
+def test_kernels_on_cpu_energy_c2(kexec):
+    # packet runs, the same-spin GEMM and the factorised product inside
+    # captured graphs, replayed
+    out = _gpu_tests_on_cpu(kexec, "tests/test_gpu_parity.py::test_energy_small_configs[0-C2]")
+    assert "1 passed" in out
