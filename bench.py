@@ -1,9 +1,12 @@
 """Benchmark: energy + adjoint-gradient evaluations per second of the 24-qubit
 workload (12 electrons, 200 sampled excitations, FP64) on one GPU, the HBM
-roofline fraction of the per-operator adjoint kernel (k_cadj, timed live on a
-plan without fused runs, so that every reverse launch is that kernel), the
-per-parameter finite-difference gradient on the same GPU, and the FP64 CPU
-oracle timed on the host cores.
+roofline fraction of its dominant kernel (the adjoint packet run, each
+launch's own start and end taken live), the per-parameter finite-difference
+gradient on the same GPU, the FP32-amplitude variant, ADAPT screening, the
+Strategy-2 loop, and the FP64 CPU oracle timed on the host cores; then the
+30-qubit workload (14 electrons, 500 operators; FP64 and FP32 rates, its
+dominant kernel's roofline, finite differences on 16 parameters extrapolated
+to all of them).
 
 Prints one JSON line.
 """
@@ -83,6 +86,78 @@ def sector_model_bytes(p, amp_bytes):
             "per_op": per_op}
 
 
+def fd_subset(plan, p, g, psi, n_params=16, h=1e-5):
+    """Central finite differences on the first n_params angles, each energy a
+    full ansatz preparation plus <H> on the GPU; the time per energy is
+    extrapolated to the 2K + 1 energies of a whole finite-difference
+    gradient (labelled as an extrapolation)."""
+    import torch
+    th = np.array(p.theta, dtype=np.float64)
+    plan.ansatz_apply(th, psi)
+    plan.energy(psi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gfd = np.zeros(n_params)
+    for k in range(n_params):
+        e = []
+        for sgn in (1.0, -1.0):
+            t = th.copy()
+            t[k] += sgn * h
+            plan.ansatz_apply(t, psi)
+            e.append(plan.energy(psi))
+        gfd[k] = (e[0] - e[1]) / (2 * h)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    per_energy = dt / (2 * n_params)
+    full = per_energy * (2 * p.n_ops + 1)
+    return {"params_measured": n_params, "measured_s": dt, "per_energy_ms": per_energy * 1e3,
+            "extrapolated_full_fd_s": full, "extrapolated": True,
+            "max_abs_diff_vs_adjoint_on_subset": float(np.abs(gfd - g[:n_params]).max())}
+
+
+def bench_c5(fsv, torch, stream, steps=5, warmup=1):
+    """The 30-qubit workload (14 electrons, 500 operators): FP64 and FP32
+    energy + adjoint-gradient rates on the sector engine, the dominant
+    kernel's roofline, and finite differences on 16 parameters.  The oracle
+    is not run at this size (the 24-qubit cpu_baseline stands)."""
+    from workloads import config
+    p = config("C5")
+    k = p.n_ops
+    psi = torch.empty(1 << p.n_qubits, dtype=torch.complex128, device=torch.device("cuda:0"))
+    lam = torch.empty_like(psi)
+    t0 = time.perf_counter()
+    plan, ms, evals_s, stages, e, g = time_engine(fsv, torch, p, 0, "sector", steps, warmup, stream, psi, lam)
+    setup_s = time.perf_counter() - t0
+    mb = sector_model_bytes(p, 8)
+    start, tiles = plan.runs(adjoint=True)
+    fused_runs = len({start[t] for t in range(k) if tiles[t] > 0})
+    if fused_runs == 0:
+        roof = roofline_of(mb, stages, k, "k_cadj<double> (sector adjoint step)",
+                           traffic_from_profile("C5", C5_PROFILE, rotation_source_hash))
+    else:
+        roof = None
+    fd = fd_subset(plan, p, g, psi)
+    fd["adjoint_speedup_extrapolated"] = fd["extrapolated_full_fd_s"] / (ms * 1e-3)
+    print(f"[bench] C5: {ms:.2f} ms/eval; FD on 16 parameters {fd['measured_s']:.2f} s, "
+          f"extrapolated {fd['extrapolated_full_fd_s']:.1f} s", file=sys.stderr, flush=True)
+    del plan
+    p32, ms32, evals32, st32, e32, g32 = time_engine(
+        fsv, torch, p, 1, "sector", steps, warmup, stream,
+        psi.view(torch.float64)[: psi.numel()].view(torch.complex64),
+        lam.view(torch.float64)[: lam.numel()].view(torch.complex64))
+    del p32
+    return {"workload": f"C5: {p.n_qubits} qubits, {p.n_alpha + p.n_beta} electrons, {k} sampled "
+                        "spin-conserving singles/doubles, energy + adjoint gradient",
+            "evals_s": evals_s, "ms_per_eval": ms, "steps": steps, "warmup": warmup, "dtype": "f64",
+            "stage_ms": stages, "energy": e, "fused_adjoint_runs": fused_runs,
+            "hbm_frac_sector_model": mb["eval"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "roofline": roof,
+            "fp32_variant": {"evals_s": evals32, "ms_per_eval": ms32, "stage_ms": st32,
+                             "abs_energy_error_vs_fp64_Ha": abs(e32 - e),
+                             "max_abs_grad_error_vs_fp64": float(np.abs(g32 - g).max())},
+            "fd_subset": fd, "plan_setup_and_timing_s": setup_s}
+
+
 def cpu_baseline(p, max_seconds=30.0):
     from oracle import sector
     sector.build()
@@ -95,7 +170,7 @@ def cpu_baseline(p, max_seconds=30.0):
         if el >= min(10.0, max_seconds):  # a sample of about 10 s of oracle work
             break
     return {"value": n / el, "unit": "evals/s", "cores": sector.num_threads(), "kind": "oracle",
-            "sample": f"{n} full energy+adjoint-gradient evaluation(s) of the same 24-qubit workload "
+            "sample": f"{n} full energy+adjoint-gradient evaluation(s) of the same {p.n_qubits}-qubit workload "
                       f"(sector-compressed FP64 C/OpenMP oracle), {el:.1f} s"}
 
 
@@ -160,6 +235,7 @@ ROTATION_SOURCE = os.path.join(ROOT, "paper_2405_11567_amd", "csrc", "fsv_sigma.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_cadj_sector_24q_fp64.md")
 PACKET_SOURCE = os.path.join(ROOT, "paper_2405_11567_amd", "csrc", "fsv_packet.hip")
 PACKET_PROFILE = os.path.join(ROOT, "profiles", "k_pkt_adjoint_24q_fp64.md")
+C5_PROFILE = os.path.join(ROOT, "profiles", "k_cadj_sector_30q_fp64.md")
 
 
 def rotation_source_hash():
@@ -368,23 +444,26 @@ def bench_multidet(fsv, torch, p, psi, lam, n_det=10000, reps=10):
             "onebody_property_ms": prop_ms, "onebody_property": val.real}
 
 
-def bench_strategy2(fsv, torch, p, psi, lam, outer=10, reps=5):
+def bench_strategy2(fsv, torch, p, psi, lam, outer=10, inner=5, kappa=0.0, reps=5):
     """The 24-qubit workload's self-consistent loop (Strategy 2): per outer
-    iteration set the one-body potential, one energy + adjoint-gradient step
-    on the angles, then the ansatz state, its energy and its 1-RDM, from which
-    the next potential is built (10 outer iterations).  Also each call of the
-    loop timed on its own."""
+    iteration set the one-body potential, five gradient-descent steps on the
+    angles (energy + adjoint gradient, theta -= 0.1 grad), then the ansatz
+    state, its energy and its 1-RDM, from which the next potential is built
+    (10 outer iterations; the stand-in functional with kappa = 0, so the
+    potential is the fixed v0).  Reports the first outer iteration whose
+    energy change is below 1e-4 Ha, and each call of the loop timed on its
+    own."""
     from paper_2405_11567_amd.scloop import self_consistent_loop
     from workloads import potential_v0
     plan = fsv.Plan(p, device=psi.device)
     v0 = potential_v0(p.n_orb)
-    self_consistent_loop(plan, p.theta, v0, p.n_alpha, p.n_beta, kappa=0.5, outer=1, inner=1, lr=0.1,
+    self_consistent_loop(plan, p.theta, v0, p.n_alpha, p.n_beta, kappa=kappa, outer=1, inner=1, lr=0.1,
                          psi=psi, lam=lam)
     quiet_gc()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = self_consistent_loop(plan, p.theta, v0, p.n_alpha, p.n_beta, kappa=0.5, outer=outer, inner=1,
-                               lr=0.1, psi=psi, lam=lam)
+    res = self_consistent_loop(plan, p.theta, v0, p.n_alpha, p.n_beta, kappa=kappa, outer=outer, inner=inner,
+                               lr=0.1, threshold=1e-4, psi=psi, lam=lam)
     torch.cuda.synchronize()
     loop_ms = (time.perf_counter() - t0) * 1e3
 
@@ -398,7 +477,9 @@ def bench_strategy2(fsv, torch, p, psi, lam, outer=10, reps=5):
         return (time.perf_counter() - t) * 1e3 / reps
 
     plan.ansatz_apply(p.theta, psi)
-    out = {"outer_iterations": outer, "inner_steps": 1, "loop_ms": loop_ms, "ms_per_outer_iteration": loop_ms / outer,
+    out = {"outer_iterations": outer, "inner_steps": inner, "kappa": kappa, "threshold_Ha": 1e-4,
+           "energies": [r.energy for r in res.records], "delta_E": [None if np.isnan(r.delta) else r.delta for r in res.records],
+           "loop_ms": loop_ms, "ms_per_outer_iteration": loop_ms / outer,
            "rdm1_ms": timed(lambda: plan.rdm1(psi)),
            "set_onebody_potential_ms": timed(lambda: plan.set_onebody_potential(v0)),
            "ansatz_apply_ms": timed(lambda: plan.ansatz_apply(p.theta, psi)),
@@ -482,6 +563,7 @@ def main():
     ap.add_argument("--no-pool", action="store_true", help="skip the ADAPT pool-screening measurement")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-amplitude variant")
     ap.add_argument("--no-scf", action="store_true", help="skip the Strategy-2 self-consistent loop")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 30-qubit leg of the default run")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (the known-size "
@@ -595,8 +677,12 @@ def main():
         strategy2 = bench_strategy2(fsv, torch, p, psi, lam)
 
     cpu = None if args.no_cpu else cpu_baseline(p)
+    c5 = None
+    if args.config == "C3" and args.precision == 0 and args.engine == "sector" and not args.no_c5:
+        del plan
+        c5 = bench_c5(fsv, torch, stream)
     out = {
-        "metric": "energy+gradient evals/s and achieved HBM GB/s at 24 qubits vs plain FD method",
+        "metric": f"energy+gradient evals/s and achieved HBM GB/s at {p.n_qubits} qubits vs plain FD method",
         "value": evals_s,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -627,6 +713,7 @@ def main():
         "multideterminant_start": multidet,
         "strategy2_loop": strategy2,
         "cpu_baseline": cpu,
+        "c5": c5,
     }
     print(json.dumps(out))
 
