@@ -447,6 +447,11 @@ __global__ __launch_bounds__(256) void k_lr_a(const A *__restrict__ C, A *__rest
     }
 }
 
+// Doubles of k_lr_b's staged factor rows (M2 rows of ws), rounded up to an
+// even count so that the intermediate rows after them start 16-byte aligned
+// (complex rows are read as 16-byte values).
+__host__ __device__ inline size_t lr_lt_words(int M2, int ws) { return ((size_t)M2 * ws + 1) & ~(size_t)1; }
+
 constexpr int kExcBatch = 8;    // beta-list words loaded together in the step-2 loop of k_lr_b
 constexpr int kExcBatchAB = 4;  // and of k_lr_ab (which must stay within 64 VGPRs: two workgroups per CU)
 
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(1024) void k_lr_b(const A *__restrict__ Y, A *__res
                                                int lc, int ys, int ws) {
     extern __shared__ double smem_d[];
     double *lt = smem_d;               // M2 x ws
-    A *yr = (A *)(lt + M2 * ws);       // nsb x ys
+    A *yr = (A *)(lt + lr_lt_words(M2, ws));  // nsb x ys, 16-byte aligned
     const int64_t Ia = blockIdx.x;
     const A *yrow = Y + Ia * nsb * RP;
     A *srow = S + Ia * nsb;
@@ -750,7 +755,7 @@ int lr_chunk(const SectorTabs &T, int rp) {
     const size_t lim = g_lds_max > 0 ? (size_t)g_lds_max : 65536;
     const size_t per = (size_t)T.M * T.M * sizeof(double) + (size_t)T.nsb * sizeof(A);
     int lc = rp;
-    while (lc > 0 && (size_t)lc * per > lim) lc >>= 1;
+    while (lc > 0 && (size_t)lc * per + sizeof(double) > lim) lc >>= 1;  // + the alignment pad
     return lc;
 }
 
@@ -773,7 +778,7 @@ void lr_strides(const SectorTabs &T, int lc, int &ys, int &ws) {
     ws = lc;
     if (lc < 4 && sizeof(A) != sizeof(double)) return;
     const int py = lc < 4 ? lc + 1 : lc + (int)(16 / sizeof(A)), pw = lc < 4 ? lc + 1 : lc + 2;
-    if ((size_t)T.M * T.M * pw * sizeof(double) + (size_t)T.nsb * py * sizeof(A) <= lim) {
+    if (lr_lt_words(T.M * T.M, pw) * sizeof(double) + (size_t)T.nsb * py * sizeof(A) <= lim) {
         ys = py;
         ws = pw;
     }
@@ -796,7 +801,7 @@ hipError_t lr_launch(const SectorTabs &T, const A *C, A *S, hipStream_t st) {
     const int M2 = T.M * T.M;
     int ys, ws;
     lr_strides<A>(T, lc, ys, ws);
-    const size_t shm = (size_t)M2 * ws * sizeof(double) + (size_t)T.nsb * ys * sizeof(A);
+    const size_t shm = lr_lt_words(M2, ws) * sizeof(double) + (size_t)T.nsb * ys * sizeof(A);
     hipLaunchKernelGGL((k_lr_b<A>), dim3((unsigned)T.nsa), dim3(1024), shm, st, Y, S, T.excBT, T.nexcB, T.Lt, M2,
                        RP, T.nsb, lc, ys, ws);
     return hipGetLastError();
