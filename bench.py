@@ -163,6 +163,48 @@ def bench_c5(fsv, torch, stream, steps=5, warmup=1):
             "fd_subset": fd, "plan_setup_and_timing_s": setup_s}
 
 
+ORACLE_SAMPLE = r"""
+import sys, time, json
+sys.path.insert(0, sys.argv[1])
+from oracle import sector
+from workloads import config
+p = config(sys.argv[2])
+sector.build()
+sector.energy_grad(p.n_orb, p.n_alpha, p.n_beta, p.ops, p.theta, p.h, p.g, p.e_core, p.ordering) if p.n_qubits < 20 else None
+t0 = time.perf_counter(); n = 0
+while True:
+    sector.energy_grad(p.n_orb, p.n_alpha, p.n_beta, p.ops, p.theta, p.h, p.g, p.e_core, p.ordering)
+    n += 1
+    el = time.perf_counter() - t0
+    if el >= float(sys.argv[3]):
+        break
+print(json.dumps({"n": n, "s": el, "threads": sector.num_threads()}))
+"""
+
+
+def oracle_sample(name, seconds, threads=None):
+    """The oracle's energy + adjoint gradient on config `name`, repeated for
+    about `seconds`, in a child process (OMP_NUM_THREADS = threads when
+    given)."""
+    import subprocess
+    env = dict(os.environ)
+    if threads:
+        env["OMP_NUM_THREADS"] = str(threads)
+    r = subprocess.run([sys.executable, "-c", ORACLE_SAMPLE, ROOT, name, str(seconds)], env=env,
+                       capture_output=True, text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, max_seconds=30.0):
     from oracle import sector
     sector.build()
@@ -174,9 +216,22 @@ def cpu_baseline(p, max_seconds=30.0):
         el = time.perf_counter() - t0
         if el >= min(10.0, max_seconds):  # a sample of about 10 s of oracle work
             break
-    return {"value": n / el, "unit": "evals/s", "cores": sector.num_threads(), "kind": "oracle",
-            "sample": f"{n} full energy+adjoint-gradient evaluation(s) of the same {p.n_qubits}-qubit workload "
-                      f"(sector-compressed FP64 C/OpenMP oracle), {el:.1f} s"}
+    out = {"value": n / el, "unit": "evals/s", "cores": sector.num_threads(), "kind": "oracle",
+           "sample": f"{n} full energy+adjoint-gradient evaluation(s) of the same {p.n_qubits}-qubit workload "
+                     f"(sector-compressed FP64 C/OpenMP oracle), {el:.1f} s",
+           "cpu_model": cpu_model(), "host_cpus": len(os.sched_getaffinity(0))}
+    # the same on one thread, and the small configurations on all threads and on one
+    one = oracle_sample("C3", 8.0, threads=1)
+    out["single_thread"] = {"value": one["n"] / one["s"], "unit": "evals/s", "cores": one["threads"],
+                            "sample": f"{one['n']} evaluation(s) of the {p.n_qubits}-qubit workload, {one['s']:.1f} s"}
+    small = {}
+    for name in ("C1", "C2"):
+        a = oracle_sample(name, 1.0)
+        b = oracle_sample(name, 1.0, threads=1)
+        small[name] = {"all_threads_evals_s": a["n"] / a["s"], "threads": a["threads"],
+                       "single_thread_evals_s": b["n"] / b["s"]}
+    out["small_configs"] = small
+    return out
 
 
 def quiet_gc():
@@ -497,10 +552,11 @@ def bench_strategy2(fsv, torch, p, psi, lam, outer=10, inner=5, kappa=0.0, reps=
     return out
 
 
-def bench_batch(args):
+def run_batch(steps, warmup, tune=False, fd=True):
     """C4: 256 independent instances (10..20 qubits), energy + adjoint gradient
-    of every instance per step, in one persistent graph launch; compared with
-    one plan per instance called in a loop."""
+    of every instance per step in one graph launch; compared with one plan
+    per instance called in a loop, and with the finite-difference gradient
+    of every instance (each plan's own 2K + 1 energies)."""
     import torch
     import paper_2405_11567_amd as fsv
     from workloads import batch_config
@@ -512,18 +568,18 @@ def bench_batch(args):
     # all angles as one flat array (the batch's own layout), so that a step
     # times the library call and not per-instance array marshalling
     thetas = np.concatenate([p.theta for p in probs])
-    tune = b.autotune() if args.tune else ""
-    if tune:
-        print(tune, file=sys.stderr, flush=True)
+    tune_report = b.autotune() if tune else ""
+    if tune_report:
+        print(tune_report, file=sys.stderr, flush=True)
     quiet_gc()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         b.energy_grad(thetas)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         e, g = b.energy_grad(thetas)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     print(f"[bench] batch of {len(probs)}: {dt*1e3:.3f} ms per step", file=sys.stderr, flush=True)
     # unbatched: one plan per instance, sector engine, called in sequence
     plans = [fsv.Plan(p, device=dev) for p in probs]
@@ -539,19 +595,90 @@ def bench_batch(args):
     torch.cuda.synchronize()
     du = time.perf_counter() - t1
     print(f"[bench] unbatched loop: {du*1e3:.3f} ms", file=sys.stderr, flush=True)
-    out = {
-        "metric": "batched energy+gradient instance-evals/s (256 instances, 10-20 qubits)",
-        "value": len(probs) / dt, "unit": "instance-evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "C4: 256 instances, qubits uniform in 10..20 (even), electrons "
-                               "n/2 +- 2, 50..150 operators each, energy + adjoint gradient",
-                   "instances": len(probs), "total_ops": int(sum(p.n_ops for p in probs))},
+    fd_out = None
+    if fd:
+        t2 = time.perf_counter()
+        worst_fd = 0.0
+        off = 0
+        for pl, p, (ps, lm) in zip(plans, probs, bufs):
+            _, gfd = pl.energy_grad_fd(p.theta, 1e-5, ps)
+            worst_fd = max(worst_fd, float(np.abs(gfd - g[off:off + p.n_ops]).max()))
+            off += p.n_ops
+        torch.cuda.synchronize()
+        dfd = time.perf_counter() - t2
+        fd_out = {"s": dfd, "energies": int(sum(2 * p.n_ops + 1 for p in probs)), "batch_speedup": dfd / dt,
+                  "max_abs_diff_vs_batch_gradient": worst_fd}
+        print(f"[bench] finite differences, every instance: {dfd:.3f} s", file=sys.stderr, flush=True)
+    return {
+        "workload": "C4: 256 instances, qubits uniform in 10..20 (even), electrons n/2 +- 2, 50..150 "
+                    "operators each, energy + adjoint gradient",
+        "instances": len(probs), "total_ops": int(sum(p.n_ops for p in probs)),
+        "instance_evals_s": len(probs) / dt, "ms_per_step": dt * 1e3, "steps": steps, "warmup": warmup,
         "unbatched": {"ms": du * 1e3, "instance_evals_s": len(probs) / du,
                       "batch_speedup": du / dt, "max_abs_dE_vs_batch": worst},
+        "fd_every_instance": fd_out,
         "batch_device_bytes": b.bytes,
     }
+
+
+def bench_batch(args):
+    r = run_batch(args.steps, args.warmup, args.tune)
+    out = {
+        "metric": "batched energy+gradient instance-evals/s (256 instances, 10-20 qubits)",
+        "value": r["instance_evals_s"], "unit": "instance-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": r["workload"], "instances": r["instances"], "total_ops": r["total_ops"]},
+        "unbatched": r["unbatched"], "fd_every_instance": r["fd_every_instance"],
+        "batch_device_bytes": r["batch_device_bytes"],
+    }
     print(json.dumps(out))
+
+
+def bench_small(fsv, torch, reps=60):
+    """C1 (energy only: the forward sweep and <H>, through the stage calls)
+    and C2 (energy + adjoint gradient, FP64, and the FP32 variant's energy
+    error): absolute rates, median and fastest of `reps` timed calls each.
+    Both states are cache-resident, so no HBM fraction is given."""
+    from workloads import config
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)) * 1e3, float(np.min(ts)) * 1e3
+
+    out = {}
+    p1 = config("C1")
+    plan = fsv.Plan(p1)
+    psi, lam = plan.new_state(), plan.new_state()
+
+    def energy_only():
+        plan.set_theta(p1.theta)
+        plan.forward_async(psi)
+        plan.sigma_async(psi, lam)
+        return plan.finish()[0]
+
+    med, mn = timed(energy_only)
+    out["C1"] = {"work": "energy only (forward sweep and <H>)", "evals_s": 1e3 / med, "median_ms": med,
+                 "min_ms": mn, "energy": energy_only()}
+    p2 = config("C2")
+    plan = fsv.Plan(p2)
+    psi, lam = plan.new_state(), plan.new_state()
+    med, mn = timed(lambda: plan.energy_grad(p2.theta, psi, lam))
+    e64, _ = plan.energy_grad(p2.theta, psi, lam)
+    p32 = fsv.Plan(p2, precision=1)
+    e32, _ = p32.energy_grad(p2.theta)
+    out["C2"] = {"work": "energy + adjoint gradient", "evals_s": 1e3 / med, "median_ms": med, "min_ms": mn,
+                 "energy": e64, "fp32_abs_energy_error_vs_fp64_Ha": abs(e32 - e64)}
+    print(f"[bench] C1 energy {out['C1']['median_ms']:.3f} ms, C2 energy+gradient {med:.3f} ms",
+          file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -568,7 +695,8 @@ def main():
     ap.add_argument("--no-pool", action="store_true", help="skip the ADAPT pool-screening measurement")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-amplitude variant")
     ap.add_argument("--no-scf", action="store_true", help="skip the Strategy-2 self-consistent loop")
-    ap.add_argument("--no-c5", action="store_true", help="skip the 30-qubit leg of the default run")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the legs of the default run beyond the 24-qubit workload (C1, C2, C4, C5)")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (the known-size "
@@ -682,9 +810,11 @@ def main():
         strategy2 = bench_strategy2(fsv, torch, p, psi, lam)
 
     cpu = None if args.no_cpu else cpu_baseline(p)
-    c5 = None
+    small = c4 = c5 = None
     if args.config == "C3" and args.precision == 0 and args.engine == "sector" and not args.no_c5:
         del plan
+        small = bench_small(fsv, torch)
+        c4 = run_batch(10, 3)
         c5 = bench_c5(fsv, torch, stream)
     out = {
         "metric": f"energy+gradient evals/s and achieved HBM GB/s at {p.n_qubits} qubits vs plain FD method",
@@ -718,6 +848,8 @@ def main():
         "multideterminant_start": multidet,
         "strategy2_loop": strategy2,
         "cpu_baseline": cpu,
+        "small_configs": small,
+        "c4": c4,
         "c5": c5,
     }
     print(json.dumps(out))
