@@ -340,8 +340,22 @@ size_t fsv_batch_arena_bytes(const fsv_batch *batch);
  * (NULL or misaligned arguments), FSV_ENONFINITE, FSV_EDEVICE. */
 int fsv_batch_energy_grad(fsv_batch *batch, const double *theta_concat, void *arena_dev, double *E_out,
                           double *grad_concat);
-/* Device bytes the batch owns (its tables; the arena is the caller's). */
+/* Device bytes the batch owns (its tables and initial-state lists; the arena
+ * is the caller's). */
 size_t fsv_batch_bytes(const fsv_batch *batch);
+/* Start instance `instance` (0-based) from a multi-determinant state instead
+ * of its reference determinant (the paper warm-starts from CIPSI
+ * wavefunctions, Computational Details): sum_d coef[d] |dets[d]>, dets = qubit
+ * strings (host, n_det uint64; bit j = qubit j in that instance's ordering),
+ * each in the instance's (n_alpha, n_beta) sector and listed once; coef:
+ * host, n_det real values, used as given.  n_det = 0 restores the reference
+ * determinant.  Every launch scheme starts that instance from the list on
+ * later evaluations (the captured graph is rebuilt).  The lists are batch
+ * tables (counted by fsv_batch_bytes).  Errors: FSV_EINVAL (instance out of
+ * range; a determinant outside the sector, repeated, or with bits above the
+ * instance's last qubit), FSV_ENONFINITE, FSV_ENOMEM, FSV_EDEVICE. */
+int fsv_batch_set_initial_state(fsv_batch *batch, int32_t instance, int32_t n_det, const uint64_t *dets,
+                                const double *coef);
 /* Autotuner: times every candidate on this batch through its own captured
  * graph and keeps the fastest: launch scheme, persistent workgroup size and
  * workgroups per CU, phased workgroups per instance, and the LDS budget of an

@@ -385,6 +385,20 @@ class Batch:
         check(self._lib.fsv_batch_autotune(self._h, ctypes.c_void_p(self.arena.data_ptr()), ctypes.byref(rep)))
         return rep.value.decode() if rep.value else ""
 
+    def set_initial_state(self, instance: int, dets=None, coef=None):
+        """Start instance `instance` from sum_d coef[d] |dets[d]> (qubit strings
+        in that instance's ordering, each in its sector); without dets: its
+        reference determinant."""
+        if dets is None:
+            check(self._lib.fsv_batch_set_initial_state(self._h, int(instance), 0, None, None))
+            return
+        x = np.ascontiguousarray(np.asarray(dets, dtype=np.uint64).reshape(-1))
+        c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).reshape(-1))
+        if x.size != c.size:
+            raise ValueError("dets and coef differ in length")
+        check(self._lib.fsv_batch_set_initial_state(self._h, int(instance), int(x.size),
+                                                    x.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _dptr(c)))
+
     def close(self):
         if getattr(self, "_h", None):
             check(self._lib.fsv_batch_destroy(self._h))

@@ -49,7 +49,7 @@ EXPORTS = [
     "set_onebody_potential",
     "fsv_set_theta", "fsv_forward_async", "fsv_sigma_async", "fsv_reverse_async", "fsv_finish",
     "fsv_autotune", "fsv_batch_create", "fsv_batch_destroy", "fsv_batch_energy_grad",
-    "fsv_batch_bytes", "fsv_batch_autotune", "fsv_pool_create", "fsv_pool_destroy", "fsv_pool_gradients",
+    "fsv_batch_bytes", "fsv_batch_autotune", "fsv_batch_set_initial_state", "fsv_pool_create", "fsv_pool_destroy", "fsv_pool_gradients",
     "fsv_set_initial_state", "onebody_expectation",
 ]
 
@@ -99,6 +99,7 @@ def load():
     lib.fsv_batch_bytes.restype = ctypes.c_size_t
     lib.fsv_batch_bytes.argtypes = [vp]
     lib.fsv_batch_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_char_p)]
+    lib.fsv_batch_set_initial_state.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), d]
     lib.fsv_pool_create.argtypes = [ctypes.POINTER(vp), vp, i32, ctypes.c_int32, ctypes.c_int32]
     lib.fsv_pool_destroy.argtypes = [vp]
     lib.fsv_pool_gradients.argtypes = [vp, d, vp, vp, d, d]

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -58,6 +59,9 @@ struct BInst {
     int32_t ssd;        // 1: k_pss computes the same-spin part of S (dense, matrix cores)
     int64_t off_hd;     // dense alpha string Hamiltonian (nsa x nsa), then the beta one
                         // transposed (nsb x nsb), both row-major
+    int64_t off_init;   // first entry of this instance's initial-state list
+    int32_t n_init;     // its length (0: the reference determinant)
+    int32_t pad_init;
     double ecore;
 };
 
@@ -323,7 +327,8 @@ __device__ double sigma_row(const BInst &I, int Ia, const double *__restrict__ C
 __global__ __launch_bounds__(1024) void k_batch(
     const BInst *__restrict__ inst, const int *__restrict__ order, int count, int *counter,
     const BOp *__restrict__ ops, const uint32_t *__restrict__ lists, const double *__restrict__ cs,
-    BTabs T, double *__restrict__ arena, double *__restrict__ grad, double *__restrict__ eout) {
+    BTabs T, double *__restrict__ arena, double *__restrict__ grad, double *__restrict__ eout,
+    const int64_t *__restrict__ init_idx, const double *__restrict__ init_val) {
     extern __shared__ double lds[];
     __shared__ int s_idx;
     for (;;) {
@@ -336,7 +341,9 @@ __global__ __launch_bounds__(1024) void k_batch(
         double *psi = arena + I.off_state;
         double *lam = psi + I.dim;
 
-        for (int64_t t = threadIdx.x; t < I.dim; t += blockDim.x) psi[t] = t == I.ref ? 1.0 : 0.0;
+        for (int64_t t = threadIdx.x; t < I.dim; t += blockDim.x) psi[t] = (I.n_init == 0 && t == I.ref) ? 1.0 : 0.0;
+        __syncthreads();
+        for (int t = threadIdx.x; t < I.n_init; t += blockDim.x) psi[init_idx[I.off_init + t]] = init_val[I.off_init + t];
         __syncthreads();
 
         for (int k = 0; k < I.K; ++k) {  // forward sweep
@@ -396,7 +403,16 @@ __global__ __launch_bounds__(256) void k_pinit(const BInst *__restrict__ inst, d
     double *psi = arena + I.off_state;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < I.dim;
          t += (int64_t)gridDim.x * blockDim.x)
-        psi[t] = t == I.ref ? 1.0 : 0.0;
+        psi[t] = (I.n_init == 0 && t == I.ref) ? 1.0 : 0.0;
+}
+
+// Multi-determinant starts: workgroup y writes instance y's list (after
+// k_pinit has cleared its state).
+__global__ __launch_bounds__(64) void k_pinit_list(const BInst *__restrict__ inst, const int64_t *__restrict__ idx,
+                                                   const double *__restrict__ val, double *__restrict__ arena) {
+    const BInst I = inst[blockIdx.y];
+    double *psi = arena + I.off_state;
+    for (int t = threadIdx.x; t < I.n_init; t += blockDim.x) psi[idx[I.off_init + t]] = val[I.off_init + t];
 }
 
 __global__ __launch_bounds__(256) void k_pfwd(const BInst *__restrict__ inst, const BOp *__restrict__ ops,
@@ -656,11 +672,22 @@ struct fsv_batch {
     int32_t *d_pcount = nullptr;
     double *d_pgpart = nullptr;
     double *d_lt = nullptr, *d_ldiag = nullptr;
+    // multi-determinant starts: per instance (qubits, alpha, beta electrons,
+    // ordering) on the host, and the concatenated sector lists on the device
+    std::vector<std::array<int32_t, 4>> shape;
+    std::vector<std::vector<int64_t>> init_idx;
+    std::vector<std::vector<double>> init_val;
+    int64_t *d_init_idx = nullptr;
+    double *d_init_val = nullptr;
+    size_t init_bytes = 0;
+    int64_t n_init_total = 0;
     BTabs tabs() const { return BTabs{d_g, d_hptr, d_hcol, d_hval, d_ellc, d_ellv, d_excA, d_excBT, d_lt, d_ldiag}; }
     ~fsv_batch() {
         if (work) (void)hipStreamSynchronize(work);
         if (graph) (void)hipGraphExecDestroy(graph);
         for (void *p : owned) (void)hipFree(p);
+        if (d_init_idx) (void)hipFree(d_init_idx);
+        if (d_init_val) (void)hipFree(d_init_val);
         if (h_pin) (void)hipHostFree(h_pin);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
@@ -723,6 +750,13 @@ hipError_t launch_sigma(fsv_batch &B, const BTabs &T) {
     return hipGetLastError();
 }
 
+hipError_t launch_init_lists(fsv_batch &B) {
+    if (B.n_init_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pinit_list, dim3(1, (unsigned)B.count), dim3(64), 0, B.work, B.d_inst, B.d_init_idx,
+                       B.d_init_val, B.d_arena);
+    return hipGetLastError();
+}
+
 int enqueue(fsv_batch &B) {
     const BTabs T = B.tabs();
     if (B.total_k) {
@@ -734,6 +768,7 @@ int enqueue(fsv_batch &B) {
         hipLaunchKernelGGL(k_pinit, dim3((unsigned)B.gx, (unsigned)B.count), dim3(256), 0, B.work, B.d_inst,
                            B.d_arena);
         BHIP(hipGetLastError());
+        BHIP(launch_init_lists(B));
         const BatchPackets &P = B.pk;
         for (int r = 0; r < P.runs; ++r)
             BHIP(launch_batch_packets(false, B.d_arena, B.d_pent + P.ent_off[r], B.d_preg + P.reg_off[r], P.wr[r],
@@ -751,6 +786,7 @@ int enqueue(fsv_batch &B) {
         const dim3 grid((unsigned)B.gx, (unsigned)B.count);
         hipLaunchKernelGGL(k_pinit, grid, dim3(256), 0, B.work, B.d_inst, B.d_arena);
         BHIP(hipGetLastError());
+        BHIP(launch_init_lists(B));
         for (int k = 0; k < B.kmax; ++k) {
             hipLaunchKernelGGL(k_pfwd, grid, dim3(256), 0, B.work, B.d_inst, B.d_ops, B.d_lists, B.d_cs,
                                B.d_arena, k);
@@ -771,7 +807,8 @@ int enqueue(fsv_batch &B) {
     BHIP(hipGetLastError());
     const int grid = std::max(1, std::min(B.count, B.cus * B.per_cu));
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(B.block), B.lds_bytes, B.work, B.d_inst, B.d_order,
-                       B.count, B.d_counter, B.d_ops, B.d_lists, B.d_cs, T, B.d_arena, B.d_grad, B.d_e);
+                       B.count, B.d_counter, B.d_ops, B.d_lists, B.d_cs, T, B.d_arena, B.d_grad, B.d_e,
+                       (const int64_t *)B.d_init_idx, (const double *)B.d_init_val);
     BHIP(hipGetLastError());
     return FSV_OK;
 }
@@ -1021,7 +1058,10 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
             }
         }
         B->inst.push_back(I);
+        B->shape.push_back({p.n_qubits, p.n_alpha, p.n_beta, p.ordering});
     }
+    B->init_idx.assign(count, {});
+    B->init_val.assign(count, {});
     B->total_k = kk;
     for (int i = 0; i < count; ++i) B->kmax = std::max(B->kmax, problems[i].n_ops);
     B->part_cap = 64;
@@ -1149,7 +1189,7 @@ int fsv_batch_destroy(fsv_batch *B) {
     return FSV_OK;
 }
 
-size_t fsv_batch_bytes(const fsv_batch *B) { return B ? B->bytes : 0; }
+size_t fsv_batch_bytes(const fsv_batch *B) { return B ? B->bytes + B->init_bytes : 0; }
 
 size_t fsv_batch_arena_bytes(const fsv_batch *B) { return B ? B->arena_bytes : 0; }
 
@@ -1158,6 +1198,46 @@ size_t fsv_batch_arena_bytes(const fsv_batch *B) { return B ? B->arena_bytes : 0
 namespace {
 // The caller's arena for this call: a different block than the captured
 // graph's drops that graph.
+// Concatenate the instances' initial-state lists, upload them, point each
+// instance at its part and drop the captured graph (it names the old lists).
+int upload_init_lists(fsv_batch &B) {
+    int64_t total = 0;
+    for (int i = 0; i < B.count; ++i) {
+        B.inst[i].off_init = total;
+        B.inst[i].n_init = (int32_t)B.init_idx[i].size();
+        total += (int64_t)B.init_idx[i].size();
+    }
+    if (B.work) BHIP(hipStreamSynchronize(B.work));
+    if (B.graph) (void)hipGraphExecDestroy(B.graph);
+    B.graph = nullptr;
+    if (B.d_init_idx) (void)hipFree(B.d_init_idx);
+    if (B.d_init_val) (void)hipFree(B.d_init_val);
+    B.d_init_idx = nullptr;
+    B.d_init_val = nullptr;
+    B.init_bytes = 0;
+    B.n_init_total = total;
+    if (total > 0) {
+        std::vector<int64_t> idx;
+        std::vector<double> val;
+        idx.reserve(total);
+        val.reserve(total);
+        for (int i = 0; i < B.count; ++i) {
+            idx.insert(idx.end(), B.init_idx[i].begin(), B.init_idx[i].end());
+            val.insert(val.end(), B.init_val[i].begin(), B.init_val[i].end());
+        }
+        if (hipMalloc((void **)&B.d_init_idx, 8 * (size_t)total) != hipSuccess ||
+            hipMalloc((void **)&B.d_init_val, 8 * (size_t)total) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FSV_ENOMEM, "hipMalloc of the initial-state lists failed");
+        }
+        B.init_bytes = 16 * (size_t)total;
+        BHIP(hipMemcpy(B.d_init_idx, idx.data(), 8 * (size_t)total, hipMemcpyHostToDevice));
+        BHIP(hipMemcpy(B.d_init_val, val.data(), 8 * (size_t)total, hipMemcpyHostToDevice));
+    }
+    BHIP(hipMemcpy(B.d_inst, B.inst.data(), sizeof(BInst) * B.inst.size(), hipMemcpyHostToDevice));
+    return FSV_OK;
+}
+
 int bind_arena(fsv_batch &B, void *arena) {
     if (!arena) return fail(FSV_EINVAL, "arena_dev is NULL");
     if ((uintptr_t)arena & 255) return fail(FSV_EINVAL, "the arena must be 256-byte aligned");
@@ -1180,6 +1260,53 @@ int fsv_batch_energy_grad(fsv_batch *B, const double *theta, void *arena_dev, do
     int rc = bind_arena(*B, arena_dev);
     if (rc) return rc;
     return run(*B, theta, E_out, grad_out);
+}
+
+int fsv_batch_set_initial_state(fsv_batch *B, int32_t instance, int32_t n_det, const uint64_t *dets,
+                                const double *coef) {
+    if (!B) return fail(FSV_EINVAL, "batch is NULL");
+    if (instance < 0 || instance >= B->count) return fail(FSV_EINVAL, "instance %d of %d", instance, B->count);
+    if (n_det < 0 || (n_det > 0 && (!dets || !coef))) return fail(FSV_EINVAL, "bad n_det / dets / coef");
+    const BInst &I = B->inst[instance];
+    if ((int64_t)n_det > I.dim) return fail(FSV_EINVAL, "more determinants than the sector holds");
+    for (int d = 0; d < n_det; ++d)
+        if (!std::isfinite(coef[d])) return fail(FSV_ENONFINITE, "non-finite coefficient %d", d);
+    const int nq = B->shape[instance][0], na = B->shape[instance][1], nb = B->shape[instance][2];
+    const int ordering = B->shape[instance][3], M = nq / 2;
+    auto qubit = [&](int so) { return ordering == 0 ? so : so / 2 + (so % 2) * M; };
+    const std::vector<uint32_t> sa = strings_of(M, na), sb = strings_of(M, nb);
+    std::vector<int32_t> ra((size_t)1 << M, -1), rb((size_t)1 << M, -1);
+    for (size_t t = 0; t < sa.size(); ++t) ra[sa[t]] = (int32_t)t;
+    for (size_t t = 0; t < sb.size(); ++t) rb[sb[t]] = (int32_t)t;
+    std::vector<int64_t> idx(n_det);
+    std::vector<double> val(n_det);
+    for (int d = 0; d < n_det; ++d) {
+        const uint64_t x = dets[d];
+        if ((x >> nq) != 0) return fail(FSV_EINVAL, "determinant %d has bits above qubit %d", d, nq - 1);
+        uint32_t a = 0, b = 0;
+        for (int p = 0; p < M; ++p) {
+            a |= (uint32_t)((x >> qubit(2 * p)) & 1u) << p;
+            b |= (uint32_t)((x >> qubit(2 * p + 1)) & 1u) << p;
+        }
+        if (ra[a] < 0 || rb[b] < 0)
+            return fail(FSV_EINVAL, "determinant %d lies outside the (%d, %d) sector", d, na, nb);
+        idx[d] = (int64_t)ra[a] * I.nsb + rb[b];
+        // alpha-first sector amplitude = qubit-basis amplitude x the
+        // determinant's reordering sign
+        val[d] = (__builtin_popcount(a & beta_prefix_parity(M, ordering, b)) & 1) ? -coef[d] : coef[d];
+    }
+    {
+        std::vector<int64_t> srt(idx);
+        std::sort(srt.begin(), srt.end());
+        for (size_t t = 1; t < srt.size(); ++t)
+            if (srt[t] == srt[t - 1]) return fail(FSV_EINVAL, "a determinant is listed twice");
+    }
+    B->init_idx[instance] = std::move(idx);
+    B->init_val[instance] = std::move(val);
+    const int rc = upload_init_lists(*B);
+    if (rc) return rc;
+    clear_error();
+    return FSV_OK;
 }
 
 int fsv_batch_autotune(fsv_batch *B, void *arena_dev, const char **report) {

@@ -389,6 +389,18 @@ std::vector<uint32_t> strings_of(int M, int N) {
     return out;
 }
 
+uint32_t beta_prefix_parity(int M, int ordering, uint32_t b) {
+    auto qubit = [&](int so) { return ordering == 0 ? so : so / 2 + (so % 2) * M; };
+    uint32_t pp = 0;
+    for (int q = 0; q < M; ++q) {
+        int c = 0;
+        for (int r = 0; r < M; ++r)
+            if ((b >> r & 1u) && qubit(2 * r + 1) < qubit(2 * q)) ++c;
+        if (c & 1) pp |= 1u << q;
+    }
+    return pp;
+}
+
 // sign of E_pq = a^+_p a_q acting on string J (q in J, p not in J \ {q})
 int sign_epq(uint32_t J, int p, int q) {
     uint64_t x = J;
@@ -1296,12 +1308,7 @@ int build_device(fsv_plan &P) {
         uint32_t pp = 0;
         for (int p = 0; p < M; ++p)
             if (P.sb[i] >> p & 1u) x |= 1ull << qubit_of(P, 2 * p + 1);
-        for (int q = 0; q < M; ++q) {
-            int c = 0;
-            for (int r = 0; r < M; ++r)
-                if ((P.sb[i] >> r & 1u) && qubit_of(P, 2 * r + 1) < qubit_of(P, 2 * q)) ++c;
-            if (c & 1) pp |= 1u << q;
-        }
+        pp = beta_prefix_parity(M, P.ordering, P.sb[i]);
         Xb[i] = x;
         PPb[i] = pp;
     }

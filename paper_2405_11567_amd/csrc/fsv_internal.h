@@ -58,6 +58,12 @@ int validate_ops(int n_qubits, int n_ops, const int32_t *ops);
 // excitation 1: a qubit excitation (no JW string: sign +1 on every pair)
 RotOp compile_op(int M, int ordering, const int32_t *op, int excitation = 0);
 std::vector<uint32_t> strings_of(int M, int N);  // popcount-N masks, ascending
+// Prefix-parity mask of a beta string b (M spatial orbitals) for a qubit
+// ordering (0: qubit 2p + s, 1: qubit p + s M): bit q is set when an odd
+// number of b's occupied beta orbitals sit on qubits below alpha orbital q's
+// qubit.  (-1)^popcount(a & mask) is the sign between the qubit-basis
+// amplitude of determinant (a, b) and its alpha-first sector amplitude.
+uint32_t beta_prefix_parity(int M, int ordering, uint32_t b);
 void build_string_h(int M, const std::vector<uint32_t> &str, const std::vector<int32_t> &rank,
                     const double *ht, const double *g, std::vector<int64_t> &ptr,
                     std::vector<int32_t> &col, std::vector<double> &val);

@@ -25,3 +25,15 @@ def oracle_energy_grad(p, theta=None, h=None):
 
 def say(*a):
     print(*a, flush=True)
+
+
+def random_dets(p, n_det, seed):
+    """n_det distinct sector determinants of problem p (qubit strings in its
+    ordering; the reference first) with random real coefficients, normalised."""
+    idx = sector.sector_qubit_index(p.n_orb, p.n_alpha, p.n_beta, p.ordering).astype(np.int64)
+    rng = np.random.default_rng(seed)
+    n_det = min(n_det, idx.size)
+    pick = np.r_[0, 1 + rng.choice(idx.size - 1, n_det - 1, replace=False)]
+    coef = rng.normal(size=n_det)
+    coef[0] += 4.0
+    return idx[pick].astype(np.uint64), coef / np.linalg.norm(coef)

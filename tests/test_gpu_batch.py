@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 from workloads import batch_config, random_problem
-from tests.gpu_helpers import oracle_energy_grad, say
+from oracle import sector
+from tests.gpu_helpers import oracle_energy_grad, random_dets, say
 
 pytestmark = pytest.mark.gpu
 
@@ -88,3 +89,59 @@ def test_batch_rejects_bad_input(fsv):
     with pytest.raises(fsv.FsvError) as ei:
         b.energy_grad([np.full(5, np.inf)])
     assert ei.value.code == -5
+
+
+def _oracle_from(p, dets, coef):
+    psi0 = sector.determinants_vector(p.n_orb, p.n_alpha, p.n_beta, dets, coef, p.ordering)
+    return sector.energy_grad(p.n_orb, p.n_alpha, p.n_beta, p.ops, p.theta, p.h, p.g, p.e_core, p.ordering,
+                              psi0=psi0, excitation=getattr(p, "excitation", 0))
+
+
+@pytest.mark.parametrize("mode", ["phased", "persistent", "packets"])
+def test_batch_multideterminant_starts(fsv, mode, monkeypatch):
+    # some instances start from multi-determinant states (both orderings,
+    # fermionic and qubit excitations), the rest from their reference; then a
+    # list is replaced by a longer one, another cleared, and bad input refused
+    monkeypatch.setenv("FSV_BATCH_MODE", mode)
+    shapes = [(8, 4, 12), (10, 5, 20), (12, 6, 30), (12, 5, 25), (14, 7, 18), (16, 8, 22)]
+    probs = []
+    for i, (n, ne, k) in enumerate(shapes):
+        p = random_problem(n, ne, k, seed=1500 + i, theta_std=0.3, replace=True, ordering=i % 2)
+        p.excitation = 1 if i == 3 else 0
+        probs.append(p)
+    say("batch multi-det", mode)
+    b = fsv.Batch(probs)
+    starts = {1: random_dets(probs[1], 20, 11), 2: random_dets(probs[2], 40, 12), 3: random_dets(probs[3], 7, 13),
+              5: random_dets(probs[5], 60, 15)}
+    for i, (d, c) in starts.items():
+        b.set_initial_state(i, d, c)
+    thetas = [p.theta for p in probs]
+
+    def check():
+        e, g = b.energy_grad(thetas)
+        for i, p in enumerate(probs):
+            if i in starts:
+                e_ref, g_ref = _oracle_from(p, *starts[i])
+            else:
+                e_ref, g_ref = oracle_energy_grad(p)
+            assert abs(e[i] - e_ref) < 1e-10, (i, e[i], e_ref)
+            assert np.abs(g[i] - g_ref).max() < 1e-9, i
+
+    check()
+    starts[2] = random_dets(probs[2], 90, 22)
+    b.set_initial_state(2, *starts[2])
+    del starts[5]
+    b.set_initial_state(5)
+    check()
+    with pytest.raises(fsv.FsvError) as ei:
+        b.set_initial_state(len(probs), *random_dets(probs[0], 3, 1))
+    assert ei.value.code == -1
+    bad = np.array([np.uint64(1)], dtype=np.uint64)  # one electron: outside every sector here
+    with pytest.raises(fsv.FsvError) as ei:
+        b.set_initial_state(0, bad, [1.0])
+    assert ei.value.code == -1
+    d, c = random_dets(probs[0], 4, 3)
+    with pytest.raises(fsv.FsvError) as ei:
+        b.set_initial_state(0, np.r_[d, d[:1]], np.r_[c, c[:1]])
+    assert ei.value.code == -1
+    check()  # refused calls leave the lists as they were

@@ -6,7 +6,7 @@ import pytest
 
 from oracle import sector
 from workloads import config, random_problem, uccsd_pool
-from tests.gpu_helpers import dense_from_sector, say
+from tests.gpu_helpers import dense_from_sector, random_dets, say
 
 pytestmark = pytest.mark.gpu
 
@@ -16,15 +16,6 @@ def fsv(gpu):
     import paper_2405_11567_amd as m
     m.load()
     return m
-
-
-def random_dets(p, n_det, seed):
-    idx = sector.sector_qubit_index(p.n_orb, p.n_alpha, p.n_beta, p.ordering).astype(np.int64)
-    rng = np.random.default_rng(seed)
-    pick = np.r_[0, 1 + rng.choice(idx.size - 1, n_det - 1, replace=False)]
-    coef = rng.normal(size=n_det)
-    coef[0] += 4.0
-    return idx[pick].astype(np.uint64), coef / np.linalg.norm(coef)
 
 
 @pytest.mark.parametrize("engine", ["sector", "dense"])
