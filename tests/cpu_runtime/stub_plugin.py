@@ -62,14 +62,18 @@ def pytest_configure(config):
     stub.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
     stub.hipFree.argtypes = [ctypes.c_void_p]
 
+    import numpy as np
+
     def stub_tensor(nbytes, dtype):
         p = ctypes.c_void_p()
         if stub.hipMalloc(ctypes.byref(p), max(nbytes, 1)) != 0:
             raise MemoryError("stand-in hipMalloc failed")
         buf = (ctypes.c_char * max(nbytes, 1)).from_address(p.value)
-        t = torch.frombuffer(buf, dtype=dtype)
-        weakref.finalize(t, stub.hipFree, p.value)
-        return t
+        # the buffer is freed when the last tensor or array over it is gone
+        # (every view keeps this array alive through its storage)
+        arr = np.frombuffer(buf, dtype=np.uint8)
+        weakref.finalize(arr, stub.hipFree, p.value)
+        return torch.from_numpy(arr).view(dtype)
 
     def new_state(self):
         return stub_tensor((1 << self.n_qubits) * (16 if self.precision == 0 else 8), self.dtype)
