@@ -794,7 +794,7 @@ void plan_segments(fsv_plan &P) {
         int e = k;
         double cost = 0.0;
         if (allow) {
-            while (e < P.K) {
+            while (e < P.K && e - k < max_fused_run()) {
                 const RotOp &r = P.rot[e];
                 if ((int)r.q[r.nt - 1] >= P.tile_bits) break;
                 cost += op_line_bytes(P, r);
@@ -814,6 +814,10 @@ void plan_segments(fsv_plan &P) {
 int upload_counts(fsv_plan &P) {
     std::vector<int> gc(std::max(P.K, 1), 0);
     for (int k = 0; k < P.K; ++k) gc[k] = (int)rot_grid(P.npairs[k], P.shape_adj);
+    // operators of a fused run: one partial per workgroup of the fused adjoint
+    for (const auto &sg : P.segs)
+        if (sg.fused)
+            for (int k = sg.k0; k < sg.k1; ++k) gc[k] = (int)fused_grid(1ull << P.n, P.tile_bits);
     return upload(P, P.d_gcount, gc.data(), (size_t)P.K);
 }
 
@@ -881,9 +885,16 @@ int enq_sigma_dense(fsv_plan &P, const void *psi, void *lam) {
 
 int enq_reverse_dense(fsv_plan &P, void *psi, void *lam) {
     const int G = max_grid();
-    for (int k = P.K - 1; k >= 0; --k)
-        HIPCHECK(launch_adj(P.precision, P.wide, psi, lam, P.rot[k], P.d_cs, k, P.npairs[k],
-                            P.shape_adj, P.d_gpart + (size_t)k * G, P.work));
+    for (auto it = P.segs.rbegin(); it != P.segs.rend(); ++it) {
+        if (it->fused) {
+            HIPCHECK(launch_adj_fused(P.precision, psi, lam, P.d_rot, P.d_cs, it->k0, it->k1, P.tile_bits,
+                                      1ull << P.n, P.d_gpart, G, P.work));
+            continue;
+        }
+        for (int k = it->k1 - 1; k >= it->k0; --k)
+            HIPCHECK(launch_adj(P.precision, P.wide, psi, lam, P.rot[k], P.d_cs, k, P.npairs[k],
+                                P.shape_adj, P.d_gpart + (size_t)k * G, P.work));
+    }
     HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_gcount, G, P.K, 2.0, P.d_out + 1, P.work));
     return FSV_OK;
 }

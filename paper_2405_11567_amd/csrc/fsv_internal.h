@@ -107,10 +107,17 @@ hipError_t launch_adj(int precision, bool wide, void *psi, void *lam, const RotO
                       const double *cs, int k, uint64_t npairs, Shape sh, double *partial,
                       hipStream_t st);
 // LDS-staged fused run: ops [k0, k1) whose targets all lie below tile_bits are
-// applied block by block in one pass over psi (forward: +theta in order;
-// adjoint=true would need gradients and is not offered here).
+// applied block by block in one pass over psi (+theta in order).
 hipError_t launch_rot_fused(int precision, void *psi, const RotOp *ops_dev, const double *cs,
                             int k0, int k1, int tile_bits, uint64_t n_amps, hipStream_t st);
+// Its adjoint: one pass over psi and lam undoes ops k1-1 .. k0 and writes each
+// operator's gradient partials to partial[k * pstride + b], b < fused_grid().
+// At most max_fused_run() operators.
+hipError_t launch_adj_fused(int precision, void *psi, void *lam, const RotOp *ops_dev, const double *cs,
+                            int k0, int k1, int tile_bits, uint64_t n_amps, double *partial, int pstride,
+                            hipStream_t st);
+unsigned fused_grid(uint64_t n_amps, int tile_bits);
+int max_fused_run();
 
 hipError_t launch_reduce_rows(const double *partial, const int *counts, int stride, int rows,
                               double scale, double *out, hipStream_t st);

@@ -215,6 +215,78 @@ __global__ __launch_bounds__(512) void k_rot_fused(typename C2<R>::T *__restrict
     }
 }
 
+// Adjoint of an LDS-staged fused run: the tile's psi and lam are staged, the
+// run's operators are undone last to first, and each operator's share of
+// Re<lam|T|psi> (T = tau - tau^+, taken before the operator is undone) is
+// summed over the workgroup's tiles and written to
+// partial[k * pstride + blockIdx.x].  The sign of a pair is that of k_adj:
+// sign0 times the parity of the pair's index, split into the tile bits and
+// the bits above.
+constexpr int kMaxFusedRun = 64;
+
+template <typename R, int TB>
+__global__ __launch_bounds__(512) void k_adj_fused(typename C2<R>::T *__restrict__ psi,
+                                                   typename C2<R>::T *__restrict__ lam,
+                                                   const RotOp *__restrict__ ops,
+                                                   const double *__restrict__ cs, int k0, int k1,
+                                                   uint64_t ntiles, double *__restrict__ partial, int pstride) {
+    using V = typename C2<R>::T;
+    extern __shared__ double smem[];
+    V *tp = (V *)smem;          // psi tile
+    V *tl = tp + (1 << TB);     // lam tile
+    __shared__ double part[kMaxFusedRun];
+    const int nops = k1 - k0;
+    for (int i = threadIdx.x; i < nops; i += blockDim.x) part[i] = 0.0;
+    for (uint64_t tix = blockIdx.x; tix < ntiles; tix += gridDim.x) {
+        const uint64_t hi = tix << TB;
+        V *gp = psi + hi, *gl = lam + hi;
+        for (uint32_t i = threadIdx.x; i < (1u << TB); i += blockDim.x) {
+            tp[i] = gp[i];
+            tl[i] = gl[i];
+        }
+        __syncthreads();
+        for (int k = k1 - 1; k >= k0; --k) {
+            const RotOp op = ops[k];
+            const R c = (R)cs[2 * k];
+            const bool flip0 = (op.sign0 < 0) != ((popc(hi & op.par) & 1) != 0);
+            const uint32_t np = 1u << (TB - op.nt);
+            double acc = 0.0;
+            for (uint32_t t = threadIdx.x; t < np; t += blockDim.x) {
+                const uint32_t base = insert_zeros<uint32_t>(t, op);
+                const uint32_t xs = base | (uint32_t)op.src, xd = base | (uint32_t)op.dst;
+                const bool odd = flip0 != ((popc((uint32_t)(base & (uint32_t)op.par)) & 1) != 0);
+                const V pa = tp[xs], pb = tp[xd], la = tl[xs], lb = tl[xd];
+                const double o = (double)lb.x * pa.x + (double)lb.y * pa.y - (double)la.x * pb.x -
+                                 (double)la.y * pb.y;
+                acc += odd ? -o : o;
+                const R sg = odd ? -(R)cs[2 * k + 1] : (R)cs[2 * k + 1];
+                V na, nb;
+                na.x = c * pa.x + sg * pb.x;
+                na.y = c * pa.y + sg * pb.y;
+                nb.x = c * pb.x - sg * pa.x;
+                nb.y = c * pb.y - sg * pa.y;
+                tp[xs] = na;
+                tp[xd] = nb;
+                na.x = c * la.x + sg * lb.x;
+                na.y = c * la.y + sg * lb.y;
+                nb.x = c * lb.x - sg * la.x;
+                nb.y = c * lb.y - sg * la.y;
+                tl[xs] = na;
+                tl[xd] = nb;
+            }
+            // the workgroup sum also orders this operator's LDS updates before the next
+            const double tot = block_sum(acc);
+            if (threadIdx.x == 0) part[k - k0] += tot;
+        }
+        for (uint32_t i = threadIdx.x; i < (1u << TB); i += blockDim.x) {
+            gp[i] = tp[i];
+            gl[i] = tl[i];
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nops; i += blockDim.x) partial[(size_t)(k0 + i) * pstride + blockIdx.x] = part[i];
+}
+
 // Row-wise ordered reduction: out[r] = scale * sum_{b < counts[r]} partial[r*stride + b].
 __global__ void k_reduce_rows(const double *__restrict__ partial, const int *__restrict__ counts,
                               int stride, double scale, double *__restrict__ out) {
@@ -339,6 +411,19 @@ int max_grid() { return kMaxGrid; }
 void init_kernels() {
     init_sigma_kernels();
     init_fused_kernels();
+    // the adjoint fused run stages psi and lam tiles: 128 KiB of dynamic LDS
+    (void)hipFuncSetAttribute((const void *)k_adj_fused<double, 12>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * (1 << 12) * (int)sizeof(double2));
+    (void)hipFuncSetAttribute((const void *)k_adj_fused<float, 13>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * (1 << 13) * (int)sizeof(float2));
+    (void)hipGetLastError();
+}
+
+int max_fused_run() { return kMaxFusedRun; }
+
+unsigned fused_grid(uint64_t n_amps, int tile_bits) {
+    const uint64_t ntiles = n_amps >> tile_bits;
+    return (unsigned)(ntiles < (uint64_t)kMaxGrid ? ntiles : (uint64_t)kMaxGrid);
 }
 
 unsigned rot_grid(uint64_t npairs, Shape sh) {
@@ -396,7 +481,7 @@ hipError_t launch_adj(int precision, bool wide, void *psi, void *lam, const RotO
 hipError_t launch_rot_fused(int precision, void *psi, const RotOp *ops_dev, const double *cs,
                             int k0, int k1, int tile_bits, uint64_t n_amps, hipStream_t st) {
     const uint64_t ntiles = n_amps >> tile_bits;
-    const unsigned grid = (unsigned)(ntiles < (uint64_t)kMaxGrid ? ntiles : (uint64_t)kMaxGrid);
+    const unsigned grid = fused_grid(n_amps, tile_bits);
     if (precision == 0) {
         if (tile_bits != 12) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_rot_fused<double, 12>), dim3(grid), dim3(512), 0, st, (double2 *)psi,
@@ -405,6 +490,24 @@ hipError_t launch_rot_fused(int precision, void *psi, const RotOp *ops_dev, cons
         if (tile_bits != 13) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_rot_fused<float, 13>), dim3(grid), dim3(512), 0, st, (float2 *)psi,
                            ops_dev, cs, k0, k1, ntiles);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_fused(int precision, void *psi, void *lam, const RotOp *ops_dev, const double *cs,
+                            int k0, int k1, int tile_bits, uint64_t n_amps, double *partial, int pstride,
+                            hipStream_t st) {
+    if (k1 - k0 < 1 || k1 - k0 > kMaxFusedRun) return hipErrorInvalidValue;
+    const uint64_t ntiles = n_amps >> tile_bits;
+    const unsigned grid = fused_grid(n_amps, tile_bits);
+    if (precision == 0) {
+        if (tile_bits != 12) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_adj_fused<double, 12>), dim3(grid), dim3(512), 2 * (1 << 12) * sizeof(double2), st,
+                           (double2 *)psi, (double2 *)lam, ops_dev, cs, k0, k1, ntiles, partial, pstride);
+    } else {
+        if (tile_bits != 13) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_adj_fused<float, 13>), dim3(grid), dim3(512), 2 * (1 << 13) * sizeof(float2), st,
+                           (float2 *)psi, (float2 *)lam, ops_dev, cs, k0, k1, ntiles, partial, pstride);
     }
     return hipGetLastError();
 }

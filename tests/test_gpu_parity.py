@@ -167,9 +167,15 @@ def test_fused_lds_path(fsv, monkeypatch):
     psi = _np(plan.ansatz_apply(p.theta))
     ref, _ = dense_from_sector(oracle_state(p), p)
     assert np.abs(psi - ref).max() < 1e-12
+    # the adjoint sweep undoes the same runs in LDS (runs of at most 64 operators)
     e, g = plan.energy_grad(p.theta)
     e_ref, g_ref = oracle_energy_grad(p)
     assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+    e2, g2 = plan.energy_grad(p.theta)
+    assert e2 == e and np.array_equal(g2, g)
+    p32 = fsv.Plan(p, engine="dense", precision=1)
+    e32, g32 = p32.energy_grad(p.theta)
+    assert abs(e32 - e_ref) < 1e-4 and np.abs(g32 - g_ref).max() < 1e-4
 
 
 @pytest.mark.parametrize("engine", ENGINES)
