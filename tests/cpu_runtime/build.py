@@ -71,17 +71,19 @@ def build_stub(verbose: bool = False) -> str:
 _DYN_LDS = re.compile(r"extern __shared__ (\w+) (\w+)\[\];")
 
 
-def build_kexec(verbose: bool = False) -> str:
-    """The kernel-executing build (see the module docstring)."""
+def build_kexec(verbose: bool = False, csrc_dir: str | None = None) -> str:
+    """The kernel-executing build (see the module docstring); csrc_dir: another
+    copy of the kernel sources to build instead of the package's."""
     build_stub(verbose)
     src_root = os.path.join(OUT, "kexec_src")
     csrc = os.path.join(src_root, "paper_2405_11567_amd", "csrc")
     os.makedirs(csrc, exist_ok=True)
     os.makedirs(os.path.join(src_root, "include"), exist_ok=True)
     shutil.copy(os.path.join(ROOT, "include", "fsv.h"), os.path.join(src_root, "include", "fsv.h"))
-    for name in os.listdir(pkg_build.CSRC):
+    src = csrc_dir or pkg_build.CSRC
+    for name in os.listdir(src):
         if name.endswith((".hip", ".h")):
-            text = open(os.path.join(pkg_build.CSRC, name)).read()
+            text = open(os.path.join(src, name)).read()
             text = _DYN_LDS.sub(lambda m: f"{m.group(1)} *{m.group(2)} = ({m.group(1)} *)fsv_cpu_dyn_lds();", text)
             open(os.path.join(csrc, name), "w").write(text)
     flags = ["-x", "c++", "-std=c++17", "-O1", "-g", "-fPIC", "-fsanitize=address,undefined",
@@ -122,6 +124,7 @@ def build(verbose: bool = False) -> tuple:
 
 if __name__ == "__main__":
     if "kexec" in sys.argv:
-        print(build_kexec(verbose="-v" in sys.argv))
+        other = [a for a in sys.argv[1:] if a not in ("kexec", "-v")]
+        print(build_kexec(verbose="-v" in sys.argv, csrc_dir=other[0] if other else None))
     else:
         print(build(verbose="-v" in sys.argv))
