@@ -1198,42 +1198,60 @@ size_t fsv_batch_arena_bytes(const fsv_batch *B) { return B ? B->arena_bytes : 0
 namespace {
 // The caller's arena for this call: a different block than the captured
 // graph's drops that graph.
-// Concatenate the instances' initial-state lists, upload them, point each
-// instance at its part and drop the captured graph (it names the old lists).
-int upload_init_lists(fsv_batch &B) {
+// Make instance `instance`'s initial-state list (idx, val) current: the
+// concatenated lists of all instances are uploaded into new device buffers
+// first, and only when that succeeded do the old buffers go, the instances
+// point at their parts and the captured graph (which names the old lists) is
+// dropped.  On failure nothing changes.
+int replace_init_list(fsv_batch &B, int instance, std::vector<int64_t> &&idx, std::vector<double> &&val) {
+    std::vector<BInst> inst = B.inst;
     int64_t total = 0;
     for (int i = 0; i < B.count; ++i) {
-        B.inst[i].off_init = total;
-        B.inst[i].n_init = (int32_t)B.init_idx[i].size();
-        total += (int64_t)B.init_idx[i].size();
+        const size_t n = i == instance ? idx.size() : B.init_idx[i].size();
+        inst[i].off_init = total;
+        inst[i].n_init = (int32_t)n;
+        total += (int64_t)n;
     }
+    int64_t *d_idx = nullptr;
+    double *d_val = nullptr;
+    if (total > 0) {
+        std::vector<int64_t> hidx;
+        std::vector<double> hval;
+        hidx.reserve(total);
+        hval.reserve(total);
+        for (int i = 0; i < B.count; ++i) {
+            const std::vector<int64_t> &si = i == instance ? idx : B.init_idx[i];
+            const std::vector<double> &sv = i == instance ? val : B.init_val[i];
+            hidx.insert(hidx.end(), si.begin(), si.end());
+            hval.insert(hval.end(), sv.begin(), sv.end());
+        }
+        if (hipMalloc((void **)&d_idx, 8 * (size_t)total) != hipSuccess ||
+            hipMalloc((void **)&d_val, 8 * (size_t)total) != hipSuccess) {
+            (void)hipGetLastError();
+            if (d_idx) (void)hipFree(d_idx);
+            return fail(FSV_ENOMEM, "hipMalloc of the initial-state lists failed");
+        }
+        if (hipMemcpy(d_idx, hidx.data(), 8 * (size_t)total, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d_val, hval.data(), 8 * (size_t)total, hipMemcpyHostToDevice) != hipSuccess) {
+            const hipError_t e = hipGetLastError();
+            (void)hipFree(d_idx);
+            (void)hipFree(d_val);
+            return fail(FSV_EDEVICE, "upload of the initial-state lists failed: %s", hipGetErrorString(e));
+        }
+    }
+    // the new lists are on the device: retire the old ones and switch over
     if (B.work) BHIP(hipStreamSynchronize(B.work));
     if (B.graph) (void)hipGraphExecDestroy(B.graph);
     B.graph = nullptr;
     if (B.d_init_idx) (void)hipFree(B.d_init_idx);
     if (B.d_init_val) (void)hipFree(B.d_init_val);
-    B.d_init_idx = nullptr;
-    B.d_init_val = nullptr;
-    B.init_bytes = 0;
+    B.d_init_idx = d_idx;
+    B.d_init_val = d_val;
+    B.init_bytes = 16 * (size_t)total;
     B.n_init_total = total;
-    if (total > 0) {
-        std::vector<int64_t> idx;
-        std::vector<double> val;
-        idx.reserve(total);
-        val.reserve(total);
-        for (int i = 0; i < B.count; ++i) {
-            idx.insert(idx.end(), B.init_idx[i].begin(), B.init_idx[i].end());
-            val.insert(val.end(), B.init_val[i].begin(), B.init_val[i].end());
-        }
-        if (hipMalloc((void **)&B.d_init_idx, 8 * (size_t)total) != hipSuccess ||
-            hipMalloc((void **)&B.d_init_val, 8 * (size_t)total) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(FSV_ENOMEM, "hipMalloc of the initial-state lists failed");
-        }
-        B.init_bytes = 16 * (size_t)total;
-        BHIP(hipMemcpy(B.d_init_idx, idx.data(), 8 * (size_t)total, hipMemcpyHostToDevice));
-        BHIP(hipMemcpy(B.d_init_val, val.data(), 8 * (size_t)total, hipMemcpyHostToDevice));
-    }
+    B.init_idx[instance] = std::move(idx);
+    B.init_val[instance] = std::move(val);
+    B.inst = std::move(inst);
     BHIP(hipMemcpy(B.d_inst, B.inst.data(), sizeof(BInst) * B.inst.size(), hipMemcpyHostToDevice));
     return FSV_OK;
 }
@@ -1301,9 +1319,7 @@ int fsv_batch_set_initial_state(fsv_batch *B, int32_t instance, int32_t n_det, c
         for (size_t t = 1; t < srt.size(); ++t)
             if (srt[t] == srt[t - 1]) return fail(FSV_EINVAL, "a determinant is listed twice");
     }
-    B->init_idx[instance] = std::move(idx);
-    B->init_val[instance] = std::move(val);
-    const int rc = upload_init_lists(*B);
+    const int rc = replace_init_list(*B, instance, std::move(idx), std::move(val));
     if (rc) return rc;
     clear_error();
     return FSV_OK;
