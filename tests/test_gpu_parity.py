@@ -485,3 +485,30 @@ def test_same_spin_paths_and_replays(fsv, monkeypatch, same_spin, lr):
                 assert e == first[0] and np.array_equal(g, first[1])
             psi2 = plan.ansatz_apply(p.theta)
             assert abs(plan.energy(psi2) - e_ref) < 1e-10
+
+
+def test_largest_state_32_qubits(fsv):
+    # the largest state of which two FP64 vectors fit in HBM: 2^32 amplitudes
+    # (64 GiB each) with 64-bit amplitude indices in the dense kernels and 16
+    # orbitals in the sector tables; few electrons, so the oracle is quick.
+    # Outside the sampled sector amplitudes the state must be zero: checked
+    # through the norm on the device.
+    import torch
+    p = random_problem(32, 3, 8, seed=3200, theta_std=0.4, replace=True, ordering=1)
+    e_ref, g_ref = oracle_energy_grad(p)
+    vec = oracle_state(p)
+    idx = torch.as_tensor(sector.sector_qubit_index(p.n_orb, p.n_alpha, p.n_beta, p.ordering).astype(np.int64))
+    for engine in ENGINES:
+        say("32 qubits", engine)
+        plan = fsv.Plan(p, engine=engine)
+        psi, lam = plan.new_state(), plan.new_state()
+        e, g = plan.energy_grad(p.theta, psi, lam)
+        assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+        plan.ansatz_apply(p.theta, psi)
+        got = psi[idx.to(psi.device)].cpu().numpy()
+        assert np.abs(got - vec).max() < 1e-12
+        total = float(torch.linalg.vector_norm(psi).item()) ** 2
+        assert abs(total - float(np.sum(np.abs(vec) ** 2))) < 1e-12
+        assert abs(plan.energy(psi) - e_ref) < 1e-10
+        del psi, lam, plan
+        torch.cuda.empty_cache()
