@@ -150,6 +150,40 @@ def hamiltonian_apply(psi, h, g, e_core, ordering=0):
     return out
 
 
+def hamiltonian_apply_at(psi, xs, h, g, e_core, ordering=0) -> np.ndarray:
+    """(H psi)[x] for the basis indices in xs only, every term of the same
+    Hamiltonian as hamiltonian_apply applied literally: for a term c F,
+    <x|F|y> is the sign of F^+ |x> = sign |y>, so (c F psi)[x] = c sign
+    psi[y].  F^+ is the factor list reversed with creators and annihilators
+    exchanged.  Costs O(#terms x len(xs)), so large states can be checked at
+    sampled outputs."""
+    m = h.shape[0]
+    q = lambda p, s: qubit_of(2 * p + s, m, ordering)  # noqa: E731
+    xs = np.asarray(xs, dtype=np.int64)
+    out = e_core * psi[xs].astype(np.complex128)
+
+    def add(factors, c):
+        adj = [(1 - d, qq) for d, qq in reversed(factors)]
+        y, sg, ok = apply_string(xs, adj)
+        out[ok] += c * sg[ok] * psi[y[ok]]
+
+    for s in (0, 1):
+        for p in range(m):
+            for qq in range(m):
+                if h[p, qq] != 0.0:
+                    add([(0, q(qq, s)), (1, q(p, s))], h[p, qq])
+    for s in (0, 1):
+        for t in (0, 1):
+            for p in range(m):
+                for qq in range(m):
+                    for r in range(m):
+                        for ss in range(m):
+                            v = g[p, qq, r, ss]
+                            if v != 0.0:
+                                add([(0, q(qq, s)), (0, q(ss, t)), (1, q(r, t)), (1, q(p, s))], 0.5 * v)
+    return out
+
+
 def energy(psi, h, g, e_core, ordering=0) -> float:
     """E = Re <psi|H|psi> (the expectation value of Fig. 1), not normalised."""
     return float(np.real(np.vdot(psi, hamiltonian_apply(psi, h, g, e_core, ordering))))

@@ -13,7 +13,7 @@ import scipy.linalg
 import scipy.optimize
 
 from oracle import brute, dense, sector
-from workloads import random_problem, uccsd_pool
+from workloads import config, random_problem, uccsd_pool
 
 
 def so_list(n_alpha, n_beta):
@@ -286,3 +286,36 @@ def test_dense_literal_matches_sector_16q_general_integrals(ne, seed, ordering):
     outside = np.ones(psi_d.size, bool)
     outside[idx] = False
     assert np.all(s_d[outside] == 0)
+
+
+# --------------------------------------- T1 at sampled outputs, 24 qubits ----
+def test_literal_hamiltonian_at_sampled_outputs_24q():
+    # the 24-qubit workload's problem: the sector tier's state after its first
+    # 10 operators against the literal 2^24 rotations, and its H psi at the
+    # full 200-operator state against every term of H applied literally at 48
+    # sampled sector outputs (the literal H psi of the whole vector is out of
+    # reach at this size)
+    p = config("C3")
+    m = p.n_orb
+    idx = sector.sector_qubit_index(m, p.n_alpha, p.n_beta, p.ordering).astype(np.int64)
+    psi_d = dense.ansatz_state(24, p.n_alpha, p.n_beta, p.ops[:10], p.theta[:10], p.ordering)
+    psi_s = sector.ansatz(m, p.n_alpha, p.n_beta, p.ops[:10], p.theta[:10], p.ordering)
+    assert np.abs(psi_d[idx] - psi_s).max() < 1e-13
+    vec = sector.ansatz(m, p.n_alpha, p.n_beta, p.ops, p.theta, p.ordering)
+    full = np.zeros(1 << 24, dtype=np.complex128)
+    full[idx] = vec
+    sig = sector.sigma(vec, p.h, p.g, 0.25, p.n_alpha, p.n_beta, p.ordering)
+    rng = np.random.default_rng(24)
+    pick = rng.choice(idx.size, 48, replace=False)
+    lit = dense.hamiltonian_apply_at(full, idx[pick], p.h, p.g, 0.25, p.ordering)
+    assert np.abs(lit - sig[pick]).max() < 1e-11
+
+
+def test_literal_hamiltonian_at_equals_full_apply():
+    # the sampled-output form of the literal H against the whole-vector form
+    p = random_problem(10, 5, 12, seed=77, theta_std=0.4, ordering=1, replace=True)
+    psi = dense.ansatz_state(10, p.n_alpha, p.n_beta, p.ops, p.theta, 1)
+    psi = psi + 0.01 * np.random.default_rng(3).normal(size=psi.size)  # other sectors too
+    xs = np.arange(psi.size)
+    assert np.abs(dense.hamiltonian_apply_at(psi, xs, p.h, p.g, 0.1, 1)
+                  - dense.hamiltonian_apply(psi, p.h, p.g, 0.1, 1)).max() < 1e-12
