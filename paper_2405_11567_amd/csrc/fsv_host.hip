@@ -203,6 +203,7 @@ struct fsv_plan {
     // graphs
     uint64_t gen = 0;  // bumped whenever captured launches may have changed
     bool use_graph = true;
+    bool defer_e = false;  // energy_grad body: E is reduced with the gradients, after the sweep
     hipGraphExec_t g_eg = nullptr;
     const void *g_eg_psi = nullptr, *g_eg_lam = nullptr;
     hipGraphExec_t g_e = nullptr;
@@ -867,7 +868,7 @@ int enq_forward_dense(fsv_plan &P, void *psi) {
 // E = Re<C|S> into d_out[0].
 int enq_sector_sigma(fsv_plan &P, bool cplex, const void *C, void *S) {
     HIPCHECK(launch_sector_sigma(cplex, P.tabs, C, S, P.d_CT, P.d_ST, P.d_epart, P.work));
-    HIPCHECK(launch_reduce_rows(P.d_epart, P.d_ecount, 0, 1, 1.0, P.d_out, P.work));
+    if (!P.defer_e) HIPCHECK(launch_reduce_rows(P.d_epart, P.d_ecount, 0, 1, 1.0, P.d_out, P.work));
     return FSV_OK;
 }
 
@@ -895,7 +896,10 @@ int enq_reverse_dense(fsv_plan &P, void *psi, void *lam) {
             HIPCHECK(launch_adj(P.precision, P.wide, psi, lam, P.rot[k], P.d_cs, k, P.npairs[k],
                                 P.shape_adj, P.d_gpart + (size_t)k * G, P.work));
     }
-    HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_gcount, G, P.K, 2.0, P.d_out + 1, P.work));
+    if (P.defer_e)
+        HIPCHECK(launch_reduce_eg(P.d_epart, P.d_ecount, P.d_gpart, P.d_gcount, G, P.K, P.d_out, P.work));
+    else
+        HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_gcount, G, P.K, 2.0, P.d_out + 1, P.work));
     return FSV_OK;
 }
 
@@ -921,12 +925,12 @@ int enq_group_fwd(fsv_plan &P, void *c, const FGroup &g, hipEvent_t t0 = nullptr
 // One group of the adjoint sweep (operators last to first).  Packet
 // schedules run on the interleaved pairs z in d_C (c and lam_c are unused).
 int enq_group_rev(fsv_plan &P, void *c, void *lam_c, const FGroup &g, hipEvent_t t0 = nullptr,
-                  hipEvent_t t1 = nullptr) {
+                  hipEvent_t t1 = nullptr, bool store = true) {
     const int G = max_grid();
     if (P.frev.packets) {
         void *z = P.d_C;
         if (g.fused) {
-            HIPCHECK(launch_packets(P.svt, true, z, P.frev, g, P.d_cs, P.d_gpart, G, P.work, t0, t1));
+            HIPCHECK(launch_packets(P.svt, true, z, P.frev, g, P.d_cs, P.d_gpart, G, P.work, t0, t1, store));
             return FSV_OK;
         }
         if (t0) HIPCHECK(hipEventRecord(t0, P.work));
@@ -998,10 +1002,14 @@ int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
     const int G = max_grid();
     if (P.frev.packets) HIPCHECK(launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work));
     for (auto it = P.frev.groups.rbegin(); it != P.frev.groups.rend(); ++it) {
-        const int rc = enq_group_rev(P, c, lam_c, *it);
+        // the sweep's last run: its un-rotated psi and lam are not needed
+        const int rc = enq_group_rev(P, c, lam_c, *it, nullptr, nullptr, std::next(it) != P.frev.groups.rend());
         if (rc) return rc;
     }
-    HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_ccount, G, P.K, 2.0, P.d_out + 1, P.work));
+    if (P.defer_e)
+        HIPCHECK(launch_reduce_eg(P.d_epart, P.d_ecount, P.d_gpart, P.d_ccount, G, P.K, P.d_out, P.work));
+    else
+        HIPCHECK(launch_reduce_rows(P.d_gpart, P.d_ccount, G, P.K, 2.0, P.d_out + 1, P.work));
     return FSV_OK;
 }
 
@@ -1108,12 +1116,15 @@ int download_out(fsv_plan &P, double *E_out, double *grad_out, bool with_grad) {
 
 typedef int (*enq_fn)(fsv_plan &, void *, void *);
 
+// The energy's partial sums wait for the gradients' reduction (one launch
+// for both, the same ordered sums).
 int run_energy_grad_body(fsv_plan &P, void *psi, void *lam) {
     int rc;
     if ((rc = enq_forward(P, psi))) return rc;
-    if ((rc = enq_sigma(P, psi, lam))) return rc;
-    if ((rc = enq_reverse(P, psi, lam))) return rc;
-    return FSV_OK;
+    P.defer_e = true;
+    if (!(rc = enq_sigma(P, psi, lam))) rc = enq_reverse(P, psi, lam);
+    P.defer_e = false;
+    return rc;
 }
 
 int run_energy_body(fsv_plan &P, void *psi) {

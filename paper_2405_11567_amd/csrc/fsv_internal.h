@@ -119,6 +119,10 @@ hipError_t launch_adj_fused(int precision, void *psi, void *lam, const RotOp *op
 unsigned fused_grid(uint64_t n_amps, int tile_bits);
 int max_fused_run();
 
+// out[0] = the energy partials' sum, out[1 + k] = 2 x operator k's gradient
+// partials' sum (rows as in launch_reduce_rows), one launch.
+hipError_t launch_reduce_eg(const double *epart, const int *ecount, const double *gpart, const int *gcount,
+                            int stride, int k, double *out, hipStream_t st);
 hipError_t launch_reduce_rows(const double *partial, const int *counts, int stride, int rows,
                               double scale, double *out, hipStream_t st);
 
@@ -324,9 +328,11 @@ int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, con
 // One packet run: forward (state = psi) or adjoint (state = the interleaved
 // (psi, lam) pairs of launch_zip; gradient partials gpart[k * gstride + workgroup]).
 // t0, t1 (optional): events given the kernel's own start and end times.
+// store = false: the run's results are not written back (nothing reads them:
+// the adjoint sweep's last run).
 hipError_t launch_packets(int vtype, bool adjoint, void *state, const FusedSched &S, const FGroup &g,
                           const double *cs, double *gpart, int gstride, hipStream_t st, hipEvent_t t0 = nullptr,
-                          hipEvent_t t1 = nullptr);
+                          hipEvent_t t1 = nullptr, bool store = true);
 void init_fused_kernels();
 size_t fused_lds_limit();
 // Forward (psi) or adjoint (psi, lam, gradient partials gpart[k * gstride + tile]).

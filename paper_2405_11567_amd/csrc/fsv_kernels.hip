@@ -287,6 +287,21 @@ __global__ __launch_bounds__(512) void k_adj_fused(typename C2<R>::T *__restrict
     for (int i = threadIdx.x; i < nops; i += blockDim.x) partial[(size_t)(k0 + i) * pstride + blockIdx.x] = part[i];
 }
 
+// Energy and gradients in one launch: out[0] = sum_{b < ecount[0]} epart[b],
+// out[1 + k] = 2 sum_{b < gcount[k]} gpart[k * stride + b]; each row summed
+// exactly as k_reduce_rows sums it.
+__global__ void k_reduce_eg(const double *__restrict__ epart, const int *__restrict__ ecount,
+                            const double *__restrict__ gpart, const int *__restrict__ gcount, int stride,
+                            double *__restrict__ out) {
+    const int r = blockIdx.x;
+    const double *partial = r == 0 ? epart : gpart + (size_t)(r - 1) * stride;
+    const int n = r == 0 ? ecount[0] : gcount[r - 1];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n; b += blockDim.x) acc += partial[b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) out[r] = r == 0 ? acc : 2.0 * acc;
+}
+
 // Row-wise ordered reduction: out[r] = scale * sum_{b < counts[r]} partial[r*stride + b].
 __global__ void k_reduce_rows(const double *__restrict__ partial, const int *__restrict__ counts,
                               int stride, double scale, double *__restrict__ out) {
@@ -509,6 +524,13 @@ hipError_t launch_adj_fused(int precision, void *psi, void *lam, const RotOp *op
         hipLaunchKernelGGL((k_adj_fused<float, 13>), dim3(grid), dim3(512), 2 * (1 << 13) * sizeof(float2), st,
                            (float2 *)psi, (float2 *)lam, ops_dev, cs, k0, k1, ntiles, partial, pstride);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_eg(const double *epart, const int *ecount, const double *gpart, const int *gcount,
+                            int stride, int k, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_eg, dim3((unsigned)(k + 1)), dim3(256), 0, st, epart, ecount, gpart, gcount, stride,
+                       out);
     return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 struct PArgs {
     int32_t k0, m, wr, n_packets, gstride;
     const double *cs;
+    int32_t store;  // 0: the run's results are not needed (the adjoint sweep's last run)
 };
 
 // Packet of workgroup slot v: XCD v % 8 gets a contiguous range of packets.
@@ -240,14 +241,16 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slo
                 __syncthreads();
             }
         }
+        if (a.store) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (x[i] != kNone) {
-                if (ADJ)
-                    z[x[i]] = tv[l + i * kWave];
-                else
-                    psi[x[i]] = tp[l + i * kWave];
-            }
+            for (int i = 0; i < 4; ++i)
+                if (x[i] != kNone) {
+                    if (ADJ)
+                        z[x[i]] = tv[l + i * kWave];
+                    else
+                        psi[x[i]] = tp[l + i * kWave];
+                }
+        }
     }
     if (ADJ) {
         const double t = wave_sum16(acc);
@@ -852,9 +855,9 @@ namespace {
 // t0 / t1 (optional): events that take the kernel's own start and end times.
 template <typename T, bool ADJ>
 hipError_t pkt_impl(void *state, const FusedSched &S, const FGroup &g, const double *cs, double *gpart, int gstride,
-                    hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
+                    hipStream_t stream, hipEvent_t t0, hipEvent_t t1, bool store) {
     using V2 = typename Slot2<T>::V;
-    PArgs a{g.k0, g.nops, g.wr, g.n_packets, gstride, cs};
+    PArgs a{g.k0, g.nops, g.wr, g.n_packets, gstride, cs, store ? 1 : 0};
     const uint32_t *ent = S.d_aprog + g.ent_off, *reg = S.d_bprog + g.reg_off;
     const uint32_t shm =
         (uint32_t)(sizeof(double) * kPktScalars + (size_t)kPkt * (ADJ ? 2 : 1) * sizeof(T) + (size_t)g.wr * 4);
@@ -966,7 +969,7 @@ hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent
 
 hipError_t launch_packets(int vtype, bool adjoint, void *state, const FusedSched &S, const FGroup &g,
                           const double *cs, double *gpart, int gstride, hipStream_t st, hipEvent_t t0,
-                          hipEvent_t t1) {
+                          hipEvent_t t1, bool store) {
     if (g.n_packets <= 0) {  // a run whose operators have no pairs here: no launch
         hipError_t e = hipSuccess;
         if (t0) e = hipEventRecord(t0, st);
@@ -974,10 +977,10 @@ hipError_t launch_packets(int vtype, bool adjoint, void *state, const FusedSched
         return e;
     }
     if (vtype == V_F64)
-        return adjoint ? pkt_impl<double, true>(state, S, g, cs, gpart, gstride, st, t0, t1)
-                       : pkt_impl<double, false>(state, S, g, cs, gpart, gstride, st, t0, t1);
-    return adjoint ? pkt_impl<float, true>(state, S, g, cs, gpart, gstride, st, t0, t1)
-                   : pkt_impl<float, false>(state, S, g, cs, gpart, gstride, st, t0, t1);
+        return adjoint ? pkt_impl<double, true>(state, S, g, cs, gpart, gstride, st, t0, t1, store)
+                       : pkt_impl<double, false>(state, S, g, cs, gpart, gstride, st, t0, t1, store);
+    return adjoint ? pkt_impl<float, true>(state, S, g, cs, gpart, gstride, st, t0, t1, store)
+                   : pkt_impl<float, false>(state, S, g, cs, gpart, gstride, st, t0, t1, store);
 }
 
 }  // namespace fsv
