@@ -684,7 +684,7 @@ def bench_small(fsv, torch, reps=60):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--precision", type=int, default=0)
@@ -764,7 +764,7 @@ def main():
     dense = None
     if args.engine == "sector" and not args.no_dense:
         dplan, dms, devals, dstages, de, dg = time_engine(fsv, torch, p, args.precision, "dense",
-                                                          max(3, args.steps // 3), 1, stream, psi, lam)
+                                                          max(3, min(args.steps // 3, 20)), 1, stream, psi, lam)
         dense = {"evals_s": devals, "ms_per_eval": dms, "stage_ms": dstages,
                  "roofline": roofline_of(mb_dense, dstages, k, "k_adj (dense adjoint step)"),
                  "dense_model_hbm_frac": mb_dense["eval"] / (dms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -814,7 +814,7 @@ def main():
     if args.config == "C3" and args.precision == 0 and args.engine == "sector" and not args.no_c5:
         del plan
         small = bench_small(fsv, torch)
-        c4 = run_batch(10, 3)
+        c4 = run_batch(50, 5)
         c5 = bench_c5(fsv, torch, stream)
     out = {
         "metric": f"energy+gradient evals/s and achieved HBM GB/s at {p.n_qubits} qubits vs plain FD method",
