@@ -138,6 +138,25 @@ __device__ __forceinline__ void rotp(T &a, T &b, T c, T s) {
     b = c * b + s * t;
 }
 
+// Streaming (non-temporal) stores of the scatter: a launch's results are read
+// by the next launch, mostly on other XCDs, so they need not stay in this
+// XCD's L2 (measured: 0.7 us less per adjoint launch at 24 qubits).
+template <typename T>
+__device__ __forceinline__ void store_stream(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+template <typename V2>
+__device__ __forceinline__ void store_stream2(V2 *p, V2 v) {
+    typedef decltype(v.x) E;
+    typedef E E2 __attribute__((ext_vector_type(2)));
+    E2 u;
+    u.x = v.x;
+    u.y = v.y;
+    __builtin_nontemporal_store(u, (E2 *)p);
+}
+__device__ __forceinline__ void store_stream(double2 *p, double2 v) { store_stream2(p, v); }
+__device__ __forceinline__ void store_stream(float2 *p, float2 v) { store_stream2(p, v); }
+
 // Forward: psi is the state.  Adjoint: z holds (psi, lam) of each amplitude
 // side by side, so one 16-byte (FP32: 8-byte) access moves both.
 template <typename T, bool ADJ, int NQ>
@@ -246,9 +265,9 @@ __global__ __launch_bounds__(kWave) void k_pkt(T *__restrict__ psi, typename Slo
             for (int i = 0; i < 4; ++i)
                 if (x[i] != kNone) {
                     if (ADJ)
-                        z[x[i]] = tv[l + i * kWave];
+                        store_stream(&z[x[i]], tv[l + i * kWave]);
                     else
-                        psi[x[i]] = tp[l + i * kWave];
+                        store_stream(&psi[x[i]], tp[l + i * kWave]);
                 }
         }
     }
