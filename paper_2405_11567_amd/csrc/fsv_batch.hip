@@ -636,7 +636,7 @@ struct fsv_batch {
     std::vector<void *> owned;
     size_t bytes = 0;
     hipStream_t user = nullptr, work = nullptr;
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t ev_in = nullptr;
     BInst *d_inst = nullptr;
     int *d_order = nullptr, *d_counter = nullptr;
     int32_t *d_tinst = nullptr;
@@ -690,7 +690,6 @@ struct fsv_batch {
         if (d_init_val) (void)hipFree(d_init_val);
         if (h_pin) (void)hipHostFree(h_pin);
         if (ev_in) (void)hipEventDestroy(ev_in);
-        if (ev_out) (void)hipEventDestroy(ev_out);
         if (work) (void)hipStreamDestroy(work);
     }
 };
@@ -842,8 +841,10 @@ int run(fsv_batch &B, const double *theta, double *E_out, double *grad_out) {
         if (!std::isfinite(theta[k])) return fail(FSV_ENONFINITE, "non-finite theta at %lld", (long long)k);
         th[k] = theta[k];
     }
-    BHIP(hipEventRecord(B.ev_in, B.user));
-    BHIP(hipStreamWaitEvent(B.work, B.ev_in, 0));
+    if (!stream_idle(B.user)) {  // an idle caller's stream has nothing to order against
+        BHIP(hipEventRecord(B.ev_in, B.user));
+        BHIP(hipStreamWaitEvent(B.work, B.ev_in, 0));
+    }
     if (B.total_k)
         BHIP(hipMemcpyAsync(B.d_theta, th, sizeof(double) * B.total_k, hipMemcpyHostToDevice, B.work));
     int rc = launch(B);
@@ -852,9 +853,7 @@ int run(fsv_batch &B, const double *theta, double *E_out, double *grad_out) {
     if (B.total_k)
         BHIP(hipMemcpyAsync(hg, B.d_grad, sizeof(double) * B.total_k, hipMemcpyDeviceToHost, B.work));
     BHIP(hipMemcpyAsync(he, B.d_e, sizeof(double) * B.count, hipMemcpyDeviceToHost, B.work));
-    BHIP(hipStreamSynchronize(B.work));
-    BHIP(hipEventRecord(B.ev_out, B.work));
-    BHIP(hipStreamWaitEvent(B.user, B.ev_out, 0));
+    BHIP(hipStreamSynchronize(B.work));  // the batch's work is complete: later work on the caller's stream follows it
     if (E_out) std::memcpy(E_out, he, sizeof(double) * B.count);
     if (grad_out && B.total_k) std::memcpy(grad_out, hg, sizeof(double) * B.total_k);
     return FSV_OK;
@@ -1095,8 +1094,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     }
     B->cus = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&B->work, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess) {
         delete B;
         return fail(FSV_EDEVICE, "stream/event creation failed");
     }

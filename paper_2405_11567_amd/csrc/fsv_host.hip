@@ -831,12 +831,23 @@ void drop_graphs(fsv_plan &P) {
     P.g_eg_psi = P.g_eg_lam = P.g_e_psi = nullptr;
 }
 
-int fence_in(fsv_plan &P) {
+// The plan's stream waits for the work queued on the caller's stream.  Calls
+// that wait for their own work on the host before returning first ask
+// whether the caller's stream is idle, in which case there is nothing to
+// wait for (an event record and a stream wait cost ~15 us of host time, a
+// query of an idle stream well under 1 us).  The stage calls fence
+// unconditionally: after the previous stage call's fence_out the caller's
+// stream is still waiting, so the query would only add its own cost.
+int fence_in(fsv_plan &P, bool skip_if_idle = false) {
+    if (skip_if_idle && stream_idle(P.user)) return FSV_OK;
     HIPCHECK(hipEventRecord(P.ev_in, P.user));
     HIPCHECK(hipStreamWaitEvent(P.work, P.ev_in, 0));
     return FSV_OK;
 }
 
+// Later work on the caller's stream waits for the plan's.  Calls that have
+// waited for their work on the host end without it: nothing queued later
+// can overtake work that has completed.
 int fence_out(fsv_plan &P) {
     HIPCHECK(hipEventRecord(P.ev_out, P.work));
     HIPCHECK(hipStreamWaitEvent(P.user, P.ev_out, 0));
@@ -1794,10 +1805,9 @@ int fsv_time_runs(fsv_plan *P, int adjoint, void *psi, void *lam, float *ms) {
 
 int fsv_set_theta(fsv_plan *P, const double *theta) {
     if (!P) return fail(FSV_EINVAL, "plan is NULL");
-    int rc;
-    if ((rc = fence_in(*P))) return rc;
-    if ((rc = upload_theta(*P, theta))) return rc;
-    return fence_out(*P);
+    // the angles go to the plan's own buffer on its own stream, ahead of the
+    // sweeps queued after this call; no caller data is read or written
+    return upload_theta(*P, theta);
 }
 
 int fsv_forward_async(fsv_plan *P, void *psi) {
@@ -1832,28 +1842,28 @@ int fsv_finish(fsv_plan *P, double *E_out, double *grad_out) {
     int rc;
     if ((rc = fence_in(*P))) return rc;
     if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
-    return fence_out(*P);
+    return FSV_OK;  // the host has waited for the plan's work
 }
 
 int ansatz_apply(fsv_plan *P, const double *theta, void *psi) {
     if (!P || !psi) return fail(FSV_EINVAL, "plan or psi is NULL");
     int rc;
-    if ((rc = fence_in(*P))) return rc;
+    if ((rc = fence_in(*P, true))) return rc;
     if ((rc = need_workspace(*P))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
     if ((rc = enq_ansatz_dense_out(*P, psi))) return rc;
     HIPCHECK(hipStreamSynchronize(P->work));
-    return fence_out(*P);
+    return FSV_OK;  // the host has waited for this call's work
 }
 
 int energy(fsv_plan *P, const void *psi, double *E_out) {
     if (!P || !psi || !E_out) return fail(FSV_EINVAL, "plan, psi or E_out is NULL");
     int rc;
-    if ((rc = fence_in(*P))) return rc;
+    if ((rc = fence_in(*P, true))) return rc;
     if ((rc = need_workspace(*P))) return rc;
     if ((rc = enq_sigma_dense(*P, psi, nullptr))) return rc;
     if ((rc = download_out(*P, E_out, nullptr, false))) return rc;
-    return fence_out(*P);
+    return FSV_OK;  // the host has waited for this call's work
 }
 
 int energy_grad(fsv_plan *P, const double *theta, void *psi, void *lam, double *E_out,
@@ -1862,12 +1872,12 @@ int energy_grad(fsv_plan *P, const double *theta, void *psi, void *lam, double *
     if (psi == lam) return fail(FSV_EINVAL, "psi and lam must be distinct buffers");
     if (P->K > 0 && !grad_out) return fail(FSV_EINVAL, "grad_out is NULL");
     int rc;
-    if ((rc = fence_in(*P))) return rc;
+    if ((rc = fence_in(*P, true))) return rc;
     if ((rc = need_workspace(*P))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
     if ((rc = launch_energy_grad(*P, psi, lam))) return rc;
     if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
-    return fence_out(*P);
+    return FSV_OK;  // the host has waited for this call's work
 }
 
 int energy_grad_noalloc(fsv_plan *P, const double *theta, void *psi, void *lam, double *E_out,
@@ -1882,7 +1892,7 @@ int energy_grad_noalloc(fsv_plan *P, const double *theta, void *psi, void *lam, 
     void *base = nullptr;
     int rc;
     if ((rc = scratch_address(&base))) return rc;
-    if ((rc = fence_in(*P))) return rc;
+    if ((rc = fence_in(*P, true))) return rc;
     if ((rc = upload_theta(*P, theta))) return rc;
     // the pass takes its parts from the scratch block: the plan's workspace
     // fields point there for the duration of the (eager) launches
@@ -1909,7 +1919,7 @@ int energy_grad_noalloc(fsv_plan *P, const double *theta, void *psi, void *lam, 
     P->d_epart = se;
     if (rc) return rc;
     if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
-    return fence_out(*P);
+    return FSV_OK;  // the host has waited for this call's work
 }
 
 int energy_grad_fd(fsv_plan *P, const double *theta, double step, void *psi, double *E_out,
@@ -1918,7 +1928,7 @@ int energy_grad_fd(fsv_plan *P, const double *theta, double step, void *psi, dou
     if (!(step > 0.0) || !std::isfinite(step)) return fail(FSV_EINVAL, "step must be > 0");
     if (P->K > 0 && !grad_out) return fail(FSV_EINVAL, "grad_out is NULL");
     int rc;
-    if ((rc = fence_in(*P))) return rc;
+    if ((rc = fence_in(*P, true))) return rc;
     if ((rc = need_workspace(*P))) return rc;
     std::vector<double> th(theta, theta + P->K);
     double e0 = 0.0;
@@ -1939,13 +1949,13 @@ int energy_grad_fd(fsv_plan *P, const double *theta, double step, void *psi, dou
         grad_out[k] = (ep - em) / (2.0 * step);
     }
     if (E_out) *E_out = e0;
-    return fence_out(*P);
+    return FSV_OK;  // the host has waited for this call's work
 }
 
 int rdm1(fsv_plan *P, const void *psi, double *gamma_out) {
     if (!P || !psi || !gamma_out) return fail(FSV_EINVAL, "plan, psi or gamma_out is NULL");
     int rc;
-    if ((rc = fence_in(*P))) return rc;
+    if ((rc = fence_in(*P, true))) return rc;
     if ((rc = need_workspace(*P))) return rc;
     hipStream_t st = P->work;
     const int M2 = P->M * P->M;
@@ -1967,7 +1977,7 @@ int rdm1(fsv_plan *P, const void *psi, double *gamma_out) {
     HIPCHECK(hipMemcpyAsync(h, P->d_gamma, sizeof(double2) * 2 * M2, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     std::memcpy(gamma_out, h, sizeof(double2) * 2 * M2);
-    return fence_out(*P);
+    return FSV_OK;  // the host has waited for this call's work
 }
 
 int set_onebody_potential(fsv_plan *P, const double *v) {
@@ -2259,7 +2269,7 @@ int fsv_pool_gradients(fsv_pool *Q, const double *theta, void *psi, void *lam, d
     fsv_plan &P = *Q->plan;
     if (P.engine != 0) return fail(FSV_ESTATE, "pool screening runs on the sector engine");
     int rc;
-    if ((rc = fence_in(P))) return rc;
+    if ((rc = fence_in(P, true))) return rc;
     if ((rc = need_workspace(P))) return rc;
     if ((rc = upload_theta(P, theta))) return rc;
     auto body = [&]() -> int {
@@ -2291,7 +2301,7 @@ int fsv_pool_gradients(fsv_pool *Q, const double *theta, void *psi, void *lam, d
     HIPCHECK(hipStreamSynchronize(P.work));
     if (E_out) *E_out = Q->h_pin[0];
     std::memcpy(grad_out, Q->h_pin + 1, sizeof(double) * Q->n);
-    return fence_out(P);
+    return FSV_OK;  // the host has waited for this call's work
 }
 
 // Batches are built in fsv_batch.hip.

@@ -53,6 +53,14 @@ __host__ __device__ inline uint32_t pack_exc(uint32_t J, uint32_t pq, int neg) {
 // ---- host helpers shared by plans and batches (fsv_host.hip) ----
 int fail(int code, const char *fmt, ...);
 void clear_error();
+// True when every operation queued on st has completed.  A query that fails
+// for any other reason counts as pending, so that the caller fences.
+inline bool stream_idle(hipStream_t st) {
+    const hipError_t q = hipStreamQuery(st);
+    if (q == hipSuccess) return true;
+    (void)hipGetLastError();
+    return false;
+}
 int validate_problem(const fsv_problem *p);
 int validate_ops(int n_qubits, int n_ops, const int32_t *ops);
 // excitation 1: a qubit excitation (no JW string: sign +1 on every pair)

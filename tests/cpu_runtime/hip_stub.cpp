@@ -690,6 +690,15 @@ hipError_t hipStreamSynchronize(hipStream_t s) {
     if (x && x->capturing) die("hipStreamSynchronize on a capturing stream");
     return hipSuccess;
 }
+// Work runs at launch here, so a stream is idle, unless FSV_STUB_BUSY_STREAMS
+// is set: then every query reports pending work and the callers' fences run.
+hipError_t hipStreamQuery(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Stream *x = stream_of(s, "hipStreamQuery");
+    if (x && x->capturing) return hipErrorStreamCaptureUnsupported;
+    static const bool busy = std::getenv("FSV_STUB_BUSY_STREAMS") != nullptr;
+    return busy ? hipErrorNotReady : hipSuccess;
+}
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned int) {
     std::lock_guard<std::mutex> lk(g_mu);
     stream_of(s, "hipStreamWaitEvent");

@@ -371,6 +371,46 @@ def test_set_theta_does_not_change_a_queued_sweep(fsv):
         assert abs(e - e2_ref) < 1e-10 and np.abs(g - g2_ref).max() < 1e-9
 
 
+def test_stream_ordering_with_busy_streams(fsv):
+    # a call skips its stream fences only when the stream in question is idle:
+    # (1) a plan bound to a busy caller's stream reads psi only after the
+    # caller's queued copy into it; (2) work queued on the caller's stream
+    # after an asynchronous stage call sees that call's output
+    import torch
+    p = config("C3")
+    s = torch.cuda.Stream()  # default priority
+    plan = fsv.Plan(p, stream=s)
+    ref = plan.ansatz_apply(p.theta)
+    e_ref = plan.energy(ref)
+    psi = plan.new_state()
+    psi.fill_(float("nan"))
+    busy = torch.randn(2048, 2048, device=ref.device)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(s):
+            for _ in range(8):
+                busy = torch.tanh(busy @ busy)
+            psi.copy_(ref)
+        e = plan.energy(psi)
+        torch.cuda.synchronize()
+        assert abs(e - e_ref) < 1e-12
+        psi.fill_(float("nan"))
+        torch.cuda.synchronize()
+    lam = plan.new_state()
+    for _ in range(3):
+        psi.fill_(7.0)  # a finite sentinel: parts of psi outside the sector state stay as they are
+        torch.cuda.synchronize()
+        plan.set_theta(p.theta)
+        plan.forward_async(psi)
+        with torch.cuda.stream(s):
+            snap = psi.clone()
+        torch.cuda.synchronize()
+        assert torch.equal(snap, psi)
+        plan.sigma_async(psi, lam)
+        plan.reverse_async(psi, lam)
+        plan.finish()
+
+
 @pytest.mark.parametrize("mode", ["auto", "none", "force", "tiles", "packets"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_fused_runs_sector(fsv, monkeypatch, mode, precision):

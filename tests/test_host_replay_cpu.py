@@ -38,8 +38,10 @@ def hostcheck():
     return rt_build.asan_runtime()
 
 
-def _replay(asan, *suites, timeout=900):
+def _replay(asan, *suites, timeout=900, busy_streams=False):
     env = dict(os.environ)
+    if busy_streams:  # every stream query reports pending work, so the calls' fences run
+        env["FSV_STUB_BUSY_STREAMS"] = "1"
     env["LD_PRELOAD"] = asan
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
     env["UBSAN_OPTIONS"] = "print_stacktrace=1"
@@ -65,6 +67,12 @@ def test_replay_pools_and_lifetimes(hostcheck):
 
 def test_replay_batches(hostcheck):
     _replay(hostcheck, "batch")
+
+
+def test_replay_with_busy_streams(hostcheck):
+    # the calls skip their stream fences when a stream is idle; here no stream
+    # is ever idle, so every fence's event record and wait are exercised
+    _replay(hostcheck, "pools", "batch", busy_streams=True)
 
 
 @pytest.fixture(scope="module")
