@@ -137,7 +137,7 @@ def bench_c5(fsv, torch, stream, steps=5, warmup=1):
     start, tiles = plan.runs(adjoint=True)
     fused_runs = len({start[t] for t in range(k) if tiles[t] > 0})
     if fused_runs == 0:
-        roof = roofline_of(mb, stages, k, "k_cadj<double> (sector adjoint step)",
+        roof = roofline_of(mb, stages, k, "k_cadj_zip<double> (sector adjoint step on (psi, lam) pairs)",
                            traffic_from_profile("C5", C5_PROFILE, rotation_source_hash))
     else:
         roof = None
@@ -292,15 +292,16 @@ def roofline_of(mb, stages, k, kernel, traffic=None):
 
 
 ROTATION_SOURCE = os.path.join(ROOT, "paper_2405_11567_amd", "csrc", "fsv_sigma.hip")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_cadj_sector_24q_fp64.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_cadj_zip_sector_24q_fp64.md")
 PACKET_SOURCE = os.path.join(ROOT, "paper_2405_11567_amd", "csrc", "fsv_packet.hip")
 PACKET_PROFILE = os.path.join(ROOT, "profiles", "k_pkt_adjoint_24q_fp64.md")
-C5_PROFILE = os.path.join(ROOT, "profiles", "k_cadj_sector_30q_fp64.md")
+C5_PROFILE = os.path.join(ROOT, "profiles", "k_cadj_zip_sector_30q_fp64.md")
 
 
 def rotation_source_hash():
     """sha256 (16 hex digits) of the rotation-kernel section of the sector
-    kernel file: the launch-grid helper, pair decoding, k_crot and k_cadj."""
+    kernel file: the launch-grid helper, pair decoding, k_crot, k_cadj, k_zip and
+    k_cadj_zip."""
     import hashlib
     text = open(ROTATION_SOURCE).read()
     a = text.index("// ------------------------------------------------------------ rotations ----")
@@ -747,8 +748,9 @@ def main():
         rev_ms = unfused_reverse(fsv, torch, p, args.precision, stream, psi, lam)
         print(f"[bench] per-operator adjoint sweep (no fused runs): {rev_ms:.3f} ms", file=sys.stderr, flush=True)
         traffic = traffic_from_profile(args.config) if args.precision == 0 else None
-        per_op = roofline_of(mb, {"reverse": rev_ms}, k, "k_cadj<double> (sector adjoint step)"
-                             if args.precision == 0 else "k_cadj<float> (sector adjoint step)", traffic)
+        per_op = roofline_of(mb, {"reverse": rev_ms}, k, "k_cadj_zip<double> (sector adjoint step on (psi, lam) pairs)"
+                             if args.precision == 0 else "k_cadj_zip<float> (sector adjoint step on (psi, lam) pairs)",
+                             traffic)
         pk_traffic = (traffic_from_profile(args.config, PACKET_PROFILE, packet_source_hash)
                       if args.precision == 0 else None)
         roof = packet_roofline(fsv, torch, plan, p, args.precision, psi, lam, pk_traffic)

@@ -188,10 +188,8 @@ __global__ __launch_bounds__(256) void k_cadj(V *__restrict__ psi, V *__restrict
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
-// ---------------------------------------------------------------- sigma ----
-// This section opens with two helpers of the adjoint sweep of packet runs,
-// which keeps psi and lam of each (real) sector amplitude side by side:
-// z[i] = (psi[i], lam[i]).
+// The adjoint sweep on real states keeps psi and lam of each sector amplitude
+// side by side, z[i] = (psi[i], lam[i]), so that one access moves both.
 template <typename R> struct Zip2;
 template <> struct Zip2<double> { using P = double2; };
 template <> struct Zip2<float> { using P = float2; };
@@ -237,6 +235,7 @@ __global__ __launch_bounds__(256) void k_cadj_zip(typename Zip2<R>::P *__restric
     if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
+// ---------------------------------------------------------------- sigma ----
 // out[I][:] = sum_k val[k] in[col[k]][:].  Blocks are dispatched row-fastest
 // over one column tile at a time (blockIdx.x = row, blockIdx.y = tile), so the
 // workgroups in flight share the input rows of the same tile in L2.
