@@ -263,6 +263,7 @@ struct FusedOpts {
     int min_block = 32;          // columns per block when blocks are split for more tiles
     int max_ops = 32;            // operators per run
     int64_t max_tiles = 8192;    // tiles per run (gradient partial slots per operator)
+    bool place_xcd = true;       // packet runs: place components by XCD (padding with empty packets)
 };
 
 struct FusedSched {

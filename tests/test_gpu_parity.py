@@ -446,6 +446,26 @@ def test_fused_runs_sector(fsv, monkeypatch, mode, precision):
         assert abs(e - e_ref) < 1e-4 and np.abs(g - g_ref).max() < 1e-3
 
 
+def test_packet_runs_placed_by_xcd(fsv):
+    # 20 qubits (63504 sector amplitudes): runs of a few hundred packets, so
+    # the components are placed by XCD and each XCD's range is padded with
+    # empty packets to a multiple of 8; both sweeps against the oracle, and
+    # a replay bit for bit
+    p = random_problem(20, 10, 80, seed=1211, theta_std=0.4, replace=True, ordering=1)
+    say("packets placed by XCD, 20 qubits")
+    plan = fsv.Plan(p)
+    start, tiles = plan.runs(adjoint=True)
+    assert tiles.max() >= 64
+    e, g = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p)
+    assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+    psi = _np(plan.ansatz_apply(p.theta))
+    ref, _ = dense_from_sector(oracle_state(p), p)
+    assert np.abs(psi - ref).max() < 1e-12
+    e2, g2 = plan.energy_grad(p.theta)
+    assert e2 == e and np.array_equal(g2, g)
+
+
 def test_packet_runs_many_packets(fsv):
     # 26 qubits (2.9 M sector amplitudes): runs hold more packets than the
     # launch grid, so workgroups carry several packets each
