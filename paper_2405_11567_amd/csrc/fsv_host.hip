@@ -204,6 +204,9 @@ struct fsv_plan {
     uint64_t gen = 0;  // bumped whenever captured launches may have changed
     bool use_graph = true;
     bool defer_e = false;  // energy_grad body: E is reduced with the gradients, after the sweep
+    // energy_grad body, real FP64 state, adjoint sweep on pairs: the product
+    // may write lam interleaved with psi into d_C (z_ready then says so)
+    bool zip_in_sigma = false, z_ready = false;
     hipGraphExec_t g_eg = nullptr;
     const void *g_eg_psi = nullptr, *g_eg_lam = nullptr;
     hipGraphExec_t g_e = nullptr;
@@ -878,7 +881,10 @@ int enq_forward_dense(fsv_plan &P, void *psi) {
 // S = H C on the sector (alpha-first basis, complex or real FP64) and
 // E = Re<C|S> into d_out[0].
 int enq_sector_sigma(fsv_plan &P, bool cplex, const void *C, void *S) {
-    HIPCHECK(launch_sector_sigma(cplex, P.tabs, C, S, P.d_CT, P.d_ST, P.d_epart, P.work));
+    bool zipped = false;
+    HIPCHECK(launch_sector_sigma(cplex, P.tabs, C, S, P.d_CT, P.d_ST, P.d_epart, P.work,
+                                 P.zip_in_sigma && !cplex ? (void *)P.d_C : nullptr, &zipped));
+    P.z_ready = zipped;
     if (!P.defer_e) HIPCHECK(launch_reduce_rows(P.d_epart, P.d_ecount, 0, 1, 1.0, P.d_out, P.work));
     return FSV_OK;
 }
@@ -1023,7 +1029,8 @@ int enq_sigma_sector(fsv_plan &P, const void *c, void *lam_c) {
 // schedules un-rotate c and lam_c in place.
 int enq_reverse_sector(fsv_plan &P, void *c, void *lam_c) {
     const int G = max_grid();
-    if (reverse_on_pairs(P)) HIPCHECK(launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work));
+    if (reverse_on_pairs(P) && !P.z_ready) HIPCHECK(launch_zip(P.svt, c, lam_c, P.d_C, P.dim, P.work));
+    P.z_ready = false;
     for (auto it = P.frev.groups.rbegin(); it != P.frev.groups.rend(); ++it) {
         // the sweep's last run: its un-rotated psi and lam are not needed
         const int rc = enq_group_rev(P, c, lam_c, *it, nullptr, nullptr, std::next(it) != P.frev.groups.rend());
@@ -1145,8 +1152,10 @@ int run_energy_grad_body(fsv_plan &P, void *psi, void *lam) {
     int rc;
     if ((rc = enq_forward(P, psi))) return rc;
     P.defer_e = true;
+    P.zip_in_sigma = P.engine == 0 && P.svt == V_F64 && reverse_on_pairs(P);
     if (!(rc = enq_sigma(P, psi, lam))) rc = enq_reverse(P, psi, lam);
     P.defer_e = false;
+    P.zip_in_sigma = P.z_ready = false;
     return rc;
 }
 

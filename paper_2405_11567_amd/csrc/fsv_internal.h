@@ -199,12 +199,15 @@ hipError_t launch_cadj_zip(int vtype, void *z, const PairOp &op, const uint32_t 
 hipError_t launch_convert(int vt_in, const void *in, int vt_out, void *out, int64_t n, hipStream_t st);
 // S = H C on the sector; C, S, CT, ST hold nsa*nsb values of type complex
 // (cplex) or real double.  Writes combine_grid(nsa*nsb) partials of Re<C|S>.
+// zout (real states, may be null): where the product's last step allows it,
+// the (C, S) pairs go to zout instead of S, and *zipped is set.
 unsigned combine_grid(int64_t dim);
 // Whether the product on a real (cplex = false) or complex sector state writes
 // the factorised intermediate YT (the two-kernel form of the alpha-beta term).
 bool lr_uses_intermediate(const SectorTabs &T, bool cplex);
 hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, void *S, void *CT,
-                               void *ST, double *epart, hipStream_t st);
+                               void *ST, double *epart, hipStream_t st, void *zout = nullptr,
+                               bool *zipped = nullptr);
 // ADAPT pool screening on a real sector state (V_F64 / V_F32): grid (gx, n_ops),
 // partial[t * gx + x] = workgroup x's share of Re<lam|T_t|psi> for pool op t.
 hipError_t launch_pool(int vtype, const void *psi, const void *lam, const PairOp *ops, const uint32_t *lists,

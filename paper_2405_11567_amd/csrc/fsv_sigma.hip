@@ -730,6 +730,24 @@ __global__ __launch_bounds__(256) void k_ecore_dot(double *__restrict__ S, const
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+// k_ecore_dot for a real state whose adjoint sweep follows on (psi, lam)
+// pairs: the pairs z[i] = (C[i], S[i] + ecore C[i]) are written instead of
+// S, so that the sweep needs no separate interleaving pass.
+__global__ __launch_bounds__(256) void k_ecore_zip(const double *__restrict__ S, const double *__restrict__ C,
+                                                   double ecore, int64_t dim, double2 *__restrict__ z,
+                                                   double *__restrict__ partial) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += (int64_t)gridDim.x * blockDim.x) {
+        const double c = C[i];
+        double s = S[i];
+        axpy(s, ecore, c);
+        z[i] = make_double2(c, s);
+        acc += c * s;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 template <typename O>  // O = double2 or float2 (dense complex amplitude)
 __global__ void k_scatter_real(O *__restrict__ lam,
                                const double *__restrict__ S, const uint64_t *__restrict__ Xa,
@@ -816,7 +834,8 @@ bool lr_uses_intermediate(const SectorTabs &T, bool cplex) {
 namespace {
 
 template <typename A>
-hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, double *epart, hipStream_t st) {
+hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, double *epart, hipStream_t st,
+                      double2 *zout, bool *zipped) {
     const int64_t nsa = T.nsa, nsb = T.nsb;
     constexpr int64_t w = sizeof(A) / sizeof(double);  // doubles per amplitude
     // same-spin alpha part (with the alpha one-body terms): dense on the
@@ -859,8 +878,14 @@ hipError_t sigma_impl(const SectorTabs &T, const A *C, A *S, A *CT, A *ST, doubl
         // real state: the beta GEMM accumulates into S directly
         const hipError_t e = dense_beta_accumulate(T.blas, T.hb_dense_t, (const double *)C, (double *)S, nsa, nsb, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_ecore_dot, dim3(combine_grid(nsa * nsb)), dim3(256), 0, st, (double *)S,
-                           (const double *)C, T.ecore, nsa * nsb, epart);
+        if (zout) {
+            hipLaunchKernelGGL(k_ecore_zip, dim3(combine_grid(nsa * nsb)), dim3(256), 0, st, (const double *)S,
+                               (const double *)C, T.ecore, nsa * nsb, zout, epart);
+            if (zipped) *zipped = true;
+        } else {
+            hipLaunchKernelGGL(k_ecore_dot, dim3(combine_grid(nsa * nsb)), dim3(256), 0, st, (double *)S,
+                               (const double *)C, T.ecore, nsa * nsb, epart);
+        }
         return hipGetLastError();
     }
     // same-spin beta part on the transpose, then combine
@@ -993,10 +1018,13 @@ hipError_t launch_convert(int vi, const void *in, int vo, void *out, int64_t n, 
 }
 
 hipError_t launch_sector_sigma(bool cplex, const SectorTabs &T, const void *C, void *S, void *CT, void *ST,
-                               double *epart, hipStream_t st) {
+                               double *epart, hipStream_t st, void *zout, bool *zipped) {
+    if (zipped) *zipped = false;
     if (cplex)
-        return sigma_impl<double2>(T, (const double2 *)C, (double2 *)S, (double2 *)CT, (double2 *)ST, epart, st);
-    return sigma_impl<double>(T, (const double *)C, (double *)S, (double *)CT, (double *)ST, epart, st);
+        return sigma_impl<double2>(T, (const double2 *)C, (double2 *)S, (double2 *)CT, (double2 *)ST, epart, st,
+                                   nullptr, nullptr);
+    return sigma_impl<double>(T, (const double *)C, (double *)S, (double *)CT, (double *)ST, epart, st,
+                              (double2 *)zout, zipped);
 }
 
 hipError_t launch_pool(int vtype, const void *psi, const void *lam, const PairOp *ops, const uint32_t *lists,
