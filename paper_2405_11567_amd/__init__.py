@@ -163,8 +163,8 @@ class Plan:
         th = self._theta(theta)
         grad = np.zeros(self.n_ops)
         e = ctypes.c_double()
-        check(self._lib.energy_grad(self._h, _dptr(th), self._check_state(psi), self._check_state(lam),
-                                    ctypes.byref(e), _dptr(grad)))
+        check(self._lib.energy_grad(self._h, th.ctypes.data, self._check_state(psi), self._check_state(lam),
+                                    ctypes.byref(e), grad.ctypes.data))
         return e.value, grad
 
     def energy_grad_noalloc(self, theta, psi, lam):

@@ -82,7 +82,7 @@ def load():
     lib.fsv_time_runs.argtypes = [vp, c_int, vp, vp, ctypes.POINTER(ctypes.c_float)]
     lib.ansatz_apply.argtypes = [vp, d, vp]
     lib.energy.argtypes = [vp, vp, d]
-    lib.energy_grad.argtypes = [vp, d, vp, vp, d, d]
+    lib.energy_grad.argtypes = [vp, vp, vp, vp, d, vp]  # theta and grad as addresses (the hot call)
     lib.energy_grad_noalloc.argtypes = [vp, d, vp, vp, d, d]
     lib.energy_grad_fd.argtypes = [vp, d, ctypes.c_double, vp, d, d]
     lib.rdm1.argtypes = [vp, vp, d]
