@@ -119,7 +119,7 @@ def fd_subset(plan, p, g, psi, lam, n_params=16, h=1e-5):
             "max_abs_diff_vs_adjoint_on_subset": float(np.abs(gfd - g[:n_params]).max())}
 
 
-def bench_c5(fsv, torch, stream, steps=5, warmup=1):
+def bench_c5(fsv, torch, stream, steps=5, warmup=1, packets=False):
     """The 30-qubit workload (14 electrons, 500 operators): FP64 and FP32
     energy + adjoint-gradient rates on the sector engine, the dominant
     kernel's roofline, and finite differences on 16 parameters.  The oracle
@@ -151,6 +151,35 @@ def bench_c5(fsv, torch, stream, steps=5, warmup=1):
         psi.view(torch.float64)[: psi.numel()].view(torch.complex64),
         lam.view(torch.float64)[: lam.numel()].view(torch.complex64))
     del p32
+    pk = None
+    if packets:
+        # component packets on request (FSV_FUSE=packets at plan creation):
+        # every run is a packet run; planning takes minutes at this size
+        print("[bench] C5 with packet runs on request: building the plan", file=sys.stderr, flush=True)
+        os.environ["FSV_FUSE"] = "packets"
+        os.environ["FSV_VERBOSE"] = "1"  # the library prints one line per planned run
+        try:
+            t0 = time.perf_counter()
+            plan_pk = fsv.Plan(p, device=psi.device)
+            plan_s = time.perf_counter() - t0
+        finally:
+            del os.environ["FSV_FUSE"]
+            del os.environ["FSV_VERBOSE"]
+        for _ in range(warmup):
+            plan_pk.energy_grad(p.theta, psi, lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e_pk, g_pk = plan_pk.energy_grad(p.theta, psi, lam)
+        torch.cuda.synchronize()
+        ms_pk = (time.perf_counter() - t0) * 1e3 / steps
+        start_pk, tiles_pk = plan_pk.runs(adjoint=True)
+        pk = {"plan_creation_s": plan_s, "device_bytes": plan_pk.device_bytes, "ms_per_eval": ms_pk,
+              "evals_s": 1e3 / ms_pk, "packet_runs": len({int(start_pk[t]) for t in range(k) if tiles_pk[t] > 0}),
+              "abs_energy_diff_vs_default": abs(e_pk - e),
+              "max_abs_grad_diff_vs_default": float(np.abs(g_pk - g).max())}
+        del plan_pk
+        print(f"[bench] C5 packets on request: {ms_pk:.2f} ms/eval, plan {plan_s:.0f} s", file=sys.stderr, flush=True)
     return {"workload": f"C5: {p.n_qubits} qubits, {p.n_alpha + p.n_beta} electrons, {k} sampled "
                         "spin-conserving singles/doubles, energy + adjoint gradient",
             "evals_s": evals_s, "ms_per_eval": ms, "steps": steps, "warmup": warmup, "dtype": "f64",
@@ -160,7 +189,7 @@ def bench_c5(fsv, torch, stream, steps=5, warmup=1):
             "fp32_variant": {"evals_s": evals32, "ms_per_eval": ms32, "stage_ms": st32,
                              "abs_energy_error_vs_fp64_Ha": abs(e32 - e),
                              "max_abs_grad_error_vs_fp64": float(np.abs(g32 - g).max())},
-            "fd_subset": fd, "plan_setup_and_timing_s": setup_s}
+            "fd_subset": fd, "plan_setup_and_timing_s": setup_s, "packets_on_request": pk}
 
 
 ORACLE_SAMPLE = r"""
@@ -698,6 +727,8 @@ def main():
     ap.add_argument("--no-scf", action="store_true", help="skip the Strategy-2 self-consistent loop")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the legs of the default run beyond the 24-qubit workload (C1, C2, C4, C5)")
+    ap.add_argument("--c5-packets", action="store_true",
+                    help="also time the 30-qubit workload with component packets on request (minutes of planning)")
     ap.add_argument("--tune", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy three times (the known-size "
@@ -817,7 +848,7 @@ def main():
         del plan
         small = bench_small(fsv, torch)
         c4 = run_batch(50, 5)
-        c5 = bench_c5(fsv, torch, stream)
+        c5 = bench_c5(fsv, torch, stream, packets=args.c5_packets)
     out = {
         "metric": f"energy+gradient evals/s and achieved HBM GB/s at {p.n_qubits} qubits vs plain FD method",
         "value": evals_s,

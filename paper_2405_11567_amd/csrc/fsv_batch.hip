@@ -1159,7 +1159,7 @@ int fsv_batch_create(fsv_batch **out, const fsv_problem *problems, int32_t count
     if ((rc = set_lds_budget(*B, B->lds_budget))) return fin(rc);
     // packet runs, when every instance is small enough (the default mode then)
     bool small = true;
-    for (const BInst &I : B->inst) small = small && I.dim <= packet_max_dim();
+    for (const BInst &I : B->inst) small = small && I.dim <= packet_default_dim();
     if (small && kk > 0) {
         std::vector<BatchPacketInst> pi;
         for (const BInst &I : B->inst) pi.push_back({I.nsa, I.nsb, I.off_state, I.off_ops, I.off_k, I.K});

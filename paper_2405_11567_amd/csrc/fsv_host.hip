@@ -196,8 +196,8 @@ struct fsv_plan {
     FusedSched ffwd, frev;
     size_t fuse_budget_fwd = 65536, fuse_budget_rev = 98304;
     // 0 LDS tiles where the cost model gains, 1 never (FSV_NO_FUSE), 2 every tile
-    // run (FSV_FORCE_FUSE), 3 component packets where the cost model gains (the
-    // default for states of at most packet_max_dim() amplitudes)
+    // run (FSV_FORCE_FUSE), 3 component packets (the default for states of at
+    // most packet_default_dim() amplitudes, where the cost model decides)
     int fuse_mode = 0;
 
     // graphs
@@ -1235,8 +1235,10 @@ int rebuild_fused(fsv_plan &P) {
     (void)hipGetLastError();
     int rc;
     if (P.fuse_mode == 3 && P.dim <= packet_max_dim()) {
-        // both sweeps run the same packet runs
-        o.mode = 0;
+        // both sweeps run the same packet runs; above the default size (only
+        // on request) every run is one: the cost model's rates are those of
+        // cache-resident states, and at 30 qubits every run pays
+        o.mode = P.dim <= packet_default_dim() ? 0 : 2;
         o.arrays = 2;
         if ((rc = build_packets(P.nsa, P.nsb, P.pops, P.h_plists, o, P.frev))) return rc;
         P.ffwd.share(P.frev);
@@ -1386,7 +1388,7 @@ int build_device(fsv_plan &P) {
     if ((rc = dalloc(P, &P.d_ccount, (size_t)std::max(P.K, 1)))) return rc;
     if ((rc = upload(P, P.d_plists, plists.data(), plists.size()))) return rc;
     if ((rc = upload(P, P.d_pops, P.pops.data(), P.pops.size()))) return rc;
-    P.fuse_mode = P.dim <= packet_max_dim() ? 3 : 0;
+    P.fuse_mode = P.dim <= packet_default_dim() ? 3 : 0;
     if (const char *e = std::getenv("FSV_FUSE")) {
         if (!std::strcmp(e, "tiles")) P.fuse_mode = 0;
         if (!std::strcmp(e, "packets")) P.fuse_mode = 3;
@@ -1630,7 +1632,7 @@ int autotune_sector(fsv_plan &P, void *psi, void *lam, std::string &rep) {
     std::vector<Cand> cands = {{1, 0, 0},          {0, 32768, 65536},   {0, 49152, 98304},
                                {0, 65536, 98304},  {0, 65536, 131072},  {0, 98304, 163840},
                                {0, 163840, 163840}};
-    if (P.dim <= packet_max_dim()) cands.push_back({3, 0, 0});
+    if (P.dim <= packet_default_dim()) cands.push_back({3, 0, 0});
     const Cand keep{P.fuse_mode, P.fuse_budget_fwd, P.fuse_budget_rev};
     std::vector<double> th(P.K, 0.1);
     int rc;

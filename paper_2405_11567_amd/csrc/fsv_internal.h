@@ -334,7 +334,10 @@ hipError_t launch_batch_packets(bool adjoint, double *arena, const uint32_t *ent
 // Packet runs (fused = 2) for sector states of at most packet_max_dim()
 // amplitudes; o.es, o.mode (0 cost model, 1 never, otherwise every run of >= 2)
 // and o.max_ops are used.  count[k] = gradient partials of operator k's run.
+// Plans use them by default up to packet_default_dim() amplitudes (above it
+// only on request: planning time and program memory grow with the state).
 int64_t packet_max_dim();
+int64_t packet_default_dim();
 int build_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
                   const FusedOpts &o, FusedSched &S);
 // One packet run: forward (state = psi) or adjoint (state = the interleaved

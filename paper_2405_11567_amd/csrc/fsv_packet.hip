@@ -39,6 +39,8 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <memory>
 #include <vector>
 
@@ -607,7 +609,9 @@ int pack_by_xcd(const std::vector<int32_t> &tv, UnionFind &uf, const std::vector
     constexpr int X = 8;
     const int nc = (int)csize.size();
     const int npk0 = pack_by_lines(tv, uf, csize, order, pk_of, w);
-    if (npk0 < 8 * X) return npk0;  // small runs: the packing by lines as it is
+    // small runs, and runs of states far beyond the caches (whose placement
+    // passes would cost seconds per run): the packing by lines as it is
+    if (npk0 < 8 * X || npk0 > 16384) return npk0;
     std::vector<int8_t> part(nc);
     {
         const int per = npk0 / X, rem = npk0 % X;
@@ -686,7 +690,8 @@ int pack_by_xcd(const std::vector<int32_t> &tv, UnionFind &uf, const std::vector
 
 }  // namespace
 
-int64_t packet_max_dim() { return (int64_t)1 << 22; }
+int64_t packet_max_dim() { return (int64_t)1 << 26; }
+int64_t packet_default_dim() { return (int64_t)1 << 22; }
 
 int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, const std::vector<uint32_t> &lists,
                  const FusedOpts &o, bool every_run, PacketPlan &S) {
@@ -700,6 +705,7 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
     if (N > packet_max_dim()) return fail(FSV_EINVAL, "internal: packet runs need at most %lld amplitudes",
                                           (long long)packet_max_dim());
     UnionFind uf(N);
+    const bool verbose = std::getenv("FSV_VERBOSE") != nullptr;
     auto pairs_of = [&](const PairOp &p) {
         return (double)(p.nA >= 0 ? p.nA : nsa) * (double)(p.nB >= 0 ? p.nB : nsb);
     };
@@ -875,6 +881,10 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
                         ++t;
                     }
             }
+        }
+        if (verbose) {  // planning a large state takes minutes: one line per run
+            std::fprintf(stderr, "[fsv] packet run at operator %d: %d operators, %d packets\n", i, m, npk);
+            std::fflush(stderr);
         }
         g.lds = sizeof(double) * kPktScalars + (size_t)kPkt * 2 * o.es + (size_t)wr * 4;
         const int grid = std::min(npk, max_grid());

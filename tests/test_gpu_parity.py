@@ -466,6 +466,25 @@ def test_packet_runs_placed_by_xcd(fsv):
     assert e2 == e and np.array_equal(g2, g)
 
 
+def test_packet_runs_on_request_above_default_size(fsv, monkeypatch):
+    # 28 qubits (11.8 M sector amplitudes, above the 2^22 default): packet
+    # runs only on request (FSV_FUSE=packets), and then every run is one
+    p = random_problem(28, 14, 30, seed=1221, theta_std=0.3, replace=True)
+    say("packets on request, 28 qubits")
+    plan = fsv.Plan(p)
+    start, tiles = plan.runs(adjoint=True)
+    assert tiles.max() == 0  # the default: one launch per operator
+    monkeypatch.setenv("FSV_FUSE", "packets")
+    plan = fsv.Plan(p)
+    start, tiles = plan.runs(adjoint=True)
+    assert (tiles > 0).all() and len(set(start.tolist())) < p.n_ops // 4
+    e, g = plan.energy_grad(p.theta)
+    e_ref, g_ref = oracle_energy_grad(p)
+    assert abs(e - e_ref) < 1e-10 and np.abs(g - g_ref).max() < 1e-9
+    e2, g2 = plan.energy_grad(p.theta)
+    assert e2 == e and np.array_equal(g2, g)
+
+
 def test_packet_runs_many_packets(fsv):
     # 26 qubits (2.9 M sector amplitudes): runs hold more packets than the
     # launch grid, so workgroups carry several packets each
