@@ -148,7 +148,7 @@ int fsv_plan_set_engine(fsv_plan *plan, int engine);
  *  - component packets (the default for sector states of at most 2^22
  *    amplitudes; FSV_FUSE=packets requests them up to 2^26, where every run
  *    becomes a packet run: at 30 qubits an evaluation takes 71 instead of
- *    83 ms, but planning takes ~5 minutes and the programs 13 GB of device
+ *    83 ms, but planning takes ~3 minutes and the programs 13 GB of device
  *    memory; FSV_VERBOSE prints a line per planned run): the connected components of the graph joining the amplitudes
  *    that some operator of the run pairs are mutually independent; runs are
  *    extended while every component has at most 256 amplitudes, and whole

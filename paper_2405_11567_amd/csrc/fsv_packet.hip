@@ -717,7 +717,7 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
     std::vector<uint32_t> &ent = S.ent, &reg = S.reg;
     std::vector<int32_t> csize, crow, order, pk_of, pfill, cnt, cur;
     PackScratch pk;
-    std::vector<int32_t> slot(N, 0), rpar(nsa);
+    std::vector<int32_t> slot(N, 0), pkt(N, 0), rpar(nsa);  // per touched amplitude: its slot and packet
     // support of the forward state from the reference (sector amplitude 0),
     // followed through the first runs while their nonzero packets are few
     bool track = !every_run;
@@ -765,7 +765,16 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
         }
         // Components, numbered in order of their smallest amplitude.
         std::vector<int32_t> &tv = uf.touched;
-        std::sort(tv.begin(), tv.end());
+        if ((int64_t)tv.size() * 8 > N) {  // most amplitudes touched: a scan of the marks beats a sort
+            tv.clear();
+            for (int64_t x = 0; x < N; ++x)
+                if (uf.seen[x]) tv.push_back((int32_t)x);
+        } else {
+            std::sort(tv.begin(), tv.end());
+        }
+        // the run's unions are final: point every touched amplitude at its
+        // root, so that the lookups below take one step (reset() undoes it)
+        for (int32_t x : tv) uf.parent[x] = uf.find(x);
         csize.clear();
         crow.clear();
         for (int32_t x : tv) {
@@ -805,12 +814,13 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
             const int sl = pfill[pk]++;
             ent[e0 + (size_t)pk * kPkt + sl] = (uint32_t)x;
             slot[x] = sl;
+            pkt[x] = pk;
         }
         // per packet and operator pair counts, then the regions
         cnt.assign((size_t)npk * m, 0);
         for (int jj = 0; jj < m; ++jj)
             for_pairs(pops[i + jj], lists, nsa, nsb, [&](int32_t s, int32_t, bool) {
-                ++cnt[(size_t)pk_of[uf.comp[uf.find(s)]] * m + jj];
+                ++cnt[(size_t)pkt[s] * m + jj];
                 return true;
             });
         int maxp = 0;
@@ -836,7 +846,7 @@ int plan_packets(int64_t nsa, int64_t nsb, const std::vector<PairOp> &pops, cons
         }
         for (int jj = 0; jj < m; ++jj)
             for_pairs(pops[i + jj], lists, nsa, nsb, [&](int32_t s, int32_t d, bool neg) {
-                const int pk = pk_of[uf.comp[uf.find(s)]];
+                const int pk = pkt[s];
                 const int at = cur[(size_t)pk * m + jj]++;
                 const uint32_t v = neg ? (uint32_t)(slot[d] | (slot[s] << 8)) : (uint32_t)(slot[s] | (slot[d] << 8));
                 reg[r0 + (size_t)pk * wr + kPktHdr + (at >> 1)] |= v << ((at & 1) << 4);
