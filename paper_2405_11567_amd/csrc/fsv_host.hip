@@ -168,6 +168,7 @@ struct fsv_plan {
     // engine): C, S, CT, ST, YT, gpart, epart offsets; [7] = end
     size_t na_off[8] = {};
     double *h_pin = nullptr;  // pinned: cs (2K) then out (K + 1) then gamma (4 M^2)
+    double *h_cs = nullptr;   // pinned, coherent: cs (2K) read by energy_grad's graph itself
     size_t pin_doubles = 0;
 
     // sector-compressed engine (default for energy_grad / ansatz_apply)
@@ -1134,6 +1135,18 @@ int upload_theta(fsv_plan &P, const double *theta) {
     return FSV_OK;
 }
 
+// energy_grad's angles: cos / sin into the coherent pinned block that the
+// graph's first node copies to the device (no separate copy call).
+int stage_theta(fsv_plan &P, const double *theta) {
+    if (P.K > 0 && !theta) return fail(FSV_EINVAL, "theta is NULL");
+    if (!finite_all(theta, (size_t)P.K)) return fail(FSV_ENONFINITE, "non-finite theta");
+    for (int k = 0; k < P.K; ++k) {
+        P.h_cs[2 * k] = std::cos(theta[k]);
+        P.h_cs[2 * k + 1] = std::sin(theta[k]);
+    }
+    return FSV_OK;
+}
+
 int download_out(fsv_plan &P, double *E_out, double *grad_out, bool with_grad) {
     double *h = P.h_pin + 2 * (size_t)P.K;
     const size_t cnt = with_grad ? (size_t)P.K + 1 : 1;
@@ -1187,11 +1200,17 @@ int capture(fsv_plan &P, F body, hipGraphExec_t *exec) {
 }
 
 int launch_energy_grad(fsv_plan &P, void *psi, void *lam) {
-    if (!P.use_graph) return run_energy_grad_body(P, psi, lam);
+    if (!P.use_graph) {
+        HIPCHECK(launch_copy_doubles(P.h_cs, P.d_cs, 2 * P.K, P.work));
+        return run_energy_grad_body(P, psi, lam);
+    }
     if (!P.g_eg || P.g_eg_psi != psi || P.g_eg_lam != lam) {
         if (P.g_eg) (void)hipGraphExecDestroy(P.g_eg);
         P.g_eg = nullptr;
-        int rc = capture(P, [&]() { return run_energy_grad_body(P, psi, lam); }, &P.g_eg);
+        int rc = capture(P, [&]() {
+            HIPCHECK(launch_copy_doubles(P.h_cs, P.d_cs, 2 * P.K, P.work));
+            return run_energy_grad_body(P, psi, lam);
+        }, &P.g_eg);
         if (rc) {
             P.g_eg = nullptr;
             return rc;
@@ -1341,6 +1360,7 @@ int build_device(fsv_plan &P) {
     const size_t M2 = (size_t)M * M;
     P.pin_doubles = 2 * (size_t)P.K + (size_t)P.K + 1 + 4 * M2 + 8;
     HIPCHECK(hipHostMalloc((void **)&P.h_pin, sizeof(double) * P.pin_doubles, hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void **)&P.h_cs, sizeof(double) * (2 * (size_t)P.K + 2), hipHostMallocCoherent));
 
     // sector tables
     P.sa = strings_of(M, P.na);
@@ -1617,6 +1637,7 @@ fsv_plan::~fsv_plan() {
     if (blas) (void)rocblas_destroy_handle(blas);
     for (auto &b : bufs) (void)hipFree(b.p);
     if (h_pin) (void)hipHostFree(h_pin);
+    if (h_cs) (void)hipHostFree(h_cs);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (ev_cs) (void)hipEventDestroy(ev_cs);
@@ -1636,7 +1657,7 @@ int autotune_sector(fsv_plan &P, void *psi, void *lam, std::string &rep) {
     const Cand keep{P.fuse_mode, P.fuse_budget_fwd, P.fuse_budget_rev};
     std::vector<double> th(P.K, 0.1);
     int rc;
-    if ((rc = upload_theta(P, th.data()))) return rc;
+    if ((rc = stage_theta(P, th.data()))) return rc;
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
@@ -1897,7 +1918,7 @@ int energy_grad(fsv_plan *P, const double *theta, void *psi, void *lam, double *
     int rc;
     if ((rc = fence_in(*P, true))) return rc;
     if ((rc = need_workspace(*P))) return rc;
-    if ((rc = upload_theta(*P, theta))) return rc;
+    if ((rc = stage_theta(*P, theta))) return rc;
     if ((rc = launch_energy_grad(*P, psi, lam))) return rc;
     if ((rc = download_out(*P, E_out, grad_out, true))) return rc;
     return FSV_OK;  // the host has waited for this call's work

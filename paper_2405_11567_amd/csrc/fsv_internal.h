@@ -102,6 +102,7 @@ void init_kernels();  // once per process, before any capture (sets kernel attri
 
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st);
 hipError_t launch_set_amp(void *psi, int vtype, uint64_t x, double re, hipStream_t st);
+hipError_t launch_copy_doubles(const double *src, double *dst, int n, hipStream_t st);
 // psi[idx[i]] = (val[i], 0) for i < n; vtype selects the storage (VType).
 hipError_t launch_set_list(void *psi, int vtype, const int64_t *idx, const double *val, int n, hipStream_t st);
 

@@ -47,6 +47,11 @@ __global__ void k_fill_tail(unsigned char *p, size_t n) {
     if (i < n) p[i] = 0;
 }
 
+// dst[i] = src[i] for i < n; src may be host memory (pinned, coherent).
+__global__ void k_copy_doubles(const double *__restrict__ src, double *__restrict__ dst, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
 // One amplitude set to (re, 0); vt selects the storage type.
 __global__ void k_set_amp(void *psi, int vt, uint64_t x, double re) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -461,6 +466,12 @@ hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t st) {
     if (tail) {
         hipLaunchKernelGGL(k_fill_tail, dim3(1), dim3(64), 0, st, (unsigned char *)ptr + n16 * 16, tail);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_doubles(const double *src, double *dst, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_doubles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
     return hipGetLastError();
 }
 
