@@ -382,8 +382,26 @@ def suite_c3():
         exercise_plan(p, engine=engine, stages=False)
 
 
+def suite_placement():
+    # 20 qubits: packet runs of a few hundred packets, placed by XCD; every
+    # XCD's range is padded to the same length, so a run's packet count is a
+    # multiple of 8, and the whole plan still passes its own program checks
+    p = random_problem(20, 10, 80, seed=1211, theta_std=0.4, replace=True, ordering=1)
+    plan = make_plan(p)
+    k = p.n_ops
+    start = np.zeros(k, np.int32)
+    tiles = np.zeros(k, np.int32)
+    ok(lib.fsv_plan_runs(plan, 1, start.ctypes.data_as(I32), tiles.ctypes.data_as(I32)), "runs")
+    placed = [int(t) for t in tiles if t >= 64]
+    if not placed or any(t % 8 for t in placed):
+        raise RuntimeError(f"packet counts of placed runs: {sorted(set(placed))}")
+    print("placement", len(set(int(start[t]) for t in range(k) if tiles[t] > 0)), "packet runs", flush=True)
+    ok(lib.fsv_plan_destroy(plan), "plan_destroy")
+    exercise_plan(p, stages=False, extras=False)
+
+
 SUITES = {"sigma": suite_sigma, "parity": suite_parity, "pools": suite_pools, "batch": suite_batch,
-          "c3": suite_c3}
+          "c3": suite_c3, "placement": suite_placement}
 
 if __name__ == "__main__":
     for name in sys.argv[1:]:

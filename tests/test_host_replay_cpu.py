@@ -69,6 +69,13 @@ def test_replay_batches(hostcheck):
     _replay(hostcheck, "batch")
 
 
+def test_replay_xcd_placement(hostcheck):
+    # a 20-qubit plan whose packet runs are placed by XCD: equal XCD ranges
+    # (packet counts multiples of 8), programs checked, calls replayed
+    out = _replay(hostcheck, "placement")
+    assert "placement" in out
+
+
 def test_replay_with_busy_streams(hostcheck):
     # the calls skip their stream fences when a stream is idle; here no stream
     # is ever idle, so every fence's event record and wait are exercised
